@@ -1,0 +1,261 @@
+/*
+ * symnmf.h -- C ABI of the MI355X (gfx950) randomized symmetric NMF library.
+ *
+ * Method: Hayashi, Aksoy, Ballard, Park, "Randomized Algorithms for Symmetric
+ * Nonnegative Matrix Factorization" (arXiv 2402.08134).  The library solves
+ * the regularised surrogate (Section 2.1.1, eq. surrogate_symnmf_obj)
+ *
+ *     min_{W, H >= 0}  ||X - W H^T||_F^2 + alpha ||W - H||_F^2
+ *
+ * by alternating updates of W (from H) then H (from W), on
+ *   - the full X (dense GEMM or CSR SpMM products),
+ *   - a low-rank approximate input X ~ U Lambda U^T (Algorithm LAI-SymNMF),
+ *   - leverage-score sampled problems (Algorithm LvS-SymNMF, hybrid sampling
+ *     of Section 4.2),
+ * with the HALS rule (eq. symhals_update2) or exact NLS by block principal
+ * pivoting (Section 2.1.1 / Appendix "Update() function").
+ *
+ * Conventions (all entry points):
+ *   - Every call returns a status code (SYMNMF_OK = 0 on success); no C++
+ *     exception crosses the ABI.  On failure, symnmf_last_error(ctx) holds a
+ *     message (for symnmf_create failures use symnmf_last_error(NULL)).
+ *   - Pointers named "device" are HIP device pointers on the current device;
+ *     "host" pointers are ordinary CPU memory.  Matrices are row-major.
+ *   - Work is ordered on the hip stream given to symnmf_create.  Calls that
+ *     return host values (create, residual, stats, history, iterate's
+ *     iteration count, sample count) synchronise that stream.
+ *   - A context is used by one host thread at a time.  Results are
+ *     deterministic (bitwise) for fixed inputs, options and seed.
+ *   - Sizes: 1 <= k <= 64; LAI rank k <= l <= 96 and l <= n.
+ */
+#ifndef SYMNMF_API_H_
+#define SYMNMF_API_H_
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define SYMNMF_OK 0
+#define SYMNMF_E_INVALID 1     /* bad argument (null pointer, size, dtype) */
+#define SYMNMF_E_UNSUPPORTED 2 /* valid but not supported combination     */
+#define SYMNMF_E_NOMEM 3       /* device allocation failed                */
+#define SYMNMF_E_DEVICE 4      /* a HIP runtime call failed               */
+#define SYMNMF_E_NUMERIC 5     /* numerical breakdown (e.g. Cholesky)     */
+#define SYMNMF_E_STATE 6       /* call not valid in the context's state   */
+
+/* matrix kinds and element types */
+#define SYMNMF_DENSE 0
+#define SYMNMF_CSR 1
+#define SYMNMF_F64 0
+#define SYMNMF_F32 1
+#define SYMNMF_BF16 2
+
+/* update rules */
+#define SYMNMF_RULE_HALS 0
+#define SYMNMF_RULE_BPP 1
+
+/* stopping modes */
+#define SYMNMF_STOP_NONE 0   /* run exactly the requested iterations         */
+#define SYMNMF_STOP_STALL 1  /* normalised residual fails to drop by more than
+                                stop_tol for stop_patience iterations
+                                (Section 6.1: 1e-4, four iterations)       */
+#define SYMNMF_STOP_TARGET 2 /* normalised residual <= target              */
+
+/* residual modes for symnmf_residual */
+#define SYMNMF_RESID_FAST 0  /* trace identity from the latest products
+                                (Appendix "Fast residual evaluation")      */
+#define SYMNMF_RESID_EXACT 1 /* FP64-accumulated pass against X            */
+#define SYMNMF_RESID_LAI 2   /* against U Lambda U^T (Appendix, LAI residual) */
+
+/* which factor */
+#define SYMNMF_W 0
+#define SYMNMF_H 1
+
+/* context modes (symnmf_stats.mode) */
+#define SYMNMF_MODE_PLAIN 0
+#define SYMNMF_MODE_LAI 1
+#define SYMNMF_MODE_LVS 2
+
+/* stats flags */
+#define SYMNMF_FLAG_LEV_SHIFT 1    /* chol(H^T H) needed a diagonal shift   */
+#define SYMNMF_FLAG_CHOLQR_SHIFT 2 /* CholeskyQR2 needed a diagonal shift   */
+
+/* The data matrix X (symmetric, n x n).  All pointers are device pointers,
+ * BORROWED: the caller keeps them alive and unchanged until symnmf_destroy.
+ *   DENSE: values = n x n row-major with leading dimension ld >= n; dtype
+ *          F64, F32 or BF16.
+ *   CSR:   row_ptr int32[n+1], col_idx int32[nnz] (sorted within each row),
+ *          values[nnz] of dtype F32 or F64.  Both triangles are stored. */
+typedef struct symnmf_matrix {
+  int32_t kind;
+  int32_t dtype;
+  int64_t n;
+  int64_t ld;
+  int64_t nnz;
+  const void* values;
+  const int32_t* row_ptr;
+  const int32_t* col_idx;
+} symnmf_matrix;
+
+/* Options; fill with symnmf_default_options() and then override fields.
+ * Defaults are the paper's settings (Section 6). */
+typedef struct symnmf_options {
+  int32_t struct_size;    /* sizeof(symnmf_options)                         */
+  int32_t rule;           /* SYMNMF_RULE_HALS (default) or SYMNMF_RULE_BPP  */
+  int32_t compute_dtype;  /* dense products: F64 (needs F64 X), F32, BF16;
+                             default: the dtype of X                         */
+  int32_t stop_mode;      /* default SYMNMF_STOP_NONE                       */
+  double stop_tol;        /* default 1e-4                                   */
+  int32_t stop_patience;  /* default 4                                      */
+  int32_t check_every;    /* iterations between host polls of the stop flag
+                             (default 8); iterations after a stop are skipped
+                             on the device                                  */
+  double target;          /* residual target for SYMNMF_STOP_TARGET         */
+  double tau;             /* hybrid threshold; < 0 means 1/s (Section 6.2)  */
+  int32_t resid_every;    /* LvS: evaluate the residual every this many
+                             iterations (needs a full product); default 1   */
+  int32_t max_history;    /* capacity of the per-iteration residual log
+                             (default 4096)                                 */
+  int32_t reserved[6];
+} symnmf_options;
+
+typedef struct symnmf_stats {
+  int32_t struct_size;
+  int32_t mode;           /* SYMNMF_MODE_*                                  */
+  int32_t iterations;     /* completed iterations (all iterate calls)       */
+  int32_t stopped;        /* 1 once the stop rule fired                     */
+  int32_t k;
+  int32_t l;              /* LAI rank (0 if none)                           */
+  int64_t n;
+  double alpha;           /* regulariser used                               */
+  double zeta;            /* mean of all n^2 entries of X                   */
+  double normsq;          /* ||X||_F^2                                      */
+  double maxval;          /* max(X)                                         */
+  double last_residual;   /* last normalised residual from the log          */
+  int64_t s_D;            /* LvS: deterministic rows in the last sample     */
+  int64_t sample_rows;    /* LvS: distinct rows in the last sample          */
+  double theta_over_k;    /* LvS: deterministic leverage mass / k           */
+  int32_t flags;          /* SYMNMF_FLAG_* */
+  int32_t reserved[7];
+} symnmf_stats;
+
+typedef struct symnmf_ctx symnmf_ctx;
+
+/* Fill *opt with the defaults listed above.  Host pointer. */
+int symnmf_default_options(symnmf_options* opt);
+
+/* Create a solver context (Section 2.1.1; initialisation of Section 6).
+ *   out:   host pointer receiving the new context (owned by the caller, freed
+ *          with symnmf_destroy).
+ *   X:     host pointer to the matrix descriptor (device data, borrowed).
+ *   k:     rank, 1..64.
+ *   alpha: regulariser; alpha <= 0 selects alpha = max(X) (Section 6.1).
+ *   s:     number of leverage-score samples per half-iteration; 0 = no
+ *          sampling, s > 0 selects LvS mode (CSR X only, else E_UNSUPPORTED).
+ *   seed:  Philox-4x32-10 key for the random initial H, the sketch and the
+ *          sample draws.
+ *   opt:   host pointer or NULL for defaults.
+ *   hip_stream: the hipStream_t to order all work on (NULL = null stream).
+ * Runs one pass over X for ||X||_F^2, mean, max and row sums, then sets
+ * H0 = U[0,1) * 2 sqrt(zeta / k) and W0 = H0.  Synchronises the stream.
+ * Errors: E_INVALID (null pointers, n < 1, k out of range, bad dtype),
+ * E_UNSUPPORTED, E_NOMEM, E_DEVICE. */
+int symnmf_create(symnmf_ctx** out, const symnmf_matrix* X, int32_t k, double alpha, int64_t s,
+                  uint64_t seed, const symnmf_options* opt, void* hip_stream);
+
+/* Build the low-rank approximate input X ~ U Lambda U^T with Algorithm
+ * Apx-EVD (randomized range finder, Algorithm RRF, with 2q+1 products by X,
+ * each followed by CholeskyQR2 in FP64; T = Q^T X Q; Jacobi EVD of T;
+ * U = Q Q_T) and switch the context to LAI mode (Algorithm LAI-SymNMF).
+ * Requires dense X and no sampling.  l: k <= l <= min(n, 96).  q >= 0.
+ * Errors: E_INVALID, E_UNSUPPORTED (CSR or s > 0), E_NUMERIC (CholeskyQR2
+ * breakdown even with the shift), E_STATE. */
+int symnmf_lai(symnmf_ctx* ctx, int32_t l, int32_t q);
+
+/* Iterative refinement (Section 3.3, "Iterative Refinement"): switch a
+ * context in LAI mode back to the full X for the following iterations, keeping
+ * the current factors.  The stop rule becomes (stop_mode, target) with the
+ * context's tolerance and patience, and its state is reset (the first refined
+ * residual starts a fresh stall count).  Errors: E_STATE (not in LAI mode),
+ * E_INVALID (stop_mode). */
+int symnmf_refine(symnmf_ctx* ctx, int32_t stop_mode, double target);
+
+/* Run up to `iters` iterations (each: W from H, then H from W) in the
+ * context's mode.  With a stop mode set, iterations after the rule fires are
+ * skipped on the device.  *done (host pointer, may be NULL) receives the
+ * iterations completed by this call.  Synchronises the stream. */
+int symnmf_iterate(symnmf_ctx* ctx, int32_t iters, int32_t* done);
+
+/* Normalised residuals of the current factors (Appendix "Stopping
+ * criteria").  out (host, 2 doubles) = { ||X - W H^T|| / ||X||,
+ * ||X - H H^T|| / ||X|| }, norms against the matrix the mode names
+ * (SYMNMF_RESID_LAI: U Lambda U^T, normalised by ||Lambda||).
+ * SYMNMF_RESID_FAST uses the trace identity and the Gram matrices of the
+ * current factors (one full product for each entry).
+ * Synchronises the stream.  Errors: E_INVALID (mode), E_STATE (LAI residual
+ * without symnmf_lai). */
+int symnmf_residual(symnmf_ctx* ctx, int32_t mode, double out[2]);
+
+/* Copy a factor (which = SYMNMF_W or SYMNMF_H) from / to caller-owned device
+ * memory holding n x k row-major values of `dtype` (F64 or F32).
+ * set_factor also refreshes the Gram matrix of that factor.  Stream-ordered. */
+int symnmf_set_factor(symnmf_ctx* ctx, int32_t which, const void* src, int32_t dtype);
+int symnmf_get_factor(symnmf_ctx* ctx, int32_t which, void* dst, int32_t dtype);
+
+/* Export the LAI factors: U (device, n x l FP64 row-major) and lambda
+ * (device, l FP64, descending).  Either may be NULL.  Errors: E_STATE. */
+int symnmf_get_lai(symnmf_ctx* ctx, void* U, void* lambda);
+
+/* Y = X * B with the context's product kernel (dense GEMM in the compute
+ * dtype, or CSR SpMM).  B: device, n x c (c <= 96) of the factor dtype
+ * (F64 when the compute dtype is F64, else F32); Y: device, n x c of the same
+ * dtype.  Stream-ordered. */
+int symnmf_apply_x(symnmf_ctx* ctx, const void* B, int32_t c, void* Y);
+
+/* One half-iteration in the context's mode: side 0 updates W from H, side 1
+ * updates H from W (W then H is the order of Algorithms LAI-SymNMF and
+ * LvS-SymNMF).  half_iter selects the Philox sub-stream of the LvS draws.
+ * Stream-ordered. */
+int symnmf_half_step(symnmf_ctx* ctx, int32_t side, int32_t half_iter);
+
+/* Leverage scores (eq. lev_score_def) of the current factor `which`, via
+ * chol(F^T F) and a triangular solve (Algorithm LvS-SymNMF):
+ * lev[i] = ||F[i,:] R^{-1}||^2.  lev: device, n doubles.  Stream-ordered. */
+int symnmf_leverage(symnmf_ctx* ctx, int32_t which, void* lev);
+
+/* Hybrid leverage-score sample (Section 4.2, eq. SH) from given scores.
+ *   lev:     device, n doubles (leverage scores of a rank-k factor).
+ *   half_iter: Philox sub-stream of the draws.
+ *   rows:    device, int32[cap]: sampled rows, ascending.
+ *   weights: device, double[cap]: the row's diagonal entry of S^T S
+ *            (1 for deterministic rows, c / (s_R p~_i) for a row drawn c times).
+ *   cap:     capacity, >= s.   count: host, receives the number of rows.
+ * Rows with lev_i / k >= tau are deterministic; s_R = s - s_D draws with
+ * replacement from p~_i = w_i / W_R, w_i = floor(lev_i 2^40).  Uses the
+ * context's k, s, tau and seed.  Synchronises the stream. */
+int symnmf_sample(symnmf_ctx* ctx, const void* lev, int32_t half_iter, void* rows, void* weights,
+                  int64_t cap, int64_t* count);
+
+/* Per-iteration normalised residual log (fast mode): host array out[cap],
+ * *count receives the number of entries (<= cap).  Synchronises. */
+int symnmf_history(symnmf_ctx* ctx, double* out, int32_t cap, int32_t* count);
+
+/* Statistics and counters (host struct; set out->struct_size).  Synchronises. */
+int symnmf_get_stats(symnmf_ctx* ctx, symnmf_stats* out);
+
+/* Last error message of the context (or of the last failed create when ctx is
+ * NULL).  The string is owned by the library and valid until the next call
+ * on the same context. */
+const char* symnmf_last_error(const symnmf_ctx* ctx);
+
+/* Free everything the context owns (never touches X).  NULL is a no-op. */
+void symnmf_destroy(symnmf_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SYMNMF_API_H_ */

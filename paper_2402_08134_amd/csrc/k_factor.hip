@@ -1,0 +1,730 @@
+// Factor-side kernels: random fills, Gram matrices, the fused end-of-iteration
+// residual / stop step, the regularised HALS sweep, row-times-small-matrix
+// products, and one-workgroup FP64 Cholesky / Jacobi EVD on k x k and l x l
+// matrices.  All reductions use fixed orders so results are bitwise
+// reproducible.
+#include "kernels.hpp"
+
+namespace {
+
+__global__ __launch_bounds__(256) void k_sum_partials(const double* __restrict__ part, int nb, double* __restrict__ out) {
+  __shared__ double sc[8];
+  double v = 0.0;
+  for (int i = threadIdx.x; i < nb; i += 256) v += part[i];
+  const double t = block_sum(v, sc);
+  if (threadIdx.x == 0) out[0] = t;
+}
+
+template <typename TF>
+__global__ __launch_bounds__(256) void k_init_uniform(TF* __restrict__ F, int64_t count, double scale, uint64_t seed) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= count) return;
+  F[e] = (TF)(u53(philox_value(seed, (uint64_t)e, 0, TAG_H0)) * scale);
+}
+
+__global__ __launch_bounds__(256) void k_gaussian(double* __restrict__ out, int64_t count, uint64_t seed, uint32_t sub,
+                                                  uint32_t tag) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= count) return;
+  uint64_t v0, v1;
+  philox_block(seed, (uint64_t)e, sub, tag, v0, v1);
+  const double a = u53(v0), b = u53(v1);
+  out[e] = sqrt(-2.0 * log(1.0 - a)) * cos(6.283185307179586 * b);
+}
+
+template <typename TS, typename TD>
+__global__ __launch_bounds__(256) void k_convert(const TS* __restrict__ src, TD* __restrict__ dst, int64_t count) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e < count) dst[e] = (TD)src[e];
+}
+
+// ---------------------------------------------------------------------------
+// Gram: part[b] = sum over this block's rows of w_r a_r^T b_r (FP64).
+// 16 x 16 threads; thread (ty, tx) owns entries (ty + 16 i, tx + 16 j).
+// ---------------------------------------------------------------------------
+template <typename TA, typename TB, int T>
+__global__ __launch_bounds__(256) void k_gram(const TA* __restrict__ A, int64_t lda, int ca, const TB* __restrict__ B,
+                                              int64_t ldb, int cb, int n, const int* __restrict__ rows,
+                                              const double* __restrict__ w, const int* __restrict__ d_count,
+                                              int rows_per_block, double* __restrict__ part,
+                                              const DevState* __restrict__ st) {
+  if (stopped(st)) return;
+  constexpr int RB = 16;
+  constexpr int CM = 16 * T;
+  __shared__ double As[RB][CM + 1];
+  __shared__ double Bs[RB][CM + 1];
+  const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
+  const int nrows = rows ? *d_count : n;
+  const int r0 = blockIdx.x * rows_per_block;
+  const int r1 = min(nrows, r0 + rows_per_block);
+  double acc[T][T];
+#pragma unroll
+  for (int i = 0; i < T; ++i)
+#pragma unroll
+    for (int j = 0; j < T; ++j) acc[i][j] = 0.0;
+  for (int rb = r0; rb < r1; rb += RB) {
+    __syncthreads();
+    for (int e = tid; e < RB * CM; e += 256) {
+      const int rr = e / CM, q = e - rr * CM;
+      const int r = rb + rr;
+      double a = 0.0, b = 0.0;
+      if (r < r1) {
+        const int src = rows ? rows[r] : r;
+        if (q < ca) a = (double)A[(int64_t)src * lda + q] * (w ? w[r] : 1.0);
+        if (q < cb) b = (double)B[(int64_t)src * ldb + q];
+      }
+      As[rr][q] = a;
+      Bs[rr][q] = b;
+    }
+    __syncthreads();
+#pragma unroll 4
+    for (int rr = 0; rr < RB; ++rr) {
+      double bv[T];
+#pragma unroll
+      for (int j = 0; j < T; ++j) bv[j] = Bs[rr][tx + 16 * j];
+#pragma unroll
+      for (int i = 0; i < T; ++i) {
+        const double a = As[rr][ty + 16 * i];
+#pragma unroll
+        for (int j = 0; j < T; ++j) acc[i][j] = fma(a, bv[j], acc[i][j]);
+      }
+    }
+  }
+  double* out = part + (int64_t)blockIdx.x * ca * cb;
+#pragma unroll
+  for (int i = 0; i < T; ++i)
+#pragma unroll
+    for (int j = 0; j < T; ++j) {
+      const int p = ty + 16 * i, q = tx + 16 * j;
+      if (p < ca && q < cb) out[p * cb + q] = acc[i][j];
+    }
+}
+
+__global__ __launch_bounds__(256) void k_gram_reduce(const double* __restrict__ part, int nb, int ca, int cb,
+                                                     double* __restrict__ G, double* __restrict__ Ghat, int kp,
+                                                     double alpha, const DevState* __restrict__ st) {
+  if (stopped(st)) return;
+  const int e = blockIdx.x * 256 + threadIdx.x;
+  const int tot = (Ghat ? kp * kp : ca * cb);
+  if (e >= max(tot, ca * cb)) return;
+  if (e < ca * cb) {
+    double acc = 0.0;
+    for (int b = 0; b < nb; ++b) acc += part[(int64_t)b * ca * cb + e];
+    if (G) G[e] = acc;
+    if (Ghat) {
+      const int p = e / cb, q = e - p * cb;
+      Ghat[p * kp + q] = acc + (p == q ? alpha : 0.0);
+    }
+  }
+  if (Ghat && e < kp * kp) {
+    const int p = e / kp, q = e - p * kp;
+    if (p >= ca || q >= cb) Ghat[e] = (p == q) ? 1.0 : 0.0;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_frob(const double* __restrict__ A, const double* __restrict__ B, int count,
+                                              double* __restrict__ out) {
+  __shared__ double sc[8];
+  double v = 0.0;
+  for (int i = threadIdx.x; i < count; i += 256) v = fma(A[i], B[i], v);
+  const double t = block_sum(v, sc);
+  if (threadIdx.x == 0) out[0] = t;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_dot(const T* __restrict__ A, const T* __restrict__ B, int64_t count,
+                                             double* __restrict__ part, const DevState* __restrict__ st) {
+  if (stopped(st)) return;
+  __shared__ double sc[8];
+  double v = 0.0;
+  const int64_t stride = (int64_t)gridDim.x * 256;
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < count; e += stride)
+    v = fma((double)A[e], (double)B[e], v);
+  const double t = block_sum(v, sc);
+  if (threadIdx.x == 0) part[blockIdx.x] = t;
+}
+
+__global__ __launch_bounds__(256) void k_finish_iteration(const double* __restrict__ dot_part, int nb,
+                                                          const double* __restrict__ Ga,
+                                                          const double* __restrict__ Gb, int k,
+                                                          const double* __restrict__ d_normsq, DevState* st,
+                                                          double* __restrict__ hist, StopRule rule) {
+  if (st->done) return;
+  if (dot_part == nullptr) {  // iteration without a residual evaluation
+    if (threadIdx.x == 0) st->iter += 1;
+    return;
+  }
+  __shared__ double sc[8];
+  double d = 0.0;
+  for (int i = threadIdx.x; i < nb; i += 256) d += dot_part[i];
+  const double dot = block_sum(d, sc);
+  double g = 0.0;
+  for (int i = threadIdx.x; i < k * k; i += 256) g = fma(Ga[i], Gb[i], g);
+  const double gg = block_sum(g, sc);
+  if (threadIdx.x == 0) {
+    const double nx = *d_normsq;
+    const double r2 = nx - 2.0 * dot + gg;
+    const double r = sqrt(fmax(r2, 0.0) / nx);
+    const int t = st->iter;
+    if (t < rule.max_hist) hist[t] = r;
+    if (t > 0) st->stall = (st->prev - r <= rule.tol) ? st->stall + 1 : 0;
+    st->prev = r;
+    st->last = r;
+    st->iter = t + 1;
+    if (rule.mode == SYMNMF_STOP_STALL && st->stall >= rule.patience) st->done = 1;
+    if (rule.mode == SYMNMF_STOP_TARGET && r <= rule.target) st->done = 1;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Regularised HALS sweep, one row per thread, FP64 arithmetic.  Ghat is read
+// with wave-uniform addresses (scalar loads); KP is k rounded up so the row
+// lives in registers.
+// ---------------------------------------------------------------------------
+template <int KP, typename TF, bool SEG>
+__global__ __launch_bounds__(64) void k_hals(int n, int k, const TF* __restrict__ Y, const int* __restrict__ seg_ptr,
+                                             const int* __restrict__ seg_src, const double* __restrict__ seg_val,
+                                             const TF* __restrict__ Src, TF* __restrict__ Dst,
+                                             const double* __restrict__ Ghat, double alpha,
+                                             const DevState* __restrict__ st) {
+  if (stopped(st)) return;
+  const int j = blockIdx.x * 64 + threadIdx.x;
+  if (j >= n) return;
+  const int64_t base = (int64_t)j * k;
+  double w[KP];
+#pragma unroll
+  for (int i = 0; i < KP; ++i) w[i] = (i < k) ? (double)Dst[base + i] : 0.0;
+  int e0 = 0, e1 = 0;
+  if (SEG) {
+    e0 = seg_ptr[j];
+    e1 = seg_ptr[j + 1];
+  }
+#pragma unroll
+  for (int i = 0; i < KP; ++i) {
+    if (i < k) {
+      double y = alpha * (double)Src[base + i];
+      if (SEG) {
+        for (int e = e0; e < e1; ++e) y = fma(seg_val[e], (double)Src[(int64_t)seg_src[e] * k + i], y);
+      } else {
+        y += (double)Y[base + i];
+      }
+      const double* g = Ghat + i * KP;
+      double sacc = 0.0;
+#pragma unroll
+      for (int l = 0; l < KP; ++l) sacc = fma(w[l], g[l], sacc);
+      w[i] = fmax(0.0, w[i] + (y - sacc) / g[i]);
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < KP; ++i)
+    if (i < k) Dst[base + i] = (TF)w[i];
+}
+
+template <typename TA, typename TO>
+__global__ __launch_bounds__(256) void k_rowmat(const TA* __restrict__ A, int64_t lda, int n, int l,
+                                                const double* __restrict__ M, const double* __restrict__ scale, int c,
+                                                TO* __restrict__ out, int64_t ldo, const DevState* __restrict__ st) {
+  if (stopped(st)) return;
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= (int64_t)n * c) return;
+  const int j = (int)(e / c), q = (int)(e - (int64_t)j * c);
+  const TA* a = A + (int64_t)j * lda;
+  double acc = 0.0;
+  if (scale) {
+    for (int p = 0; p < l; ++p) acc = fma((double)a[p] * scale[p], M[p * c + q], acc);
+  } else {
+    for (int p = 0; p < l; ++p) acc = fma((double)a[p], M[p * c + q], acc);
+  }
+  out[(int64_t)j * ldo + q] = (TO)acc;
+}
+
+// ---------------------------------------------------------------------------
+// One-workgroup Cholesky (upper R, R^T R = G + shift I) and R^{-1}.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_chol_inverse(const double* __restrict__ G, int k, double* __restrict__ R,
+                                                      double* __restrict__ Rinv, int* d_flags, int flag_bit,
+                                                      int* d_fail) {
+  extern __shared__ double A[];  // k x (k + 1)
+  __shared__ int bad;
+  __shared__ double shift;
+  const int lda = k + 1;
+  const int tid = threadIdx.x;
+  double trace = 0.0;
+  for (int i = 0; i < k; ++i) trace += G[i * k + i];
+  for (int attempt = 0; attempt < 6; ++attempt) {
+    if (tid == 0) {
+      bad = 0;
+      shift = attempt == 0 ? 0.0 : 1e-12 * pow(100.0, (double)(attempt - 1)) * fmax(trace, 1e-300) / k;
+    }
+    __syncthreads();
+    for (int e = tid; e < k * k; e += 256) {
+      const int p = e / k, q = e - p * k;
+      A[p * lda + q] = G[e] + (p == q ? shift : 0.0);
+    }
+    __syncthreads();
+    for (int j = 0; j < k; ++j) {
+      if (tid == 0) {
+        const double d = A[j * lda + j];
+        if (!(d > 0.0) || !isfinite(d)) bad = 1;
+        A[j * lda + j] = bad ? 1.0 : sqrt(d);
+      }
+      __syncthreads();
+      if (bad) break;
+      const double djj = A[j * lda + j];
+      for (int q = j + 1 + tid; q < k; q += 256) A[j * lda + q] /= djj;
+      __syncthreads();
+      const int m = k - j - 1;
+      for (int e = tid; e < m * m; e += 256) {
+        const int p = j + 1 + e / m, q = j + 1 + e % m;
+        if (q >= p) A[p * lda + q] -= A[j * lda + p] * A[j * lda + q];
+      }
+      __syncthreads();
+    }
+    if (!bad) break;
+    __syncthreads();
+  }
+  if (bad) {
+    if (tid == 0) *d_fail = 1;
+    return;
+  }
+  if (tid == 0 && shift > 0.0 && d_flags) atomicOr(d_flags, flag_bit);
+  for (int e = tid; e < k * k; e += 256) {
+    const int p = e / k, q = e - p * k;
+    R[e] = (q >= p) ? A[p * lda + q] : 0.0;
+  }
+  // Rinv column c: solve R x = e_c by back substitution (x_i = 0 for i > c).
+  for (int c = tid; c < k; c += 256) {
+    for (int i = k - 1; i >= 0; --i) {
+      double v = 0.0;
+      if (i <= c) {
+        v = (i == c) ? 1.0 : 0.0;
+        for (int p = i + 1; p <= c; ++p) v -= A[i * lda + p] * Rinv[p * k + c];
+        v /= A[i * lda + i];
+      }
+      Rinv[i * k + c] = v;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Parallel cyclic Jacobi (round-robin pairing) on A = (T + T^T) / 2 in LDS;
+// V accumulated in global memory (`Vw`), then columns sorted by descending
+// eigenvalue into V.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_jacobi(const double* __restrict__ T, int l, double* __restrict__ Vw,
+                                                double* __restrict__ V, double* __restrict__ lam) {
+  extern __shared__ double A[];  // l x (l + 1)
+  __shared__ double cs[64], sn[64];
+  __shared__ int pp[64], qq[64];
+  __shared__ int perm[128];
+  __shared__ double red[8];
+  __shared__ int order[128];
+  __shared__ int conv;
+  const int lda = l + 1;
+  const int tid = threadIdx.x;
+  const int m = l + (l & 1);
+  const int half = m / 2;
+  for (int e = tid; e < l * l; e += 256) {
+    const int p = e / l, q = e - p * l;
+    A[p * lda + q] = 0.5 * (T[p * l + q] + T[q * l + p]);
+    Vw[e] = (p == q) ? 1.0 : 0.0;
+  }
+  for (int i = tid; i < m; i += 256) perm[i] = i;
+  __syncthreads();
+  for (int sweep = 0; sweep < 40; ++sweep) {
+    double off = 0.0, dg = 0.0;
+    for (int e = tid; e < l * l; e += 256) {
+      const int p = e / l, q = e - p * l;
+      const double a = A[p * lda + q];
+      if (p == q) dg += a * a; else off += a * a;
+    }
+    const double toff = block_sum(off, red);
+    __syncthreads();
+    const double tdg = block_sum(dg, red);
+    if (tid == 0) conv = (toff <= 1e-30 * (toff + tdg)) ? 1 : 0;
+    __syncthreads();
+    if (conv) break;
+    for (int step = 0; step < m - 1; ++step) {
+      if (tid < half) {
+        int p = perm[tid], q = perm[m - 1 - tid];
+        if (p > q) { const int t = p; p = q; q = t; }
+        double c = 1.0, s = 0.0;
+        if (q < l) {
+          const double apq = A[p * lda + q];
+          if (fabs(apq) > 1e-300) {
+            const double theta = (A[q * lda + q] - A[p * lda + p]) / (2.0 * apq);
+            const double t = (theta >= 0.0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(1.0 + theta * theta));
+            c = 1.0 / sqrt(1.0 + t * t);
+            s = t * c;
+          }
+        }
+        pp[tid] = p;
+        qq[tid] = q;
+        cs[tid] = c;
+        sn[tid] = s;
+      }
+      __syncthreads();
+      // columns p, q of A and V
+      for (int e = tid; e < half * l; e += 256) {
+        const int i = e / l, r = e - i * l;
+        const int p = pp[i], q = qq[i];
+        if (q < l && sn[i] != 0.0) {
+          const double c = cs[i], s = sn[i];
+          const double ap = A[r * lda + p], aq = A[r * lda + q];
+          A[r * lda + p] = c * ap - s * aq;
+          A[r * lda + q] = s * ap + c * aq;
+          const double vp = Vw[r * l + p], vq = Vw[r * l + q];
+          Vw[r * l + p] = c * vp - s * vq;
+          Vw[r * l + q] = s * vp + c * vq;
+        }
+      }
+      __syncthreads();
+      // rows p, q of A
+      for (int e = tid; e < half * l; e += 256) {
+        const int i = e / l, r = e - i * l;
+        const int p = pp[i], q = qq[i];
+        if (q < l && sn[i] != 0.0) {
+          const double c = cs[i], s = sn[i];
+          const double ap = A[p * lda + r], aq = A[q * lda + r];
+          A[p * lda + r] = c * ap - s * aq;
+          A[q * lda + r] = s * ap + c * aq;
+        }
+      }
+      __syncthreads();
+      if (tid == 0) {
+        const int last = perm[m - 1];
+        for (int j = m - 1; j >= 2; --j) perm[j] = perm[j - 1];
+        perm[1] = last;
+      }
+      __syncthreads();
+    }
+  }
+  if (tid == 0) {
+    for (int i = 0; i < l; ++i) order[i] = i;
+    for (int i = 0; i < l; ++i) {
+      int best = i;
+      for (int j = i + 1; j < l; ++j)
+        if (A[order[j] * lda + order[j]] > A[order[best] * lda + order[best]]) best = j;
+      const int t = order[i];
+      order[i] = order[best];
+      order[best] = t;
+    }
+  }
+  __syncthreads();
+  for (int i = tid; i < l; i += 256) lam[i] = A[order[i] * lda + order[i]];
+  for (int e = tid; e < l * l; e += 256) {
+    const int r = e / l, j = e - r * l;
+    V[e] = Vw[r * l + order[j]];
+  }
+}
+
+__global__ __launch_bounds__(256) void k_col_argmax(const double* __restrict__ U, int n, int l, double* __restrict__ sgn) {
+  __shared__ double bv[256];
+  __shared__ int bi[256];
+  const int j = blockIdx.x;
+  double best = -1.0;
+  int bidx = 0x7fffffff;
+  for (int i = threadIdx.x; i < n; i += 256) {
+    const double a = fabs(U[(int64_t)i * l + j]);
+    if (a > best) {
+      best = a;
+      bidx = i;
+    }
+  }
+  bv[threadIdx.x] = best;
+  bi[threadIdx.x] = bidx;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) {
+      const double a = bv[threadIdx.x + o];
+      const int ai = bi[threadIdx.x + o];
+      if (a > bv[threadIdx.x] || (a == bv[threadIdx.x] && ai < bi[threadIdx.x])) {
+        bv[threadIdx.x] = a;
+        bi[threadIdx.x] = ai;
+      }
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) sgn[j] = (U[(int64_t)bi[0] * l + j] < 0.0) ? -1.0 : 1.0;
+}
+
+__global__ __launch_bounds__(256) void k_col_scale(double* __restrict__ U, int n, int l, const double* __restrict__ sgn) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= (int64_t)n * l) return;
+  U[e] *= sgn[e % l];
+}
+
+// ---------------------------------------------------------------------------
+// Scans: 1024 items per block (4 per thread), block totals scanned by one
+// block, then offsets added.
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ T block_exclusive_scan(T v, T* wsum, T& total) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  T x = v;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const T y = __shfl_up(x, o, 64);
+    if (lane >= o) x += y;
+  }
+  if (lane == 63) wsum[w] = x;
+  __syncthreads();
+  T off = 0;
+  for (int i = 0; i < w; ++i) off += wsum[i];
+  total = 0;
+  for (int i = 0; i < 4; ++i) total += wsum[i];
+  __syncthreads();
+  return off + x - v;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_scan_blocks(const T* __restrict__ in, int n, T* __restrict__ bsum) {
+  __shared__ T ws[4];
+  const int base = blockIdx.x * 1024 + threadIdx.x * 4;
+  T s = 0;
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+    if (base + u < n) s += in[base + u];
+  T tot;
+  block_exclusive_scan<T>(s, ws, tot);
+  if (threadIdx.x == 0) bsum[blockIdx.x] = tot;
+}
+
+template <typename T>
+__global__ void k_scan_totals(T* bsum, int nb, T* grand) {
+  if (threadIdx.x != 0) return;
+  T acc = 0;
+  for (int b = 0; b < nb; ++b) {
+    const T v = bsum[b];
+    bsum[b] = acc;
+    acc += v;
+  }
+  if (grand) *grand = acc;
+}
+
+template <typename T, bool INCLUSIVE>
+__global__ __launch_bounds__(256) void k_scan_apply(const T* __restrict__ in, int n, const T* __restrict__ boff,
+                                                    T* __restrict__ out) {
+  __shared__ T ws[4];
+  const int base = blockIdx.x * 1024 + threadIdx.x * 4;
+  T v[4];
+  T s = 0;
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    v[u] = (base + u < n) ? in[base + u] : (T)0;
+    s += v[u];
+  }
+  T tot;
+  T run = block_exclusive_scan<T>(s, ws, tot) + boff[blockIdx.x];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    if (INCLUSIVE) run += v[u];
+    if (base + u < n) out[base + u] = run;
+    if (!INCLUSIVE) run += v[u];
+  }
+}
+
+template <int KP, typename TF>
+void hals_launch(int n, int k, const void* Y, const int* sp, const int* ss, const double* sv, const void* Src,
+                 void* Dst, const double* Ghat, double alpha, const DevState* st, hipStream_t s) {
+  const int nb = ceil_div(n, 64);
+  if (sp)
+    k_hals<KP, TF, true><<<nb, 64, 0, s>>>(n, k, (const TF*)Y, sp, ss, sv, (const TF*)Src, (TF*)Dst, Ghat, alpha, st);
+  else
+    k_hals<KP, TF, false><<<nb, 64, 0, s>>>(n, k, (const TF*)Y, sp, ss, sv, (const TF*)Src, (TF*)Dst, Ghat, alpha, st);
+}
+
+template <typename TA, typename TB, int T>
+void gram_launch(const void* A, int64_t lda, int ca, const void* B, int64_t ldb, int cb, int n, const int* rows,
+                 const double* w, const int* d_count, int nb, int rpb, double* part, const DevState* st,
+                 hipStream_t s) {
+  k_gram<TA, TB, T><<<nb, 256, 0, s>>>((const TA*)A, lda, ca, (const TB*)B, ldb, cb, n, rows, w, d_count, rpb, part,
+                                       st);
+}
+
+template <typename TA, typename TB>
+void gram_t(int t, const void* A, int64_t lda, int ca, const void* B, int64_t ldb, int cb, int n, const int* rows,
+            const double* w, const int* d_count, int nb, int rpb, double* part, const DevState* st, hipStream_t s) {
+  switch (t) {
+    case 1: gram_launch<TA, TB, 1>(A, lda, ca, B, ldb, cb, n, rows, w, d_count, nb, rpb, part, st, s); break;
+    case 2: gram_launch<TA, TB, 2>(A, lda, ca, B, ldb, cb, n, rows, w, d_count, nb, rpb, part, st, s); break;
+    case 3: gram_launch<TA, TB, 3>(A, lda, ca, B, ldb, cb, n, rows, w, d_count, nb, rpb, part, st, s); break;
+    case 4: gram_launch<TA, TB, 4>(A, lda, ca, B, ldb, cb, n, rows, w, d_count, nb, rpb, part, st, s); break;
+    case 5: gram_launch<TA, TB, 5>(A, lda, ca, B, ldb, cb, n, rows, w, d_count, nb, rpb, part, st, s); break;
+    default: gram_launch<TA, TB, 6>(A, lda, ca, B, ldb, cb, n, rows, w, d_count, nb, rpb, part, st, s); break;
+  }
+}
+
+}  // namespace
+
+// ===========================================================================
+// Launchers
+// ===========================================================================
+
+void sum_partials(const double* part, int nb, double* out, hipStream_t s) {
+  k_sum_partials<<<1, 256, 0, s>>>(part, nb, out);
+}
+
+int init_uniform_factor(void* F, int fdtype, int n, int k, double scale, uint64_t seed, hipStream_t s) {
+  const int64_t cnt = (int64_t)n * k;
+  if (fdtype == SYMNMF_F64)
+    k_init_uniform<double><<<ceil_div(cnt, 256), 256, 0, s>>>((double*)F, cnt, scale, seed);
+  else
+    k_init_uniform<float><<<ceil_div(cnt, 256), 256, 0, s>>>((float*)F, cnt, scale, seed);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int gen_gaussian(double* out, int64_t count, uint64_t seed, uint32_t sub, uint32_t tag, hipStream_t s) {
+  k_gaussian<<<ceil_div(count, 256), 256, 0, s>>>(out, count, seed, sub, tag);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int copy_convert(const void* src, int sdtype, void* dst, int ddtype, int64_t count, hipStream_t s) {
+  const int nb = ceil_div(count, 256);
+  if (sdtype == SYMNMF_F64 && ddtype == SYMNMF_F64)
+    k_convert<double, double><<<nb, 256, 0, s>>>((const double*)src, (double*)dst, count);
+  else if (sdtype == SYMNMF_F64 && ddtype == SYMNMF_F32)
+    k_convert<double, float><<<nb, 256, 0, s>>>((const double*)src, (float*)dst, count);
+  else if (sdtype == SYMNMF_F32 && ddtype == SYMNMF_F64)
+    k_convert<float, double><<<nb, 256, 0, s>>>((const float*)src, (double*)dst, count);
+  else if (sdtype == SYMNMF_F32 && ddtype == SYMNMF_F32)
+    k_convert<float, float><<<nb, 256, 0, s>>>((const float*)src, (float*)dst, count);
+  else
+    return -1;
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int gram(const void* A, int adtype, int64_t lda, int ca, const void* B, int bdtype, int64_t ldb, int cb, int n,
+         const int* rows, const double* w, const int* d_count, int max_rows, Workspace& ws, double* G, double* Ghat,
+         int kp, double alpha, const DevState* st, hipStream_t s) {
+  if (ca > 96 || cb > 96 || ca < 1 || cb < 1) return -1;
+  const int t = ceil_div(std::max(ca, cb), 16);
+  const int nrows = rows ? max_rows : n;
+  const int nb = std::max(1, std::min(256, ceil_div(std::max(nrows, 1), 256)));
+  const int rpb = 16 * ceil_div(ceil_div(std::max(nrows, 1), nb), 16);
+  double* part = ws.dbl((size_t)nb * ca * cb);
+  if (!part) return -1;
+  if (adtype == SYMNMF_F64 && bdtype == SYMNMF_F64)
+    gram_t<double, double>(t, A, lda, ca, B, ldb, cb, n, rows, w, d_count, nb, rpb, part, st, s);
+  else if (adtype == SYMNMF_F32 && bdtype == SYMNMF_F32)
+    gram_t<float, float>(t, A, lda, ca, B, ldb, cb, n, rows, w, d_count, nb, rpb, part, st, s);
+  else if (adtype == SYMNMF_F64 && bdtype == SYMNMF_F32)
+    gram_t<double, float>(t, A, lda, ca, B, ldb, cb, n, rows, w, d_count, nb, rpb, part, st, s);
+  else if (adtype == SYMNMF_F32 && bdtype == SYMNMF_F64)
+    gram_t<float, double>(t, A, lda, ca, B, ldb, cb, n, rows, w, d_count, nb, rpb, part, st, s);
+  else
+    return -1;
+  const int tot = std::max(ca * cb, Ghat ? kp * kp : 0);
+  k_gram_reduce<<<ceil_div(tot, 256), 256, 0, s>>>(part, nb, ca, cb, G, Ghat, kp, alpha, st);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int dot_partials(const void* A, const void* B, int dtype, int64_t count, Workspace& ws, double** part,
+                 const DevState* st, hipStream_t s) {
+  const int nb = std::max(1, std::min(512, ceil_div(count, 256 * 16)));
+  *part = ws.dbl(nb);
+  if (!*part) return -1;
+  if (dtype == SYMNMF_F64)
+    k_dot<double><<<nb, 256, 0, s>>>((const double*)A, (const double*)B, count, *part, st);
+  else
+    k_dot<float><<<nb, 256, 0, s>>>((const float*)A, (const float*)B, count, *part, st);
+  return hipGetLastError() == hipSuccess ? nb : -1;
+}
+
+void frob_dot(const double* A, const double* B, int count, double* out, hipStream_t s) {
+  k_frob<<<1, 256, 0, s>>>(A, B, count, out);
+}
+
+void finish_iteration(const double* dot_part, int nb, const double* Ga, const double* Gb, int k,
+                      const double* d_normsq, DevState* st, double* hist, StopRule rule, hipStream_t s) {
+  k_finish_iteration<<<1, 256, 0, s>>>(dot_part, nb, Ga, Gb, k, d_normsq, st, hist, rule);
+}
+
+int hals_update(int n, int k, int kp, const void* Y, const int* seg_ptr, const int* seg_src, const double* seg_val,
+                const void* Src, void* Dst, int fdtype, const double* Ghat, double alpha, const DevState* st,
+                hipStream_t s) {
+  if (fdtype == SYMNMF_F64) {
+    switch (kp) {
+      case 16: hals_launch<16, double>(n, k, Y, seg_ptr, seg_src, seg_val, Src, Dst, Ghat, alpha, st, s); break;
+      case 32: hals_launch<32, double>(n, k, Y, seg_ptr, seg_src, seg_val, Src, Dst, Ghat, alpha, st, s); break;
+      case 64: hals_launch<64, double>(n, k, Y, seg_ptr, seg_src, seg_val, Src, Dst, Ghat, alpha, st, s); break;
+      default: return -1;
+    }
+  } else {
+    switch (kp) {
+      case 16: hals_launch<16, float>(n, k, Y, seg_ptr, seg_src, seg_val, Src, Dst, Ghat, alpha, st, s); break;
+      case 32: hals_launch<32, float>(n, k, Y, seg_ptr, seg_src, seg_val, Src, Dst, Ghat, alpha, st, s); break;
+      case 64: hals_launch<64, float>(n, k, Y, seg_ptr, seg_src, seg_val, Src, Dst, Ghat, alpha, st, s); break;
+      default: return -1;
+    }
+  }
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int rowmat(const void* A, int adtype, int64_t lda, int n, int l, const double* M, const double* scale, int c,
+           void* out, int odtype, int64_t ldo, const DevState* st, hipStream_t s) {
+  const int nb = ceil_div((int64_t)n * c, 256);
+  if (adtype == SYMNMF_F64 && odtype == SYMNMF_F64)
+    k_rowmat<double, double><<<nb, 256, 0, s>>>((const double*)A, lda, n, l, M, scale, c, (double*)out, ldo, st);
+  else if (adtype == SYMNMF_F64 && odtype == SYMNMF_F32)
+    k_rowmat<double, float><<<nb, 256, 0, s>>>((const double*)A, lda, n, l, M, scale, c, (float*)out, ldo, st);
+  else if (adtype == SYMNMF_F32 && odtype == SYMNMF_F64)
+    k_rowmat<float, double><<<nb, 256, 0, s>>>((const float*)A, lda, n, l, M, scale, c, (double*)out, ldo, st);
+  else if (adtype == SYMNMF_F32 && odtype == SYMNMF_F32)
+    k_rowmat<float, float><<<nb, 256, 0, s>>>((const float*)A, lda, n, l, M, scale, c, (float*)out, ldo, st);
+  else
+    return -1;
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int chol_inverse(const double* G, int k, double* R, double* Rinv, int* d_flags, int flag_bit, int* d_fail,
+                 hipStream_t s) {
+  const size_t lds = (size_t)k * (k + 1) * sizeof(double);
+  if (k > 96) return -1;
+  if (lds > 65536) {
+    if (hipFuncSetAttribute((const void*)k_chol_inverse, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) !=
+        hipSuccess)
+      return -1;
+  }
+  k_chol_inverse<<<1, 256, lds, s>>>(G, k, R, Rinv, d_flags, flag_bit, d_fail);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int jacobi_evd(const double* T, int l, double* Vw, double* V, double* lam, hipStream_t s) {
+  if (l > 96) return -1;
+  const size_t lds = (size_t)l * (l + 1) * sizeof(double);
+  if (lds > 65536) {
+    if (hipFuncSetAttribute((const void*)k_jacobi, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
+      return -1;
+  }
+  k_jacobi<<<1, 256, lds, s>>>(T, l, Vw, V, lam);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int column_sign_fix(double* U, int n, int l, Workspace& ws, hipStream_t s) {
+  double* sgn = ws.dbl(l);
+  if (!sgn) return -1;
+  k_col_argmax<<<l, 256, 0, s>>>(U, n, l, sgn);
+  k_col_scale<<<ceil_div((int64_t)n * l, 256), 256, 0, s>>>(U, n, l, sgn);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int exclusive_scan_i32(const int* in, int* out, int n, Workspace& ws, hipStream_t s) {
+  const int nb = std::max(1, ceil_div(n, 1024));
+  int* bsum = ws.i32(nb);
+  if (!bsum) return -1;
+  k_scan_blocks<int><<<nb, 256, 0, s>>>(in, n, bsum);
+  k_scan_totals<int><<<1, 64, 0, s>>>(bsum, nb, out + n);
+  k_scan_apply<int, false><<<nb, 256, 0, s>>>(in, n, bsum, out);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int inclusive_scan_u64(const uint64_t* in, uint64_t* out, int n, Workspace& ws, hipStream_t s) {
+  const int nb = std::max(1, ceil_div(n, 1024));
+  uint64_t* bsum = ws.u64(nb);
+  if (!bsum) return -1;
+  k_scan_blocks<uint64_t><<<nb, 256, 0, s>>>(in, n, bsum);
+  k_scan_totals<uint64_t><<<1, 64, 0, s>>>(bsum, nb, (uint64_t*)nullptr);
+  k_scan_apply<uint64_t, true><<<nb, 256, 0, s>>>(in, n, bsum, out);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}

@@ -1,0 +1,198 @@
+// CSR-X kernels: scalars pass, SpMM Y = X B and the cross term of the exact
+// residual.  The sparse product is the "MM" cost of the sparse experiments
+// (Section 6.2); a wavefront owns one row, its lanes own the output columns
+// (so every B-row gather is one contiguous 64..512-byte read) and, for narrow
+// B, several lane groups walk different nonzeros of the row and are combined
+// by a fixed shuffle tree.
+#include "kernels.hpp"
+
+namespace {
+
+template <typename TV>
+__global__ __launch_bounds__(256) void k_csr_rowstats(const int* __restrict__ rp, const TV* __restrict__ val, int n,
+                                                      double* __restrict__ rowsum, double* __restrict__ bpart) {
+  __shared__ double sc[8];
+  __shared__ double smax[256];
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  double s = 0.0, q = 0.0, m = -INFINITY;
+  if (i < n) {
+    for (int e = rp[i]; e < rp[i + 1]; ++e) {
+      const double v = (double)val[e];
+      s += v;
+      q += v * v;
+      m = fmax(m, v);
+    }
+    rowsum[i] = s;
+  }
+  const double ts = block_sum(s, sc);
+  const double tq = block_sum(q, sc);
+  smax[threadIdx.x] = m;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) smax[threadIdx.x] = fmax(smax[threadIdx.x], smax[threadIdx.x + o]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    bpart[3 * blockIdx.x + 0] = ts;
+    bpart[3 * blockIdx.x + 1] = tq;
+    bpart[3 * blockIdx.x + 2] = smax[0];
+  }
+}
+
+__global__ void k_csr_scalars_final(int nb, const double* __restrict__ bpart, double* __restrict__ out) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double s = 0.0, q = 0.0, m = -INFINITY;
+  for (int b = 0; b < nb; ++b) {
+    s += bpart[3 * b];
+    q += bpart[3 * b + 1];
+    m = fmax(m, bpart[3 * b + 2]);
+  }
+  out[0] = q;
+  out[1] = s;
+  out[2] = m;
+}
+
+// Wave per row.  CW lanes per group cover the columns (CPL columns per lane,
+// lane li owns columns li, li + CW, ...); 64 / CW groups take every G-th
+// nonzero.  FP64 accumulation.
+template <typename TV, typename TB, typename TY, int CW, int CPL>
+__global__ __launch_bounds__(256) void k_csr_spmm(const int* __restrict__ rp, const int* __restrict__ ci,
+                                                  const TV* __restrict__ val, int n, const TB* __restrict__ B, int c,
+                                                  TY* __restrict__ Y, const DevState* __restrict__ st) {
+  if (stopped(st)) return;
+  constexpr int G = 64 / CW;
+  const int lane = threadIdx.x & 63;
+  const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (row >= n) return;
+  const int g = lane / CW, li = lane - g * CW;
+  double acc[CPL];
+#pragma unroll
+  for (int q = 0; q < CPL; ++q) acc[q] = 0.0;
+  const int e0 = rp[row], e1 = rp[row + 1];
+  int e = e0 + g;
+  for (; e + 3 * G < e1; e += 4 * G) {
+    int j[4];
+    double v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      j[u] = ci[e + u * G];
+      v[u] = (double)val[e + u * G];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const TB* brow = B + (int64_t)j[u] * c;
+#pragma unroll
+      for (int q = 0; q < CPL; ++q) {
+        const int col = li + q * CW;
+        if (col < c) acc[q] = fma(v[u], (double)brow[col], acc[q]);
+      }
+    }
+  }
+  for (; e < e1; e += G) {
+    const int j = ci[e];
+    const double v = (double)val[e];
+    const TB* brow = B + (int64_t)j * c;
+#pragma unroll
+    for (int q = 0; q < CPL; ++q) {
+      const int col = li + q * CW;
+      if (col < c) acc[q] = fma(v, (double)brow[col], acc[q]);
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < CPL; ++q) {
+#pragma unroll
+    for (int o = CW; o < 64; o <<= 1) acc[q] += __shfl_xor(acc[q], o, 64);
+  }
+  if (g == 0) {
+#pragma unroll
+    for (int q = 0; q < CPL; ++q) {
+      const int col = li + q * CW;
+      if (col < c) Y[(int64_t)row * c + col] = (TY)acc[q];
+    }
+  }
+}
+
+// sum over stored (i, j) of X_ij (w_i . h_j); wave per row, lane per column.
+template <typename TV, typename TF>
+__global__ __launch_bounds__(256) void k_csr_cross(const int* __restrict__ rp, const int* __restrict__ ci,
+                                                   const TV* __restrict__ val, int n, int k, const TF* __restrict__ W,
+                                                   const TF* __restrict__ H, double* __restrict__ part) {
+  __shared__ double sc[8];
+  const int lane = threadIdx.x & 63;
+  const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
+  double acc = 0.0;
+  if (row < n && lane < k) {
+    const double wi = (double)W[(int64_t)row * k + lane];
+    for (int e = rp[row]; e < rp[row + 1]; ++e) acc = fma((double)val[e] * wi, (double)H[(int64_t)ci[e] * k + lane], acc);
+  }
+  const double t = block_sum(acc, sc);
+  if (threadIdx.x == 0) part[blockIdx.x] = t;
+}
+
+template <typename TV, typename TB, typename TY>
+void spmm_dispatch(const int* rp, const int* ci, const TV* val, int n, const TB* B, int c, TY* Y, const DevState* st,
+                   hipStream_t s) {
+  const int nb = ceil_div(n, 4);
+  if (c <= 16)
+    k_csr_spmm<TV, TB, TY, 16, 1><<<nb, 256, 0, s>>>(rp, ci, val, n, B, c, Y, st);
+  else if (c <= 32)
+    k_csr_spmm<TV, TB, TY, 32, 1><<<nb, 256, 0, s>>>(rp, ci, val, n, B, c, Y, st);
+  else if (c <= 64)
+    k_csr_spmm<TV, TB, TY, 64, 1><<<nb, 256, 0, s>>>(rp, ci, val, n, B, c, Y, st);
+  else
+    k_csr_spmm<TV, TB, TY, 64, 2><<<nb, 256, 0, s>>>(rp, ci, val, n, B, c, Y, st);
+}
+
+}  // namespace
+
+int csr_scalars(const int* rp, const void* val, int vdtype, int n, int64_t nnz, Workspace& ws, double* d_rowsum,
+                double* d_out3, hipStream_t s) {
+  (void)nnz;
+  const int nb = ceil_div(n, 256);
+  double* bpart = ws.dbl(3 * (size_t)nb);
+  if (!bpart) return -1;
+  if (vdtype == SYMNMF_F64)
+    k_csr_rowstats<double><<<nb, 256, 0, s>>>(rp, (const double*)val, n, d_rowsum, bpart);
+  else
+    k_csr_rowstats<float><<<nb, 256, 0, s>>>(rp, (const float*)val, n, d_rowsum, bpart);
+  k_csr_scalars_final<<<1, 64, 0, s>>>(nb, bpart, d_out3);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int csr_spmm(const int* rp, const int* ci, const void* val, int vdtype, int n, const void* B, int bdtype, int c,
+             void* Y, int ydtype, const DevState* st, hipStream_t s) {
+  if (c > 128) return -1;
+  if (vdtype == SYMNMF_F64) {
+    if (bdtype != SYMNMF_F64 || ydtype != SYMNMF_F64) return -1;
+    spmm_dispatch<double, double, double>(rp, ci, (const double*)val, n, (const double*)B, c, (double*)Y, st, s);
+  } else {
+    if (bdtype == SYMNMF_F32 && ydtype == SYMNMF_F32)
+      spmm_dispatch<float, float, float>(rp, ci, (const float*)val, n, (const float*)B, c, (float*)Y, st, s);
+    else if (bdtype == SYMNMF_F64 && ydtype == SYMNMF_F64)
+      spmm_dispatch<float, double, double>(rp, ci, (const float*)val, n, (const double*)B, c, (double*)Y, st, s);
+    else
+      return -1;
+  }
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int csr_resid_cross(const int* rp, const int* ci, const void* val, int vdtype, int n, int k, const void* W,
+                    const void* H, int fdtype, Workspace& ws, double* d_sum, hipStream_t s) {
+  if (k > 64) return -1;
+  const int nb = ceil_div(n, 4);
+  double* part = ws.dbl(nb);
+  if (!part) return -1;
+  if (vdtype == SYMNMF_F64 && fdtype == SYMNMF_F64)
+    k_csr_cross<double, double><<<nb, 256, 0, s>>>(rp, ci, (const double*)val, n, k, (const double*)W,
+                                                   (const double*)H, part);
+  else if (vdtype == SYMNMF_F32 && fdtype == SYMNMF_F32)
+    k_csr_cross<float, float><<<nb, 256, 0, s>>>(rp, ci, (const float*)val, n, k, (const float*)W,
+                                                 (const float*)H, part);
+  else if (vdtype == SYMNMF_F32 && fdtype == SYMNMF_F64)
+    k_csr_cross<float, double><<<nb, 256, 0, s>>>(rp, ci, (const float*)val, n, k, (const double*)W,
+                                                  (const double*)H, part);
+  else
+    return -1;
+  sum_partials(part, nb, d_sum, s);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}

@@ -1,0 +1,156 @@
+// Host-side launchers of the gfx950 kernels (internal to libsymnmf).
+#pragma once
+
+#include <algorithm>
+#include <cstddef>
+#include <cstdint>
+
+#include "common.hpp"
+#include "../../include/symnmf.h"
+
+// A bump allocator over one device buffer owned by the context.  Every
+// launcher that needs temporaries takes them from here; launches happen on
+// one in-order stream, so a later launcher may reuse the space as soon as the
+// previous launcher's kernels have been enqueued.  Requests beyond the
+// capacity return nullptr and the launcher fails before launching anything.
+struct Workspace {
+  char* base = nullptr;
+  size_t cap = 0;
+  size_t off = 0;
+  void reset() { off = 0; }
+  void* raw(size_t bytes) {
+    const size_t a = (off + 255) & ~(size_t)255;
+    if (base == nullptr || a + bytes > cap) return nullptr;
+    off = a + bytes;
+    return base + a;
+  }
+  double* dbl(size_t n) { return (double*)raw(n * sizeof(double)); }
+  int* i32(size_t n) { return (int*)raw(n * sizeof(int)); }
+  uint64_t* u64(size_t n) { return (uint64_t*)raw(n * sizeof(uint64_t)); }
+};
+
+inline size_t dtype_size(int dt) { return dt == SYMNMF_F64 ? 8 : (dt == SYMNMF_F32 ? 4 : 2); }
+
+// ---- dense X ---------------------------------------------------------------
+int dense_scalars(const void* X, int dtype, int64_t ld, int n, Workspace& ws, double* d_rowsum, double* d_out3,
+                  hipStream_t s);
+
+struct GemmPlan {
+  int cp = 16;      // output columns padded to a multiple of 16
+  int kchunk = 64;  // K range per split
+  int splits = 1;   // number of K splits (partial outputs)
+};
+GemmPlan gemm_plan(int n, int c, int compute_dtype);
+// Y = X B.  X dtype F64 / F32 / BF16; B F64 or F32 (F64 only with F64 X);
+// P: partials buffer of splits * n * cp elements of the accumulator type
+// (double for F64 X, float otherwise); Y of ydtype with leading dim ldy.
+int dense_gemm(const void* X, int xdtype, int64_t ldx, const void* B, int bdtype, int64_t ldb, int n, int c,
+               const GemmPlan& p, void* P, void* Y, int ydtype, int64_t ldy, const DevState* st, hipStream_t s);
+int convert_f32_bf16(const float* src, int64_t lds, void* dst, int64_t ldd, int n, hipStream_t s);
+// d_sum = sum_ij (X_ij - w_i . h_j)^2, k <= 64.
+int dense_resid_exact(const void* X, int xdtype, int64_t ldx, int n, int k, const void* W, const void* H, int fdtype,
+                      Workspace& ws, double* d_sum, hipStream_t s);
+
+// ---- CSR X -----------------------------------------------------------------
+int csr_scalars(const int* rp, const void* val, int vdtype, int n, int64_t nnz, Workspace& ws, double* d_rowsum,
+                double* d_out3, hipStream_t s);
+// Y = X B (B n x c of bdtype, Y n x c of ydtype, c <= 128).
+int csr_spmm(const int* rp, const int* ci, const void* val, int vdtype, int n, const void* B, int bdtype, int c,
+             void* Y, int ydtype, const DevState* st, hipStream_t s);
+// d_sum = sum over stored (i, j) of X_ij (w_i . h_j).
+int csr_resid_cross(const int* rp, const int* ci, const void* val, int vdtype, int n, int k, const void* W,
+                    const void* H, int fdtype, Workspace& ws, double* d_sum, hipStream_t s);
+
+// ---- factor-side kernels ----------------------------------------------------
+// out[0] = sum of part[0..nb) in a fixed order.
+void sum_partials(const double* part, int nb, double* out, hipStream_t s);
+int init_uniform_factor(void* F, int fdtype, int n, int k, double scale, uint64_t seed, hipStream_t s);
+int gen_gaussian(double* out, int64_t count, uint64_t seed, uint32_t sub, uint32_t tag, hipStream_t s);
+int copy_convert(const void* src, int sdtype, void* dst, int ddtype, int64_t count, hipStream_t s);
+
+// G (ca x cb, FP64, ld cb) = A^T diag(w) B over rows (all rows, or the rows
+// listed in `rows` with count *d_count when rows != nullptr; w == nullptr
+// means unit weights).  If Ghat != nullptr it also receives G + alpha I
+// padded to kp x kp with the identity.  ca, cb <= 128.
+int gram(const void* A, int adtype, int64_t lda, int ca, const void* B, int bdtype, int64_t ldb, int cb, int n,
+         const int* rows, const double* w, const int* d_count, int max_rows, Workspace& ws, double* G,
+         double* Ghat, int kp, double alpha, const DevState* st, hipStream_t s);
+// part[b] partial sums of sum_e A[e] B[e] over count elements; returns nb.
+int dot_partials(const void* A, const void* B, int dtype, int64_t count, Workspace& ws, double** part,
+                 const DevState* st, hipStream_t s);
+
+// out[0] = sum_i A[i] B[i] (one workgroup, fixed order).
+void frob_dot(const double* A, const double* B, int count, double* out, hipStream_t s);
+
+// Fused end-of-iteration step: residual r = sqrt(max(normsq - 2 dot +
+// <Ga, Gb>, 0) / normsq), log, stop rule.  dot_part == nullptr only counts
+// the iteration (no residual evaluated).
+struct StopRule {
+  int mode;
+  double tol;
+  int patience;
+  double target;
+  int max_hist;
+};
+void finish_iteration(const double* dot_part, int nb, const double* Ga, const double* Gb, int k,
+                      const double* d_normsq, DevState* st, double* hist, StopRule rule, hipStream_t s);
+
+// Regularised HALS sweep (Ghat = G + alpha I padded to kp): for each row j,
+// columns i = 0..k-1 in order,
+//   w_i <- max(0, w_i + (y_i + alpha src_i - sum_l w_l Ghat_li) / Ghat_ii)
+// with y from a dense n x k matrix (Y != nullptr) or from a segment list
+// (seg_ptr/seg_src/seg_val: y_ji = sum_e seg_val[e] src[seg_src[e]][i]).
+int hals_update(int n, int k, int kp, const void* Y, const int* seg_ptr, const int* seg_src, const double* seg_val,
+                const void* Src, void* Dst, int fdtype, const double* Ghat, double alpha, const DevState* st,
+                hipStream_t s);
+// Exact NLS per row by block principal pivoting, same inputs as hals_update.
+int bpp_update(int n, int k, int kp, const void* Y, const int* seg_ptr, const int* seg_src, const double* seg_val,
+               const void* Src, void* Dst, int fdtype, const double* Ghat, double alpha, Workspace& ws,
+               const DevState* st, hipStream_t s);
+
+// out (n x c, odtype, ld ldo) = A (n x l, adtype, lda) * diag(scale) * M
+// (l x c FP64 row-major; scale may be nullptr).
+int rowmat(const void* A, int adtype, int64_t lda, int n, int l, const double* M, const double* scale, int c,
+           void* out, int odtype, int64_t ldo, const DevState* st, hipStream_t s);
+
+// One-workgroup dense kernels on small FP64 matrices.
+// R upper with R^T R = G + shift I (shift 0 first, then growing shifts if a
+// pivot is not positive); Rinv = R^{-1}; flag bit set when a shift was used;
+// sets *d_fail when even the last shift failed.
+int chol_inverse(const double* G, int k, double* R, double* Rinv, int* d_flags, int flag_bit, int* d_fail,
+                 hipStream_t s);
+// Symmetric EVD of the l x l matrix (T + T^T)/2 by parallel cyclic Jacobi;
+// eigenvalues descending in lam, eigenvectors as columns of V (l x l).
+int jacobi_evd(const double* T, int l, double* Vwork, double* V, double* lam, hipStream_t s);
+// Flip the sign of each column of U (n x l FP64) so that its entry of largest
+// magnitude is positive (first such row on ties).
+int column_sign_fix(double* U, int n, int l, Workspace& ws, hipStream_t s);
+
+// Scans.
+int exclusive_scan_i32(const int* in, int* out, int n, Workspace& ws, hipStream_t s);  // out has n+1 entries
+int inclusive_scan_u64(const uint64_t* in, uint64_t* out, int n, Workspace& ws, hipStream_t s);
+
+// ---- leverage-score sampling -----------------------------------------------
+int leverage_scores(const void* F, int fdtype, int n, int k, const double* Rinv, double* lev, const DevState* st,
+                    hipStream_t s);
+
+struct SampleBuffers {
+  uint64_t* w = nullptr;       // n quantised weights
+  uint64_t* prefix = nullptr;  // n inclusive prefix sums
+  int* counts = nullptr;       // n draw counts (kept zero between calls)
+  int* flags = nullptr;        // n+1 selection flags / positions
+  int* info = nullptr;         // [0] s_D, [1] s_R, [2] rows kept (<= cap), [3] rows selected
+  double* theta = nullptr;     // deterministic leverage mass
+};
+// rows/weights: capacity >= s; the number of rows lands in info[2].
+int hybrid_sample(const double* lev, int n, int k, int64_t s_total, double tau, uint64_t seed, uint32_t half_iter,
+                  SampleBuffers& sb, int* rows, double* weights, int64_t cap, Workspace& ws, const DevState* st,
+                  hipStream_t s);
+
+// Transposed slab of the sampled rows: for each listed row r (weight w_r) and
+// each stored X[r][i], an entry (src r, value X[r][i] w_r) in segment i; the
+// segments are sorted by src.  seg_ptr has n+1 entries; seg_cnt (n ints) must
+// be zero on entry and is zero again on exit.
+int sampled_slab(const int* rp, const int* ci, const void* val, int vdtype, int n, const int* rows,
+                 const double* weights, const int* d_count, int max_rows, int* seg_cnt, int* seg_ptr, int* seg_src,
+                 double* seg_val, int64_t seg_cap, Workspace& ws, const DevState* st, hipStream_t s);

@@ -1,0 +1,774 @@
+// Host orchestration and C ABI of libsymnmf.
+//
+// One context = one symmetric X (borrowed), the two factors W and H (owned),
+// their FP64 Gram matrices and every workspace the modes need.  All work is
+// enqueued on the caller's stream; the stop rule is evaluated on the device
+// (DevState) so an iteration never waits for the host.  The host polls the
+// stop flag every `check_every` iterations; iterations enqueued after the
+// rule fired return at kernel entry.
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <functional>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "kernels.hpp"
+
+namespace {
+
+thread_local std::string g_create_error;
+
+struct Fail {
+  int code;
+  std::string msg;
+};
+
+#define HIPCHK(expr)                                                                       \
+  do {                                                                                     \
+    hipError_t e_ = (expr);                                                                \
+    if (e_ != hipSuccess) throw Fail{SYMNMF_E_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)}; \
+  } while (0)
+#define LCHK(expr)                                                             \
+  do {                                                                         \
+    if ((expr) != 0) throw Fail{SYMNMF_E_DEVICE, std::string("launch failed: ") + #expr}; \
+  } while (0)
+
+template <typename T>
+T* dalloc(size_t count) {
+  void* p = nullptr;
+  if (count == 0) count = 1;
+  if (hipMalloc(&p, count * sizeof(T)) != hipSuccess) {
+    (void)hipGetLastError();
+    throw Fail{SYMNMF_E_NOMEM, "device allocation of " + std::to_string(count * sizeof(T)) + " bytes failed"};
+  }
+  return (T*)p;
+}
+void dfree(void* p) {
+  if (p) (void)hipFree(p);
+}
+
+int kpad(int k) { return k <= 16 ? 16 : (k <= 32 ? 32 : 64); }
+
+constexpr int CMAX = 96;  // widest product operand (LAI basis)
+
+}  // namespace
+
+struct symnmf_ctx {
+  // data
+  int kind = 0, xdtype = 0, n = 0;
+  int64_t ld = 0, nnz = 0;
+  const void* Xv = nullptr;
+  const int* rp = nullptr;
+  const int* ci = nullptr;
+  int cdtype = 0;  // product compute dtype
+  int fdtype = 0;  // factor / product-output dtype
+  const void* Xc = nullptr;
+  void* Xb_owned = nullptr;
+  // problem
+  int k = 0, kp = 16;
+  double alpha = 0.0;
+  int64_t s = 0;
+  double tau = 0.0;
+  uint64_t seed = 0;
+  symnmf_options opt{};
+  hipStream_t st = nullptr;
+  int mode = SYMNMF_MODE_PLAIN;
+  int64_t iter_host = 0;  // iterations enqueued (drives the LvS sub-streams)
+  // Stop-flag gate handed to iteration kernels: the device state while an
+  // iteration is being enqueued, nullptr for every other call (those must run
+  // even after the stop rule fired).
+  const DevState* gate_ = nullptr;
+  // scalars
+  double normsq = 0, total = 0, maxval = 0, zeta = 0, normsq_lai = 0;
+  // device buffers
+  void *W = nullptr, *H = nullptr, *Y = nullptr;
+  void* P = nullptr;
+  double *G_W = nullptr, *G_H = nullptr, *Gh_W = nullptr, *Gh_H = nullptr, *Gh_S = nullptr;
+  double* d_scal = nullptr;  // [0] ||X||^2 [1] sum [2] max [3..7] scratch [8] ||Lambda||^2
+  double* rowsum = nullptr;
+  DevState* dstate = nullptr;
+  double* hist = nullptr;
+  int* d_fail = nullptr;
+  double* hbuf = nullptr;  // pinned host readback buffer (64 doubles)
+  Workspace ws;
+  // LAI
+  int l = 0;
+  double *Q = nullptr, *Q1 = nullptr, *U = nullptr, *YQ = nullptr;
+  double *Tm = nullptr, *QT = nullptr, *Vw = nullptr, *lam = nullptr, *Rl = nullptr, *Rlinv = nullptr, *Z = nullptr;
+  // LvS / leverage
+  SampleBuffers sb;
+  int* rows = nullptr;
+  double* weights = nullptr;
+  int64_t max_sel = 0;
+  int* seg_cnt = nullptr;
+  int* seg_ptr = nullptr;
+  int* seg_src = nullptr;
+  double* seg_val = nullptr;
+  int64_t seg_cap = 0;
+  double* lev = nullptr;
+  double *R = nullptr, *Rinv = nullptr;
+  std::vector<int> host_rp;
+  std::string err;
+
+  ~symnmf_ctx() {
+    if (st) (void)hipStreamSynchronize(st);
+    else (void)hipDeviceSynchronize();
+    void* ptrs[] = {Xb_owned, W, H, Y, P, G_W, G_H, Gh_W, Gh_H, Gh_S, d_scal, rowsum, dstate, hist, d_fail,
+                    ws.base, Q, Q1, U, YQ, Tm, QT, Vw, lam, Rl, Rlinv, Z, sb.w, sb.prefix, sb.counts, sb.flags,
+                    sb.info, sb.theta, rows, weights, seg_cnt, seg_ptr, seg_src, seg_val, lev, R, Rinv};
+    for (void* p : ptrs) dfree(p);
+    if (hbuf) (void)hipHostFree(hbuf);
+  }
+
+  size_t fsize() const { return dtype_size(fdtype); }
+  int64_t nk() const { return (int64_t)n * k; }
+
+  void sync() { HIPCHK(hipStreamSynchronize(st)); }
+
+  // Copy `count` doubles from device to the pinned buffer and wait.
+  const double* readback(const double* d, int count) {
+    HIPCHK(hipMemcpyAsync(hbuf, d, count * sizeof(double), hipMemcpyDeviceToHost, st));
+    sync();
+    return hbuf;
+  }
+
+  StopRule rule() const {
+    StopRule r;
+    r.mode = opt.stop_mode;
+    r.tol = opt.stop_tol;
+    r.patience = opt.stop_patience;
+    r.target = opt.target;
+    r.max_hist = opt.max_history;
+    return r;
+  }
+
+  // ---- products -----------------------------------------------------------
+  // Y (n x c, fdtype) = X B with B of bdtype (the factor dtype or F64).
+  void product(const void* B, int bdtype, int c, void* Yout) {
+    if (kind == SYMNMF_DENSE) {
+      const GemmPlan p = gemm_plan(n, c, cdtype);
+      LCHK(dense_gemm(Xc, cdtype, cdtype == SYMNMF_BF16 && xdtype != SYMNMF_BF16 ? n : ld, B, bdtype, c, n, c, p, P,
+                      Yout, fdtype, c, gate_, st));
+    } else {
+      LCHK(csr_spmm(rp, ci, Xv, xdtype, n, B, bdtype, c, Yout, fdtype, gate_, st));
+    }
+  }
+
+  // Y = (LAI operator) Src = U (Lambda (U^T Src)).
+  void lai_product(const void* Src, void* Yout) {
+    ws.reset();
+    LCHK(gram(U, SYMNMF_F64, l, l, Src, fdtype, k, k, n, nullptr, nullptr, nullptr, 0, ws, Z, nullptr, 0, 0.0,
+              gate_, st));
+    LCHK(rowmat(U, SYMNMF_F64, l, n, l, Z, lam, k, Yout, fdtype, k, gate_, st));
+  }
+
+  void refresh_gram(const void* F, double* G, double* Gh) {
+    ws.reset();
+    LCHK(gram(F, fdtype, k, k, F, fdtype, k, k, n, nullptr, nullptr, nullptr, 0, ws, G, Gh, kp, alpha, gate_, st));
+  }
+
+  void update(const void* Yin, const int* sp, const int* ss, const double* sv, const void* Src, void* Dst,
+              const double* Gh) {
+    if (opt.rule == SYMNMF_RULE_HALS) {
+      LCHK(hals_update(n, k, kp, Yin, sp, ss, sv, Src, Dst, fdtype, Gh, alpha, gate_, st));
+    } else {
+      ws.reset();
+      LCHK(bpp_update(n, k, kp, Yin, sp, ss, sv, Src, Dst, fdtype, Gh, alpha, ws, gate_, st));
+    }
+  }
+
+  // One half-iteration: Dst from Src (side 0: W from H; side 1: H from W).
+  void half_step(int side, int64_t half_iter) {
+    void* Src = side == 0 ? H : W;
+    void* Dst = side == 0 ? W : H;
+    double* Gs = side == 0 ? G_H : G_W;      // Gram of Src (current)
+    double* Ghs = side == 0 ? Gh_H : Gh_W;   // regularised Gram of Src
+    double* Gd = side == 0 ? G_W : G_H;      // Gram of Dst (refreshed after)
+    double* Ghd = side == 0 ? Gh_W : Gh_H;
+    if (mode == SYMNMF_MODE_LVS) {
+      ws.reset();
+      LCHK(chol_inverse(Gs, k, R, Rinv, &dstate->flags, SYMNMF_FLAG_LEV_SHIFT, d_fail, st));
+      LCHK(leverage_scores(Src, fdtype, n, k, Rinv, lev, gate_, st));
+      LCHK(hybrid_sample(lev, n, k, s, tau, seed, (uint32_t)half_iter, sb, rows, weights, max_sel, ws, gate_, st));
+      ws.reset();
+      LCHK(gram(Src, fdtype, k, k, Src, fdtype, k, k, n, rows, weights, sb.info + 2, (int)max_sel, ws, nullptr, Gh_S,
+                kp, alpha, gate_, st));
+      ws.reset();
+      LCHK(sampled_slab(rp, ci, Xv, xdtype, n, rows, weights, sb.info + 2, (int)max_sel, seg_cnt, seg_ptr, seg_src,
+                        seg_val, seg_cap, ws, gate_, st));
+      update(nullptr, seg_ptr, seg_src, seg_val, Src, Dst, Gh_S);
+    } else {
+      if (mode == SYMNMF_MODE_LAI) lai_product(Src, Y);
+      else product(Src, fdtype, k, Y);
+      update(Y, nullptr, nullptr, nullptr, Src, Dst, Ghs);
+    }
+    (void)Gs;
+    refresh_gram(Dst, Gd, Ghd);
+  }
+
+  struct Gate {
+    symnmf_ctx* c;
+    explicit Gate(symnmf_ctx* cc) : c(cc) { c->gate_ = c->dstate; }
+    ~Gate() { c->gate_ = nullptr; }
+  };
+
+  void one_iteration() {
+    Gate g(this);
+    const int64_t t = iter_host++;
+    half_step(0, 2 * t);
+    half_step(1, 2 * t + 1);
+    const double* nrm = d_scal + (mode == SYMNMF_MODE_LAI ? 8 : 0);
+    bool with_resid = true;
+    if (mode == SYMNMF_MODE_LVS) {
+      const int every = opt.resid_every > 0 ? opt.resid_every : 1;
+      with_resid = ((t + 1) % every) == 0;
+      if (with_resid) product(W, fdtype, k, Y);
+    }
+    if (with_resid) {
+      ws.reset();
+      double* part = nullptr;
+      const int nb = dot_partials(H, Y, fdtype, nk(), ws, &part, gate_, st);
+      if (nb < 0) throw Fail{SYMNMF_E_DEVICE, "dot launch failed"};
+      finish_iteration(part, nb, G_W, G_H, k, nrm, dstate, hist, rule(), st);
+    } else {
+      finish_iteration(nullptr, 0, G_W, G_H, k, nrm, dstate, hist, rule(), st);
+    }
+  }
+
+  DevState read_state() {
+    static_assert(sizeof(DevState) <= 64 * sizeof(double), "state fits the readback buffer");
+    HIPCHK(hipMemcpyAsync(hbuf, dstate, sizeof(DevState), hipMemcpyDeviceToHost, st));
+    sync();
+    DevState d;
+    std::memcpy(&d, hbuf, sizeof(DevState));
+    return d;
+  }
+
+  // Trace-identity residual ||op - A B^T|| / ||op|| with op = X, or U Lambda U^T
+  // when lai is set; uses fresh Grams of A and B.
+  double trace_residual(const void* A, const void* B, bool lai) {
+    if (lai) lai_product(A, Y);
+    else product(A, fdtype, k, Y);
+    ws.reset();
+    double* part = nullptr;
+    const int nb = dot_partials(B, Y, fdtype, nk(), ws, &part, nullptr, st);
+    if (nb < 0) throw Fail{SYMNMF_E_DEVICE, "dot launch failed"};
+    sum_partials(part, nb, d_scal + 3, st);
+    double* ga = ws.dbl((size_t)k * k);
+    double* gb = ws.dbl((size_t)k * k);
+    if (!ga || !gb) throw Fail{SYMNMF_E_NOMEM, "workspace"};
+    LCHK(gram(A, fdtype, k, k, A, fdtype, k, k, n, nullptr, nullptr, nullptr, 0, ws, ga, nullptr, 0, 0.0, nullptr,
+              st));
+    LCHK(gram(B, fdtype, k, k, B, fdtype, k, k, n, nullptr, nullptr, nullptr, 0, ws, gb, nullptr, 0, 0.0, nullptr,
+              st));
+    frob_dot(ga, gb, k * k, d_scal + 4, st);
+    const double* h = readback(d_scal + 3, 2);
+    const double nx = lai ? normsq_lai : normsq;
+    return std::sqrt(std::fmax(nx - 2.0 * h[0] + h[1], 0.0) / nx);
+  }
+
+  double exact_residual(const void* A, const void* B) {
+    ws.reset();
+    if (kind == SYMNMF_DENSE) {
+      LCHK(dense_resid_exact(Xv, xdtype, ld, n, k, A, B, fdtype, ws, d_scal + 3, st));
+      const double* h = readback(d_scal + 3, 1);
+      return std::sqrt(h[0] / normsq);
+    }
+    LCHK(csr_resid_cross(rp, ci, Xv, xdtype, n, k, A, B, fdtype, ws, d_scal + 3, st));
+    double* ga = ws.dbl((size_t)k * k);
+    double* gb = ws.dbl((size_t)k * k);
+    if (!ga || !gb) throw Fail{SYMNMF_E_NOMEM, "workspace"};
+    LCHK(gram(A, fdtype, k, k, A, fdtype, k, k, n, nullptr, nullptr, nullptr, 0, ws, ga, nullptr, 0, 0.0, nullptr, st));
+    LCHK(gram(B, fdtype, k, k, B, fdtype, k, k, n, nullptr, nullptr, nullptr, 0, ws, gb, nullptr, 0, 0.0, nullptr, st));
+    frob_dot(ga, gb, k * k, d_scal + 4, st);
+    const double* h = readback(d_scal + 3, 2);
+    return std::sqrt(std::fmax(normsq - 2.0 * h[0] + h[1], 0.0) / normsq);
+  }
+
+  // CholeskyQR2: Qout (n x l, FP64) = orthonormal factor of Yin (n x l, fdtype).
+  void cholqr2(const void* Yin) {
+    ws.reset();
+    LCHK(gram(Yin, fdtype, l, l, Yin, fdtype, l, l, n, nullptr, nullptr, nullptr, 0, ws, Tm, nullptr, 0, 0.0,
+              nullptr, st));
+    LCHK(chol_inverse(Tm, l, Rl, Rlinv, &dstate->flags, SYMNMF_FLAG_CHOLQR_SHIFT, d_fail, st));
+    LCHK(rowmat(Yin, fdtype, l, n, l, Rlinv, nullptr, l, Q1, SYMNMF_F64, l, nullptr, st));
+    ws.reset();
+    LCHK(gram(Q1, SYMNMF_F64, l, l, Q1, SYMNMF_F64, l, l, n, nullptr, nullptr, nullptr, 0, ws, Tm, nullptr, 0, 0.0,
+              nullptr, st));
+    LCHK(chol_inverse(Tm, l, Rl, Rlinv, &dstate->flags, SYMNMF_FLAG_CHOLQR_SHIFT, d_fail, st));
+    LCHK(rowmat(Q1, SYMNMF_F64, l, n, l, Rlinv, nullptr, l, Q, SYMNMF_F64, l, nullptr, st));
+  }
+
+  void ensure_sampling_buffers() {
+    if (sb.w) return;
+    sb.w = dalloc<uint64_t>(n);
+    sb.prefix = dalloc<uint64_t>(n);
+    sb.counts = dalloc<int>(n);
+    sb.flags = dalloc<int>((size_t)n + 1);
+    sb.info = dalloc<int>(8);
+    sb.theta = dalloc<double>(1);
+    HIPCHK(hipMemsetAsync(sb.counts, 0, sizeof(int) * n, st));
+    HIPCHK(hipMemsetAsync(sb.info, 0, sizeof(int) * 8, st));
+    HIPCHK(hipMemsetAsync(sb.theta, 0, sizeof(double), st));
+  }
+};
+
+namespace {
+
+int fail(symnmf_ctx* c, const Fail& f) {
+  if (c) c->err = f.msg;
+  else g_create_error = f.msg;
+  return f.code;
+}
+
+template <typename Fn>
+int guarded(symnmf_ctx* c, Fn&& fn) {
+  if (!c) {
+    g_create_error = "null context";
+    return SYMNMF_E_INVALID;
+  }
+  try {
+    fn();
+    return SYMNMF_OK;
+  } catch (const Fail& f) {
+    return fail(c, f);
+  } catch (const std::bad_alloc&) {
+    return fail(c, Fail{SYMNMF_E_NOMEM, "host allocation failed"});
+  } catch (...) {
+    return fail(c, Fail{SYMNMF_E_DEVICE, "unexpected internal error"});
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+int symnmf_default_options(symnmf_options* opt) {
+  if (!opt) return SYMNMF_E_INVALID;
+  std::memset(opt, 0, sizeof(*opt));
+  opt->struct_size = (int32_t)sizeof(symnmf_options);
+  opt->rule = SYMNMF_RULE_HALS;
+  opt->compute_dtype = -1;
+  opt->stop_mode = SYMNMF_STOP_NONE;
+  opt->stop_tol = 1e-4;
+  opt->stop_patience = 4;
+  opt->check_every = 8;
+  opt->target = 0.0;
+  opt->tau = -1.0;
+  opt->resid_every = 1;
+  opt->max_history = 4096;
+  return SYMNMF_OK;
+}
+
+int symnmf_create(symnmf_ctx** out, const symnmf_matrix* X, int32_t k, double alpha, int64_t s, uint64_t seed,
+                  const symnmf_options* opt, void* hip_stream) {
+  if (!out || !X) {
+    g_create_error = "null argument";
+    return SYMNMF_E_INVALID;
+  }
+  *out = nullptr;
+  symnmf_ctx* c = nullptr;
+  try {
+    c = new symnmf_ctx();
+  } catch (...) {
+    g_create_error = "host allocation failed";
+    return SYMNMF_E_NOMEM;
+  }
+  try {
+    symnmf_default_options(&c->opt);
+    if (opt) {
+      if (opt->struct_size != (int32_t)sizeof(symnmf_options)) throw Fail{SYMNMF_E_INVALID, "options struct_size"};
+      c->opt = *opt;
+    }
+    if (c->opt.check_every < 1) c->opt.check_every = 1;
+    if (c->opt.max_history < 1) c->opt.max_history = 1;
+    if (c->opt.rule != SYMNMF_RULE_HALS && c->opt.rule != SYMNMF_RULE_BPP) throw Fail{SYMNMF_E_INVALID, "rule"};
+    c->st = (hipStream_t)hip_stream;
+    c->kind = X->kind;
+    c->xdtype = X->dtype;
+    if (X->n < 1 || X->n > 0x7fffffff) throw Fail{SYMNMF_E_INVALID, "n out of range"};
+    c->n = (int)X->n;
+    if (k < 1 || k > 64) throw Fail{SYMNMF_E_INVALID, "k must be in 1..64"};
+    if (k > c->n) throw Fail{SYMNMF_E_INVALID, "k > n"};
+    c->k = k;
+    c->kp = kpad(k);
+    if (s < 0) throw Fail{SYMNMF_E_INVALID, "s < 0"};
+    c->s = s;
+    c->seed = seed;
+    c->Xv = X->values;
+    if (c->kind == SYMNMF_DENSE) {
+      if (!X->values) throw Fail{SYMNMF_E_INVALID, "null values"};
+      if (X->dtype != SYMNMF_F64 && X->dtype != SYMNMF_F32 && X->dtype != SYMNMF_BF16)
+        throw Fail{SYMNMF_E_INVALID, "dtype"};
+      c->ld = X->ld;
+      if (c->ld < c->n) throw Fail{SYMNMF_E_INVALID, "ld < n"};
+      if (s > 0) throw Fail{SYMNMF_E_UNSUPPORTED, "leverage-score sampling needs CSR X"};
+      int cd = c->opt.compute_dtype < 0 ? X->dtype : c->opt.compute_dtype;
+      if (cd == SYMNMF_F64 && X->dtype != SYMNMF_F64) throw Fail{SYMNMF_E_UNSUPPORTED, "F64 compute needs F64 X"};
+      if (X->dtype == SYMNMF_F64 && cd != SYMNMF_F64) throw Fail{SYMNMF_E_UNSUPPORTED, "F64 X needs F64 compute"};
+      if (X->dtype == SYMNMF_BF16 && cd != SYMNMF_BF16) throw Fail{SYMNMF_E_UNSUPPORTED, "BF16 X needs BF16 compute"};
+      if (cd != SYMNMF_F64 && cd != SYMNMF_F32 && cd != SYMNMF_BF16) throw Fail{SYMNMF_E_INVALID, "compute dtype"};
+      c->cdtype = cd;
+      c->fdtype = cd == SYMNMF_F64 ? SYMNMF_F64 : SYMNMF_F32;
+    } else if (c->kind == SYMNMF_CSR) {
+      if (X->dtype != SYMNMF_F64 && X->dtype != SYMNMF_F32) throw Fail{SYMNMF_E_INVALID, "CSR dtype"};
+      if (!X->row_ptr || (X->nnz > 0 && (!X->col_idx || !X->values))) throw Fail{SYMNMF_E_INVALID, "null CSR array"};
+      if (X->nnz < 0 || X->nnz > 0x7fffffff) throw Fail{SYMNMF_E_INVALID, "nnz out of range"};
+      c->nnz = X->nnz;
+      c->rp = X->row_ptr;
+      c->ci = X->col_idx;
+      c->cdtype = X->dtype;
+      c->fdtype = X->dtype;
+    } else {
+      throw Fail{SYMNMF_E_INVALID, "matrix kind"};
+    }
+    if (c->opt.rule == SYMNMF_RULE_BPP) throw Fail{SYMNMF_E_UNSUPPORTED, "BPP rule not available yet"};
+
+    const int n = c->n;
+    // workspace: the largest temporaries of any launcher
+    size_t wsd = (size_t)256 * CMAX * CMAX + 4096;
+    if (c->kind == SYMNMF_DENSE) {
+      wsd = std::max(wsd, (size_t)195 * n + 4096);
+      const size_t nb = (size_t)ceil_div(n, 64);
+      wsd = std::max(wsd, nb * nb + 4096);
+    }
+    wsd = std::max(wsd, (size_t)3 * n + 65536);
+    c->ws.cap = wsd * sizeof(double);
+    c->ws.base = dalloc<char>(c->ws.cap);
+
+    const size_t fs = c->fsize();
+    c->W = dalloc<char>((size_t)n * k * fs);
+    c->H = dalloc<char>((size_t)n * k * fs);
+    c->Y = dalloc<char>((size_t)n * CMAX * fs);
+    if (c->kind == SYMNMF_DENSE) {
+      const GemmPlan p = gemm_plan(n, CMAX, c->cdtype);
+      const size_t acc = c->cdtype == SYMNMF_F64 ? 8 : 4;
+      c->P = dalloc<char>((size_t)p.splits * n * p.cp * acc);
+    }
+    c->G_W = dalloc<double>((size_t)k * k);
+    c->G_H = dalloc<double>((size_t)k * k);
+    c->Gh_W = dalloc<double>((size_t)c->kp * c->kp);
+    c->Gh_H = dalloc<double>((size_t)c->kp * c->kp);
+    c->Gh_S = dalloc<double>((size_t)c->kp * c->kp);
+    c->d_scal = dalloc<double>(16);
+    c->rowsum = dalloc<double>(n);
+    c->dstate = dalloc<DevState>(1);
+    c->hist = dalloc<double>(c->opt.max_history);
+    c->d_fail = dalloc<int>(1);
+    c->R = dalloc<double>((size_t)k * k);
+    c->Rinv = dalloc<double>((size_t)k * k);
+    c->lev = dalloc<double>(n);
+    if (hipHostMalloc((void**)&c->hbuf, 64 * sizeof(double), hipHostMallocDefault) != hipSuccess)
+      throw Fail{SYMNMF_E_NOMEM, "pinned host buffer"};
+    HIPCHK(hipMemsetAsync(c->dstate, 0, sizeof(DevState), c->st));
+    HIPCHK(hipMemsetAsync(c->d_fail, 0, sizeof(int), c->st));
+    HIPCHK(hipMemsetAsync(c->d_scal, 0, 16 * sizeof(double), c->st));
+
+    // compute copy of X
+    c->Xc = c->Xv;
+    if (c->kind == SYMNMF_DENSE && c->cdtype == SYMNMF_BF16 && c->xdtype == SYMNMF_F32) {
+      c->Xb_owned = dalloc<char>((size_t)n * n * 2);
+      LCHK(convert_f32_bf16((const float*)c->Xv, c->ld, c->Xb_owned, n, n, c->st));
+      c->Xc = c->Xb_owned;
+    }
+
+    // one pass over X for the scalars
+    c->ws.reset();
+    if (c->kind == SYMNMF_DENSE)
+      LCHK(dense_scalars(c->Xv, c->xdtype, c->ld, n, c->ws, c->rowsum, c->d_scal, c->st));
+    else
+      LCHK(csr_scalars(c->rp, c->Xv, c->xdtype, n, c->nnz, c->ws, c->rowsum, c->d_scal, c->st));
+    const double* h = c->readback(c->d_scal, 3);
+    c->normsq = h[0];
+    c->total = h[1];
+    c->maxval = h[2];
+    if (c->kind == SYMNMF_CSR && (double)c->nnz < (double)n * (double)n) c->maxval = std::fmax(c->maxval, 0.0);
+    if (!std::isfinite(c->normsq) || !std::isfinite(c->total)) throw Fail{SYMNMF_E_INVALID, "X has NaN or Inf"};
+    if (!(c->normsq > 0.0)) throw Fail{SYMNMF_E_INVALID, "X is zero"};
+    c->alpha = alpha > 0.0 ? alpha : c->maxval;
+    if (!(c->alpha > 0.0)) throw Fail{SYMNMF_E_INVALID, "alpha = max(X) is not positive"};
+    c->zeta = c->total / ((double)n * (double)n);
+    if (!(c->zeta > 0.0)) throw Fail{SYMNMF_E_INVALID, "mean of X is not positive"};
+    c->tau = c->opt.tau >= 0.0 ? c->opt.tau : (s > 0 ? 1.0 / (double)s : 0.0);
+
+    // H0 = U[0,1) * 2 sqrt(zeta / k), W0 = H0 (Section 6 initialisation)
+    LCHK(init_uniform_factor(c->H, c->fdtype, n, k, 2.0 * std::sqrt(c->zeta / k), seed, c->st));
+    HIPCHK(hipMemcpyAsync(c->W, c->H, (size_t)n * k * fs, hipMemcpyDeviceToDevice, c->st));
+    c->refresh_gram(c->H, c->G_H, c->Gh_H);
+    c->refresh_gram(c->W, c->G_W, c->Gh_W);
+
+    if (s > 0) {
+      if (c->kind != SYMNMF_CSR) throw Fail{SYMNMF_E_UNSUPPORTED, "sampling needs CSR X"};
+      c->mode = SYMNMF_MODE_LVS;
+      // bound on selected rows: the s draws plus the rows with p_i >= tau
+      // (sum p_i = 1 up to rounding, so at most about 1/tau of them)
+      int64_t ms = c->tau > 0.0 ? s + (int64_t)std::ceil(1.01 / c->tau) + 1 : (int64_t)n;
+      c->max_sel = std::min<int64_t>(ms, n);
+      c->host_rp.resize((size_t)n + 1);
+      HIPCHK(hipMemcpyAsync(c->host_rp.data(), c->rp, sizeof(int) * (n + 1), hipMemcpyDeviceToHost, c->st));
+      c->sync();
+      std::vector<int> len(n);
+      for (int i = 0; i < n; ++i) len[i] = c->host_rp[i + 1] - c->host_rp[i];
+      std::nth_element(len.begin(), len.begin() + (c->max_sel - 1), len.end(), std::greater<int>());
+      int64_t cap = 0;
+      for (int64_t i = 0; i < c->max_sel; ++i) cap += len[i];
+      c->seg_cap = std::max<int64_t>(cap, 1);
+      c->ensure_sampling_buffers();
+      c->rows = dalloc<int>(c->max_sel);
+      c->weights = dalloc<double>(c->max_sel);
+      c->seg_cnt = dalloc<int>(n);
+      c->seg_ptr = dalloc<int>((size_t)n + 1);
+      c->seg_src = dalloc<int>(c->seg_cap);
+      c->seg_val = dalloc<double>(c->seg_cap);
+      HIPCHK(hipMemsetAsync(c->seg_cnt, 0, sizeof(int) * n, c->st));
+    }
+    c->sync();
+  } catch (const Fail& f) {
+    g_create_error = f.msg;
+    delete c;
+    return f.code;
+  } catch (const std::bad_alloc&) {
+    g_create_error = "host allocation failed";
+    delete c;
+    return SYMNMF_E_NOMEM;
+  } catch (...) {
+    g_create_error = "unexpected internal error";
+    delete c;
+    return SYMNMF_E_DEVICE;
+  }
+  *out = c;
+  return SYMNMF_OK;
+}
+
+int symnmf_lai(symnmf_ctx* c, int32_t l, int32_t q) {
+  return guarded(c, [&] {
+    if (c->kind != SYMNMF_DENSE) throw Fail{SYMNMF_E_UNSUPPORTED, "LAI needs dense X"};
+    if (c->mode == SYMNMF_MODE_LVS) throw Fail{SYMNMF_E_UNSUPPORTED, "LAI with sampling"};
+    if (l < c->k || l > 96 || l > c->n) throw Fail{SYMNMF_E_INVALID, "need k <= l <= min(n, 96)"};
+    if (q < 0 || q > 64) throw Fail{SYMNMF_E_INVALID, "q out of range"};
+    const int n = c->n;
+    if (c->l != l) {
+      double** bufs[] = {&c->Q, &c->Q1, &c->U, &c->YQ, &c->Tm, &c->QT, &c->Vw, &c->lam, &c->Rl, &c->Rlinv, &c->Z};
+      c->sync();
+      for (double** b : bufs) {
+        dfree(*b);
+        *b = nullptr;
+      }
+      c->l = l;
+      c->Q = dalloc<double>((size_t)n * l);
+      c->Q1 = dalloc<double>((size_t)n * l);
+      c->U = dalloc<double>((size_t)n * l);
+      c->YQ = dalloc<double>((size_t)n * l);  // holds fdtype values
+      c->Tm = dalloc<double>((size_t)l * l);
+      c->QT = dalloc<double>((size_t)l * l);
+      c->Vw = dalloc<double>((size_t)l * l);
+      c->lam = dalloc<double>(l);
+      c->Rl = dalloc<double>((size_t)l * l);
+      c->Rlinv = dalloc<double>((size_t)l * l);
+      c->Z = dalloc<double>((size_t)l * c->k);
+    }
+    HIPCHK(hipMemsetAsync(c->d_fail, 0, sizeof(int), c->st));
+    // Algorithm RRF: Omega Gaussian (Philox), then 2q+1 products each followed
+    // by CholeskyQR2 (re-orthonormalising after every product).
+    LCHK(gen_gaussian(c->Q, (int64_t)n * l, c->seed, 0, TAG_OMEGA, c->st));
+    for (int it = 0; it < 2 * q + 1; ++it) {
+      c->product(c->Q, SYMNMF_F64, l, c->YQ);
+      c->cholqr2(c->YQ);
+    }
+    // Algorithm Apx-EVD: T = Q^T (X Q), T = Q_T Lambda Q_T^T, U = Q Q_T.
+    c->product(c->Q, SYMNMF_F64, l, c->YQ);
+    c->ws.reset();
+    LCHK(gram(c->Q, SYMNMF_F64, l, l, c->YQ, c->fdtype, l, l, n, nullptr, nullptr, nullptr, 0, c->ws, c->Tm, nullptr,
+              0, 0.0, nullptr, c->st));
+    LCHK(jacobi_evd(c->Tm, l, c->Vw, c->QT, c->lam, c->st));
+    LCHK(rowmat(c->Q, SYMNMF_F64, l, n, l, c->QT, nullptr, l, c->U, SYMNMF_F64, l, nullptr, c->st));
+    c->ws.reset();
+    LCHK(column_sign_fix(c->U, n, l, c->ws, c->st));
+    frob_dot(c->lam, c->lam, l, c->d_scal + 8, c->st);
+    HIPCHK(hipMemcpyAsync(c->hbuf, c->d_scal + 8, sizeof(double), hipMemcpyDeviceToHost, c->st));
+    HIPCHK(hipMemcpyAsync(c->hbuf + 1, c->d_fail, sizeof(int), hipMemcpyDeviceToHost, c->st));
+    c->sync();
+    c->normsq_lai = c->hbuf[0];
+    int failed = 0;
+    std::memcpy(&failed, c->hbuf + 1, sizeof(int));
+    if (failed) throw Fail{SYMNMF_E_NUMERIC, "CholeskyQR2 broke down"};
+    if (!(c->normsq_lai > 0.0)) throw Fail{SYMNMF_E_NUMERIC, "low-rank approximation is zero"};
+    c->mode = SYMNMF_MODE_LAI;
+  });
+}
+
+int symnmf_refine(symnmf_ctx* c, int32_t stop_mode, double target) {
+  return guarded(c, [&] {
+    if (c->mode != SYMNMF_MODE_LAI) throw Fail{SYMNMF_E_STATE, "refinement needs a context in LAI mode"};
+    if (stop_mode < SYMNMF_STOP_NONE || stop_mode > SYMNMF_STOP_TARGET) throw Fail{SYMNMF_E_INVALID, "stop_mode"};
+    DevState d = c->read_state();
+    d.done = 0;
+    d.stall = 0;
+    d.prev = INFINITY;
+    std::memcpy(c->hbuf, &d, sizeof(DevState));
+    HIPCHK(hipMemcpyAsync(c->dstate, c->hbuf, sizeof(DevState), hipMemcpyHostToDevice, c->st));
+    c->sync();
+    c->opt.stop_mode = stop_mode;
+    c->opt.target = target;
+    c->mode = SYMNMF_MODE_PLAIN;
+  });
+}
+
+int symnmf_iterate(symnmf_ctx* c, int32_t iters, int32_t* done) {
+  return guarded(c, [&] {
+    if (iters < 0) throw Fail{SYMNMF_E_INVALID, "iters < 0"};
+    const DevState before = c->read_state();
+    if (!before.done) {
+      const int every = c->opt.stop_mode == SYMNMF_STOP_NONE ? iters : c->opt.check_every;
+      for (int t = 0; t < iters; ++t) {
+        c->one_iteration();
+        if (c->opt.stop_mode != SYMNMF_STOP_NONE && ((t + 1) % every) == 0 && t + 1 < iters) {
+          if (c->read_state().done) break;
+        }
+      }
+    }
+    const DevState after = c->read_state();
+    if (done) *done = after.iter - before.iter;
+  });
+}
+
+int symnmf_residual(symnmf_ctx* c, int32_t mode, double out[2]) {
+  return guarded(c, [&] {
+    if (!out) throw Fail{SYMNMF_E_INVALID, "null out"};
+    if (mode == SYMNMF_RESID_FAST) {
+      const bool lai = c->mode == SYMNMF_MODE_LAI;
+      out[0] = c->trace_residual(c->W, c->H, lai);
+      out[1] = c->trace_residual(c->H, c->H, lai);
+    } else if (mode == SYMNMF_RESID_EXACT) {
+      if (c->k > 64) throw Fail{SYMNMF_E_UNSUPPORTED, "k"};
+      out[0] = c->exact_residual(c->W, c->H);
+      out[1] = c->exact_residual(c->H, c->H);
+    } else if (mode == SYMNMF_RESID_LAI) {
+      if (c->l == 0 || c->mode != SYMNMF_MODE_LAI) throw Fail{SYMNMF_E_STATE, "no LAI factors"};
+      out[0] = c->trace_residual(c->W, c->H, true);
+      out[1] = c->trace_residual(c->H, c->H, true);
+    } else {
+      throw Fail{SYMNMF_E_INVALID, "residual mode"};
+    }
+  });
+}
+
+int symnmf_set_factor(symnmf_ctx* c, int32_t which, const void* src, int32_t dtype) {
+  return guarded(c, [&] {
+    if (!src || (which != SYMNMF_W && which != SYMNMF_H)) throw Fail{SYMNMF_E_INVALID, "argument"};
+    if (dtype != SYMNMF_F64 && dtype != SYMNMF_F32) throw Fail{SYMNMF_E_INVALID, "dtype"};
+    void* dst = which == SYMNMF_W ? c->W : c->H;
+    LCHK(copy_convert(src, dtype, dst, c->fdtype, c->nk(), c->st));
+    if (which == SYMNMF_W) c->refresh_gram(c->W, c->G_W, c->Gh_W);
+    else c->refresh_gram(c->H, c->G_H, c->Gh_H);
+  });
+}
+
+int symnmf_get_factor(symnmf_ctx* c, int32_t which, void* dst, int32_t dtype) {
+  return guarded(c, [&] {
+    if (!dst || (which != SYMNMF_W && which != SYMNMF_H)) throw Fail{SYMNMF_E_INVALID, "argument"};
+    if (dtype != SYMNMF_F64 && dtype != SYMNMF_F32) throw Fail{SYMNMF_E_INVALID, "dtype"};
+    LCHK(copy_convert(which == SYMNMF_W ? c->W : c->H, c->fdtype, dst, dtype, c->nk(), c->st));
+  });
+}
+
+int symnmf_get_lai(symnmf_ctx* c, void* U, void* lambda) {
+  return guarded(c, [&] {
+    if (c->l == 0) throw Fail{SYMNMF_E_STATE, "symnmf_lai has not run"};
+    if (U) HIPCHK(hipMemcpyAsync(U, c->U, sizeof(double) * c->n * c->l, hipMemcpyDeviceToDevice, c->st));
+    if (lambda) HIPCHK(hipMemcpyAsync(lambda, c->lam, sizeof(double) * c->l, hipMemcpyDeviceToDevice, c->st));
+  });
+}
+
+int symnmf_apply_x(symnmf_ctx* c, const void* B, int32_t cols, void* Yout) {
+  return guarded(c, [&] {
+    if (!B || !Yout || cols < 1 || cols > CMAX) throw Fail{SYMNMF_E_INVALID, "argument"};
+    if (c->kind == SYMNMF_CSR && cols > 128) throw Fail{SYMNMF_E_INVALID, "cols"};
+    c->product(B, c->fdtype, cols, Yout);
+  });
+}
+
+int symnmf_half_step(symnmf_ctx* c, int32_t side, int32_t half_iter) {
+  return guarded(c, [&] {
+    if (side != 0 && side != 1) throw Fail{SYMNMF_E_INVALID, "side"};
+    if (half_iter < 0) throw Fail{SYMNMF_E_INVALID, "half_iter"};
+    c->half_step(side, half_iter);
+  });
+}
+
+int symnmf_leverage(symnmf_ctx* c, int32_t which, void* lev) {
+  return guarded(c, [&] {
+    if (!lev || (which != SYMNMF_W && which != SYMNMF_H)) throw Fail{SYMNMF_E_INVALID, "argument"};
+    const double* G = which == SYMNMF_W ? c->G_W : c->G_H;
+    LCHK(chol_inverse(G, c->k, c->R, c->Rinv, &c->dstate->flags, SYMNMF_FLAG_LEV_SHIFT, c->d_fail, c->st));
+    LCHK(leverage_scores(which == SYMNMF_W ? c->W : c->H, c->fdtype, c->n, c->k, c->Rinv, (double*)lev, nullptr,
+                         c->st));
+  });
+}
+
+int symnmf_sample(symnmf_ctx* c, const void* lev, int32_t half_iter, void* rows, void* weights, int64_t cap,
+                  int64_t* count) {
+  return guarded(c, [&] {
+    if (!lev || !rows || !weights || !count || cap < 1) throw Fail{SYMNMF_E_INVALID, "argument"};
+    if (c->s < 1) throw Fail{SYMNMF_E_STATE, "context has s = 0"};
+    c->ensure_sampling_buffers();
+    c->ws.reset();
+    LCHK(hybrid_sample((const double*)lev, c->n, c->k, c->s, c->tau, c->seed, (uint32_t)half_iter, c->sb,
+                       (int*)rows, (double*)weights, cap, c->ws, nullptr, c->st));
+    HIPCHK(hipMemcpyAsync(c->hbuf, c->sb.info, 4 * sizeof(int), hipMemcpyDeviceToHost, c->st));
+    c->sync();
+    int info[4];
+    std::memcpy(info, c->hbuf, sizeof(info));
+    if ((int64_t)info[3] > cap) throw Fail{SYMNMF_E_INVALID, "capacity smaller than the number of sampled rows"};
+    *count = info[3];
+  });
+}
+
+int symnmf_history(symnmf_ctx* c, double* out, int32_t cap, int32_t* count) {
+  return guarded(c, [&] {
+    if (!out || !count || cap < 0) throw Fail{SYMNMF_E_INVALID, "argument"};
+    const DevState d = c->read_state();
+    const int m = std::min(std::min(d.iter, c->opt.max_history), cap);
+    if (m > 0) HIPCHK(hipMemcpy(out, c->hist, sizeof(double) * m, hipMemcpyDeviceToHost));
+    *count = m;
+  });
+}
+
+int symnmf_get_stats(symnmf_ctx* c, symnmf_stats* out) {
+  return guarded(c, [&] {
+    if (!out || out->struct_size != (int32_t)sizeof(symnmf_stats)) throw Fail{SYMNMF_E_INVALID, "stats struct"};
+    const DevState d = c->read_state();
+    std::memset(out, 0, sizeof(*out));
+    out->struct_size = sizeof(symnmf_stats);
+    out->mode = c->mode;
+    out->iterations = d.iter;
+    out->stopped = d.done;
+    out->k = c->k;
+    out->l = c->l;
+    out->n = c->n;
+    out->alpha = c->alpha;
+    out->zeta = c->zeta;
+    out->normsq = c->normsq;
+    out->maxval = c->maxval;
+    out->last_residual = d.last;
+    out->flags = d.flags;
+    if (c->sb.info) {
+      HIPCHK(hipMemcpyAsync(c->hbuf, c->sb.info, 4 * sizeof(int), hipMemcpyDeviceToHost, c->st));
+      HIPCHK(hipMemcpyAsync(c->hbuf + 2, c->sb.theta, sizeof(double), hipMemcpyDeviceToHost, c->st));
+      c->sync();
+      int info[4];
+      std::memcpy(info, c->hbuf, sizeof(info));
+      out->s_D = info[0];
+      out->sample_rows = info[3];
+      out->theta_over_k = c->hbuf[2] / c->k;
+    }
+  });
+}
+
+const char* symnmf_last_error(const symnmf_ctx* c) { return c ? c->err.c_str() : g_create_error.c_str(); }
+
+void symnmf_destroy(symnmf_ctx* c) { delete c; }
+
+}  // extern "C"

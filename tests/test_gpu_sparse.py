@@ -1,0 +1,139 @@
+"""GPU parity of the CSR path and of leverage-score sampling (Algorithm
+LvS-SymNMF with hybrid sampling) against the FP64 oracle, through the C ABI."""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+from oracle import symnmf as O
+import workloads
+
+from gpu_common import P, torch, require_gpu, dev, host, rel, factor, round_to, csr_dev, log
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    require_gpu()
+
+
+def _sbm(n=6000, blocks=12, deg=24.0, seed=0):
+    X, lab = workloads.sbm(n, blocks, deg, 20.0, seed=seed)
+    return X
+
+
+def _X64(X):
+    return sp.csr_matrix((X.data.astype(np.float64), X.indices, X.indptr), shape=X.shape)
+
+
+@pytest.mark.parametrize("c", [1, 10, 16, 33, 64, 80])
+def test_spmm_parity(c):
+    X = _sbm(5003, 7, 20.0, seed=c)
+    ctx = P.symnmf_create(csr_dev(X), min(c, 64), 0.0, 0, 0)
+    B = workloads.random_factor(X.shape[0], c, seed=c)
+    Bd = dev(B, torch.float32)
+    Yd = torch.empty_like(Bd)
+    P.symnmf_apply_x(ctx, Bd, Yd)
+    ref = _X64(X) @ round_to(B, torch.float32)
+    assert rel(host(Yd), ref) <= 1e-6
+
+
+def test_csr_plain_parity_and_exact_residual():
+    X = _sbm()
+    n, k = X.shape[0], 12
+    ctx = P.symnmf_create(csr_dev(X), k, 0.0, 0, 3)
+    iters = 25
+    P.symnmf_iterate(ctx, iters)
+    X64 = _X64(X)
+    sc = O.data_scalars(X64)
+    H0 = round_to(O.initial_factor(n, k, sc["zeta"], 3), torch.float32)
+    Wo, Ho, hist = O.plain_symnmf(X64, k, sc["maxval"], H0, iters)
+    hg = np.array(P.symnmf_history(ctx))
+    log(f"csr plain: history max rel {np.max(np.abs(hg - hist) / hist):.2e}")
+    assert np.max(np.abs(hg - hist) / hist) <= 1e-4
+    r = P.symnmf_residual(ctx, P.RESID_EXACT)
+    ro = O.residual_direct(X64, Wo, Ho) / np.sqrt(sc["normsq"])
+    assert abs(r[0] - ro) / ro <= 1e-4
+
+
+def test_leverage_parity():
+    X = _sbm()
+    n, k = X.shape[0], 16
+    ctx = P.symnmf_create(csr_dev(X), k, 0.0, 100, 0)
+    H = workloads.random_factor(n, k, seed=5) ** 2
+    P.symnmf_set_factor(ctx, P.H, dev(H))
+    lev = torch.empty(n, dtype=torch.float64, device="cuda")
+    P.symnmf_leverage(ctx, P.H, lev)
+    lo = O.leverage_scores(round_to(H, torch.float32))
+    lg = host(lev)
+    assert rel(lg, lo) <= 1e-10
+    assert abs(lg.sum() - k) <= 1e-9 * k
+
+
+@pytest.mark.parametrize("tau", [-1.0, 0.3e-3, 0.0])
+def test_sampler_bitwise(tau):
+    n, k, s = 20000, 16, 2000
+    X = _sbm(n, 10, 8.0, seed=2)
+    o = P.symnmf_default_options(tau=tau)
+    ctx = P.symnmf_create(csr_dev(X), k, 0.0, s, 77, o)
+    lev = workloads.skewed_scores(n, k, seed=3, heavy=40)
+    cap = n
+    rows = torch.empty(cap, dtype=torch.int32, device="cuda")
+    w = torch.empty(cap, dtype=torch.float64, device="cuda")
+    for h in (0, 1, 5):
+        cnt = P.symnmf_sample(ctx, dev(lev), h, rows, w)
+        tau_eff = 1.0 / s if tau < 0 else tau
+        ro, wo, info = O.hybrid_sample(lev, k, s, tau_eff, 77, h)
+        rg = rows[:cnt].cpu().numpy()
+        wg = w[:cnt].cpu().numpy()
+        log(f"sampler tau={tau} h={h}: rows {cnt} (det {info['s_D']})")
+        assert cnt == ro.shape[0]
+        assert np.array_equal(rg, ro)
+        assert np.array_equal(wg, wo)
+        st = P.symnmf_get_stats(ctx)
+        assert st.s_D == info["s_D"]
+
+
+def test_lvs_half_step_identical_inputs():
+    X = _sbm(8000, 16, 30.0, seed=4)
+    n, k, s = X.shape[0], 16, 800
+    ctx = P.symnmf_create(csr_dev(X), k, 0.0, s, 9)
+    alpha = P.symnmf_get_stats(ctx).alpha
+    H = workloads.random_factor(n, k, seed=6, scale=0.2)
+    W = workloads.random_factor(n, k, seed=7, scale=0.2)
+    P.symnmf_set_factor(ctx, P.H, dev(H))
+    P.symnmf_set_factor(ctx, P.W, dev(W))
+    H32, W32 = round_to(H, torch.float32), round_to(W, torch.float32)
+    P.symnmf_half_step(ctx, 0, 4)
+    Wo, info = O.lvs_half_step(_X64(X), H32, W32, alpha, s, 1.0 / s, 9, 4)
+    log(f"lvs half step: rows {len(info['rows'])} det {info['s_D']}")
+    assert rel(factor(ctx, P.W), Wo) <= 1e-5
+
+
+def test_lvs_run_parity():
+    X = _sbm(8000, 16, 30.0, seed=5)
+    n, k, s = X.shape[0], 16, 1000
+    ctx = P.symnmf_create(csr_dev(X), k, 0.0, s, 21)
+    iters = 8
+    P.symnmf_iterate(ctx, iters)
+    X64 = _X64(X)
+    sc = O.data_scalars(X64)
+    H0 = round_to(O.initial_factor(n, k, sc["zeta"], 21), torch.float32)
+    Wo, Ho, hist = O.lvs_symnmf(X64, k, sc["maxval"], H0, iters, s, 1.0 / s, 21)
+    hg = np.array(P.symnmf_history(ctx))
+    log(f"lvs run: gpu {hg[-1]:.6f} oracle {hist[-1]:.6f}")
+    assert np.max(np.abs(hg - hist) / hist) <= 1e-4
+    r = P.symnmf_residual(ctx, P.RESID_EXACT)
+    ro = O.residual_direct(X64, Wo, Ho) / np.sqrt(sc["normsq"])
+    assert abs(r[0] - ro) / ro <= 1e-4
+
+
+def test_lvs_tau_zero_matches_plain():
+    X = _sbm(3000, 6, 20.0, seed=6)
+    k = 8
+    o = P.symnmf_default_options(tau=0.0)
+    a = P.symnmf_create(csr_dev(X), k, 0.0, 50, 2, o)
+    b = P.symnmf_create(csr_dev(X), k, 0.0, 0, 2)
+    P.symnmf_iterate(a, 5)
+    P.symnmf_iterate(b, 5)
+    assert rel(factor(a, P.H), factor(b, P.H)) <= 1e-5
