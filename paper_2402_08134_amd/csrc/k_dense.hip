@@ -84,47 +84,79 @@ __global__ void k_scalars_final(int nb, const double* __restrict__ bpart, double
 }
 
 // ---------------------------------------------------------------------------
-// MFMA product P[split] = X[:, krange] B[krange, :], FP32 or FP64 operands.
+// MFMA product P[split] = X[:, krange] B[krange, :].
+//
+// The B operand is first written transposed and zero padded, Bt[q][j] =
+// B[j][q] (q < cp, j < npad), so a lane fetches its B values for four
+// consecutive K with one 16-byte load, exactly like its X values.  No LDS and
+// no barrier: each wave owns 16*RT rows of X, streams its K range tile by
+// tile and prefetches the next X tile into registers while the MFMAs of the
+// current one run (B tiles are small and come from L1/L2, issued before the
+// X prefetch so waiting on them does not wait on the prefetch).
+//
 // v_mfma_{f32,f64}_16x16x4: lane l supplies A[l%16][l/16] and B[l/16][l%16];
-// accumulator element v of lane l is D[4*(l/16)+v][l%16].  A lane reads four
-// consecutive columns of its X row (k0+4g..k0+4g+3, g = l/16) and issues one
-// MFMA per column, pairing it with the matching row of the staged B tile,
-// which covers the 16 columns k0..k0+15 per sub-step.
+// the accumulator layout is given by Mfma<T>::out_row.  A lane holds four
+// consecutive K values (4g..4g+3 of a 16-wide sub-step, g = l/16) and issues
+// one MFMA per value.
 // ---------------------------------------------------------------------------
+// Accumulator rows differ between the two instructions (measured on gfx950):
+// f32: element v of lane l is row 4*(l/16) + v; f64: row (l/16) + 4*v.  The
+// column is l%16 for both.
 template <typename T> struct Mfma;
 template <> struct Mfma<float> {
   using acc_t = floatx4;
   static __device__ __forceinline__ acc_t mma(float a, float b, acc_t c) {
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
   }
+  static __device__ __forceinline__ int out_row(int lg, int v) { return 4 * lg + v; }
 };
 template <> struct Mfma<double> {
   using acc_t = doublex4;
   static __device__ __forceinline__ acc_t mma(double a, double b, acc_t c) {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
   }
+  static __device__ __forceinline__ int out_row(int lg, int v) { return lg + 4 * v; }
 };
 
 template <typename T> struct Vec4;
 template <> struct Vec4<float> { using type = floatx4; };
 template <> struct Vec4<double> { using type = doublex4; };
 
-constexpr int GEMM_KT = 64;
+constexpr int GEMM_KT = 64;   // K per tile, FP32 / FP64 (4 sub-steps of 16)
+constexpr int BF_KT = 128;    // K per tile, BF16 (4 sub-steps of 32)
+constexpr int BT_PAD = 128;   // Bt row length is n rounded up to this
 
-template <typename TX, typename TB, int NT, int RT>
-__global__ __launch_bounds__(256) void k_gemm_mfma(const TX* __restrict__ X, int64_t ldx, const TB* __restrict__ B,
-                                                   int64_t ldb, int n, int c, int kchunk, TX* __restrict__ P, int cp,
+template <typename TB, typename TO>
+__global__ __launch_bounds__(256) void k_transpose_pad(const TB* __restrict__ B, int64_t ldb, int n, int c,
+                                                       TO* __restrict__ Bt, int64_t ldt, int cp,
+                                                       const DevState* __restrict__ st) {
+  if (stopped(st)) return;
+  __shared__ double tile[32][33];
+  const int j0 = blockIdx.x * 32, q0 = blockIdx.y * 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8
+  for (int r = ty; r < 32; r += 8) {
+    const int j = j0 + r, q = q0 + tx;
+    tile[r][tx] = (j < n && q < c) ? (double)B[(int64_t)j * ldb + q] : 0.0;
+  }
+  __syncthreads();
+  for (int r = ty; r < 32; r += 8) {
+    const int q = q0 + r, j = j0 + tx;
+    if (q < cp && j < ldt) Bt[(int64_t)q * ldt + j] = (TO)tile[tx][r];
+  }
+}
+
+template <typename TX, int NT, int RT, bool VEC>
+__global__ __launch_bounds__(256) void k_gemm_mfma(const TX* __restrict__ X, int64_t ldx, const TX* __restrict__ Bt,
+                                                   int64_t ldt, int n, int kchunk, TX* __restrict__ P, int cp,
                                                    const DevState* __restrict__ st) {
   if (stopped(st)) return;
   using M = Mfma<TX>;
   using acc_t = typename M::acc_t;
-  constexpr int CP = 16 * NT;
-  constexpr int LDB = CP + 4;
-  __shared__ TX Bs[GEMM_KT * LDB];
-
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  using V4 = typename Vec4<TX>::type;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int li = lane & 15, lg = lane >> 4;
-  const int row_base = blockIdx.x * (64 * RT) + wave * (16 * RT);
+  const int row_base = (blockIdx.x * 4 + wave) * (16 * RT);
+  if (row_base >= n) return;
   const int kb = blockIdx.y * kchunk;
   const int ke = min(n, kb + kchunk);
 
@@ -136,97 +168,104 @@ __global__ __launch_bounds__(256) void k_gemm_mfma(const TX* __restrict__ X, int
 
   const TX* xrow[RT];
 #pragma unroll
-  for (int r = 0; r < RT; ++r) {
-    const int rr = min(row_base + 16 * r + li, n - 1);
-    xrow[r] = X + (int64_t)rr * ldx;
-  }
-  const bool vec_ok = ((ldx & 3) == 0) && ((((uintptr_t)X) & (4 * sizeof(TX) - 1)) == 0);
+  for (int r = 0; r < RT; ++r) xrow[r] = X + (int64_t)min(row_base + 16 * r + li, n - 1) * ldx + 4 * lg;
+  const TX* brow[NT];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) brow[t] = Bt + (int64_t)(16 * t + li) * ldt + 4 * lg;
 
-  for (int k0 = kb; k0 < ke; k0 += GEMM_KT) {
-    // Issue the X loads for this tile first so they overlap the B staging.
-    TX xv[RT][4][4];
-    if (vec_ok && k0 + GEMM_KT <= ke) {
+  const int nfull = VEC ? (ke - kb) / GEMM_KT : 0;
+  // Software pipeline with two register buffers used in turn (no copies, so
+  // the compiler cannot merge them): the X and B operands of the next tile
+  // are loaded while the MFMAs of the current one run.  Everything consumed
+  // by a compute step was issued before the loads it overlaps, so the
+  // in-order load counter never makes it wait for the prefetch.
+  V4 x0[RT][4], b0[NT][4], x1[RT][4], b1[NT][4];
+  auto load = [&](V4 (&xv)[RT][4], V4 (&bv)[NT][4], int k0) {
 #pragma unroll
-      for (int r = 0; r < RT; ++r)
+    for (int r = 0; r < RT; ++r)
 #pragma unroll
-        for (int ss = 0; ss < 4; ++ss) {
-          typename Vec4<TX>::type v =
-              __builtin_nontemporal_load((const typename Vec4<TX>::type*)(xrow[r] + k0 + 16 * ss + 4 * lg));
-          xv[r][ss][0] = v.x;
-          xv[r][ss][1] = v.y;
-          xv[r][ss][2] = v.z;
-          xv[r][ss][3] = v.w;
-        }
-    } else {
+      for (int ss = 0; ss < 4; ++ss) xv[r][ss] = __builtin_nontemporal_load((const V4*)(xrow[r] + k0 + 16 * ss));
 #pragma unroll
-      for (int r = 0; r < RT; ++r)
+    for (int ct = 0; ct < NT; ++ct)
 #pragma unroll
-        for (int ss = 0; ss < 4; ++ss)
-#pragma unroll
-          for (int t = 0; t < 4; ++t) {
-            const int col = k0 + 16 * ss + 4 * lg + t;
-            xv[r][ss][t] = (col < ke) ? xrow[r][col] : (TX)0;
-          }
-    }
-    __syncthreads();
-    for (int e = tid; e < GEMM_KT * CP; e += 256) {
-      const int kk = e / CP, cc = e - kk * CP;
-      const int kg = k0 + kk;
-      TX v = (TX)0;
-      if (kg < ke && cc < c) v = (TX)B[(int64_t)kg * ldb + cc];
-      Bs[kk * LDB + cc] = v;
-    }
-    __syncthreads();
+      for (int ss = 0; ss < 4; ++ss) bv[ct][ss] = *(const V4*)(brow[ct] + k0 + 16 * ss);
+  };
+  auto compute = [&](const V4 (&xv)[RT][4], const V4 (&bv)[NT][4]) {
 #pragma unroll
     for (int ss = 0; ss < 4; ++ss)
 #pragma unroll
-      for (int t = 0; t < 4; ++t) {
-        const TX* brow = Bs + (16 * ss + 4 * lg + t) * LDB + li;
+      for (int u = 0; u < 4; ++u)
 #pragma unroll
-        for (int ct = 0; ct < NT; ++ct) {
-          const TX b = brow[16 * ct];
+        for (int ct = 0; ct < NT; ++ct)
 #pragma unroll
-          for (int r = 0; r < RT; ++r) acc[r][ct] = M::mma(xv[r][ss][t], b, acc[r][ct]);
-        }
+          for (int r = 0; r < RT; ++r) acc[r][ct] = M::mma(xv[r][ss][u], bv[ct][ss][u], acc[r][ct]);
+  };
+  int t = 0;
+  if (nfull > 0) load(x0, b0, kb);
+  for (; t + 2 < nfull; t += 2) {
+    load(x1, b1, kb + (t + 1) * GEMM_KT);
+    compute(x0, b0);
+    load(x0, b0, kb + (t + 2) * GEMM_KT);
+    compute(x1, b1);
+  }
+  if (t + 1 < nfull) {
+    load(x1, b1, kb + (t + 1) * GEMM_KT);
+    compute(x0, b0);
+    compute(x1, b1);
+  } else if (t < nfull) {
+    compute(x0, b0);
+  }
+  // Remaining K (partial last tile, or every tile when X is not aligned for
+  // vector loads): guarded scalar loads of X; Bt is zero padded.
+  for (int k0 = kb + nfull * GEMM_KT; k0 < ke; k0 += GEMM_KT) {
+#pragma unroll
+    for (int ss = 0; ss < 4; ++ss) {
+      TX xs[RT][4];
+      TX bs[NT][4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int col = k0 + 16 * ss + 4 * lg + u;
+#pragma unroll
+        for (int r = 0; r < RT; ++r) xs[r][u] = (col < ke) ? xrow[r][col - 4 * lg] : (TX)0;
+#pragma unroll
+        for (int ct = 0; ct < NT; ++ct) bs[ct][u] = brow[ct][k0 + 16 * ss + u];
       }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int ct = 0; ct < NT; ++ct)
+#pragma unroll
+          for (int r = 0; r < RT; ++r) acc[r][ct] = M::mma(xs[r][u], bs[ct][u], acc[r][ct]);
+    }
   }
   TX* out = P + (int64_t)blockIdx.y * n * cp;
 #pragma unroll
   for (int r = 0; r < RT; ++r)
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
-      const int row = row_base + 16 * r + 4 * lg + v;
+      const int row = row_base + 16 * r + M::out_row(lg, v);
       if (row < n) {
 #pragma unroll
-        for (int ct = 0; ct < NT; ++ct) {
-          const int col = 16 * ct + li;
-          if (col < cp) out[(int64_t)row * cp + col] = acc[r][ct][v];
-        }
+        for (int ct = 0; ct < NT; ++ct) out[(int64_t)row * cp + 16 * ct + li] = acc[r][ct][v];
       }
     }
 }
 
 // ---------------------------------------------------------------------------
 // BF16 MFMA product (FP32 accumulate): v_mfma_f32_16x16x32_bf16.  Lane l
-// supplies 8 consecutive K values of A row l%16 and of B column l%16, group
-// g = l/16 covering K offsets 8g..8g+7 of the 32-wide step; accumulator layout
-// as above.  B is rounded to BF16 (nearest even) while staged, transposed, in
-// LDS so a lane reads its 8 values with one 16-byte load.
+// supplies 8 consecutive K values of A row l%16 and of B column l%16 (group
+// g = l/16 covers K offsets 8g..8g+7 of the 32-wide step); accumulator layout
+// as the f32 instruction.  Bt holds B rounded to BF16 (nearest even).
 // ---------------------------------------------------------------------------
-constexpr int BF_KT = 128;
-
-template <typename TB, int NT, int RT>
+template <int NT, int RT, bool VEC>
 __global__ __launch_bounds__(256) void k_gemm_bf16(const __bf16* __restrict__ X, int64_t ldx,
-                                                   const TB* __restrict__ B, int64_t ldb, int n, int c, int kchunk,
+                                                   const __bf16* __restrict__ Bt, int64_t ldt, int n, int kchunk,
                                                    float* __restrict__ P, int cp, const DevState* __restrict__ st) {
   if (stopped(st)) return;
-  constexpr int CP = 16 * NT;
-  constexpr int LDK = BF_KT + 8;  // bf16 elements per staged B column
-  __shared__ __bf16 Bs[CP * LDK];
-
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int li = lane & 15, lg = lane >> 4;
-  const int row_base = blockIdx.x * (64 * RT) + wave * (16 * RT);
+  const int row_base = (blockIdx.x * 4 + wave) * (16 * RT);
+  if (row_base >= n) return;
   const int kb = blockIdx.y * kchunk;
   const int ke = min(n, kb + kchunk);
 
@@ -238,49 +277,66 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(const __bf16* __restrict__ X,
 
   const __bf16* xrow[RT];
 #pragma unroll
-  for (int r = 0; r < RT; ++r) {
-    const int rr = min(row_base + 16 * r + li, n - 1);
-    xrow[r] = X + (int64_t)rr * ldx;
-  }
-  const bool vec_ok = ((ldx & 7) == 0) && ((((uintptr_t)X) & 15) == 0);
+  for (int r = 0; r < RT; ++r) xrow[r] = X + (int64_t)min(row_base + 16 * r + li, n - 1) * ldx + 8 * lg;
+  const __bf16* brow[NT];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) brow[t] = Bt + (int64_t)(16 * t + li) * ldt + 8 * lg;
 
-  for (int k0 = kb; k0 < ke; k0 += BF_KT) {
-    bf16x8 xv[RT][4];
-    if (vec_ok && k0 + BF_KT <= ke) {
+  const int nfull = VEC ? (ke - kb) / BF_KT : 0;
+  bf16x8 x0[RT][4], b0[NT][4], x1[RT][4], b1[NT][4];
+  auto load = [&](bf16x8 (&xv)[RT][4], bf16x8 (&bv)[NT][4], int k0) {
 #pragma unroll
-      for (int r = 0; r < RT; ++r)
+    for (int r = 0; r < RT; ++r)
 #pragma unroll
-        for (int ss = 0; ss < 4; ++ss)
-          xv[r][ss] = __builtin_nontemporal_load((const bf16x8*)(xrow[r] + k0 + 32 * ss + 8 * lg));
-    } else {
+      for (int ss = 0; ss < 4; ++ss)
+        xv[r][ss] = __builtin_nontemporal_load((const bf16x8*)(xrow[r] + k0 + 32 * ss));
 #pragma unroll
-      for (int r = 0; r < RT; ++r)
+    for (int ct = 0; ct < NT; ++ct)
 #pragma unroll
-        for (int ss = 0; ss < 4; ++ss)
-#pragma unroll
-          for (int t = 0; t < 8; ++t) {
-            const int col = k0 + 32 * ss + 8 * lg + t;
-            xv[r][ss][t] = (col < ke) ? xrow[r][col] : (__bf16)0.0f;
-          }
-    }
-    __syncthreads();
-    for (int e = tid; e < BF_KT * CP; e += 256) {
-      const int kk = e / CP, cc = e - kk * CP;
-      const int kg = k0 + kk;
-      float v = 0.0f;
-      if (kg < ke && cc < c) v = (float)B[(int64_t)kg * ldb + cc];
-      Bs[cc * LDK + kk] = (__bf16)v;
-    }
-    __syncthreads();
+      for (int ss = 0; ss < 4; ++ss) bv[ct][ss] = *(const bf16x8*)(brow[ct] + k0 + 32 * ss);
+  };
+  auto compute = [&](const bf16x8 (&xv)[RT][4], const bf16x8 (&bv)[NT][4]) {
 #pragma unroll
     for (int ss = 0; ss < 4; ++ss)
 #pragma unroll
-      for (int ct = 0; ct < NT; ++ct) {
-        const bf16x8 b = *(const bf16x8*)(Bs + (16 * ct + li) * LDK + 32 * ss + 8 * lg);
+      for (int ct = 0; ct < NT; ++ct)
 #pragma unroll
         for (int r = 0; r < RT; ++r)
-          acc[r][ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xv[r][ss], b, acc[r][ct], 0, 0, 0);
+          acc[r][ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xv[r][ss], bv[ct][ss], acc[r][ct], 0, 0, 0);
+  };
+  int t = 0;
+  if (nfull > 0) load(x0, b0, kb);
+  for (; t + 2 < nfull; t += 2) {
+    load(x1, b1, kb + (t + 1) * BF_KT);
+    compute(x0, b0);
+    load(x0, b0, kb + (t + 2) * BF_KT);
+    compute(x1, b1);
+  }
+  if (t + 1 < nfull) {
+    load(x1, b1, kb + (t + 1) * BF_KT);
+    compute(x0, b0);
+    compute(x1, b1);
+  } else if (t < nfull) {
+    compute(x0, b0);
+  }
+  for (int k0 = kb + nfull * BF_KT; k0 < ke; k0 += BF_KT) {
+#pragma unroll
+    for (int ss = 0; ss < 4; ++ss) {
+      bf16x8 xs[RT], bs[NT];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int col = k0 + 32 * ss + 8 * lg + u;
+#pragma unroll
+        for (int r = 0; r < RT; ++r) xs[r][u] = (col < ke) ? xrow[r][col - 8 * lg] : (__bf16)0.0f;
+#pragma unroll
+        for (int ct = 0; ct < NT; ++ct) bs[ct][u] = brow[ct][k0 + 32 * ss + u];
       }
+#pragma unroll
+      for (int ct = 0; ct < NT; ++ct)
+#pragma unroll
+        for (int r = 0; r < RT; ++r)
+          acc[r][ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xs[r], bs[ct], acc[r][ct], 0, 0, 0);
+    }
   }
   float* out = P + (int64_t)blockIdx.y * n * cp;
 #pragma unroll
@@ -290,10 +346,7 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(const __bf16* __restrict__ X,
       const int row = row_base + 16 * r + 4 * lg + v;
       if (row < n) {
 #pragma unroll
-        for (int ct = 0; ct < NT; ++ct) {
-          const int col = 16 * ct + li;
-          if (col < cp) out[(int64_t)row * cp + col] = acc[r][ct][v];
-        }
+        for (int ct = 0; ct < NT; ++ct) out[(int64_t)row * cp + 16 * ct + li] = acc[r][ct][v];
       }
     }
 }
@@ -387,91 +440,137 @@ int dense_scalars(const void* X, int dtype, int64_t ld, int n, Workspace& ws, do
 }
 
 namespace {
-template <typename TX, typename TB, int NT>
-void launch_mfma_nt(const TX* X, int64_t ldx, const TB* B, int64_t ldb, int n, int c, int kchunk, int splits, TX* P,
-                    int cp, const DevState* st, hipStream_t s) {
-  constexpr int RT = 2;
-  dim3 g(ceil_div(n, 64 * RT), splits);
-  k_gemm_mfma<TX, TB, NT, RT><<<g, 256, 0, s>>>(X, ldx, B, ldb, n, c, kchunk, P, cp, st);
+template <typename TX, int NT, int RT>
+void launch_mfma(const TX* X, int64_t ldx, bool vec, const TX* Bt, int64_t ldt, int n, const GemmPlan& p, TX* P,
+                 const DevState* st, hipStream_t s) {
+  dim3 g(ceil_div(ceil_div(n, 16 * RT), 4), p.splits);
+  if (vec)
+    k_gemm_mfma<TX, NT, RT, true><<<g, 256, 0, s>>>(X, ldx, Bt, ldt, n, p.kchunk, P, p.cp, st);
+  else
+    k_gemm_mfma<TX, NT, RT, false><<<g, 256, 0, s>>>(X, ldx, Bt, ldt, n, p.kchunk, P, p.cp, st);
 }
-template <typename TB, int NT>
-void launch_bf16_nt(const __bf16* X, int64_t ldx, const TB* B, int64_t ldb, int n, int c, int kchunk, int splits,
-                    float* P, int cp, const DevState* st, hipStream_t s) {
-  constexpr int RT = 2;
-  dim3 g(ceil_div(n, 64 * RT), splits);
-  k_gemm_bf16<TB, NT, RT><<<g, 256, 0, s>>>(X, ldx, B, ldb, n, c, kchunk, P, cp, st);
+template <int NT, int RT>
+void launch_bf16(const __bf16* X, int64_t ldx, bool vec, const __bf16* Bt, int64_t ldt, int n, const GemmPlan& p,
+                 float* P, const DevState* st, hipStream_t s) {
+  dim3 g(ceil_div(ceil_div(n, 16 * RT), 4), p.splits);
+  if (vec)
+    k_gemm_bf16<NT, RT, true><<<g, 256, 0, s>>>(X, ldx, Bt, ldt, n, p.kchunk, P, p.cp, st);
+  else
+    k_gemm_bf16<NT, RT, false><<<g, 256, 0, s>>>(X, ldx, Bt, ldt, n, p.kchunk, P, p.cp, st);
 }
 
-template <typename TX, typename TB>
-void dispatch_mfma(int nt, const TX* X, int64_t ldx, const TB* B, int64_t ldb, int n, int c, int kchunk, int splits,
-                   TX* P, int cp, const DevState* st, hipStream_t s) {
-  switch (nt) {
-    case 1: launch_mfma_nt<TX, TB, 1>(X, ldx, B, ldb, n, c, kchunk, splits, P, cp, st, s); break;
-    case 2: launch_mfma_nt<TX, TB, 2>(X, ldx, B, ldb, n, c, kchunk, splits, P, cp, st, s); break;
-    case 3: launch_mfma_nt<TX, TB, 3>(X, ldx, B, ldb, n, c, kchunk, splits, P, cp, st, s); break;
-    case 4: launch_mfma_nt<TX, TB, 4>(X, ldx, B, ldb, n, c, kchunk, splits, P, cp, st, s); break;
-    case 5: launch_mfma_nt<TX, TB, 5>(X, ldx, B, ldb, n, c, kchunk, splits, P, cp, st, s); break;
-    default: launch_mfma_nt<TX, TB, 6>(X, ldx, B, ldb, n, c, kchunk, splits, P, cp, st, s); break;
-  }
+// Rows per wave (16 * RT) by operand width: more rows amortise the B loads,
+// fewer keep the registers of wide B panels in budget.
+int pick_rt(int compute_dtype, int nt) {
+  if (compute_dtype == SYMNMF_F64) return nt <= 2 ? 2 : 1;
+  return nt <= 2 ? 4 : 2;
 }
-template <typename TB>
-void dispatch_bf16(int nt, const __bf16* X, int64_t ldx, const TB* B, int64_t ldb, int n, int c, int kchunk,
-                   int splits, float* P, int cp, const DevState* st, hipStream_t s) {
-  switch (nt) {
-    case 1: launch_bf16_nt<TB, 1>(X, ldx, B, ldb, n, c, kchunk, splits, P, cp, st, s); break;
-    case 2: launch_bf16_nt<TB, 2>(X, ldx, B, ldb, n, c, kchunk, splits, P, cp, st, s); break;
-    case 3: launch_bf16_nt<TB, 3>(X, ldx, B, ldb, n, c, kchunk, splits, P, cp, st, s); break;
-    case 4: launch_bf16_nt<TB, 4>(X, ldx, B, ldb, n, c, kchunk, splits, P, cp, st, s); break;
-    case 5: launch_bf16_nt<TB, 5>(X, ldx, B, ldb, n, c, kchunk, splits, P, cp, st, s); break;
-    default: launch_bf16_nt<TB, 6>(X, ldx, B, ldb, n, c, kchunk, splits, P, cp, st, s); break;
-  }
+
+template <typename TX>
+int dispatch_mfma(int nt, int rt, const TX* X, int64_t ldx, bool vec, const TX* Bt, int64_t ldt, int n,
+                  const GemmPlan& p, TX* P, const DevState* st, hipStream_t s) {
+#define CASE(NT_, RT_) \
+  if (nt == NT_ && rt == RT_) { launch_mfma<TX, NT_, RT_>(X, ldx, vec, Bt, ldt, n, p, P, st, s); return 0; }
+  CASE(1, 4) CASE(2, 4) CASE(1, 2) CASE(2, 2) CASE(3, 2) CASE(4, 2) CASE(5, 2) CASE(6, 2)
+  CASE(1, 1) CASE(2, 1) CASE(3, 1) CASE(4, 1) CASE(5, 1) CASE(6, 1)
+#undef CASE
+  return -1;
+}
+int dispatch_bf16(int nt, int rt, const __bf16* X, int64_t ldx, bool vec, const __bf16* Bt, int64_t ldt, int n,
+                  const GemmPlan& p, float* P, const DevState* st, hipStream_t s) {
+#define CASE(NT_, RT_) \
+  if (nt == NT_ && rt == RT_) { launch_bf16<NT_, RT_>(X, ldx, vec, Bt, ldt, n, p, P, st, s); return 0; }
+  CASE(1, 4) CASE(2, 4) CASE(3, 2) CASE(4, 2) CASE(5, 2) CASE(6, 2)
+#undef CASE
+  return -1;
 }
 }  // namespace
 
 GemmPlan gemm_plan(int n, int c, int compute_dtype) {
   GemmPlan p;
   p.cp = 16 * ceil_div(c, 16);
+  p.rt = pick_rt(compute_dtype, p.cp / 16);
   const int kt = compute_dtype == SYMNMF_BF16 ? BF_KT : GEMM_KT;
-  const int row_blocks = ceil_div(n, 128);
-  int splits = std::max(1, ceil_div(1024, row_blocks));
-  const int max_splits = std::max(1, ceil_div(n, kt));
-  splits = std::min(splits, max_splits);
+  const int waves = ceil_div(n, 16 * p.rt);
+  // Measured on MI355X: the software-pipelined schedule runs best with about
+  // one wave per SIMD at 64 rows per wave, two at 32 rows (256 CUs x 4 SIMDs).
+  const int target = p.rt >= 4 ? 1024 : 2048;
+  int splits = std::max(1, ceil_div(target, waves));
+  splits = std::min(splits, std::max(1, ceil_div(n, 4 * kt)));
   p.kchunk = kt * ceil_div(ceil_div(n, splits), kt);
   p.splits = ceil_div(n, p.kchunk);
+  p.ldt = (int64_t)BT_PAD * ceil_div(n, BT_PAD);
   return p;
 }
 
+size_t gemm_bt_bytes(int n, int cmax) { return (size_t)16 * ceil_div(cmax, 16) * BT_PAD * ceil_div(n, BT_PAD) * 8; }
+
+int dense_gemm_bt(const void* X, int xdtype, int64_t ldx, const void* Bt, int n, int c, const GemmPlan& p, void* P,
+                  const DevState* st, hipStream_t s) {
+  const int nt = p.cp / 16;
+  if (nt < 1 || nt > 6 || p.cp < c) return -1;
+  int rc;
+  if (xdtype == SYMNMF_F64) {
+    const bool vec = (ldx % 4 == 0) && ((uintptr_t)X % 32 == 0);
+    rc = dispatch_mfma<double>(nt, p.rt, (const double*)X, ldx, vec, (const double*)Bt, p.ldt, n, p, (double*)P, st, s);
+  } else if (xdtype == SYMNMF_F32) {
+    const bool vec = (ldx % 4 == 0) && ((uintptr_t)X % 16 == 0);
+    rc = dispatch_mfma<float>(nt, p.rt, (const float*)X, ldx, vec, (const float*)Bt, p.ldt, n, p, (float*)P, st, s);
+  } else {
+    const bool vec = (ldx % 8 == 0) && ((uintptr_t)X % 16 == 0);
+    rc = dispatch_bf16(nt, p.rt, (const __bf16*)X, ldx, vec, (const __bf16*)Bt, p.ldt, n, p, (float*)P, st, s);
+  }
+  if (rc) return rc;
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int factor_transpose(const void* F, int fdtype, int n, int k, void* Bt, int cdtype, const GemmPlan& p,
+                     const DevState* st, hipStream_t s) {
+  dim3 tg(ceil_div(p.ldt, 32), ceil_div(p.cp, 32));
+  if (fdtype == SYMNMF_F64 && cdtype == SYMNMF_F64)
+    k_transpose_pad<double, double><<<tg, 256, 0, s>>>((const double*)F, k, n, k, (double*)Bt, p.ldt, p.cp, st);
+  else if (fdtype == SYMNMF_F32 && cdtype == SYMNMF_F32)
+    k_transpose_pad<float, float><<<tg, 256, 0, s>>>((const float*)F, k, n, k, (float*)Bt, p.ldt, p.cp, st);
+  else if (fdtype == SYMNMF_F32 && cdtype == SYMNMF_BF16)
+    k_transpose_pad<float, __bf16><<<tg, 256, 0, s>>>((const float*)F, k, n, k, (__bf16*)Bt, p.ldt, p.cp, st);
+  else
+    return -1;
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
 int dense_gemm(const void* X, int xdtype, int64_t ldx, const void* B, int bdtype, int64_t ldb, int n, int c,
-               const GemmPlan& p, void* P, void* Y, int ydtype, int64_t ldy, const DevState* st, hipStream_t s) {
+               const GemmPlan& p, void* Bt, void* P, void* Y, int ydtype, int64_t ldy, const DevState* st,
+               hipStream_t s) {
   const int nt = p.cp / 16;
   if (nt < 1 || nt > 6) return -1;
+  dim3 tg(ceil_div(p.ldt, 32), ceil_div(p.cp, 32));
+  const int64_t tot = (int64_t)n * c;
   if (xdtype == SYMNMF_F64) {
-    if (bdtype != SYMNMF_F64) return -1;
-    dispatch_mfma<double, double>(nt, (const double*)X, ldx, (const double*)B, ldb, n, c, p.kchunk, p.splits,
-                                  (double*)P, p.cp, st, s);
-    const int64_t tot = (int64_t)n * c;
-    if (ydtype == SYMNMF_F64)
-      k_splitk_reduce<double, double><<<ceil_div(tot, 256), 256, 0, s>>>((const double*)P, p.splits, n, c, p.cp,
-                                                                          (double*)Y, ldy, st);
+    if (bdtype != SYMNMF_F64 || ydtype != SYMNMF_F64) return -1;
+    k_transpose_pad<double, double><<<tg, 256, 0, s>>>((const double*)B, ldb, n, c, (double*)Bt, p.ldt, p.cp, st);
+    const bool vec = (ldx % 4 == 0) && ((uintptr_t)X % 32 == 0);
+    if (dispatch_mfma<double>(nt, p.rt, (const double*)X, ldx, vec, (const double*)Bt, p.ldt, n, p, (double*)P, st, s))
+      return -1;
+    k_splitk_reduce<double, double><<<ceil_div(tot, 256), 256, 0, s>>>((const double*)P, p.splits, n, c, p.cp,
+                                                                        (double*)Y, ldy, st);
+  } else if (xdtype == SYMNMF_F32) {
+    if (bdtype == SYMNMF_F32)
+      k_transpose_pad<float, float><<<tg, 256, 0, s>>>((const float*)B, ldb, n, c, (float*)Bt, p.ldt, p.cp, st);
     else
+      k_transpose_pad<double, float><<<tg, 256, 0, s>>>((const double*)B, ldb, n, c, (float*)Bt, p.ldt, p.cp, st);
+    const bool vec = (ldx % 4 == 0) && ((uintptr_t)X % 16 == 0);
+    if (dispatch_mfma<float>(nt, p.rt, (const float*)X, ldx, vec, (const float*)Bt, p.ldt, n, p, (float*)P, st, s))
       return -1;
   } else {
-    if (xdtype == SYMNMF_F32) {
-      if (bdtype == SYMNMF_F32)
-        dispatch_mfma<float, float>(nt, (const float*)X, ldx, (const float*)B, ldb, n, c, p.kchunk, p.splits,
-                                    (float*)P, p.cp, st, s);
-      else
-        dispatch_mfma<float, double>(nt, (const float*)X, ldx, (const double*)B, ldb, n, c, p.kchunk, p.splits,
-                                     (float*)P, p.cp, st, s);
-    } else {
-      if (bdtype == SYMNMF_F32)
-        dispatch_bf16<float>(nt, (const __bf16*)X, ldx, (const float*)B, ldb, n, c, p.kchunk, p.splits, (float*)P,
-                             p.cp, st, s);
-      else
-        dispatch_bf16<double>(nt, (const __bf16*)X, ldx, (const double*)B, ldb, n, c, p.kchunk, p.splits,
-                              (float*)P, p.cp, st, s);
-    }
-    const int64_t tot = (int64_t)n * c;
+    if (bdtype == SYMNMF_F32)
+      k_transpose_pad<float, __bf16><<<tg, 256, 0, s>>>((const float*)B, ldb, n, c, (__bf16*)Bt, p.ldt, p.cp, st);
+    else
+      k_transpose_pad<double, __bf16><<<tg, 256, 0, s>>>((const double*)B, ldb, n, c, (__bf16*)Bt, p.ldt, p.cp, st);
+    const bool vec = (ldx % 8 == 0) && ((uintptr_t)X % 16 == 0);
+    if (dispatch_bf16(nt, p.rt, (const __bf16*)X, ldx, vec, (const __bf16*)Bt, p.ldt, n, p, (float*)P, st, s))
+      return -1;
+  }
+  if (xdtype != SYMNMF_F64) {
     if (ydtype == SYMNMF_F32)
       k_splitk_reduce<float, float><<<ceil_div(tot, 256), 256, 0, s>>>((const float*)P, p.splits, n, c, p.cp,
                                                                         (float*)Y, ldy, st);

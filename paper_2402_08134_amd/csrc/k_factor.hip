@@ -102,7 +102,8 @@ __global__ __launch_bounds__(256) void k_gram(const TA* __restrict__ A, int64_t 
 
 __global__ __launch_bounds__(256) void k_gram_reduce(const double* __restrict__ part, int nb, int ca, int cb,
                                                      double* __restrict__ G, double* __restrict__ Ghat, int kp,
-                                                     double alpha, const DevState* __restrict__ st) {
+                                                     double alpha, double* __restrict__ Ginv,
+                                                     const DevState* __restrict__ st) {
   if (stopped(st)) return;
   const int e = blockIdx.x * 256 + threadIdx.x;
   const int tot = (Ghat ? kp * kp : ca * cb);
@@ -114,6 +115,7 @@ __global__ __launch_bounds__(256) void k_gram_reduce(const double* __restrict__ 
     if (Ghat) {
       const int p = e / cb, q = e - p * cb;
       Ghat[p * kp + q] = acc + (p == q ? alpha : 0.0);
+      if (Ginv && p == q) Ginv[p] = 1.0 / (acc + alpha);
     }
   }
   if (Ghat && e < kp * kp) {
@@ -176,50 +178,6 @@ __global__ __launch_bounds__(256) void k_finish_iteration(const double* __restri
   }
 }
 
-// ---------------------------------------------------------------------------
-// Regularised HALS sweep, one row per thread, FP64 arithmetic.  Ghat is read
-// with wave-uniform addresses (scalar loads); KP is k rounded up so the row
-// lives in registers.
-// ---------------------------------------------------------------------------
-template <int KP, typename TF, bool SEG>
-__global__ __launch_bounds__(64) void k_hals(int n, int k, const TF* __restrict__ Y, const int* __restrict__ seg_ptr,
-                                             const int* __restrict__ seg_src, const double* __restrict__ seg_val,
-                                             const TF* __restrict__ Src, TF* __restrict__ Dst,
-                                             const double* __restrict__ Ghat, double alpha,
-                                             const DevState* __restrict__ st) {
-  if (stopped(st)) return;
-  const int j = blockIdx.x * 64 + threadIdx.x;
-  if (j >= n) return;
-  const int64_t base = (int64_t)j * k;
-  double w[KP];
-#pragma unroll
-  for (int i = 0; i < KP; ++i) w[i] = (i < k) ? (double)Dst[base + i] : 0.0;
-  int e0 = 0, e1 = 0;
-  if (SEG) {
-    e0 = seg_ptr[j];
-    e1 = seg_ptr[j + 1];
-  }
-#pragma unroll
-  for (int i = 0; i < KP; ++i) {
-    if (i < k) {
-      double y = alpha * (double)Src[base + i];
-      if (SEG) {
-        for (int e = e0; e < e1; ++e) y = fma(seg_val[e], (double)Src[(int64_t)seg_src[e] * k + i], y);
-      } else {
-        y += (double)Y[base + i];
-      }
-      const double* g = Ghat + i * KP;
-      double sacc = 0.0;
-#pragma unroll
-      for (int l = 0; l < KP; ++l) sacc = fma(w[l], g[l], sacc);
-      w[i] = fmax(0.0, w[i] + (y - sacc) / g[i]);
-    }
-  }
-#pragma unroll
-  for (int i = 0; i < KP; ++i)
-    if (i < k) Dst[base + i] = (TF)w[i];
-}
-
 template <typename TA, typename TO>
 __global__ __launch_bounds__(256) void k_rowmat(const TA* __restrict__ A, int64_t lda, int n, int l,
                                                 const double* __restrict__ M, const double* __restrict__ scale, int c,
@@ -244,7 +202,8 @@ __global__ __launch_bounds__(256) void k_rowmat(const TA* __restrict__ A, int64_
 __global__ __launch_bounds__(256) void k_chol_inverse(const double* __restrict__ G, int k, double* __restrict__ R,
                                                       double* __restrict__ Rinv, int* d_flags, int flag_bit,
                                                       int* d_fail) {
-  extern __shared__ double A[];  // k x (k + 1)
+  extern __shared__ double A[];  // k x (k + 1) factor, then k x (k + 1) inverse
+  double* Xi = A + k * (k + 1);
   __shared__ int bad;
   __shared__ double shift;
   const int lda = k + 1;
@@ -292,44 +251,49 @@ __global__ __launch_bounds__(256) void k_chol_inverse(const double* __restrict__
     const int p = e / k, q = e - p * k;
     R[e] = (q >= p) ? A[p * lda + q] : 0.0;
   }
-  // Rinv column c: solve R x = e_c by back substitution (x_i = 0 for i > c).
+  // Rinv column c: solve R x = e_c by back substitution (x_i = 0 for i > c),
+  // the column kept in LDS.
   for (int c = tid; c < k; c += 256) {
     for (int i = k - 1; i >= 0; --i) {
       double v = 0.0;
       if (i <= c) {
         v = (i == c) ? 1.0 : 0.0;
-        for (int p = i + 1; p <= c; ++p) v -= A[i * lda + p] * Rinv[p * k + c];
+        for (int p = i + 1; p <= c; ++p) v -= A[i * lda + p] * Xi[p * lda + c];
         v /= A[i * lda + i];
       }
-      Rinv[i * k + c] = v;
+      Xi[i * lda + c] = v;
     }
+  }
+  __syncthreads();
+  for (int e = tid; e < k * k; e += 256) {
+    const int p = e / k, q = e - p * k;
+    Rinv[e] = Xi[p * lda + q];
   }
 }
 
 // ---------------------------------------------------------------------------
 // Parallel cyclic Jacobi (round-robin pairing) on A = (T + T^T) / 2 in LDS;
-// V accumulated in global memory (`Vw`), then columns sorted by descending
+// V accumulated in LDS next to A, then columns sorted by descending
 // eigenvalue into V.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_jacobi(const double* __restrict__ T, int l, double* __restrict__ Vw,
-                                                double* __restrict__ V, double* __restrict__ lam) {
-  extern __shared__ double A[];  // l x (l + 1)
+__global__ __launch_bounds__(256) void k_jacobi(const double* __restrict__ T, int l, double* __restrict__ V,
+                                                double* __restrict__ lam) {
+  extern __shared__ double A[];  // l x (l + 1) matrix, then l x (l + 1) eigenvectors
+  double* Vw = A + l * (l + 1);
   __shared__ double cs[64], sn[64];
   __shared__ int pp[64], qq[64];
-  __shared__ int perm[128];
   __shared__ double red[8];
   __shared__ int order[128];
   __shared__ int conv;
   const int lda = l + 1;
   const int tid = threadIdx.x;
-  const int m = l + (l & 1);
+  const int m = l + (l & 1);  // even; index l is a dummy when l is odd
   const int half = m / 2;
   for (int e = tid; e < l * l; e += 256) {
     const int p = e / l, q = e - p * l;
     A[p * lda + q] = 0.5 * (T[p * l + q] + T[q * l + p]);
-    Vw[e] = (p == q) ? 1.0 : 0.0;
+    Vw[p * lda + q] = (p == q) ? 1.0 : 0.0;
   }
-  for (int i = tid; i < m; i += 256) perm[i] = i;
   __syncthreads();
   for (int sweep = 0; sweep < 40; ++sweep) {
     double off = 0.0, dg = 0.0;
@@ -345,8 +309,10 @@ __global__ __launch_bounds__(256) void k_jacobi(const double* __restrict__ T, in
     __syncthreads();
     if (conv) break;
     for (int step = 0; step < m - 1; ++step) {
+      // round-robin (circle) pairing: index 0 fixed, 1..m-1 rotate by `step`
       if (tid < half) {
-        int p = perm[tid], q = perm[m - 1 - tid];
+        int p = tid == 0 ? 0 : 1 + (tid - 1 + step) % (m - 1);
+        int q = 1 + (m - 2 - tid + step) % (m - 1);
         if (p > q) { const int t = p; p = q; q = t; }
         double c = 1.0, s = 0.0;
         if (q < l) {
@@ -373,9 +339,9 @@ __global__ __launch_bounds__(256) void k_jacobi(const double* __restrict__ T, in
           const double ap = A[r * lda + p], aq = A[r * lda + q];
           A[r * lda + p] = c * ap - s * aq;
           A[r * lda + q] = s * ap + c * aq;
-          const double vp = Vw[r * l + p], vq = Vw[r * l + q];
-          Vw[r * l + p] = c * vp - s * vq;
-          Vw[r * l + q] = s * vp + c * vq;
+          const double vp = Vw[r * lda + p], vq = Vw[r * lda + q];
+          Vw[r * lda + p] = c * vp - s * vq;
+          Vw[r * lda + q] = s * vp + c * vq;
         }
       }
       __syncthreads();
@@ -391,30 +357,23 @@ __global__ __launch_bounds__(256) void k_jacobi(const double* __restrict__ T, in
         }
       }
       __syncthreads();
-      if (tid == 0) {
-        const int last = perm[m - 1];
-        for (int j = m - 1; j >= 2; --j) perm[j] = perm[j - 1];
-        perm[1] = last;
-      }
-      __syncthreads();
     }
   }
-  if (tid == 0) {
-    for (int i = 0; i < l; ++i) order[i] = i;
-    for (int i = 0; i < l; ++i) {
-      int best = i;
-      for (int j = i + 1; j < l; ++j)
-        if (A[order[j] * lda + order[j]] > A[order[best] * lda + order[best]]) best = j;
-      const int t = order[i];
-      order[i] = order[best];
-      order[best] = t;
+  // rank of each eigenvalue in descending order (ties by index)
+  for (int i = tid; i < l; i += 256) {
+    const double v = A[i * lda + i];
+    int rank = 0;
+    for (int j = 0; j < l; ++j) {
+      const double u = A[j * lda + j];
+      rank += (u > v || (u == v && j < i)) ? 1 : 0;
     }
+    order[rank] = i;
   }
   __syncthreads();
   for (int i = tid; i < l; i += 256) lam[i] = A[order[i] * lda + order[i]];
   for (int e = tid; e < l * l; e += 256) {
     const int r = e / l, j = e - r * l;
-    V[e] = Vw[r * l + order[j]];
+    V[e] = Vw[r * lda + order[j]];
   }
 }
 
@@ -524,16 +483,6 @@ __global__ __launch_bounds__(256) void k_scan_apply(const T* __restrict__ in, in
   }
 }
 
-template <int KP, typename TF>
-void hals_launch(int n, int k, const void* Y, const int* sp, const int* ss, const double* sv, const void* Src,
-                 void* Dst, const double* Ghat, double alpha, const DevState* st, hipStream_t s) {
-  const int nb = ceil_div(n, 64);
-  if (sp)
-    k_hals<KP, TF, true><<<nb, 64, 0, s>>>(n, k, (const TF*)Y, sp, ss, sv, (const TF*)Src, (TF*)Dst, Ghat, alpha, st);
-  else
-    k_hals<KP, TF, false><<<nb, 64, 0, s>>>(n, k, (const TF*)Y, sp, ss, sv, (const TF*)Src, (TF*)Dst, Ghat, alpha, st);
-}
-
 template <typename TA, typename TB, int T>
 void gram_launch(const void* A, int64_t lda, int ca, const void* B, int64_t ldb, int cb, int n, const int* rows,
                  const double* w, const int* d_count, int nb, int rpb, double* part, const DevState* st,
@@ -596,7 +545,7 @@ int copy_convert(const void* src, int sdtype, void* dst, int ddtype, int64_t cou
 
 int gram(const void* A, int adtype, int64_t lda, int ca, const void* B, int bdtype, int64_t ldb, int cb, int n,
          const int* rows, const double* w, const int* d_count, int max_rows, Workspace& ws, double* G, double* Ghat,
-         int kp, double alpha, const DevState* st, hipStream_t s) {
+         int kp, double alpha, const DevState* st, hipStream_t s, double* Ginv) {
   if (ca > 96 || cb > 96 || ca < 1 || cb < 1) return -1;
   const int t = ceil_div(std::max(ca, cb), 16);
   const int nrows = rows ? max_rows : n;
@@ -615,7 +564,7 @@ int gram(const void* A, int adtype, int64_t lda, int ca, const void* B, int bdty
   else
     return -1;
   const int tot = std::max(ca * cb, Ghat ? kp * kp : 0);
-  k_gram_reduce<<<ceil_div(tot, 256), 256, 0, s>>>(part, nb, ca, cb, G, Ghat, kp, alpha, st);
+  k_gram_reduce<<<ceil_div(tot, 256), 256, 0, s>>>(part, nb, ca, cb, G, Ghat, kp, alpha, Ginv, st);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
@@ -640,27 +589,6 @@ void finish_iteration(const double* dot_part, int nb, const double* Ga, const do
   k_finish_iteration<<<1, 256, 0, s>>>(dot_part, nb, Ga, Gb, k, d_normsq, st, hist, rule);
 }
 
-int hals_update(int n, int k, int kp, const void* Y, const int* seg_ptr, const int* seg_src, const double* seg_val,
-                const void* Src, void* Dst, int fdtype, const double* Ghat, double alpha, const DevState* st,
-                hipStream_t s) {
-  if (fdtype == SYMNMF_F64) {
-    switch (kp) {
-      case 16: hals_launch<16, double>(n, k, Y, seg_ptr, seg_src, seg_val, Src, Dst, Ghat, alpha, st, s); break;
-      case 32: hals_launch<32, double>(n, k, Y, seg_ptr, seg_src, seg_val, Src, Dst, Ghat, alpha, st, s); break;
-      case 64: hals_launch<64, double>(n, k, Y, seg_ptr, seg_src, seg_val, Src, Dst, Ghat, alpha, st, s); break;
-      default: return -1;
-    }
-  } else {
-    switch (kp) {
-      case 16: hals_launch<16, float>(n, k, Y, seg_ptr, seg_src, seg_val, Src, Dst, Ghat, alpha, st, s); break;
-      case 32: hals_launch<32, float>(n, k, Y, seg_ptr, seg_src, seg_val, Src, Dst, Ghat, alpha, st, s); break;
-      case 64: hals_launch<64, float>(n, k, Y, seg_ptr, seg_src, seg_val, Src, Dst, Ghat, alpha, st, s); break;
-      default: return -1;
-    }
-  }
-  return hipGetLastError() == hipSuccess ? 0 : -1;
-}
-
 int rowmat(const void* A, int adtype, int64_t lda, int n, int l, const double* M, const double* scale, int c,
            void* out, int odtype, int64_t ldo, const DevState* st, hipStream_t s) {
   const int nb = ceil_div((int64_t)n * c, 256);
@@ -679,7 +607,7 @@ int rowmat(const void* A, int adtype, int64_t lda, int n, int l, const double* M
 
 int chol_inverse(const double* G, int k, double* R, double* Rinv, int* d_flags, int flag_bit, int* d_fail,
                  hipStream_t s) {
-  const size_t lds = (size_t)k * (k + 1) * sizeof(double);
+  const size_t lds = 2 * (size_t)k * (k + 1) * sizeof(double);
   if (k > 96) return -1;
   if (lds > 65536) {
     if (hipFuncSetAttribute((const void*)k_chol_inverse, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) !=
@@ -690,14 +618,14 @@ int chol_inverse(const double* G, int k, double* R, double* Rinv, int* d_flags, 
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
-int jacobi_evd(const double* T, int l, double* Vw, double* V, double* lam, hipStream_t s) {
+int jacobi_evd(const double* T, int l, double* V, double* lam, hipStream_t s) {
   if (l > 96) return -1;
-  const size_t lds = (size_t)l * (l + 1) * sizeof(double);
+  const size_t lds = 2 * (size_t)l * (l + 1) * sizeof(double);
   if (lds > 65536) {
     if (hipFuncSetAttribute((const void*)k_jacobi, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
       return -1;
   }
-  k_jacobi<<<1, 256, lds, s>>>(T, l, Vw, V, lam);
+  k_jacobi<<<1, 256, lds, s>>>(T, l, V, lam);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 

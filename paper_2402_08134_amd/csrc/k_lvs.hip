@@ -32,7 +32,10 @@ __global__ __launch_bounds__(64) void k_leverage(const TF* __restrict__ F, int n
   if (j >= n) return;
   double h[KP];
 #pragma unroll
-  for (int i = 0; i < KP; ++i) h[i] = (i < k) ? (double)F[(int64_t)j * k + i] : 0.0;
+  for (int i = 0; i < KP; ++i) {
+    const double x = (double)F[(int64_t)j * k + (i < k ? i : k - 1)];
+    h[i] = i < k ? x : 0.0;
+  }
   double acc = 0.0;
 #pragma unroll
   for (int i = 0; i < KP; ++i) {

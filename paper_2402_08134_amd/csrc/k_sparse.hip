@@ -58,7 +58,7 @@ __global__ void k_csr_scalars_final(int nb, const double* __restrict__ bpart, do
 template <typename TV, typename TB, typename TY, int CW, int CPL>
 __global__ __launch_bounds__(256) void k_csr_spmm(const int* __restrict__ rp, const int* __restrict__ ci,
                                                   const TV* __restrict__ val, int n, const TB* __restrict__ B, int c,
-                                                  TY* __restrict__ Y, const DevState* __restrict__ st) {
+                                                  TY* __restrict__ Y, int64_t ldy, const DevState* __restrict__ st) {
   if (stopped(st)) return;
   constexpr int G = 64 / CW;
   const int lane = threadIdx.x & 63;
@@ -78,13 +78,16 @@ __global__ __launch_bounds__(256) void k_csr_spmm(const int* __restrict__ rp, co
       j[u] = ci[e + u * G];
       v[u] = (double)val[e + u * G];
     }
+    // column index clamped and masked instead of a branch per load (a branch
+    // around each load serialises them)
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       const TB* brow = B + (int64_t)j[u] * c;
 #pragma unroll
       for (int q = 0; q < CPL; ++q) {
         const int col = li + q * CW;
-        if (col < c) acc[q] = fma(v[u], (double)brow[col], acc[q]);
+        const double b = (double)brow[col < c ? col : c - 1];
+        acc[q] = fma(v[u], col < c ? b : 0.0, acc[q]);
       }
     }
   }
@@ -95,7 +98,8 @@ __global__ __launch_bounds__(256) void k_csr_spmm(const int* __restrict__ rp, co
 #pragma unroll
     for (int q = 0; q < CPL; ++q) {
       const int col = li + q * CW;
-      if (col < c) acc[q] = fma(v, (double)brow[col], acc[q]);
+      const double b = (double)brow[col < c ? col : c - 1];
+      acc[q] = fma(v, col < c ? b : 0.0, acc[q]);
     }
   }
 #pragma unroll
@@ -107,7 +111,7 @@ __global__ __launch_bounds__(256) void k_csr_spmm(const int* __restrict__ rp, co
 #pragma unroll
     for (int q = 0; q < CPL; ++q) {
       const int col = li + q * CW;
-      if (col < c) Y[(int64_t)row * c + col] = (TY)acc[q];
+      if (col < c) Y[(int64_t)row * ldy + col] = (TY)acc[q];
     }
   }
 }
@@ -130,17 +134,17 @@ __global__ __launch_bounds__(256) void k_csr_cross(const int* __restrict__ rp, c
 }
 
 template <typename TV, typename TB, typename TY>
-void spmm_dispatch(const int* rp, const int* ci, const TV* val, int n, const TB* B, int c, TY* Y, const DevState* st,
-                   hipStream_t s) {
+void spmm_dispatch(const int* rp, const int* ci, const TV* val, int n, const TB* B, int c, TY* Y, int64_t ldy,
+                   const DevState* st, hipStream_t s) {
   const int nb = ceil_div(n, 4);
   if (c <= 16)
-    k_csr_spmm<TV, TB, TY, 16, 1><<<nb, 256, 0, s>>>(rp, ci, val, n, B, c, Y, st);
+    k_csr_spmm<TV, TB, TY, 16, 1><<<nb, 256, 0, s>>>(rp, ci, val, n, B, c, Y, ldy, st);
   else if (c <= 32)
-    k_csr_spmm<TV, TB, TY, 32, 1><<<nb, 256, 0, s>>>(rp, ci, val, n, B, c, Y, st);
+    k_csr_spmm<TV, TB, TY, 32, 1><<<nb, 256, 0, s>>>(rp, ci, val, n, B, c, Y, ldy, st);
   else if (c <= 64)
-    k_csr_spmm<TV, TB, TY, 64, 1><<<nb, 256, 0, s>>>(rp, ci, val, n, B, c, Y, st);
+    k_csr_spmm<TV, TB, TY, 64, 1><<<nb, 256, 0, s>>>(rp, ci, val, n, B, c, Y, ldy, st);
   else
-    k_csr_spmm<TV, TB, TY, 64, 2><<<nb, 256, 0, s>>>(rp, ci, val, n, B, c, Y, st);
+    k_csr_spmm<TV, TB, TY, 64, 2><<<nb, 256, 0, s>>>(rp, ci, val, n, B, c, Y, ldy, st);
 }
 
 }  // namespace
@@ -160,16 +164,17 @@ int csr_scalars(const int* rp, const void* val, int vdtype, int n, int64_t nnz, 
 }
 
 int csr_spmm(const int* rp, const int* ci, const void* val, int vdtype, int n, const void* B, int bdtype, int c,
-             void* Y, int ydtype, const DevState* st, hipStream_t s) {
+             void* Y, int ydtype, const DevState* st, hipStream_t s, int64_t ldy) {
   if (c > 128) return -1;
+  if (ldy <= 0) ldy = c;
   if (vdtype == SYMNMF_F64) {
     if (bdtype != SYMNMF_F64 || ydtype != SYMNMF_F64) return -1;
-    spmm_dispatch<double, double, double>(rp, ci, (const double*)val, n, (const double*)B, c, (double*)Y, st, s);
+    spmm_dispatch<double, double, double>(rp, ci, (const double*)val, n, (const double*)B, c, (double*)Y, ldy, st, s);
   } else {
     if (bdtype == SYMNMF_F32 && ydtype == SYMNMF_F32)
-      spmm_dispatch<float, float, float>(rp, ci, (const float*)val, n, (const float*)B, c, (float*)Y, st, s);
+      spmm_dispatch<float, float, float>(rp, ci, (const float*)val, n, (const float*)B, c, (float*)Y, ldy, st, s);
     else if (bdtype == SYMNMF_F64 && ydtype == SYMNMF_F64)
-      spmm_dispatch<float, double, double>(rp, ci, (const float*)val, n, (const double*)B, c, (double*)Y, st, s);
+      spmm_dispatch<float, double, double>(rp, ci, (const float*)val, n, (const double*)B, c, (double*)Y, ldy, st, s);
     else
       return -1;
   }

@@ -36,16 +36,30 @@ int dense_scalars(const void* X, int dtype, int64_t ld, int n, Workspace& ws, do
                   hipStream_t s);
 
 struct GemmPlan {
-  int cp = 16;      // output columns padded to a multiple of 16
-  int kchunk = 64;  // K range per split
-  int splits = 1;   // number of K splits (partial outputs)
+  int cp = 16;       // output columns padded to a multiple of 16
+  int rt = 1;        // 16-row MFMA tiles per wave
+  int kchunk = 64;   // K range per split
+  int splits = 1;    // number of K splits (partial outputs)
+  int64_t ldt = 0;   // row length of the transposed B panel
 };
 GemmPlan gemm_plan(int n, int c, int compute_dtype);
+// Bytes of the transposed-B scratch for products with up to cmax columns.
+size_t gemm_bt_bytes(int n, int cmax);
 // Y = X B.  X dtype F64 / F32 / BF16; B F64 or F32 (F64 only with F64 X);
-// P: partials buffer of splits * n * cp elements of the accumulator type
-// (double for F64 X, float otherwise); Y of ydtype with leading dim ldy.
+// Bt: scratch of gemm_bt_bytes; P: partials buffer of splits * n * cp
+// elements of the accumulator type (double for F64 X, float otherwise); Y of
+// ydtype with leading dim ldy.
 int dense_gemm(const void* X, int xdtype, int64_t ldx, const void* B, int bdtype, int64_t ldb, int n, int c,
-               const GemmPlan& p, void* P, void* Y, int ydtype, int64_t ldy, const DevState* st, hipStream_t s);
+               const GemmPlan& p, void* Bt, void* P, void* Y, int ydtype, int64_t ldy, const DevState* st,
+               hipStream_t s);
+// P = X Bt^T from an already transposed, zero-padded B panel (cp rows of
+// ldt elements: FP64 for F64 X, FP32 for F32 X, BF16 for BF16 X); the split-K
+// partials stay in P for the consumer to reduce.
+int dense_gemm_bt(const void* X, int xdtype, int64_t ldx, const void* Bt, int n, int c, const GemmPlan& p, void* P,
+                  const DevState* st, hipStream_t s);
+// Bt (cp x ldt, element type of the compute dtype) = F^T zero padded.
+int factor_transpose(const void* F, int fdtype, int n, int k, void* Bt, int cdtype, const GemmPlan& p,
+                     const DevState* st, hipStream_t s);
 int convert_f32_bf16(const float* src, int64_t lds, void* dst, int64_t ldd, int n, hipStream_t s);
 // d_sum = sum_ij (X_ij - w_i . h_j)^2, k <= 64.
 int dense_resid_exact(const void* X, int xdtype, int64_t ldx, int n, int k, const void* W, const void* H, int fdtype,
@@ -56,7 +70,7 @@ int csr_scalars(const int* rp, const void* val, int vdtype, int n, int64_t nnz, 
                 double* d_out3, hipStream_t s);
 // Y = X B (B n x c of bdtype, Y n x c of ydtype, c <= 128).
 int csr_spmm(const int* rp, const int* ci, const void* val, int vdtype, int n, const void* B, int bdtype, int c,
-             void* Y, int ydtype, const DevState* st, hipStream_t s);
+             void* Y, int ydtype, const DevState* st, hipStream_t s, int64_t ldy = 0);
 // d_sum = sum over stored (i, j) of X_ij (w_i . h_j).
 int csr_resid_cross(const int* rp, const int* ci, const void* val, int vdtype, int n, int k, const void* W,
                     const void* H, int fdtype, Workspace& ws, double* d_sum, hipStream_t s);
@@ -74,7 +88,7 @@ int copy_convert(const void* src, int sdtype, void* dst, int ddtype, int64_t cou
 // padded to kp x kp with the identity.  ca, cb <= 128.
 int gram(const void* A, int adtype, int64_t lda, int ca, const void* B, int bdtype, int64_t ldb, int cb, int n,
          const int* rows, const double* w, const int* d_count, int max_rows, Workspace& ws, double* G,
-         double* Ghat, int kp, double alpha, const DevState* st, hipStream_t s);
+         double* Ghat, int kp, double alpha, const DevState* st, hipStream_t s, double* Ginv = nullptr);
 // part[b] partial sums of sum_e A[e] B[e] over count elements; returns nb.
 int dot_partials(const void* A, const void* B, int dtype, int64_t count, Workspace& ws, double** part,
                  const DevState* st, hipStream_t s);
@@ -95,15 +109,45 @@ struct StopRule {
 void finish_iteration(const double* dot_part, int nb, const double* Ga, const double* Gb, int k,
                       const double* d_normsq, DevState* st, double* hist, StopRule rule, hipStream_t s);
 
-// Regularised HALS sweep (Ghat = G + alpha I padded to kp): for each row j,
-// columns i = 0..k-1 in order,
-//   w_i <- max(0, w_i + (y_i + alpha src_i - sum_l w_l Ghat_li) / Ghat_ii)
-// with y from a dense n x k matrix (Y != nullptr) or from a segment list
-// (seg_ptr/seg_src/seg_val: y_ji = sum_e seg_val[e] src[seg_src[e]][i]).
-int hals_update(int n, int k, int kp, const void* Y, const int* seg_ptr, const int* seg_src, const double* seg_val,
-                const void* Src, void* Dst, int fdtype, const double* Ghat, double alpha, const DevState* st,
-                hipStream_t s);
-// Exact NLS per row by block principal pivoting, same inputs as hals_update.
+// Fused half-step update (right-hand side, HALS sweep, factor write-back,
+// block partials of the next Gram / U^T F / residual dot).
+struct UpdateArgs {
+  int n = 0, k = 0, l = 0, splits = 1, cp = 0;
+  int64_t ldt = 0;
+  const void* P = nullptr;           // YMODE 0: partials [splits][n][cp]
+  const int* seg_ptr = nullptr;      // YMODE 1: transposed sampled slab
+  const int* seg_src = nullptr;
+  const double* seg_val = nullptr;
+  const double* U = nullptr;         // YMODE 2: U (n x l) and M = Lambda U^T F (l x k)
+  const double* M = nullptr;
+  const void* Src = nullptr;         // the fixed factor (alpha term, YMODE 1 rows)
+  void* Dst = nullptr;               // the factor being updated (in place)
+  void* Dt = nullptr;                // optional transposed copy of Dst (cp x ldt)
+  const double* Ghat = nullptr;      // G + alpha I padded to kp x kp
+  double alpha = 0.0;
+  double* gpart = nullptr;           // [nb][k*k]
+  double* zpart = nullptr;           // [nb][l*k] (YMODE 2)
+  double* dpart = nullptr;           // [nb] or nullptr
+};
+// Read-only small operands of the update, passed as separate restrict-
+// qualified kernel arguments so the compiler reads them with scalar loads.
+struct UpdateRO {
+  const double* Ghat = nullptr;  // kp x kp
+  const double* Ginv = nullptr;  // kp reciprocals of diag(Ghat)
+  const double* M = nullptr;     // YMODE 2
+};
+int update_blocks(int n, int fdtype);
+// pdtype: element type of P (F32 or F64); tdtype: element type of Dt.
+int fused_update(const UpdateArgs& a, const UpdateRO& ro, int kp, int ymode, int fdtype, int pdtype, int tdtype,
+                 int nb, const DevState* st, hipStream_t s);
+int update_reduce(const double* gpart, const double* zpart, int nb, int k, int l, int kp, double alpha,
+                  const double* lam, double* G, double* Ghat, double* Ginv, double* M, const DevState* st,
+                  hipStream_t s);
+int pad_identity(double* Ghat, double* Ginv, int k, int kp, hipStream_t s);
+// M (l x kp, zero padded) = diag(lam) Z, Z l x k.
+int scale_rows(const double* Z, const double* lam, int l, int k, int kp, double* M, hipStream_t s);
+
+// Exact NLS per row by block principal pivoting (inputs as the fused update).
 int bpp_update(int n, int k, int kp, const void* Y, const int* seg_ptr, const int* seg_src, const double* seg_val,
                const void* Src, void* Dst, int fdtype, const double* Ghat, double alpha, Workspace& ws,
                const DevState* st, hipStream_t s);
@@ -121,7 +165,7 @@ int chol_inverse(const double* G, int k, double* R, double* Rinv, int* d_flags, 
                  hipStream_t s);
 // Symmetric EVD of the l x l matrix (T + T^T)/2 by parallel cyclic Jacobi;
 // eigenvalues descending in lam, eigenvectors as columns of V (l x l).
-int jacobi_evd(const double* T, int l, double* Vwork, double* V, double* lam, hipStream_t s);
+int jacobi_evd(const double* T, int l, double* V, double* lam, hipStream_t s);
 // Flip the sign of each column of U (n x l FP64) so that its entry of largest
 // magnitude is positive (first such row on ties).
 int column_sign_fix(double* U, int n, int l, Workspace& ws, hipStream_t s);

@@ -49,7 +49,9 @@ void dfree(void* p) {
   if (p) (void)hipFree(p);
 }
 
-int kpad(int k) { return k <= 16 ? 16 : (k <= 32 ? 32 : 64); }
+// k rounded up to the 16-column MFMA tile (the padded width of every k-wide
+// operand of the update).
+int kpad(int k) { return 16 * ((k + 15) / 16); }
 
 constexpr int CMAX = 96;  // widest product operand (LAI basis)
 
@@ -84,8 +86,20 @@ struct symnmf_ctx {
   double normsq = 0, total = 0, maxval = 0, zeta = 0, normsq_lai = 0;
   // device buffers
   void *W = nullptr, *H = nullptr, *Y = nullptr;
+  void* Yk = nullptr;  // CSR product in the update's padded layout (n x kp)
   void* P = nullptr;
+  void* Bt = nullptr;
+  void* BtW = nullptr;  // transposed factor panels for the dense product
+  void* BtH = nullptr;
+  bool btW_ok = false, btH_ok = false;
+  double* gpart = nullptr;  // fused-update block partials
+  double* zpart = nullptr;
+  double* dpart = nullptr;
+  int nbu = 1;              // blocks of the fused update
+  double *M_W = nullptr, *M_H = nullptr;  // LAI: Lambda U^T W, Lambda U^T H
+  bool mW_ok = false, mH_ok = false;
   double *G_W = nullptr, *G_H = nullptr, *Gh_W = nullptr, *Gh_H = nullptr, *Gh_S = nullptr;
+  double *Gi_W = nullptr, *Gi_H = nullptr, *Gi_S = nullptr;  // 1 / diag of the regularised Grams
   double* d_scal = nullptr;  // [0] ||X||^2 [1] sum [2] max [3..7] scratch [8] ||Lambda||^2
   double* rowsum = nullptr;
   DevState* dstate = nullptr;
@@ -115,7 +129,7 @@ struct symnmf_ctx {
   ~symnmf_ctx() {
     if (st) (void)hipStreamSynchronize(st);
     else (void)hipDeviceSynchronize();
-    void* ptrs[] = {Xb_owned, W, H, Y, P, G_W, G_H, Gh_W, Gh_H, Gh_S, d_scal, rowsum, dstate, hist, d_fail,
+    void* ptrs[] = {Xb_owned, W, H, Y, Yk, P, Bt, BtW, BtH, gpart, zpart, dpart, M_W, M_H, Gi_W, Gi_H, Gi_S, G_W, G_H, Gh_W, Gh_H, Gh_S, d_scal, rowsum, dstate, hist, d_fail,
                     ws.base, Q, Q1, U, YQ, Tm, QT, Vw, lam, Rl, Rlinv, Z, sb.w, sb.prefix, sb.counts, sb.flags,
                     sb.info, sb.theta, rows, weights, seg_cnt, seg_ptr, seg_src, seg_val, lev, R, Rinv};
     for (void* p : ptrs) dfree(p);
@@ -149,8 +163,7 @@ struct symnmf_ctx {
   void product(const void* B, int bdtype, int c, void* Yout) {
     if (kind == SYMNMF_DENSE) {
       const GemmPlan p = gemm_plan(n, c, cdtype);
-      LCHK(dense_gemm(Xc, cdtype, cdtype == SYMNMF_BF16 && xdtype != SYMNMF_BF16 ? n : ld, B, bdtype, c, n, c, p, P,
-                      Yout, fdtype, c, gate_, st));
+      LCHK(dense_gemm(Xc, cdtype, ldxc(), B, bdtype, c, n, c, p, Bt, P, Yout, fdtype, c, gate_, st));
     } else {
       LCHK(csr_spmm(rp, ci, Xv, xdtype, n, B, bdtype, c, Yout, fdtype, gate_, st));
     }
@@ -164,29 +177,64 @@ struct symnmf_ctx {
     LCHK(rowmat(U, SYMNMF_F64, l, n, l, Z, lam, k, Yout, fdtype, k, gate_, st));
   }
 
-  void refresh_gram(const void* F, double* G, double* Gh) {
+  void refresh_gram(const void* F, double* G, double* Gh, double* Gi) {
     ws.reset();
-    LCHK(gram(F, fdtype, k, k, F, fdtype, k, k, n, nullptr, nullptr, nullptr, 0, ws, G, Gh, kp, alpha, gate_, st));
+    LCHK(gram(F, fdtype, k, k, F, fdtype, k, k, n, nullptr, nullptr, nullptr, 0, ws, G, Gh, kp, alpha, gate_, st,
+              Gi));
   }
 
-  void update(const void* Yin, const int* sp, const int* ss, const double* sv, const void* Src, void* Dst,
-              const double* Gh) {
-    if (opt.rule == SYMNMF_RULE_HALS) {
-      LCHK(hals_update(n, k, kp, Yin, sp, ss, sv, Src, Dst, fdtype, Gh, alpha, gate_, st));
-    } else {
-      ws.reset();
-      LCHK(bpp_update(n, k, kp, Yin, sp, ss, sv, Src, Dst, fdtype, Gh, alpha, ws, gate_, st));
+  void invalidate(int which) {
+    if (which == SYMNMF_W) btW_ok = mW_ok = false;
+    else btH_ok = mH_ok = false;
+  }
+
+  // The product-side operand of a factor, brought up to date if needed: its
+  // transposed panel (dense plain mode) or M = Lambda U^T F (LAI mode).
+  void ensure_operand(int which) {
+    void* F = which == SYMNMF_W ? W : H;
+    if (mode == SYMNMF_MODE_LAI) {
+      bool& ok = which == SYMNMF_W ? mW_ok : mH_ok;
+      if (!ok) {
+        ws.reset();
+        LCHK(gram(U, SYMNMF_F64, l, l, F, fdtype, k, k, n, nullptr, nullptr, nullptr, 0, ws, Z, nullptr, 0, 0.0,
+                  nullptr, st));
+        LCHK(scale_rows(Z, lam, l, k, kp, which == SYMNMF_W ? M_W : M_H, st));
+        ok = true;
+      }
+    } else if (mode == SYMNMF_MODE_PLAIN && kind == SYMNMF_DENSE) {
+      bool& ok = which == SYMNMF_W ? btW_ok : btH_ok;
+      if (!ok) {
+        const GemmPlan p = gemm_plan(n, k, cdtype);
+        LCHK(factor_transpose(F, fdtype, n, k, which == SYMNMF_W ? BtW : BtH, cdtype, p, nullptr, st));
+        ok = true;
+      }
     }
   }
 
   // One half-iteration: Dst from Src (side 0: W from H; side 1: H from W).
-  void half_step(int side, int64_t half_iter) {
+  // want_dot: also accumulate <Dst_new, product part> for the residual.
+  void half_step(int side, int64_t half_iter, bool want_dot) {
+    const int src_id = side == 0 ? SYMNMF_H : SYMNMF_W;
+    const int dst_id = side == 0 ? SYMNMF_W : SYMNMF_H;
     void* Src = side == 0 ? H : W;
     void* Dst = side == 0 ? W : H;
     double* Gs = side == 0 ? G_H : G_W;      // Gram of Src (current)
     double* Ghs = side == 0 ? Gh_H : Gh_W;   // regularised Gram of Src
-    double* Gd = side == 0 ? G_W : G_H;      // Gram of Dst (refreshed after)
+    double* Gis = side == 0 ? Gi_H : Gi_W;
+    double* Gid = side == 0 ? Gi_W : Gi_H;
+    double* Gd = side == 0 ? G_W : G_H;      // Gram of Dst (refreshed here)
     double* Ghd = side == 0 ? Gh_W : Gh_H;
+    ensure_operand(src_id);
+    UpdateArgs a;
+    a.n = n;
+    a.k = k;
+    a.Src = Src;
+    a.Dst = Dst;
+    a.Ghat = Ghs;
+    a.alpha = alpha;
+    a.gpart = gpart;
+    a.dpart = want_dot ? dpart : nullptr;
+    int ymode = 0, pdt = fdtype, tdt = fdtype;
     if (mode == SYMNMF_MODE_LVS) {
       ws.reset();
       LCHK(chol_inverse(Gs, k, R, Rinv, &dstate->flags, SYMNMF_FLAG_LEV_SHIFT, d_fail, st));
@@ -194,19 +242,62 @@ struct symnmf_ctx {
       LCHK(hybrid_sample(lev, n, k, s, tau, seed, (uint32_t)half_iter, sb, rows, weights, max_sel, ws, gate_, st));
       ws.reset();
       LCHK(gram(Src, fdtype, k, k, Src, fdtype, k, k, n, rows, weights, sb.info + 2, (int)max_sel, ws, nullptr, Gh_S,
-                kp, alpha, gate_, st));
+                kp, alpha, gate_, st, Gi_S));
       ws.reset();
       LCHK(sampled_slab(rp, ci, Xv, xdtype, n, rows, weights, sb.info + 2, (int)max_sel, seg_cnt, seg_ptr, seg_src,
                         seg_val, seg_cap, ws, gate_, st));
-      update(nullptr, seg_ptr, seg_src, seg_val, Src, Dst, Gh_S);
+      a.seg_ptr = seg_ptr;
+      a.seg_src = seg_src;
+      a.seg_val = seg_val;
+      a.Ghat = Gh_S;
+      Gis = Gi_S;
+      a.dpart = nullptr;
+      ymode = 1;
+    } else if (mode == SYMNMF_MODE_LAI) {
+      a.U = U;
+      a.M = side == 0 ? M_H : M_W;
+      a.l = l;
+      a.zpart = zpart;
+      ymode = 2;
+    } else if (kind == SYMNMF_DENSE) {
+      const GemmPlan p = gemm_plan(n, k, cdtype);
+      LCHK(dense_gemm_bt(Xc, cdtype, ldxc(), side == 0 ? BtH : BtW, n, k, p, P, gate_, st));
+      a.P = P;
+      a.splits = p.splits;
+      a.cp = p.cp;
+      a.Dt = side == 0 ? BtW : BtH;
+      a.ldt = p.ldt;
+      pdt = cdtype == SYMNMF_F64 ? SYMNMF_F64 : SYMNMF_F32;
+      tdt = cdtype;
     } else {
-      if (mode == SYMNMF_MODE_LAI) lai_product(Src, Y);
-      else product(Src, fdtype, k, Y);
-      update(Y, nullptr, nullptr, nullptr, Src, Dst, Ghs);
+      LCHK(csr_spmm(rp, ci, Xv, xdtype, n, Src, fdtype, k, Yk, fdtype, gate_, st, kp));
+      a.P = Yk;
+      a.splits = 1;
+      a.cp = kp;
     }
-    (void)Gs;
-    refresh_gram(Dst, Gd, Ghd);
+    if (opt.rule == SYMNMF_RULE_HALS) {
+      UpdateRO ro;
+      ro.Ghat = a.Ghat;
+      ro.Ginv = Gis;
+      ro.M = a.M;
+      LCHK(fused_update(a, ro, kp, ymode, fdtype, pdt, tdt, nbu, gate_, st));
+      LCHK(update_reduce(gpart, ymode == 2 ? zpart : nullptr, nbu, k, l, kp, alpha, lam, Gd, Ghd, Gid,
+                         side == 0 ? M_W : M_H, gate_, st));
+    } else {
+      throw Fail{SYMNMF_E_UNSUPPORTED, "BPP rule not available yet"};
+    }
+    invalidate(dst_id);
+    if (ymode == 0 && a.Dt) {
+      if (dst_id == SYMNMF_W) btW_ok = true;
+      else btH_ok = true;
+    }
+    if (ymode == 2) {
+      if (dst_id == SYMNMF_W) mW_ok = true;
+      else mH_ok = true;
+    }
   }
+
+  int64_t ldxc() const { return cdtype == SYMNMF_BF16 && xdtype != SYMNMF_BF16 ? n : ld; }
 
   struct Gate {
     symnmf_ctx* c;
@@ -217,24 +308,26 @@ struct symnmf_ctx {
   void one_iteration() {
     Gate g(this);
     const int64_t t = iter_host++;
-    half_step(0, 2 * t);
-    half_step(1, 2 * t + 1);
     const double* nrm = d_scal + (mode == SYMNMF_MODE_LAI ? 8 : 0);
-    bool with_resid = true;
     if (mode == SYMNMF_MODE_LVS) {
+      half_step(0, 2 * t, false);
+      half_step(1, 2 * t + 1, false);
       const int every = opt.resid_every > 0 ? opt.resid_every : 1;
-      with_resid = ((t + 1) % every) == 0;
-      if (with_resid) product(W, fdtype, k, Y);
+      if (((t + 1) % every) == 0) {
+        product(W, fdtype, k, Y);
+        ws.reset();
+        double* part = nullptr;
+        const int nb = dot_partials(H, Y, fdtype, nk(), ws, &part, gate_, st);
+        if (nb < 0) throw Fail{SYMNMF_E_DEVICE, "dot launch failed"};
+        finish_iteration(part, nb, G_W, G_H, k, nrm, dstate, hist, rule(), st);
+      } else {
+        finish_iteration(nullptr, 0, G_W, G_H, k, nrm, dstate, hist, rule(), st);
+      }
+      return;
     }
-    if (with_resid) {
-      ws.reset();
-      double* part = nullptr;
-      const int nb = dot_partials(H, Y, fdtype, nk(), ws, &part, gate_, st);
-      if (nb < 0) throw Fail{SYMNMF_E_DEVICE, "dot launch failed"};
-      finish_iteration(part, nb, G_W, G_H, k, nrm, dstate, hist, rule(), st);
-    } else {
-      finish_iteration(nullptr, 0, G_W, G_H, k, nrm, dstate, hist, rule(), st);
-    }
+    half_step(0, 2 * t, false);
+    half_step(1, 2 * t + 1, true);
+    finish_iteration(dpart, nbu, G_W, G_H, k, nrm, dstate, hist, rule(), st);
   }
 
   DevState read_state() {
@@ -442,10 +535,24 @@ int symnmf_create(symnmf_ctx** out, const symnmf_matrix* X, int32_t k, double al
     c->W = dalloc<char>((size_t)n * k * fs);
     c->H = dalloc<char>((size_t)n * k * fs);
     c->Y = dalloc<char>((size_t)n * CMAX * fs);
+    if (c->kind == SYMNMF_CSR) {
+      c->Yk = dalloc<char>((size_t)n * c->kp * fs);
+      HIPCHK(hipMemsetAsync(c->Yk, 0, (size_t)n * c->kp * fs, c->st));
+    }
     if (c->kind == SYMNMF_DENSE) {
-      const GemmPlan p = gemm_plan(n, CMAX, c->cdtype);
+      // partials buffer: the largest splits * cp over every product width
+      size_t pmax = 0;
+      for (int cc = 16; cc <= CMAX; cc += 16) {
+        const GemmPlan p = gemm_plan(n, cc, c->cdtype);
+        pmax = std::max(pmax, (size_t)p.splits * p.cp);
+      }
       const size_t acc = c->cdtype == SYMNMF_F64 ? 8 : 4;
-      c->P = dalloc<char>((size_t)p.splits * n * p.cp * acc);
+      c->P = dalloc<char>(pmax * n * acc);
+      c->Bt = dalloc<char>(gemm_bt_bytes(n, CMAX));
+      c->BtW = dalloc<char>(gemm_bt_bytes(n, k));
+      c->BtH = dalloc<char>(gemm_bt_bytes(n, k));
+      HIPCHK(hipMemsetAsync(c->BtW, 0, gemm_bt_bytes(n, k), c->st));
+      HIPCHK(hipMemsetAsync(c->BtH, 0, gemm_bt_bytes(n, k), c->st));
     }
     c->G_W = dalloc<double>((size_t)k * k);
     c->G_H = dalloc<double>((size_t)k * k);
@@ -453,6 +560,15 @@ int symnmf_create(symnmf_ctx** out, const symnmf_matrix* X, int32_t k, double al
     c->Gh_H = dalloc<double>((size_t)c->kp * c->kp);
     c->Gh_S = dalloc<double>((size_t)c->kp * c->kp);
     c->d_scal = dalloc<double>(16);
+    c->nbu = update_blocks(n, c->fdtype);
+    c->gpart = dalloc<double>((size_t)c->nbu * k * k);
+    c->dpart = dalloc<double>(c->nbu);
+    c->Gi_W = dalloc<double>(c->kp);
+    c->Gi_H = dalloc<double>(c->kp);
+    c->Gi_S = dalloc<double>(c->kp);
+    LCHK(pad_identity(c->Gh_W, c->Gi_W, k, c->kp, c->st));
+    LCHK(pad_identity(c->Gh_H, c->Gi_H, k, c->kp, c->st));
+    LCHK(pad_identity(c->Gh_S, c->Gi_S, k, c->kp, c->st));
     c->rowsum = dalloc<double>(n);
     c->dstate = dalloc<DevState>(1);
     c->hist = dalloc<double>(c->opt.max_history);
@@ -496,8 +612,8 @@ int symnmf_create(symnmf_ctx** out, const symnmf_matrix* X, int32_t k, double al
     // H0 = U[0,1) * 2 sqrt(zeta / k), W0 = H0 (Section 6 initialisation)
     LCHK(init_uniform_factor(c->H, c->fdtype, n, k, 2.0 * std::sqrt(c->zeta / k), seed, c->st));
     HIPCHK(hipMemcpyAsync(c->W, c->H, (size_t)n * k * fs, hipMemcpyDeviceToDevice, c->st));
-    c->refresh_gram(c->H, c->G_H, c->Gh_H);
-    c->refresh_gram(c->W, c->G_W, c->Gh_W);
+    c->refresh_gram(c->H, c->G_H, c->Gh_H, c->Gi_H);
+    c->refresh_gram(c->W, c->G_W, c->Gh_W, c->Gi_W);
 
     if (s > 0) {
       if (c->kind != SYMNMF_CSR) throw Fail{SYMNMF_E_UNSUPPORTED, "sampling needs CSR X"};
@@ -568,6 +684,14 @@ int symnmf_lai(symnmf_ctx* c, int32_t l, int32_t q) {
       c->Rl = dalloc<double>((size_t)l * l);
       c->Rlinv = dalloc<double>((size_t)l * l);
       c->Z = dalloc<double>((size_t)l * c->k);
+      dfree(c->zpart);
+      dfree(c->M_W);
+      dfree(c->M_H);
+      c->zpart = dalloc<double>((size_t)c->nbu * l * c->k);
+      c->M_W = dalloc<double>((size_t)l * c->kp);
+      c->M_H = dalloc<double>((size_t)l * c->kp);
+      HIPCHK(hipMemsetAsync(c->M_W, 0, sizeof(double) * l * c->kp, c->st));
+      HIPCHK(hipMemsetAsync(c->M_H, 0, sizeof(double) * l * c->kp, c->st));
     }
     HIPCHK(hipMemsetAsync(c->d_fail, 0, sizeof(int), c->st));
     // Algorithm RRF: Omega Gaussian (Philox), then 2q+1 products each followed
@@ -582,7 +706,7 @@ int symnmf_lai(symnmf_ctx* c, int32_t l, int32_t q) {
     c->ws.reset();
     LCHK(gram(c->Q, SYMNMF_F64, l, l, c->YQ, c->fdtype, l, l, n, nullptr, nullptr, nullptr, 0, c->ws, c->Tm, nullptr,
               0, 0.0, nullptr, c->st));
-    LCHK(jacobi_evd(c->Tm, l, c->Vw, c->QT, c->lam, c->st));
+    LCHK(jacobi_evd(c->Tm, l, c->QT, c->lam, c->st));
     LCHK(rowmat(c->Q, SYMNMF_F64, l, n, l, c->QT, nullptr, l, c->U, SYMNMF_F64, l, nullptr, c->st));
     c->ws.reset();
     LCHK(column_sign_fix(c->U, n, l, c->ws, c->st));
@@ -596,6 +720,7 @@ int symnmf_lai(symnmf_ctx* c, int32_t l, int32_t q) {
     if (failed) throw Fail{SYMNMF_E_NUMERIC, "CholeskyQR2 broke down"};
     if (!(c->normsq_lai > 0.0)) throw Fail{SYMNMF_E_NUMERIC, "low-rank approximation is zero"};
     c->mode = SYMNMF_MODE_LAI;
+    c->mW_ok = c->mH_ok = false;
   });
 }
 
@@ -613,6 +738,7 @@ int symnmf_refine(symnmf_ctx* c, int32_t stop_mode, double target) {
     c->opt.stop_mode = stop_mode;
     c->opt.target = target;
     c->mode = SYMNMF_MODE_PLAIN;
+    c->btW_ok = c->btH_ok = false;
   });
 }
 
@@ -661,8 +787,9 @@ int symnmf_set_factor(symnmf_ctx* c, int32_t which, const void* src, int32_t dty
     if (dtype != SYMNMF_F64 && dtype != SYMNMF_F32) throw Fail{SYMNMF_E_INVALID, "dtype"};
     void* dst = which == SYMNMF_W ? c->W : c->H;
     LCHK(copy_convert(src, dtype, dst, c->fdtype, c->nk(), c->st));
-    if (which == SYMNMF_W) c->refresh_gram(c->W, c->G_W, c->Gh_W);
-    else c->refresh_gram(c->H, c->G_H, c->Gh_H);
+    if (which == SYMNMF_W) c->refresh_gram(c->W, c->G_W, c->Gh_W, c->Gi_W);
+    else c->refresh_gram(c->H, c->G_H, c->Gh_H, c->Gi_H);
+    c->invalidate(which);
   });
 }
 
@@ -694,7 +821,7 @@ int symnmf_half_step(symnmf_ctx* c, int32_t side, int32_t half_iter) {
   return guarded(c, [&] {
     if (side != 0 && side != 1) throw Fail{SYMNMF_E_INVALID, "side"};
     if (half_iter < 0) throw Fail{SYMNMF_E_INVALID, "half_iter"};
-    c->half_step(side, half_iter);
+    c->half_step(side, half_iter, false);
   });
 }
 
