@@ -257,8 +257,17 @@ __global__ __launch_bounds__(256) void k_chol_inverse(const double* __restrict__
     for (int i = k - 1; i >= 0; --i) {
       double v = 0.0;
       if (i <= c) {
-        v = (i == c) ? 1.0 : 0.0;
-        for (int p = i + 1; p <= c; ++p) v -= A[i * lda + p] * Xi[p * lda + c];
+        // four independent partial sums shorten the dependent chain
+        double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+        int p = i + 1;
+        for (; p + 3 <= c; p += 4) {
+          s0 = fma(A[i * lda + p], Xi[p * lda + c], s0);
+          s1 = fma(A[i * lda + p + 1], Xi[(p + 1) * lda + c], s1);
+          s2 = fma(A[i * lda + p + 2], Xi[(p + 2) * lda + c], s2);
+          s3 = fma(A[i * lda + p + 3], Xi[(p + 3) * lda + c], s3);
+        }
+        for (; p <= c; ++p) s0 = fma(A[i * lda + p], Xi[p * lda + c], s0);
+        v = ((i == c) ? 1.0 : 0.0) - ((s0 + s1) + (s2 + s3));
         v /= A[i * lda + i];
       }
       Xi[i * lda + c] = v;
@@ -310,10 +319,10 @@ __global__ __launch_bounds__(256) void k_jacobi(const double* __restrict__ T, in
     if (conv) break;
     for (int step = 0; step < m - 1; ++step) {
       // round-robin (circle) pairing: index 0 fixed, 1..m-1 rotate by `step`
-      if (tid < half) {
-        int p = tid == 0 ? 0 : 1 + (tid - 1 + step) % (m - 1);
-        int q = 1 + (m - 2 - tid + step) % (m - 1);
-        if (p > q) { const int t = p; p = q; q = t; }
+      for (int pr = tid; pr < half; pr += 256) {
+        int p = pr == 0 ? 0 : 1 + (pr - 1 + step) % (m - 1);
+        int q = 1 + (m - 2 - pr + step) % (m - 1);
+        if (p > q) { const int sw = p; p = q; q = sw; }
         double c = 1.0, s = 0.0;
         if (q < l) {
           const double apq = A[p * lda + q];
@@ -324,10 +333,10 @@ __global__ __launch_bounds__(256) void k_jacobi(const double* __restrict__ T, in
             s = t * c;
           }
         }
-        pp[tid] = p;
-        qq[tid] = q;
-        cs[tid] = c;
-        sn[tid] = s;
+        pp[pr] = p;
+        qq[pr] = q;
+        cs[pr] = c;
+        sn[pr] = s;
       }
       __syncthreads();
       // columns p, q of A and V

@@ -15,52 +15,73 @@
 
 namespace {
 
-template <int KP, int LP, typename TF, typename TP, typename TT, int YMODE, int NTH>
-__global__ __launch_bounds__(NTH) void k_update(UpdateArgs a, const double* __restrict__ Gh,
+// Sum of a double over the 16 lanes of a DPP row, every lane receiving the
+// total: quad_perm [1,0,3,2] and [2,3,0,1] (pairs, quads), then
+// row_half_mirror and row_mirror (halves, full row).  DPP moves are plain
+// VALU operations, unlike the LDS permutes behind __shfl_xor.
+template <int CTRL>
+__device__ __forceinline__ double dpp_double(double v) {
+  const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ double row16_sum(double v) {
+  v += dpp_double<0xB1>(v);   // quad_perm(1,0,3,2)
+  v += dpp_double<0x4E>(v);   // quad_perm(2,3,0,1)
+  v += dpp_double<0x141>(v);  // row_half_mirror
+  v += dpp_double<0x140>(v);  // row_mirror
+  return v;
+}
+
+// 16 lanes per row, 16 rows per 256-thread block.  Lane g of a row owns the
+// columns q = g + 16 c (c < KP / 16).  The HALS sweep over column i sums
+// w_q Ghat[i][q] over the row's lanes (a DPP row) and the lane owning column
+// i applies the update.
+template <int KP, int LP, typename TF, typename TP, typename TT, int YMODE>
+__global__ __launch_bounds__(256) void k_update(UpdateArgs a, const double* __restrict__ Gh,
                                                 const double* __restrict__ Ginv, const double* __restrict__ M,
                                                 const TF* __restrict__ Src, const DevState* __restrict__ st) {
   if (stopped(st)) return;
-  constexpr int TY = NTH / 16;
-  constexpr int GI = KP / TY;
-  constexpr int GJ = KP / 16;
-  constexpr int ZI = LP > 0 ? LP / TY : 1;
+  constexpr int NTH = 256, RPB = 16;
+  constexpr int CPL = KP / 16;
+  constexpr int ZI = LP > 0 ? LP / 16 : 1;
   constexpr int LW = KP + 1;
   constexpr int LU = LP + 1;
-  // LDS: Ghat (KP x KP) and M (l x KP) as FP64, then the chunk's new rows and
-  // (LAI) U rows.  Ghat and M are read with wave-uniform addresses
-  // (broadcast); holding them in scalar registers instead would spill.
   extern __shared__ __align__(16) unsigned char smem[];
-  double* gs = reinterpret_cast<double*>(smem);
-  double* ms = gs + KP * KP;
-  TF* wl = reinterpret_cast<TF*>(ms + (LP > 0 ? LP * KP : 0));  // NTH x LW
-  TF* us = wl + NTH * LW;                                        // NTH x LU
+  double* gs = reinterpret_cast<double*>(smem);          // KP x KP
+  double* gi = gs + KP * KP;                              // KP
+  double* ms = gi + KP;                                   // l x KP (LAI)
+  TF* wl = reinterpret_cast<TF*>(ms + (LP > 0 ? LP * KP : 0));  // RPB x LW
+  TF* us = wl + RPB * LW;                                         // RPB x LU (LAI)
   __shared__ double sc[8];
-  const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
+  const int tid = threadIdx.x;
+  const int g = tid & 15, rs = tid >> 4;       // lane in row, row slot
+  const int tx = tid & 15, ty = tid >> 4;      // Gram / U^T F tile coordinates
   const int n = a.n, k = a.k, l = a.l;
   TF* __restrict__ Dst = (TF*)a.Dst;
   const double alpha = a.alpha;
   for (int e = tid; e < KP * KP; e += NTH) gs[e] = Gh[e];
+  for (int e = tid; e < KP; e += NTH) gi[e] = Ginv[e];
   if (LP > 0)
     for (int e = tid; e < l * KP; e += NTH) ms[e] = M[e];
   __syncthreads();
 
-  double gacc[GI][GJ];
-  double zacc[ZI][GJ];
+  double gacc[CPL][CPL];
+  double zacc[ZI][CPL];
 #pragma unroll
-  for (int i = 0; i < GI; ++i)
+  for (int i = 0; i < CPL; ++i)
 #pragma unroll
-    for (int j = 0; j < GJ; ++j) gacc[i][j] = 0.0;
+    for (int j = 0; j < CPL; ++j) gacc[i][j] = 0.0;
 #pragma unroll
   for (int i = 0; i < ZI; ++i)
 #pragma unroll
-    for (int j = 0; j < GJ; ++j) zacc[i][j] = 0.0;
+    for (int j = 0; j < CPL; ++j) zacc[i][j] = 0.0;
   double dot = 0.0;
 
-  for (int base = blockIdx.x * NTH; base < n; base += gridDim.x * NTH) {
-    const int row = base + tid;
+  for (int base = blockIdx.x * RPB; base < n; base += gridDim.x * RPB) {
+    const int row = base + rs;
     if (LP > 0) {
-      // stage the chunk's U rows (coalesced)
-      for (int e = tid; e < NTH * l; e += NTH) {
+      for (int e = tid; e < RPB * l; e += NTH) {
         const int r = e / l, p = e - r * l;
         us[r * LU + p] = (base + r < n) ? (TF)a.U[(int64_t)(base + r) * l + p] : (TF)0;
       }
@@ -68,18 +89,18 @@ __global__ __launch_bounds__(NTH) void k_update(UpdateArgs a, const double* __re
     }
     if (row < n) {
       const int64_t rb = (int64_t)row * k;
-      double y[KP];
+      double y[CPL], w[CPL], sv[CPL];
 #pragma unroll
-      for (int i = 0; i < KP; ++i) y[i] = 0.0;
+      for (int c = 0; c < CPL; ++c) y[c] = 0.0;
       // Loads are never guarded by a branch (a branch per element makes the
       // compiler wait for each load in turn): padded buffers are read in
       // full, factor rows with a clamped column index and a zero mask.
       if (YMODE == 0) {
-        const TP* pr = (const TP*)a.P + (int64_t)row * a.cp;  // cp == KP, zero padded
+        const TP* pr = (const TP*)a.P + (int64_t)row * a.cp + g;  // cp == KP, zero padded
         const int64_t sstride = (int64_t)n * a.cp;
         for (int sp = 0; sp < a.splits; ++sp) {
 #pragma unroll
-          for (int i = 0; i < KP; ++i) y[i] += (double)pr[sp * sstride + i];
+          for (int c = 0; c < CPL; ++c) y[c] += (double)pr[sp * sstride + 16 * c];
         }
       } else if (YMODE == 1) {
         const int e1 = a.seg_ptr[row + 1];
@@ -87,112 +108,97 @@ __global__ __launch_bounds__(NTH) void k_update(UpdateArgs a, const double* __re
           const double v = a.seg_val[e];
           const TF* sr = Src + (int64_t)a.seg_src[e] * k;
 #pragma unroll
-          for (int i = 0; i < KP; ++i) {
-            const double x = (double)sr[i < k ? i : k - 1];
-            y[i] = fma(v, i < k ? x : 0.0, y[i]);
+          for (int c = 0; c < CPL; ++c) {
+            const int q = g + 16 * c;
+            const double x = (double)sr[q < k ? q : k - 1];
+            y[c] = fma(v, q < k ? x : 0.0, y[c]);
           }
         }
       } else {
-        const TF* u = us + tid * LU;
+        const TF* u = us + rs * LU;
         for (int p = 0; p < l; ++p) {
           const double up = (double)u[p];
-          const double* m = ms + p * KP;  // l x KP, zero padded
 #pragma unroll
-          for (int i = 0; i < KP; ++i) y[i] = fma(up, m[i], y[i]);
+          for (int c = 0; c < CPL; ++c) y[c] = fma(up, ms[p * KP + g + 16 * c], y[c]);
         }
       }
-      // HALS target y + alpha src, and the current row
-      double w[KP];
-      double sv[KP];
 #pragma unroll
-      for (int i = 0; i < KP; ++i) {
-        const int ic = i < k ? i : k - 1;
-        const double xs = (double)Src[rb + ic];
-        const double xd = (double)Dst[rb + ic];
-        sv[i] = i < k ? xs : 0.0;
-        w[i] = i < k ? xd : 0.0;
-        y[i] = fma(alpha, sv[i], y[i]);
+      for (int c = 0; c < CPL; ++c) {
+        const int q = g + 16 * c;
+        const int qc = q < k ? q : k - 1;
+        const double xs = (double)Src[rb + qc];
+        const double xd = (double)Dst[rb + qc];
+        sv[c] = q < k ? xs : 0.0;
+        w[c] = q < k ? xd : 0.0;
+        y[c] = fma(alpha, sv[c], y[c]);   // HALS target y + alpha src
       }
       // Regularised HALS sweep over the KP columns in order.  Padded columns
       // have Ghat = identity, zero target and zero start, so they stay zero.
 #pragma unroll
       for (int i = 0; i < KP; ++i) {
-        const double* g = gs + i * KP;
-        double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+        double part = 0.0;
 #pragma unroll
-        for (int q = 0; q < KP; q += 4) {
-          s0 = fma(w[q], g[q], s0);
-          s1 = fma(w[q + 1], g[q + 1], s1);
-          s2 = fma(w[q + 2], g[q + 2], s2);
-          s3 = fma(w[q + 3], g[q + 3], s3);
-        }
-        const double sum = (s0 + s1) + (s2 + s3);
-        w[i] = fmax(0.0, fma(y[i] - sum, Ginv[i], w[i]));
+        for (int c = 0; c < CPL; ++c) part = fma(w[c], gs[i * KP + g + 16 * c], part);
+        part = row16_sum(part);
+        const int ci = i >> 4;
+        const double cand = fmax(0.0, fma(y[ci] - part, gi[i], w[ci]));
+        w[ci] = (g == (i & 15)) ? cand : w[ci];
       }
 #pragma unroll
-      for (int i = 0; i < KP; ++i) {
-        const TF wt = (TF)w[i];
-        // product part of the target: y - alpha src (zero on padded columns)
-        dot = fma((double)wt, fma(-alpha, sv[i], y[i]), dot);
-        wl[tid * LW + i] = wt;
-      }
-#pragma unroll
-      for (int i = 0; i < KP; ++i) {
-        if (i < k) {
-          Dst[rb + i] = wl[tid * LW + i];
-          if (a.Dt) ((TT*)a.Dt)[(int64_t)i * a.ldt + row] = (TT)wl[tid * LW + i];
+      for (int c = 0; c < CPL; ++c) {
+        const int q = g + 16 * c;
+        const TF wt = (TF)w[c];
+        dot = fma((double)wt, fma(-alpha, sv[c], y[c]), dot);   // product part of the target
+        wl[rs * LW + q] = wt;
+        if (q < k) {
+          Dst[rb + q] = wt;
+          if (a.Dt) ((TT*)a.Dt)[(int64_t)q * a.ldt + row] = (TT)wt;
         }
       }
     } else {
 #pragma unroll
-      for (int i = 0; i < KP; ++i) wl[tid * LW + i] = (TF)0;
+      for (int c = 0; c < CPL; ++c) wl[rs * LW + g + 16 * c] = (TF)0;
     }
     __syncthreads();
-    // block partial of F^T F over this chunk
-#pragma unroll 4
-    for (int r = 0; r < NTH; ++r) {
-      double bv[GJ];
+    // block partials of F^T F and (LAI) U^T F over this chunk
 #pragma unroll
-      for (int j = 0; j < GJ; ++j) bv[j] = (double)wl[r * LW + tx + 16 * j];
+    for (int r = 0; r < RPB; ++r) {
+      double bv[CPL];
 #pragma unroll
-      for (int i = 0; i < GI; ++i) {
-        const double av = (double)wl[r * LW + ty + TY * i];
+      for (int j = 0; j < CPL; ++j) bv[j] = (double)wl[r * LW + tx + 16 * j];
 #pragma unroll
-        for (int j = 0; j < GJ; ++j) gacc[i][j] = fma(av, bv[j], gacc[i][j]);
+      for (int i = 0; i < CPL; ++i) {
+        const double av = (double)wl[r * LW + ty + 16 * i];
+#pragma unroll
+        for (int j = 0; j < CPL; ++j) gacc[i][j] = fma(av, bv[j], gacc[i][j]);
       }
-    }
-    // block partial of U^T F (LAI: the next half-step's M)
-    if (LP > 0) {
-#pragma unroll 4
-      for (int r = 0; r < NTH; ++r) {
-        double bv[GJ];
-#pragma unroll
-        for (int j = 0; j < GJ; ++j) bv[j] = (double)wl[r * LW + tx + 16 * j];
+      if (LP > 0) {
 #pragma unroll
         for (int i = 0; i < ZI; ++i) {
-          const double uv = (double)us[r * LU + ty + TY * i];
+          const double uv = (double)us[r * LU + ty + 16 * i];
 #pragma unroll
-          for (int j = 0; j < GJ; ++j) zacc[i][j] = fma(uv, bv[j], zacc[i][j]);
+          for (int j = 0; j < CPL; ++j) zacc[i][j] = fma(uv, bv[j], zacc[i][j]);
         }
       }
     }
     __syncthreads();
   }
-  double* gp = a.gpart + (int64_t)blockIdx.x * k * k;
+  // unified partial row of this block: [F^T F (k x k) | U^T F (l x k)]
+  double* gp = a.part + (int64_t)blockIdx.x * a.pstride;
 #pragma unroll
-  for (int i = 0; i < GI; ++i)
+  for (int i = 0; i < CPL; ++i)
 #pragma unroll
-    for (int j = 0; j < GJ; ++j) {
-      const int p = ty + TY * i, q = tx + 16 * j;
+    for (int j = 0; j < CPL; ++j) {
+      const int p = ty + 16 * i, q = tx + 16 * j;
       if (p < k && q < k) gp[p * k + q] = gacc[i][j];
     }
   if (LP > 0) {
-    double* zp = a.zpart + (int64_t)blockIdx.x * l * k;
+    double* zp = gp + k * k;
 #pragma unroll
     for (int i = 0; i < ZI; ++i)
 #pragma unroll
-      for (int j = 0; j < GJ; ++j) {
-        const int p = ty + TY * i, q = tx + 16 * j;
+      for (int j = 0; j < CPL; ++j) {
+        const int p = ty + 16 * i, q = tx + 16 * j;
         if (p < l && q < k) zp[p * k + q] = zacc[i][j];
       }
   }
@@ -202,10 +208,12 @@ __global__ __launch_bounds__(NTH) void k_update(UpdateArgs a, const double* __re
   }
 }
 
-// Fixed-order reduction of the block partials: G (k x k), Ghat = G + alpha I
-// (k x k part of the kp x kp padded matrix; the padding is set once), the
-// reciprocals of its diagonal, and, when zpart is given, M = diag(lam) Z with
-// Z (l x k) the reduced U^T F.
+// Fixed-order reduction of the block partials (unified rows of E = k*k
+// [+ l*k] doubles): G (k x k), Ghat = G + alpha I (k x k part of the kp x kp
+// padded matrix; the padding is set once), the reciprocals of its diagonal,
+// and, for the LAI path, M = diag(lam) Z (l x kp, zero padded) with Z the
+// reduced U^T F.  Large partial counts go through a first level that sums
+// fixed groups of 32 rows.
 __device__ __forceinline__ double sum_strided(const double* __restrict__ p, int nb, int64_t stride) {
   double acc = 0.0;
   int b = 0;
@@ -220,25 +228,37 @@ __device__ __forceinline__ double sum_strided(const double* __restrict__ p, int 
   return acc;
 }
 
-__global__ __launch_bounds__(256) void k_update_reduce(const double* __restrict__ gpart,
-                                                       const double* __restrict__ zpart, int nb, int k, int l, int kp,
-                                                       double alpha, const double* __restrict__ lam,
+constexpr int REDUCE_GROUP = 32;
+
+__global__ __launch_bounds__(256) void k_reduce_level1(const double* __restrict__ part, int nb, int E,
+                                                       double* __restrict__ out, const DevState* __restrict__ st) {
+  if (stopped(st)) return;
+  const int e = blockIdx.x * 256 + threadIdx.x;
+  if (e >= E) return;
+  const int b0 = blockIdx.y * REDUCE_GROUP;
+  const int cnt = min(REDUCE_GROUP, nb - b0);
+  out[(int64_t)blockIdx.y * E + e] = sum_strided(part + (int64_t)b0 * E + e, cnt, E);
+}
+
+__global__ __launch_bounds__(256) void k_update_reduce(const double* __restrict__ part, int nb, int E, int k, int l,
+                                                       int kp, double alpha, const double* __restrict__ lam,
                                                        double* __restrict__ G, double* __restrict__ Ghat,
                                                        double* __restrict__ Ginv, double* __restrict__ M,
                                                        const DevState* __restrict__ st) {
   if (stopped(st)) return;
   const int e = blockIdx.x * 256 + threadIdx.x;
   const int kk = k * k;
+  if (e >= E) return;
+  const double acc = sum_strided(part + e, nb, E);
   if (e < kk) {
-    const double acc = sum_strided(gpart + e, nb, kk);
     const int p = e / k, q = e - p * k;
     if (G) G[e] = acc;
     if (Ghat) Ghat[p * kp + q] = acc + (p == q ? alpha : 0.0);
     if (Ginv && p == q) Ginv[p] = 1.0 / (acc + alpha);
-  } else if (zpart && e < kk + l * k) {
+  } else {
     const int f = e - kk;
     const int p = f / k, q = f - p * k;
-    M[p * kp + q] = lam[p] * sum_strided(zpart + f, nb, (int64_t)l * k);  // l x kp, padding stays 0
+    M[p * kp + q] = lam[p] * acc;  // l x kp, padding stays 0
   }
 }
 
@@ -259,24 +279,16 @@ __global__ __launch_bounds__(256) void k_pad_identity(double* __restrict__ Ghat,
   if (Ginv && e < kp && e >= k) Ginv[e] = 1.0;
 }
 
-template <int KP, int LP, typename TF>
-constexpr size_t update_lds(int nth) {
-  return 8 * (size_t)KP * (KP + LP) + sizeof(TF) * (size_t)nth * ((KP + 1) + (LP > 0 ? LP + 1 : 0));
-}
-
 template <int KP, int LP, typename TF, typename TP, typename TT, int YMODE>
 int launch_update(const UpdateArgs& a, const UpdateRO& ro, int nb, const DevState* st, hipStream_t s) {
-  // 128 threads (rows) per block for FP32 factors unless the LDS footprint
-  // would exceed the 160 KB of a CU; 64 for FP64 factors.
-  constexpr int NTH = (sizeof(TF) == 8 || update_lds<KP, LP, TF>(128) > 160 * 1024) ? 64 : 128;
-  const size_t lds = update_lds<KP, LP, TF>(NTH);
-  auto kern = k_update<KP, LP, TF, TP, TT, YMODE, NTH>;
+  const size_t lds = 8 * (size_t)KP * (KP + 1 + LP) + sizeof(TF) * 16 * ((KP + 1) + (LP > 0 ? LP + 1 : 0));
+  auto kern = k_update<KP, LP, TF, TP, TT, YMODE>;
   if (lds > 65536 &&
       hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
     return -1;
   // exactly nb blocks (the reduction reads nb partials); rows beyond
-  // nb * NTH are covered by the grid-stride loop
-  kern<<<nb, NTH, lds, s>>>(a, ro.Ghat, ro.Ginv, ro.M, (const TF*)a.Src, st);
+  // 16 * nb are covered by the grid-stride loop
+  kern<<<nb, 256, lds, s>>>(a, ro.Ghat, ro.Ginv, ro.M, (const TF*)a.Src, st);
   return 0;
 }
 
@@ -311,8 +323,8 @@ int dispatch_kp(const UpdateArgs& a, const UpdateRO& ro, int kp, int ymode, int 
 }  // namespace
 
 int update_blocks(int n, int fdtype) {
-  const int nth = fdtype == SYMNMF_F64 ? 64 : 128;
-  return std::max(1, std::min(1024, ceil_div(n, nth)));
+  (void)fdtype;
+  return std::max(1, std::min(1024, ceil_div(n, 16)));
 }
 
 int fused_update(const UpdateArgs& a, const UpdateRO& ro, int kp, int ymode, int fdtype, int pdtype, int tdtype,
@@ -331,11 +343,19 @@ int fused_update(const UpdateArgs& a, const UpdateRO& ro, int kp, int ymode, int
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
-int update_reduce(const double* gpart, const double* zpart, int nb, int k, int l, int kp, double alpha,
+int update_reduce(const double* part, int nb, int E, double* l1, int k, int l, int kp, double alpha,
                   const double* lam, double* G, double* Ghat, double* Ginv, double* M, const DevState* st,
                   hipStream_t s) {
-  const int E = k * k + (zpart ? l * k : 0);
-  k_update_reduce<<<ceil_div(E, 256), 256, 0, s>>>(gpart, zpart, nb, k, l, kp, alpha, lam, G, Ghat, Ginv, M, st);
+  const double* src = part;
+  int cnt = nb;
+  if (nb > REDUCE_GROUP) {
+    const int groups = ceil_div(nb, REDUCE_GROUP);
+    dim3 g1(ceil_div(E, 256), groups);
+    k_reduce_level1<<<g1, 256, 0, s>>>(part, nb, E, l1, st);
+    src = l1;
+    cnt = groups;
+  }
+  k_update_reduce<<<ceil_div(E, 256), 256, 0, s>>>(src, cnt, E, k, l, kp, alpha, lam, G, Ghat, Ginv, M, st);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 

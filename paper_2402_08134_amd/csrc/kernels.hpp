@@ -125,8 +125,8 @@ struct UpdateArgs {
   void* Dt = nullptr;                // optional transposed copy of Dst (cp x ldt)
   const double* Ghat = nullptr;      // G + alpha I padded to kp x kp
   double alpha = 0.0;
-  double* gpart = nullptr;           // [nb][k*k]
-  double* zpart = nullptr;           // [nb][l*k] (YMODE 2)
+  double* part = nullptr;            // [nb][pstride]: F^T F (k*k) then U^T F (l*k, YMODE 2)
+  int pstride = 0;
   double* dpart = nullptr;           // [nb] or nullptr
 };
 // Read-only small operands of the update, passed as separate restrict-
@@ -140,7 +140,9 @@ int update_blocks(int n, int fdtype);
 // pdtype: element type of P (F32 or F64); tdtype: element type of Dt.
 int fused_update(const UpdateArgs& a, const UpdateRO& ro, int kp, int ymode, int fdtype, int pdtype, int tdtype,
                  int nb, const DevState* st, hipStream_t s);
-int update_reduce(const double* gpart, const double* zpart, int nb, int k, int l, int kp, double alpha,
+// Reduce nb partial rows of E doubles (E = k*k, or k*k + l*k when M is
+// wanted); l1: scratch of ceil(nb / 32) * E doubles.
+int update_reduce(const double* part, int nb, int E, double* l1, int k, int l, int kp, double alpha,
                   const double* lam, double* G, double* Ghat, double* Ginv, double* M, const DevState* st,
                   hipStream_t s);
 int pad_identity(double* Ghat, double* Ginv, int k, int kp, hipStream_t s);

@@ -92,8 +92,9 @@ struct symnmf_ctx {
   void* BtW = nullptr;  // transposed factor panels for the dense product
   void* BtH = nullptr;
   bool btW_ok = false, btH_ok = false;
-  double* gpart = nullptr;  // fused-update block partials
-  double* zpart = nullptr;
+  double* part = nullptr;   // fused-update block partials (nbu x pcap)
+  double* part_l1 = nullptr;
+  size_t pcap = 0;          // doubles per partial row
   double* dpart = nullptr;
   int nbu = 1;              // blocks of the fused update
   double *M_W = nullptr, *M_H = nullptr;  // LAI: Lambda U^T W, Lambda U^T H
@@ -129,7 +130,7 @@ struct symnmf_ctx {
   ~symnmf_ctx() {
     if (st) (void)hipStreamSynchronize(st);
     else (void)hipDeviceSynchronize();
-    void* ptrs[] = {Xb_owned, W, H, Y, Yk, P, Bt, BtW, BtH, gpart, zpart, dpart, M_W, M_H, Gi_W, Gi_H, Gi_S, G_W, G_H, Gh_W, Gh_H, Gh_S, d_scal, rowsum, dstate, hist, d_fail,
+    void* ptrs[] = {Xb_owned, W, H, Y, Yk, P, Bt, BtW, BtH, part, part_l1, dpart, M_W, M_H, Gi_W, Gi_H, Gi_S, G_W, G_H, Gh_W, Gh_H, Gh_S, d_scal, rowsum, dstate, hist, d_fail,
                     ws.base, Q, Q1, U, YQ, Tm, QT, Vw, lam, Rl, Rlinv, Z, sb.w, sb.prefix, sb.counts, sb.flags,
                     sb.info, sb.theta, rows, weights, seg_cnt, seg_ptr, seg_src, seg_val, lev, R, Rinv};
     for (void* p : ptrs) dfree(p);
@@ -232,7 +233,8 @@ struct symnmf_ctx {
     a.Dst = Dst;
     a.Ghat = Ghs;
     a.alpha = alpha;
-    a.gpart = gpart;
+    a.part = part;
+    a.pstride = k * k;
     a.dpart = want_dot ? dpart : nullptr;
     int ymode = 0, pdt = fdtype, tdt = fdtype;
     if (mode == SYMNMF_MODE_LVS) {
@@ -257,7 +259,7 @@ struct symnmf_ctx {
       a.U = U;
       a.M = side == 0 ? M_H : M_W;
       a.l = l;
-      a.zpart = zpart;
+      a.pstride = k * k + l * k;
       ymode = 2;
     } else if (kind == SYMNMF_DENSE) {
       const GemmPlan p = gemm_plan(n, k, cdtype);
@@ -281,7 +283,7 @@ struct symnmf_ctx {
       ro.Ginv = Gis;
       ro.M = a.M;
       LCHK(fused_update(a, ro, kp, ymode, fdtype, pdt, tdt, nbu, gate_, st));
-      LCHK(update_reduce(gpart, ymode == 2 ? zpart : nullptr, nbu, k, l, kp, alpha, lam, Gd, Ghd, Gid,
+      LCHK(update_reduce(part, nbu, a.pstride, part_l1, k, l, kp, alpha, lam, Gd, Ghd, Gid,
                          side == 0 ? M_W : M_H, gate_, st));
     } else {
       throw Fail{SYMNMF_E_UNSUPPORTED, "BPP rule not available yet"};
@@ -561,7 +563,9 @@ int symnmf_create(symnmf_ctx** out, const symnmf_matrix* X, int32_t k, double al
     c->Gh_S = dalloc<double>((size_t)c->kp * c->kp);
     c->d_scal = dalloc<double>(16);
     c->nbu = update_blocks(n, c->fdtype);
-    c->gpart = dalloc<double>((size_t)c->nbu * k * k);
+    c->pcap = (size_t)k * k;
+    c->part = dalloc<double>((size_t)c->nbu * c->pcap);
+    c->part_l1 = dalloc<double>((size_t)ceil_div(c->nbu, 32) * c->pcap);
     c->dpart = dalloc<double>(c->nbu);
     c->Gi_W = dalloc<double>(c->kp);
     c->Gi_H = dalloc<double>(c->kp);
@@ -684,10 +688,18 @@ int symnmf_lai(symnmf_ctx* c, int32_t l, int32_t q) {
       c->Rl = dalloc<double>((size_t)l * l);
       c->Rlinv = dalloc<double>((size_t)l * l);
       c->Z = dalloc<double>((size_t)l * c->k);
-      dfree(c->zpart);
       dfree(c->M_W);
       dfree(c->M_H);
-      c->zpart = dalloc<double>((size_t)c->nbu * l * c->k);
+      const size_t need = (size_t)c->k * c->k + (size_t)l * c->k;
+      if (need > c->pcap) {
+        dfree(c->part);
+        dfree(c->part_l1);
+        c->part = nullptr;
+        c->part_l1 = nullptr;
+        c->pcap = need;
+        c->part = dalloc<double>((size_t)c->nbu * c->pcap);
+        c->part_l1 = dalloc<double>((size_t)ceil_div(c->nbu, 32) * c->pcap);
+      }
       c->M_W = dalloc<double>((size_t)l * c->kp);
       c->M_H = dalloc<double>((size_t)l * c->kp);
       HIPCHK(hipMemsetAsync(c->M_W, 0, sizeof(double) * l * c->kp, c->st));
