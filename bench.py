@@ -12,8 +12,11 @@ iterations).  `value` is seconds per solve of the plain method; the LAI
 method (Algorithm LAI-SymNMF, l = k + 16, q = 2, followed by refinement on X
 when the LAI alone does not reach r*) is reported beside it.
 
-Also reported: the live roofline of the dominant kernel (the X H product) and
-the FP64 CPU oracle timed on a bounded sample on the host cores.
+Also reported: the live roofline of the dominant kernel (the X H product,
+timed with HIP events on the solve stream inside the timed solves), the
+per-phase device time, and the FP64 CPU oracle timed on a bounded sample on
+the host cores.  `--pmc-probe` runs the short fixed workload the rocprofv3
+counter passes are taken on.
 """
 import argparse
 import json
@@ -41,12 +44,17 @@ def main():
     ap.add_argument("--dim", type=int, default=64)
     ap.add_argument("--comps", type=int, default=32)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--roofline-launches", type=int, default=20)
+    ap.add_argument("--pmc-probe", action="store_true",
+                    help="run the short counter-collection workload and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(run with --gpus 1)", file=sys.stderr)
         sys.exit(2)
+
+    if args.pmc_probe:
+        pmc_probe(args)
+        return
 
     import numpy as np
     import torch
@@ -74,14 +82,14 @@ def main():
     log(f"[bench] plain converged: {iters_conv} iterations, residual {r_conv:.6f}; r* = {r_star:.6f}")
 
     def solve_plain(seed):
-        o = P.symnmf_default_options(stop_mode=P.STOP_TARGET, target=r_star, check_every=4)
+        o = P.symnmf_default_options(stop_mode=P.STOP_TARGET, target=r_star, check_every=4, timing=1)
         c = P.symnmf_create(X, k, 0.0, 0, seed, o)
         it = P.symnmf_iterate(c, 4000)
         return c, it
 
     def solve_lai(seed):
         # LAI phase until its own residual stalls, then refinement on X.
-        o = P.symnmf_default_options(stop_mode=P.STOP_STALL, check_every=8)
+        o = P.symnmf_default_options(stop_mode=P.STOP_STALL, check_every=8, timing=1)
         c = P.symnmf_create(X, k, 0.0, 0, seed, o)
         P.symnmf_lai(c, l, q)
         it = P.symnmf_iterate(c, 2000)
@@ -107,6 +115,7 @@ def main():
     torch.cuda.synchronize()
     t_plain = (time.perf_counter() - t0) / args.steps
     plain_res = [P.symnmf_residual(c, P.RESID_EXACT)[0] for c in ctxs]
+    plain_phases = phase_totals(P, ctxs)
     del ctxs
 
     # timed: LAI + refinement
@@ -121,29 +130,21 @@ def main():
     torch.cuda.synchronize()
     t_lai = (time.perf_counter() - t0) / args.steps
     lai_res = [P.symnmf_residual(c, P.RESID_EXACT)[0] for c in ctxs]
+    lai_phases = phase_totals(P, ctxs)
     del ctxs
     log(f"[bench] plain {t_plain * 1e3:.2f} ms/solve iters {plain_iters} res {plain_res}")
     log(f"[bench] lai   {t_lai * 1e3:.2f} ms/solve iters {lai_iters} (refine {lai_refine}) res {lai_res}")
 
-    # Live roofline of the dominant kernel: the X H product (one GEMM launch
-    # plus its split-K reduction per call), timed with events on the stream
-    # the library launches on.
-    c = P.symnmf_create(X, k, 0.0, 0, 1)
-    Hd = torch.rand((n, k), dtype=torch.float32, device="cuda")
-    Yd = torch.empty_like(Hd)
-    for _ in range(3):
-        P.symnmf_apply_x(c, Hd, Yd)
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    e0.record(stream)
-    for _ in range(args.roofline_launches):
-        P.symnmf_apply_x(c, Hd, Yd)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    t_prod = e0.elapsed_time(e1) / 1e3 / args.roofline_launches
+    # Live roofline of the dominant kernel, the X H product of each
+    # half-iteration (one GEMM launch): its device time comes from the HIP
+    # events the library records around that launch on the solve stream
+    # during the timed plain solves above.
+    ms, calls = plain_phases["product"]
+    t_prod = ms / 1e3 / calls
     alg_bytes = float(n) * n * 4 + 2.0 * n * k * 4
     achieved = alg_bytes / t_prod / 1e9
-    log(f"[bench] X*H product {t_prod * 1e6:.1f} us  -> {achieved:.0f} GB/s algorithmic")
+    log(f"[bench] X*H product {t_prod * 1e6:.1f} us over {calls} launches -> {achieved:.0f} GB/s algorithmic")
+    traffic = stored_traffic(n, k)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -169,12 +170,73 @@ def main():
                    "lai": {"l": l, "q": q, "s_per_solve": t_lai, "iterations": lai_iters,
                            "refine_iterations": lai_refine, "speedup_vs_plain": t_plain / t_lai}},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "k_gemm_mfma<float,float,2,2> + split-K reduce",
-                     "us_per_launch": t_prod * 1e6},
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "kernel": "k_gemm_mfma<float,2,4,true> (X H, one launch per half-iteration)",
+                     "us_per_launch": t_prod * 1e6, "launches": calls,
+                     "algorithmic_bytes_per_launch": alg_bytes},
+        "phases_ms_per_solve": {"plain": {kk: v[0] / args.steps for kk, v in plain_phases.items()},
+                                "lai": {kk: v[0] / args.steps for kk, v in lai_phases.items()}},
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
+
+
+def phase_totals(P, ctxs):
+    """Summed (ms, launches) per phase over the contexts of a timed loop."""
+    names = {P.PHASE_PRODUCT: "product", P.PHASE_UPDATE: "update", P.PHASE_SAMPLE: "sample", P.PHASE_LAI: "lai"}
+    tot = {v: [0.0, 0] for v in names.values()}
+    for c in ctxs:
+        st = P.symnmf_get_stats(c)
+        for ph, name in names.items():
+            tot[name][0] += st.phase_ms[ph]
+            tot[name][1] += st.phase_calls[ph]
+    return tot
+
+
+def stored_traffic(n, k):
+    """HBM bytes per launch of the product kernel from the committed
+    rocprofv3 counter summary, or None when that summary is missing, was
+    taken at another size, or the kernel source changed since."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "k_gemm_mfma_f32_gk16384_k32_pmc.txt")
+    src = os.path.join(ROOT, "paper_2402_08134_amd", "csrc", "k_dense.hip")
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    for line in open(path):
+        if ":" in line and not line.startswith(" "):
+            key, _, val = line.partition(":")
+            kv[key.strip()] = val.strip()
+    digest = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    if kv.get("k_dense.hip sha256") != digest or kv.get("n") != str(n) or kv.get("k") != str(k):
+        return None
+    try:
+        return float(kv["hbm bytes per launch (scaled)"])
+    except (KeyError, ValueError):
+        return None
+
+
+def pmc_probe(args):
+    """Short fixed workload for the rocprofv3 counter passes: a 1 GiB device
+    copy (the calibration kernel of known traffic), then ten plain
+    iterations at the bench size."""
+    import numpy as np
+    import torch
+    import paper_2402_08134_amd as P
+    import workloads
+    Xh, _ = workloads.gaussian_kernel(args.n, args.dim, args.comps, seed=0, dtype=np.float32)
+    X = torch.from_numpy(Xh).cuda()
+    a = torch.empty(1 << 28, dtype=torch.float32, device="cuda").fill_(1.0)
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    log("[pmc-probe] copies done (3 x 1 GiB read + 1 GiB write)")
+    c = P.symnmf_create(X, args.k, 0.0, 0, 1)
+    P.symnmf_iterate(c, 10)
+    torch.cuda.synchronize()
+    log("[pmc-probe] 10 plain iterations done")
 
 
 def cpu_baseline(Xh, k, iters_gpu):

@@ -79,6 +79,17 @@ extern "C" {
 #define SYMNMF_MODE_LAI 1
 #define SYMNMF_MODE_LVS 2
 
+/* phases of symnmf_stats.phase_ms (options.timing = 1):
+ *   PRODUCT: the X-product kernel of each half-iteration (dense GEMM or CSR
+ *            SpMM; one launch each), and the residual products of LvS
+ *   UPDATE:  the fused NLS update and its partial-sum reduction
+ *   SAMPLE:  LvS leverage scores, sampler and sampled operands
+ *   LAI:     the whole randomized range finder and Apx-EVD (symnmf_lai) */
+#define SYMNMF_PHASE_PRODUCT 0
+#define SYMNMF_PHASE_UPDATE 1
+#define SYMNMF_PHASE_SAMPLE 2
+#define SYMNMF_PHASE_LAI 3
+
 /* stats flags */
 #define SYMNMF_FLAG_LEV_SHIFT 1    /* chol(H^T H) needed a diagonal shift   */
 #define SYMNMF_FLAG_CHOLQR_SHIFT 2 /* CholeskyQR2 needed a diagonal shift   */
@@ -119,7 +130,11 @@ typedef struct symnmf_options {
                              iterations (needs a full product); default 1   */
   int32_t max_history;    /* capacity of the per-iteration residual log
                              (default 4096)                                 */
-  int32_t reserved[6];
+  int32_t timing;         /* 1: bracket the kernels of each phase with HIP
+                             events on the stream and accumulate their
+                             durations into symnmf_stats.phase_ms (default 0;
+                             adds two event records per timed launch)       */
+  int32_t reserved[5];
 } symnmf_options;
 
 typedef struct symnmf_stats {
@@ -140,6 +155,9 @@ typedef struct symnmf_stats {
   double theta_over_k;    /* LvS: deterministic leverage mass / k           */
   int32_t flags;          /* SYMNMF_FLAG_* */
   int32_t reserved[7];
+  double phase_ms[4];     /* with options.timing: summed device time of the
+                             timed launches per SYMNMF_PHASE_*              */
+  int64_t phase_calls[4]; /* number of timed launches per phase            */
 } symnmf_stats;
 
 typedef struct symnmf_ctx symnmf_ctx;

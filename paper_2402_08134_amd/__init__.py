@@ -20,6 +20,7 @@ STOP_NONE, STOP_STALL, STOP_TARGET = 0, 1, 2
 RESID_FAST, RESID_EXACT, RESID_LAI = 0, 1, 2
 W, H = 0, 1
 MODE_PLAIN, MODE_LAI, MODE_LVS = 0, 1, 2
+PHASE_PRODUCT, PHASE_UPDATE, PHASE_SAMPLE, PHASE_LAI = 0, 1, 2, 3
 
 
 class SymNMFError(RuntimeError):
@@ -39,7 +40,7 @@ class Options(ctypes.Structure):
                 ("stop_mode", ctypes.c_int32), ("stop_tol", ctypes.c_double), ("stop_patience", ctypes.c_int32),
                 ("check_every", ctypes.c_int32), ("target", ctypes.c_double), ("tau", ctypes.c_double),
                 ("resid_every", ctypes.c_int32), ("max_history", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 6)]
+                ("timing", ctypes.c_int32), ("reserved", ctypes.c_int32 * 5)]
 
 
 class Stats(ctypes.Structure):
@@ -48,7 +49,8 @@ class Stats(ctypes.Structure):
                 ("alpha", ctypes.c_double), ("zeta", ctypes.c_double), ("normsq", ctypes.c_double),
                 ("maxval", ctypes.c_double), ("last_residual", ctypes.c_double), ("s_D", ctypes.c_int64),
                 ("sample_rows", ctypes.c_int64), ("theta_over_k", ctypes.c_double), ("flags", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 7)]
+                ("reserved", ctypes.c_int32 * 7), ("phase_ms", ctypes.c_double * 4),
+                ("phase_calls", ctypes.c_int64 * 4)]
 
 
 _VP = ctypes.c_void_p

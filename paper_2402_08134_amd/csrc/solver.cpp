@@ -126,6 +126,16 @@ struct symnmf_ctx {
   double *R = nullptr, *Rinv = nullptr;
   std::vector<int> host_rp;
   std::string err;
+  // phase timing (options.timing): event pairs recorded on the stream,
+  // harvested into phase_ms when the pool fills or the stats are read
+  struct TimedPair {
+    hipEvent_t a, b;
+    int phase;
+  };
+  std::vector<hipEvent_t> ev_free;
+  std::vector<TimedPair> ev_pending;
+  double phase_ms[4] = {0, 0, 0, 0};
+  int64_t phase_calls[4] = {0, 0, 0, 0};
 
   ~symnmf_ctx() {
     if (st) (void)hipStreamSynchronize(st);
@@ -135,7 +145,67 @@ struct symnmf_ctx {
                     sb.info, sb.theta, rows, weights, seg_cnt, seg_ptr, seg_src, seg_val, lev, R, Rinv};
     for (void* p : ptrs) dfree(p);
     if (hbuf) (void)hipHostFree(hbuf);
+    for (auto& t : ev_pending) {
+      (void)hipEventDestroy(t.a);
+      (void)hipEventDestroy(t.b);
+    }
+    for (hipEvent_t e : ev_free) (void)hipEventDestroy(e);
   }
+
+  hipEvent_t take_event() {
+    if (!ev_free.empty()) {
+      hipEvent_t e = ev_free.back();
+      ev_free.pop_back();
+      return e;
+    }
+    hipEvent_t e;
+    HIPCHK(hipEventCreate(&e));
+    return e;
+  }
+
+  // Wait for every pending pair and add its duration to its phase.
+  void harvest_timers() {
+    for (auto& t : ev_pending) {
+      float ms = 0.f;
+      HIPCHK(hipEventSynchronize(t.b));
+      HIPCHK(hipEventElapsedTime(&ms, t.a, t.b));
+      phase_ms[t.phase] += ms;
+      phase_calls[t.phase] += 1;
+      ev_free.push_back(t.a);
+      ev_free.push_back(t.b);
+    }
+    ev_pending.clear();
+  }
+
+  // Brackets the launches of its scope with an event pair when timing is on.
+  struct Timed {
+    symnmf_ctx* c;
+    hipEvent_t a = nullptr;
+    int phase;
+    Timed(symnmf_ctx* cc, int ph) : c(cc), phase(ph) {
+      if (!c->opt.timing) return;
+      if (c->ev_pending.size() >= 4096) c->harvest_timers();
+      a = c->take_event();
+      HIPCHK(hipEventRecord(a, c->st));
+    }
+    ~Timed() {
+      if (!a) return;
+      hipEvent_t b = nullptr;
+      try {
+        b = c->take_event();
+      } catch (...) {
+        c->ev_free.push_back(a);
+        return;
+      }
+      if (hipEventRecord(b, c->st) != hipSuccess) {
+        (void)hipGetLastError();
+        c->ev_free.push_back(a);
+        c->ev_free.push_back(b);
+        return;
+      }
+      c->ev_pending.push_back({a, b, phase});
+    }
+  };
 
   size_t fsize() const { return dtype_size(fdtype); }
   int64_t nk() const { return (int64_t)n * k; }
@@ -238,6 +308,7 @@ struct symnmf_ctx {
     a.dpart = want_dot ? dpart : nullptr;
     int ymode = 0, pdt = fdtype, tdt = fdtype;
     if (mode == SYMNMF_MODE_LVS) {
+      Timed tm(this, SYMNMF_PHASE_SAMPLE);
       ws.reset();
       LCHK(chol_inverse(Gs, k, R, Rinv, &dstate->flags, SYMNMF_FLAG_LEV_SHIFT, d_fail, st));
       LCHK(leverage_scores(Src, fdtype, n, k, Rinv, lev, gate_, st));
@@ -263,7 +334,10 @@ struct symnmf_ctx {
       ymode = 2;
     } else if (kind == SYMNMF_DENSE) {
       const GemmPlan p = gemm_plan(n, k, cdtype);
-      LCHK(dense_gemm_bt(Xc, cdtype, ldxc(), side == 0 ? BtH : BtW, n, k, p, P, gate_, st));
+      {
+        Timed tm(this, SYMNMF_PHASE_PRODUCT);
+        LCHK(dense_gemm_bt(Xc, cdtype, ldxc(), side == 0 ? BtH : BtW, n, k, p, P, gate_, st));
+      }
       a.P = P;
       a.splits = p.splits;
       a.cp = p.cp;
@@ -272,12 +346,16 @@ struct symnmf_ctx {
       pdt = cdtype == SYMNMF_F64 ? SYMNMF_F64 : SYMNMF_F32;
       tdt = cdtype;
     } else {
-      LCHK(csr_spmm(rp, ci, Xv, xdtype, n, Src, fdtype, k, Yk, fdtype, gate_, st, kp));
+      {
+        Timed tm(this, SYMNMF_PHASE_PRODUCT);
+        LCHK(csr_spmm(rp, ci, Xv, xdtype, n, Src, fdtype, k, Yk, fdtype, gate_, st, kp));
+      }
       a.P = Yk;
       a.splits = 1;
       a.cp = kp;
     }
     if (opt.rule == SYMNMF_RULE_HALS) {
+      Timed tm(this, SYMNMF_PHASE_UPDATE);
       UpdateRO ro;
       ro.Ghat = a.Ghat;
       ro.Ginv = Gis;
@@ -316,7 +394,10 @@ struct symnmf_ctx {
       half_step(1, 2 * t + 1, false);
       const int every = opt.resid_every > 0 ? opt.resid_every : 1;
       if (((t + 1) % every) == 0) {
-        product(W, fdtype, k, Y);
+        {
+          Timed tm(this, SYMNMF_PHASE_PRODUCT);
+          product(W, fdtype, k, Y);
+        }
         ws.reset();
         double* part = nullptr;
         const int nb = dot_partials(H, Y, fdtype, nk(), ws, &part, gate_, st);
@@ -708,21 +789,24 @@ int symnmf_lai(symnmf_ctx* c, int32_t l, int32_t q) {
     HIPCHK(hipMemsetAsync(c->d_fail, 0, sizeof(int), c->st));
     // Algorithm RRF: Omega Gaussian (Philox), then 2q+1 products each followed
     // by CholeskyQR2 (re-orthonormalising after every product).
-    LCHK(gen_gaussian(c->Q, (int64_t)n * l, c->seed, 0, TAG_OMEGA, c->st));
-    for (int it = 0; it < 2 * q + 1; ++it) {
+    {
+      symnmf_ctx::Timed tm(c, SYMNMF_PHASE_LAI);
+      LCHK(gen_gaussian(c->Q, (int64_t)n * l, c->seed, 0, TAG_OMEGA, c->st));
+      for (int it = 0; it < 2 * q + 1; ++it) {
+        c->product(c->Q, SYMNMF_F64, l, c->YQ);
+        c->cholqr2(c->YQ);
+      }
+      // Algorithm Apx-EVD: T = Q^T (X Q), T = Q_T Lambda Q_T^T, U = Q Q_T.
       c->product(c->Q, SYMNMF_F64, l, c->YQ);
-      c->cholqr2(c->YQ);
+      c->ws.reset();
+      LCHK(gram(c->Q, SYMNMF_F64, l, l, c->YQ, c->fdtype, l, l, n, nullptr, nullptr, nullptr, 0, c->ws, c->Tm,
+                nullptr, 0, 0.0, nullptr, c->st));
+      LCHK(jacobi_evd(c->Tm, l, c->QT, c->lam, c->st));
+      LCHK(rowmat(c->Q, SYMNMF_F64, l, n, l, c->QT, nullptr, l, c->U, SYMNMF_F64, l, nullptr, c->st));
+      c->ws.reset();
+      LCHK(column_sign_fix(c->U, n, l, c->ws, c->st));
+      frob_dot(c->lam, c->lam, l, c->d_scal + 8, c->st);
     }
-    // Algorithm Apx-EVD: T = Q^T (X Q), T = Q_T Lambda Q_T^T, U = Q Q_T.
-    c->product(c->Q, SYMNMF_F64, l, c->YQ);
-    c->ws.reset();
-    LCHK(gram(c->Q, SYMNMF_F64, l, l, c->YQ, c->fdtype, l, l, n, nullptr, nullptr, nullptr, 0, c->ws, c->Tm, nullptr,
-              0, 0.0, nullptr, c->st));
-    LCHK(jacobi_evd(c->Tm, l, c->QT, c->lam, c->st));
-    LCHK(rowmat(c->Q, SYMNMF_F64, l, n, l, c->QT, nullptr, l, c->U, SYMNMF_F64, l, nullptr, c->st));
-    c->ws.reset();
-    LCHK(column_sign_fix(c->U, n, l, c->ws, c->st));
-    frob_dot(c->lam, c->lam, l, c->d_scal + 8, c->st);
     HIPCHK(hipMemcpyAsync(c->hbuf, c->d_scal + 8, sizeof(double), hipMemcpyDeviceToHost, c->st));
     HIPCHK(hipMemcpyAsync(c->hbuf + 1, c->d_fail, sizeof(int), hipMemcpyDeviceToHost, c->st));
     c->sync();
@@ -893,6 +977,11 @@ int symnmf_get_stats(symnmf_ctx* c, symnmf_stats* out) {
     out->maxval = c->maxval;
     out->last_residual = d.last;
     out->flags = d.flags;
+    c->harvest_timers();
+    for (int p = 0; p < 4; ++p) {
+      out->phase_ms[p] = c->phase_ms[p];
+      out->phase_calls[p] = c->phase_calls[p];
+    }
     if (c->sb.info) {
       HIPCHK(hipMemcpyAsync(c->hbuf, c->sb.info, 4 * sizeof(int), hipMemcpyDeviceToHost, c->st));
       HIPCHK(hipMemcpyAsync(c->hbuf + 2, c->sb.theta, sizeof(double), hipMemcpyDeviceToHost, c->st));

@@ -47,12 +47,32 @@ def test_default_options_match_the_paper():
     assert o.tau < 0  # tau = 1/s (Section 6.2)
 
 
-def test_struct_layouts_match_header():
+def test_struct_layouts_match_header(tmp_path):
+    """Every field offset and struct size of the binding equals what a C
+    compiler makes of include/symnmf.h."""
+    import shutil
+    import subprocess
     import paper_2402_08134_amd as P
-    # field order and sizes mirror the C structs (checked against offsets)
-    assert ctypes.sizeof(P.Matrix) == 56
-    assert P.Options.stop_tol.offset == 16 and P.Options.target.offset == 32
-    assert P.Stats.n.offset == 24 and P.Stats.alpha.offset == 32
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    structs = {"symnmf_matrix": P.Matrix, "symnmf_options": P.Options, "symnmf_stats": P.Stats}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "symnmf.h"', "int main(void) {"]
+    for cname, py in structs.items():
+        lines.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')
+        for fname, _ in py._fields_:
+            lines.append(f'  printf("{cname} {fname} %zu\\n", offsetof({cname}, {fname}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {tuple(l.split()[:2]): int(l.split()[2]) for l in out if l.strip()}
+    for cname, py in structs.items():
+        assert got[(cname, "size")] == ctypes.sizeof(py), cname
+        for fname, _ in py._fields_:
+            assert got[(cname, fname)] == getattr(py, fname).offset, (cname, fname)
 
 
 def test_create_rejects_null_arguments_without_gpu():
