@@ -53,7 +53,9 @@ extern "C" {
 #define SYMNMF_F32 1
 #define SYMNMF_BF16 2
 
-/* update rules */
+/* update rules (the NLS subproblems of eq. ANLS4symNMF, Section 2.1):
+ *   HALS: one sweep of the regularised HALS rule (eq. symhals_update2)
+ *   BPP:  the exact per-row NLS solution by block principal pivoting */
 #define SYMNMF_RULE_HALS 0
 #define SYMNMF_RULE_BPP 1
 
@@ -93,6 +95,9 @@ extern "C" {
 /* stats flags */
 #define SYMNMF_FLAG_LEV_SHIFT 1    /* chol(H^T H) needed a diagonal shift   */
 #define SYMNMF_FLAG_CHOLQR_SHIFT 2 /* CholeskyQR2 needed a diagonal shift   */
+#define SYMNMF_FLAG_BPP_CAP 4      /* a BPP row hit the pivoting cap (5 kp + 10
+                                      exchanges); its last iterate, clamped at
+                                      zero, was kept                         */
 
 /* The data matrix X (symmetric, n x n).  All pointers are device pointers,
  * BORROWED: the caller keeps them alive and unchanged until symnmf_destroy.

@@ -21,6 +21,7 @@ RESID_FAST, RESID_EXACT, RESID_LAI = 0, 1, 2
 W, H = 0, 1
 MODE_PLAIN, MODE_LAI, MODE_LVS = 0, 1, 2
 PHASE_PRODUCT, PHASE_UPDATE, PHASE_SAMPLE, PHASE_LAI = 0, 1, 2, 3
+FLAG_LEV_SHIFT, FLAG_CHOLQR_SHIFT, FLAG_BPP_CAP = 1, 2, 4
 
 
 class SymNMFError(RuntimeError):

@@ -132,27 +132,37 @@ __global__ __launch_bounds__(256) void k_update(UpdateArgs a, const double* __re
         w[c] = q < k ? xd : 0.0;
         y[c] = fma(alpha, sv[c], y[c]);   // HALS target y + alpha src
       }
-      // Regularised HALS sweep over the KP columns in order.  Padded columns
-      // have Ghat = identity, zero target and zero start, so they stay zero.
+      if (a.rule == 1) {
 #pragma unroll
-      for (int i = 0; i < KP; ++i) {
-        double part = 0.0;
+        for (int c = 0; c < CPL; ++c) a.Yhat[(int64_t)row * KP + g + 16 * c] = y[c];
+      } else if (a.rule == 2) {
 #pragma unroll
-        for (int c = 0; c < CPL; ++c) part = fma(w[c], gs[i * KP + g + 16 * c], part);
-        part = row16_sum(part);
-        const int ci = i >> 4;
-        const double cand = fmax(0.0, fma(y[ci] - part, gi[i], w[ci]));
-        w[ci] = (g == (i & 15)) ? cand : w[ci];
+        for (int c = 0; c < CPL; ++c) w[c] = a.Yhat[(int64_t)row * KP + g + 16 * c];
+      } else {
+        // Regularised HALS sweep over the KP columns in order.  Padded columns
+        // have Ghat = identity, zero target and zero start, so they stay zero.
+#pragma unroll
+        for (int i = 0; i < KP; ++i) {
+          double part = 0.0;
+#pragma unroll
+          for (int c = 0; c < CPL; ++c) part = fma(w[c], gs[i * KP + g + 16 * c], part);
+          part = row16_sum(part);
+          const int ci = i >> 4;
+          const double cand = fmax(0.0, fma(y[ci] - part, gi[i], w[ci]));
+          w[ci] = (g == (i & 15)) ? cand : w[ci];
+        }
       }
+      if (a.rule != 1) {
 #pragma unroll
-      for (int c = 0; c < CPL; ++c) {
-        const int q = g + 16 * c;
-        const TF wt = (TF)w[c];
-        dot = fma((double)wt, fma(-alpha, sv[c], y[c]), dot);   // product part of the target
-        wl[rs * LW + q] = wt;
-        if (q < k) {
-          Dst[rb + q] = wt;
-          if (a.Dt) ((TT*)a.Dt)[(int64_t)q * a.ldt + row] = (TT)wt;
+        for (int c = 0; c < CPL; ++c) {
+          const int q = g + 16 * c;
+          const TF wt = (TF)w[c];
+          dot = fma((double)wt, fma(-alpha, sv[c], y[c]), dot);   // product part of the target
+          wl[rs * LW + q] = wt;
+          if (q < k) {
+            Dst[rb + q] = wt;
+            if (a.Dt) ((TT*)a.Dt)[(int64_t)q * a.ldt + row] = (TT)wt;
+          }
         }
       }
     } else {
@@ -160,29 +170,33 @@ __global__ __launch_bounds__(256) void k_update(UpdateArgs a, const double* __re
       for (int c = 0; c < CPL; ++c) wl[rs * LW + g + 16 * c] = (TF)0;
     }
     __syncthreads();
-    // block partials of F^T F and (LAI) U^T F over this chunk
+    // block partials of F^T F and (LAI) U^T F over this chunk (none when
+    // only the right-hand side is written)
+    if (a.rule != 1) {
 #pragma unroll
-    for (int r = 0; r < RPB; ++r) {
-      double bv[CPL];
+      for (int r = 0; r < RPB; ++r) {
+        double bv[CPL];
 #pragma unroll
-      for (int j = 0; j < CPL; ++j) bv[j] = (double)wl[r * LW + tx + 16 * j];
+        for (int j = 0; j < CPL; ++j) bv[j] = (double)wl[r * LW + tx + 16 * j];
 #pragma unroll
-      for (int i = 0; i < CPL; ++i) {
-        const double av = (double)wl[r * LW + ty + 16 * i];
+        for (int i = 0; i < CPL; ++i) {
+          const double av = (double)wl[r * LW + ty + 16 * i];
 #pragma unroll
-        for (int j = 0; j < CPL; ++j) gacc[i][j] = fma(av, bv[j], gacc[i][j]);
-      }
-      if (LP > 0) {
+          for (int j = 0; j < CPL; ++j) gacc[i][j] = fma(av, bv[j], gacc[i][j]);
+        }
+        if (LP > 0) {
 #pragma unroll
-        for (int i = 0; i < ZI; ++i) {
-          const double uv = (double)us[r * LU + ty + 16 * i];
+          for (int i = 0; i < ZI; ++i) {
+            const double uv = (double)us[r * LU + ty + 16 * i];
 #pragma unroll
-          for (int j = 0; j < CPL; ++j) zacc[i][j] = fma(uv, bv[j], zacc[i][j]);
+            for (int j = 0; j < CPL; ++j) zacc[i][j] = fma(uv, bv[j], zacc[i][j]);
+          }
         }
       }
     }
     __syncthreads();
   }
+  if (a.rule == 1) return;
   // unified partial row of this block: [F^T F (k x k) | U^T F (l x k)]
   double* gp = a.part + (int64_t)blockIdx.x * a.pstride;
 #pragma unroll

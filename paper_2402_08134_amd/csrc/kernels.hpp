@@ -128,6 +128,11 @@ struct UpdateArgs {
   double* part = nullptr;            // [nb][pstride]: F^T F (k*k) then U^T F (l*k, YMODE 2)
   int pstride = 0;
   double* dpart = nullptr;           // [nb] or nullptr
+  // rule: 0 HALS sweep; 1 only write the regularised right-hand side
+  // y + alpha src of every row to Yhat (n x kp FP64) and stop; 2 take the
+  // new rows from Yhat (an exact NLS solution) instead of the sweep
+  int rule = 0;
+  double* Yhat = nullptr;
 };
 // Read-only small operands of the update, passed as separate restrict-
 // qualified kernel arguments so the compiler reads them with scalar loads.
@@ -149,10 +154,13 @@ int pad_identity(double* Ghat, double* Ginv, int k, int kp, hipStream_t s);
 // M (l x kp, zero padded) = diag(lam) Z, Z l x k.
 int scale_rows(const double* Z, const double* lam, int l, int k, int kp, double* M, hipStream_t s);
 
-// Exact NLS per row by block principal pivoting (inputs as the fused update).
-int bpp_update(int n, int k, int kp, const void* Y, const int* seg_ptr, const int* seg_src, const double* seg_val,
-               const void* Src, void* Dst, int fdtype, const double* Ghat, double alpha, Workspace& ws,
-               const DevState* st, hipStream_t s);
+// Exact NLS per row by block principal pivoting.  Yhat (n x kp FP64): the
+// regularised right-hand side on entry, the solution on exit.  Dst (n x k,
+// fdtype) is the current factor, whose support starts the pivoting.  Ghat:
+// kp x kp FP64, identity in the padding.  Sets flag_bit in *d_flags for a row
+// that hit the pivoting cap (its clamped last iterate is kept).
+int bpp_update(int n, int k, int kp, double* Yhat, const void* Dst, int fdtype, const double* Ghat, int* d_flags,
+               int flag_bit, const DevState* st, hipStream_t s);
 
 // out (n x c, odtype, ld ldo) = A (n x l, adtype, lda) * diag(scale) * M
 // (l x c FP64 row-major; scale may be nullptr).

@@ -92,6 +92,7 @@ struct symnmf_ctx {
   void* BtW = nullptr;  // transposed factor panels for the dense product
   void* BtH = nullptr;
   bool btW_ok = false, btH_ok = false;
+  double* Yhat = nullptr;   // BPP: right-hand sides, then solutions (n x kp FP64)
   double* part = nullptr;   // fused-update block partials (nbu x pcap)
   double* part_l1 = nullptr;
   size_t pcap = 0;          // doubles per partial row
@@ -140,7 +141,7 @@ struct symnmf_ctx {
   ~symnmf_ctx() {
     if (st) (void)hipStreamSynchronize(st);
     else (void)hipDeviceSynchronize();
-    void* ptrs[] = {Xb_owned, W, H, Y, Yk, P, Bt, BtW, BtH, part, part_l1, dpart, M_W, M_H, Gi_W, Gi_H, Gi_S, G_W, G_H, Gh_W, Gh_H, Gh_S, d_scal, rowsum, dstate, hist, d_fail,
+    void* ptrs[] = {Xb_owned, W, H, Y, Yk, Yhat, P, Bt, BtW, BtH, part, part_l1, dpart, M_W, M_H, Gi_W, Gi_H, Gi_S, G_W, G_H, Gh_W, Gh_H, Gh_S, d_scal, rowsum, dstate, hist, d_fail,
                     ws.base, Q, Q1, U, YQ, Tm, QT, Vw, lam, Rl, Rlinv, Z, sb.w, sb.prefix, sb.counts, sb.flags,
                     sb.info, sb.theta, rows, weights, seg_cnt, seg_ptr, seg_src, seg_val, lev, R, Rinv};
     for (void* p : ptrs) dfree(p);
@@ -364,7 +365,22 @@ struct symnmf_ctx {
       LCHK(update_reduce(part, nbu, a.pstride, part_l1, k, l, kp, alpha, lam, Gd, Ghd, Gid,
                          side == 0 ? M_W : M_H, gate_, st));
     } else {
-      throw Fail{SYMNMF_E_UNSUPPORTED, "BPP rule not available yet"};
+      // BPP: the update kernel writes the right-hand sides, the pivoting
+      // kernel solves every row in place, and the update kernel then takes
+      // the solutions through its usual write-back and partials.
+      Timed tm(this, SYMNMF_PHASE_UPDATE);
+      UpdateRO ro;
+      ro.Ghat = a.Ghat;
+      ro.Ginv = Gis;
+      ro.M = a.M;
+      a.Yhat = Yhat;
+      a.rule = 1;
+      LCHK(fused_update(a, ro, kp, ymode, fdtype, pdt, tdt, nbu, gate_, st));
+      LCHK(bpp_update(n, k, kp, Yhat, Dst, fdtype, a.Ghat, &dstate->flags, SYMNMF_FLAG_BPP_CAP, gate_, st));
+      a.rule = 2;
+      LCHK(fused_update(a, ro, kp, ymode, fdtype, pdt, tdt, nbu, gate_, st));
+      LCHK(update_reduce(part, nbu, a.pstride, part_l1, k, l, kp, alpha, lam, Gd, Ghd, Gid,
+                         side == 0 ? M_W : M_H, gate_, st));
     }
     invalidate(dst_id);
     if (ymode == 0 && a.Dt) {
@@ -600,7 +616,6 @@ int symnmf_create(symnmf_ctx** out, const symnmf_matrix* X, int32_t k, double al
     } else {
       throw Fail{SYMNMF_E_INVALID, "matrix kind"};
     }
-    if (c->opt.rule == SYMNMF_RULE_BPP) throw Fail{SYMNMF_E_UNSUPPORTED, "BPP rule not available yet"};
 
     const int n = c->n;
     // workspace: the largest temporaries of any launcher
@@ -637,6 +652,7 @@ int symnmf_create(symnmf_ctx** out, const symnmf_matrix* X, int32_t k, double al
       HIPCHK(hipMemsetAsync(c->BtW, 0, gemm_bt_bytes(n, k), c->st));
       HIPCHK(hipMemsetAsync(c->BtH, 0, gemm_bt_bytes(n, k), c->st));
     }
+    if (c->opt.rule == SYMNMF_RULE_BPP) c->Yhat = dalloc<double>((size_t)n * c->kp);
     c->G_W = dalloc<double>((size_t)k * k);
     c->G_H = dalloc<double>((size_t)k * k);
     c->Gh_W = dalloc<double>((size_t)c->kp * c->kp);
