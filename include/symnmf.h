@@ -86,11 +86,14 @@ extern "C" {
  *            SpMM; one launch each), and the residual products of LvS
  *   UPDATE:  the fused NLS update and its partial-sum reduction
  *   SAMPLE:  LvS leverage scores, sampler and sampled operands
- *   LAI:     the whole randomized range finder and Apx-EVD (symnmf_lai) */
+ *   LAI:     the whole randomized range finder and Apx-EVD (symnmf_lai)
+ *   WARM:    the learned warm start (symnmf_warmstart) */
 #define SYMNMF_PHASE_PRODUCT 0
 #define SYMNMF_PHASE_UPDATE 1
 #define SYMNMF_PHASE_SAMPLE 2
 #define SYMNMF_PHASE_LAI 3
+#define SYMNMF_PHASE_WARM 4   /* symnmf_warmstart: features, network, scale fit */
+#define SYMNMF_NUM_PHASES 5
 
 /* stats flags */
 #define SYMNMF_FLAG_LEV_SHIFT 1    /* chol(H^T H) needed a diagonal shift   */
@@ -160,9 +163,9 @@ typedef struct symnmf_stats {
   double theta_over_k;    /* LvS: deterministic leverage mass / k           */
   int32_t flags;          /* SYMNMF_FLAG_* */
   int32_t reserved[7];
-  double phase_ms[4];     /* with options.timing: summed device time of the
-                             timed launches per SYMNMF_PHASE_*              */
-  int64_t phase_calls[4]; /* number of timed launches per phase            */
+  double phase_ms[SYMNMF_NUM_PHASES];     /* with options.timing: summed
+                             device time of the timed launches per phase    */
+  int64_t phase_calls[SYMNMF_NUM_PHASES]; /* timed launches per phase       */
 } symnmf_stats;
 
 typedef struct symnmf_ctx symnmf_ctx;
@@ -276,6 +279,61 @@ const char* symnmf_last_error(const symnmf_ctx* ctx);
 
 /* Free everything the context owns (never touches X).  NULL is a no-op. */
 void symnmf_destroy(symnmf_ctx* ctx);
+
+/* ---- learned warm start ----------------------------------------------------
+ * Not part of the paper's method: the paper starts from a random H (Section 6,
+ * experimental setup) and mentions SVD-based starts as the alternative.  This
+ * start builds on the LAI basis of Section 3.  For every entry (i, j), j < k,
+ * of H, six features are taken from the embedding (c_j = sqrt(n) U[:, j],
+ * s_j the sign whose part of c_j has the larger norm, a_ij = s_j c_ij, r_i the
+ * norm of row i of c_0..c_{k-1}, m_i = max_j a_ij, d the row sums of X):
+ *   f_ij = [a_ij, r_i, m_i, a_ij - m_i, lam_j / lam_0, log(max(d_i/mean d, 1e-6))]
+ * A network shared by all columns, 6 -> 64 -> 64 -> 64 -> 1 with ReLU and a
+ * softplus output, maps f_ij to Ht[i, j] >= 0; the start is H0 = W0 = beta Ht
+ * with beta^2 = tr(Ht^T X Ht) / ||Ht^T Ht||_F^2 (the least-squares multiple).
+ * Parameters: W1 (6 x 64) b1 (64) W2 (64 x 64) b2 W3 (64 x 64) b3 W4 (64 x 1)
+ * b4 (1), each W row-major (in x out), FP32, contiguous in that order. */
+#define SYMNMF_MLP_FEATURES 6
+#define SYMNMF_MLP_HIDDEN 64
+
+typedef struct symnmf_mlp symnmf_mlp;
+
+/* New network of the given hidden width (only SYMNMF_MLP_HIDDEN), weights
+ * W = (2u - 1) sqrt(6 / fan_in) with u the Philox uniforms of stream
+ * (seed, sub = layer index 0..3, tag 6) in row-major order, biases 0.  Its
+ * kernels run on hip_stream (NULL: the default stream).  Synchronises. */
+int symnmf_mlp_create(symnmf_mlp** out, int32_t hidden, uint64_t seed, void* hip_stream);
+int symnmf_mlp_num_params(const symnmf_mlp* net, int64_t* count);
+/* Copy all parameters from / to caller-owned DEVICE memory (FP32, layout
+ * above).  set_params also clears the Adam state. */
+int symnmf_mlp_set_params(symnmf_mlp* net, const float* params);
+int symnmf_mlp_get_params(symnmf_mlp* net, float* params);
+/* Y[e] = network(F[e]) for rows x 6 feature rows (device FP32, row-major);
+ * rows == 0 is a no-op. */
+int symnmf_mlp_forward(symnmf_mlp* net, const float* F, int64_t rows, float* Y);
+/* Gradient of L = 1/(2 rows) sum_e (Y[e] - T[e])^2 with respect to every
+ * parameter, into grad (device FP32, parameter layout).  *loss (host, may be
+ * NULL; when given, the call synchronises) receives L. */
+int symnmf_mlp_gradient(symnmf_mlp* net, const float* F, const float* T, int64_t rows, float* grad, double* loss);
+/* One Adam step (b1 0.9, b2 0.999, eps 1e-8, bias-corrected, step count kept
+ * by the network) on the gradient of L for this batch; *loss as above (the
+ * loss before the step). */
+int symnmf_mlp_train_step(symnmf_mlp* net, const float* F, const float* T, int64_t rows, double lr, double* loss);
+const char* symnmf_mlp_last_error(const symnmf_mlp* net);
+void symnmf_mlp_destroy(symnmf_mlp* net);
+
+/* The (n k) x 6 feature rows f_ij (row-major over (i, j), FP32) of the
+ * context's LAI basis into caller-owned device memory.  Needs symnmf_lai
+ * (E_STATE otherwise). */
+int symnmf_warm_features(symnmf_ctx* ctx, float* F);
+/* Replace W and H by the learned start beta Ht.  Needs symnmf_lai (E_STATE
+ * otherwise); the context stays in its mode (LAI: iterate on U Lambda U^T, or
+ * symnmf_refine to continue on X).  When the fit is not positive, or lam_0 <= 0,
+ * the random start is kept and beta = 0.  *beta_out (host, may be NULL;
+ * when given, the call synchronises).  The network's stream must have
+ * finished updating its parameters.  Allocates temporaries of (n k)(6 + 1)
+ * floats plus n k factor elements for the duration of the call. */
+int symnmf_warmstart(symnmf_ctx* ctx, const symnmf_mlp* net, double* beta_out);
 
 #ifdef __cplusplus
 }

@@ -20,7 +20,9 @@ STOP_NONE, STOP_STALL, STOP_TARGET = 0, 1, 2
 RESID_FAST, RESID_EXACT, RESID_LAI = 0, 1, 2
 W, H = 0, 1
 MODE_PLAIN, MODE_LAI, MODE_LVS = 0, 1, 2
-PHASE_PRODUCT, PHASE_UPDATE, PHASE_SAMPLE, PHASE_LAI = 0, 1, 2, 3
+PHASE_PRODUCT, PHASE_UPDATE, PHASE_SAMPLE, PHASE_LAI, PHASE_WARM = 0, 1, 2, 3, 4
+NUM_PHASES = 5
+MLP_FEATURES, MLP_HIDDEN = 6, 64
 FLAG_LEV_SHIFT, FLAG_CHOLQR_SHIFT, FLAG_BPP_CAP = 1, 2, 4
 
 
@@ -50,8 +52,8 @@ class Stats(ctypes.Structure):
                 ("alpha", ctypes.c_double), ("zeta", ctypes.c_double), ("normsq", ctypes.c_double),
                 ("maxval", ctypes.c_double), ("last_residual", ctypes.c_double), ("s_D", ctypes.c_int64),
                 ("sample_rows", ctypes.c_int64), ("theta_over_k", ctypes.c_double), ("flags", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 7), ("phase_ms", ctypes.c_double * 4),
-                ("phase_calls", ctypes.c_int64 * 4)]
+                ("reserved", ctypes.c_int32 * 7), ("phase_ms", ctypes.c_double * 5),
+                ("phase_calls", ctypes.c_int64 * 5)]
 
 
 _VP = ctypes.c_void_p
@@ -76,6 +78,18 @@ _SIGS = {
     "symnmf_get_stats": (ctypes.c_int, [_VP, ctypes.POINTER(Stats)]),
     "symnmf_last_error": (ctypes.c_char_p, [_VP]),
     "symnmf_destroy": (None, [_VP]),
+    "symnmf_mlp_create": (ctypes.c_int, [ctypes.POINTER(_VP), ctypes.c_int32, ctypes.c_uint64, _VP]),
+    "symnmf_mlp_num_params": (ctypes.c_int, [_VP, ctypes.POINTER(ctypes.c_int64)]),
+    "symnmf_mlp_set_params": (ctypes.c_int, [_VP, _VP]),
+    "symnmf_mlp_get_params": (ctypes.c_int, [_VP, _VP]),
+    "symnmf_mlp_forward": (ctypes.c_int, [_VP, _VP, ctypes.c_int64, _VP]),
+    "symnmf_mlp_gradient": (ctypes.c_int, [_VP, _VP, _VP, ctypes.c_int64, _VP, ctypes.POINTER(ctypes.c_double)]),
+    "symnmf_mlp_train_step": (ctypes.c_int, [_VP, _VP, _VP, ctypes.c_int64, ctypes.c_double,
+                                             ctypes.POINTER(ctypes.c_double)]),
+    "symnmf_mlp_last_error": (ctypes.c_char_p, [_VP]),
+    "symnmf_mlp_destroy": (None, [_VP]),
+    "symnmf_warm_features": (ctypes.c_int, [_VP, _VP]),
+    "symnmf_warmstart": (ctypes.c_int, [_VP, _VP, ctypes.POINTER(ctypes.c_double)]),
 }
 
 _lib = None
@@ -238,3 +252,83 @@ def symnmf_destroy(ctx):
     h, ctx.handle = ctx.handle, None
     if h:
         lib().symnmf_destroy(h)
+
+
+# ---- learned warm start -------------------------------------------------------
+
+class Mlp:
+    """A symnmf_mlp* (the warm-start network)."""
+
+    def __init__(self, handle):
+        self.handle = handle
+
+    def __del__(self):
+        h, self.handle = getattr(self, "handle", None), None
+        if h and _lib is not None:
+            _lib.symnmf_mlp_destroy(h)
+
+
+def _mcheck(rc, net):
+    if rc != OK:
+        msg = lib().symnmf_mlp_last_error(net.handle if net is not None else None)
+        raise SymNMFError(rc, msg.decode() if msg else "")
+
+
+def symnmf_mlp_create(hidden=MLP_HIDDEN, seed=0, stream=None):
+    h = ctypes.c_void_p()
+    _mcheck(lib().symnmf_mlp_create(ctypes.byref(h), int(hidden), int(seed), _stream_ptr(stream)), None)
+    return Mlp(h)
+
+
+def symnmf_mlp_num_params(net):
+    c = ctypes.c_int64()
+    _mcheck(lib().symnmf_mlp_num_params(net.handle, ctypes.byref(c)), net)
+    return c.value
+
+
+def symnmf_mlp_set_params(net, params):
+    assert params.is_contiguous() and params.numel() == symnmf_mlp_num_params(net)
+    _mcheck(lib().symnmf_mlp_set_params(net.handle, params.data_ptr()), net)
+
+
+def symnmf_mlp_get_params(net, out):
+    assert out.is_contiguous() and out.numel() == symnmf_mlp_num_params(net)
+    _mcheck(lib().symnmf_mlp_get_params(net.handle, out.data_ptr()), net)
+
+
+def symnmf_mlp_forward(net, F, Y):
+    assert F.is_contiguous() and Y.is_contiguous() and F.shape[0] == Y.numel() and F.shape[1] == MLP_FEATURES
+    _mcheck(lib().symnmf_mlp_forward(net.handle, F.data_ptr(), int(F.shape[0]), Y.data_ptr()), net)
+
+
+def symnmf_mlp_gradient(net, F, T, grad):
+    assert F.is_contiguous() and T.is_contiguous() and grad.is_contiguous()
+    loss = ctypes.c_double()
+    _mcheck(lib().symnmf_mlp_gradient(net.handle, F.data_ptr(), T.data_ptr(), int(F.shape[0]), grad.data_ptr(),
+                                      ctypes.byref(loss)), net)
+    return loss.value
+
+
+def symnmf_mlp_train_step(net, F, T, lr, want_loss=True):
+    assert F.is_contiguous() and T.is_contiguous() and F.shape[0] == T.numel()
+    loss = ctypes.c_double()
+    _mcheck(lib().symnmf_mlp_train_step(net.handle, F.data_ptr(), T.data_ptr(), int(F.shape[0]), float(lr),
+                                        ctypes.byref(loss) if want_loss else None), net)
+    return loss.value if want_loss else None
+
+
+def symnmf_mlp_destroy(net):
+    h, net.handle = net.handle, None
+    if h:
+        lib().symnmf_mlp_destroy(h)
+
+
+def symnmf_warm_features(ctx, F):
+    assert F.is_contiguous() and F.numel() == ctx.n * ctx.k * MLP_FEATURES
+    _check(lib().symnmf_warm_features(ctx.handle, F.data_ptr()), ctx.handle)
+
+
+def symnmf_warmstart(ctx, net):
+    beta = ctypes.c_double()
+    _check(lib().symnmf_warmstart(ctx.handle, net.handle, ctypes.byref(beta)), ctx.handle)
+    return beta.value

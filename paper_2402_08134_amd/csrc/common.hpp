@@ -30,7 +30,7 @@ __device__ __forceinline__ bool stopped(const DevState* st) { return st != nullp
 // tag); a block's words (w0, w1, w2, w3) give 64-bit values w0|w1<<32 and
 // w2|w3<<32; value e of a stream lives in block e/2.
 // ---------------------------------------------------------------------------
-enum : uint32_t { TAG_H0 = 1, TAG_OMEGA = 2, TAG_SAMPLE = 3 };
+enum : uint32_t { TAG_H0 = 1, TAG_OMEGA = 2, TAG_SAMPLE = 3, TAG_MLP = 6 };
 
 __device__ __forceinline__ void philox_block(uint64_t seed, uint64_t block, uint32_t sub, uint32_t tag,
                                              uint64_t& v0, uint64_t& v1) {

@@ -208,3 +208,32 @@ int hybrid_sample(const double* lev, int n, int k, int64_t s_total, double tau, 
 int sampled_slab(const int* rp, const int* ci, const void* val, int vdtype, int n, const int* rows,
                  const double* weights, const int* d_count, int max_rows, int* seg_cnt, int* seg_ptr, int* seg_src,
                  double* seg_val, int64_t seg_cap, Workspace& ws, const DevState* st, hipStream_t s);
+
+// ---- learned warm start ------------------------------------------------------
+constexpr int MLP_D_IN = 6;     // features per entry of H
+constexpr int MLP_HIDDEN = 64;  // width of the three hidden layers
+// Number of parameters (W1 b1 W2 b2 W3 b3 W4 b4, each W in x out row-major),
+// or -1 for an unsupported width.
+int mlp_param_count(int hidden);
+// Philox initialisation (tag MLP, sub = layer): W = (2u - 1) sqrt(6 / in), b = 0.
+int mlp_init(float* p, uint64_t seed, hipStream_t s);
+// Y[e] = softplus(network(F[e])) for rows x 6 features.
+int mlp_forward(const float* p, const float* F, int64_t rows, float* Y, hipStream_t s);
+// Doubles of scratch mlp_gradient needs for `rows` entries.
+size_t mlp_train_scratch_doubles(int64_t rows);
+// Gradient of 1/(2 rows) sum (y - t)^2 into grad (parameter layout); the loss
+// sum (not halved, not divided) lands in *d_losssum.  h1..h3: rows x HIDDEN;
+// dza, dzb: rows x HIDDEN.
+int mlp_gradient(const float* p, const float* F, const float* T, int64_t rows, float* h1, float* h2, float* h3,
+                 float* dza, float* dzb, float* grad, double* scratch, double* d_losssum, hipStream_t s);
+// One Adam step (b1 0.9, b2 0.999, eps 1e-8) with step count t >= 1.
+int mlp_adam(float* p, const float* g, float* m, float* v, int np, double lr, int64_t t, hipStream_t s);
+// Entry features ((n k) x 6 FP32) from the LAI basis U (n x l FP64), lam, the
+// row sums and their total; info: 2k + 2 doubles (signs, eigenvalue ratios,
+// mean row sum, a flag set when lam_0 <= 0).
+int warm_features(const double* U, int n, int l, int k, const double* lam, const double* rowsum,
+                  const double* d_total, float* F, double* info, Workspace& ws, hipStream_t s);
+// H = W = beta Ht (fdtype) with beta = sqrt(*num / *den) when both are
+// positive and *flag == 0; beta or 0 to *beta_out.
+int warm_apply(const float* Ht, int64_t count, const double* num, const double* den, const double* flag, void* H,
+               void* W, int fdtype, double* beta_out, hipStream_t s);

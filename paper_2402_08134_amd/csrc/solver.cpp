@@ -135,8 +135,8 @@ struct symnmf_ctx {
   };
   std::vector<hipEvent_t> ev_free;
   std::vector<TimedPair> ev_pending;
-  double phase_ms[4] = {0, 0, 0, 0};
-  int64_t phase_calls[4] = {0, 0, 0, 0};
+  double phase_ms[SYMNMF_NUM_PHASES] = {};
+  int64_t phase_calls[SYMNMF_NUM_PHASES] = {};
 
   ~symnmf_ctx() {
     if (st) (void)hipStreamSynchronize(st);
@@ -507,6 +507,46 @@ struct symnmf_ctx {
   }
 };
 
+// A network of the learned warm start: parameters, Adam state and the
+// training buffers (grown to the largest batch seen).
+struct symnmf_mlp {
+  int hidden = MLP_HIDDEN;
+  int np = 0;
+  hipStream_t st = nullptr;
+  float *p = nullptr, *m = nullptr, *v = nullptr, *g = nullptr;
+  int64_t cap = 0;
+  float *h1 = nullptr, *h2 = nullptr, *h3 = nullptr, *dza = nullptr, *dzb = nullptr;
+  double* scratch = nullptr;
+  double* d_loss = nullptr;
+  double* hbuf = nullptr;
+  int64_t t = 0;
+  std::string err;
+
+  ~symnmf_mlp() {
+    if (st) (void)hipStreamSynchronize(st);
+    else (void)hipDeviceSynchronize();
+    void* ptrs[] = {p, m, v, g, h1, h2, h3, dza, dzb, scratch, d_loss};
+    for (void* q : ptrs) dfree(q);
+    if (hbuf) (void)hipHostFree(hbuf);
+  }
+
+  void ensure(int64_t rows) {
+    if (rows <= cap) return;
+    HIPCHK(hipStreamSynchronize(st));
+    float** bufs[] = {&h1, &h2, &h3, &dza, &dzb};
+    for (float** b : bufs) {
+      dfree(*b);
+      *b = nullptr;
+    }
+    dfree(scratch);
+    scratch = nullptr;
+    cap = 0;
+    for (float** b : bufs) *b = dalloc<float>((size_t)rows * hidden);
+    scratch = dalloc<double>(mlp_train_scratch_doubles(rows));
+    cap = rows;
+  }
+};
+
 namespace {
 
 int fail(symnmf_ctx* c, const Fail& f) {
@@ -533,6 +573,35 @@ int guarded(symnmf_ctx* c, Fn&& fn) {
   }
 }
 
+template <typename Fn>
+int mlp_guarded(symnmf_mlp* net, Fn&& fn) {
+  if (!net) return SYMNMF_E_INVALID;
+  try {
+    fn();
+    return SYMNMF_OK;
+  } catch (const Fail& f) {
+    net->err = f.msg;
+    return f.code;
+  } catch (const std::bad_alloc&) {
+    net->err = "host allocation failed";
+    return SYMNMF_E_NOMEM;
+  } catch (...) {
+    net->err = "unexpected internal error";
+    return SYMNMF_E_DEVICE;
+  }
+}
+
+void mlp_grad(symnmf_mlp* net, const float* F, const float* T, int64_t rows, double* loss) {
+  if (rows < 1 || !F || !T) throw Fail{SYMNMF_E_INVALID, "argument"};
+  net->ensure(rows);
+  LCHK(mlp_gradient(net->p, F, T, rows, net->h1, net->h2, net->h3, net->dza, net->dzb, net->g, net->scratch,
+                    net->d_loss, net->st));
+  if (loss) {
+    HIPCHK(hipMemcpyAsync(net->hbuf, net->d_loss, sizeof(double), hipMemcpyDeviceToHost, net->st));
+    HIPCHK(hipStreamSynchronize(net->st));
+    *loss = 0.5 * net->hbuf[0] / (double)rows;
+  }
+}
 }  // namespace
 
 extern "C" {
@@ -994,7 +1063,7 @@ int symnmf_get_stats(symnmf_ctx* c, symnmf_stats* out) {
     out->last_residual = d.last;
     out->flags = d.flags;
     c->harvest_timers();
-    for (int p = 0; p < 4; ++p) {
+    for (int p = 0; p < SYMNMF_NUM_PHASES; ++p) {
       out->phase_ms[p] = c->phase_ms[p];
       out->phase_calls[p] = c->phase_calls[p];
     }
@@ -1008,6 +1077,155 @@ int symnmf_get_stats(symnmf_ctx* c, symnmf_stats* out) {
       out->sample_rows = info[3];
       out->theta_over_k = c->hbuf[2] / c->k;
     }
+  });
+}
+
+// ---- learned warm start ------------------------------------------------------
+
+
+int symnmf_mlp_create(symnmf_mlp** out, int32_t hidden, uint64_t seed, void* hip_stream) {
+  if (!out) return SYMNMF_E_INVALID;
+  *out = nullptr;
+  if (mlp_param_count(hidden) < 0) {
+    g_create_error = "unsupported hidden width";
+    return SYMNMF_E_INVALID;
+  }
+  symnmf_mlp* net = new (std::nothrow) symnmf_mlp();
+  if (!net) return SYMNMF_E_NOMEM;
+  const int rc = mlp_guarded(net, [&] {
+    net->hidden = hidden;
+    net->st = (hipStream_t)hip_stream;
+    net->np = mlp_param_count(hidden);
+    net->p = dalloc<float>(net->np);
+    net->m = dalloc<float>(net->np);
+    net->v = dalloc<float>(net->np);
+    net->g = dalloc<float>(net->np);
+    net->d_loss = dalloc<double>(1);
+    if (hipHostMalloc((void**)&net->hbuf, 8 * sizeof(double), hipHostMallocDefault) != hipSuccess)
+      throw Fail{SYMNMF_E_NOMEM, "pinned allocation failed"};
+    LCHK(mlp_init(net->p, seed, net->st));
+    HIPCHK(hipMemsetAsync(net->m, 0, sizeof(float) * net->np, net->st));
+    HIPCHK(hipMemsetAsync(net->v, 0, sizeof(float) * net->np, net->st));
+    HIPCHK(hipStreamSynchronize(net->st));
+  });
+  if (rc != SYMNMF_OK) {
+    g_create_error = net->err;
+    delete net;
+    return rc;
+  }
+  *out = net;
+  return SYMNMF_OK;
+}
+
+int symnmf_mlp_num_params(const symnmf_mlp* net, int64_t* count) {
+  if (!net || !count) return SYMNMF_E_INVALID;
+  *count = net->np;
+  return SYMNMF_OK;
+}
+
+int symnmf_mlp_set_params(symnmf_mlp* net, const float* src) {
+  return mlp_guarded(net, [&] {
+    if (!src) throw Fail{SYMNMF_E_INVALID, "null parameters"};
+    HIPCHK(hipMemcpyAsync(net->p, src, sizeof(float) * net->np, hipMemcpyDeviceToDevice, net->st));
+    HIPCHK(hipMemsetAsync(net->m, 0, sizeof(float) * net->np, net->st));
+    HIPCHK(hipMemsetAsync(net->v, 0, sizeof(float) * net->np, net->st));
+    net->t = 0;
+  });
+}
+
+int symnmf_mlp_get_params(symnmf_mlp* net, float* dst) {
+  return mlp_guarded(net, [&] {
+    if (!dst) throw Fail{SYMNMF_E_INVALID, "null destination"};
+    HIPCHK(hipMemcpyAsync(dst, net->p, sizeof(float) * net->np, hipMemcpyDeviceToDevice, net->st));
+  });
+}
+
+int symnmf_mlp_forward(symnmf_mlp* net, const float* F, int64_t rows, float* Y) {
+  return mlp_guarded(net, [&] {
+    if (rows < 0 || (rows > 0 && (!F || !Y))) throw Fail{SYMNMF_E_INVALID, "argument"};
+    LCHK(mlp_forward(net->p, F, rows, Y, net->st));
+  });
+}
+
+
+int symnmf_mlp_gradient(symnmf_mlp* net, const float* F, const float* T, int64_t rows, float* grad, double* loss) {
+  return mlp_guarded(net, [&] {
+    if (!grad) throw Fail{SYMNMF_E_INVALID, "null gradient"};
+    mlp_grad(net, F, T, rows, loss);
+    HIPCHK(hipMemcpyAsync(grad, net->g, sizeof(float) * net->np, hipMemcpyDeviceToDevice, net->st));
+  });
+}
+
+int symnmf_mlp_train_step(symnmf_mlp* net, const float* F, const float* T, int64_t rows, double lr, double* loss) {
+  return mlp_guarded(net, [&] {
+    if (!(lr > 0.0)) throw Fail{SYMNMF_E_INVALID, "learning rate"};
+    mlp_grad(net, F, T, rows, loss);
+    net->t += 1;
+    LCHK(mlp_adam(net->p, net->g, net->m, net->v, net->np, lr, net->t, net->st));
+  });
+}
+
+const char* symnmf_mlp_last_error(const symnmf_mlp* net) { return net ? net->err.c_str() : g_create_error.c_str(); }
+
+void symnmf_mlp_destroy(symnmf_mlp* net) { delete net; }
+
+int symnmf_warm_features(symnmf_ctx* c, float* F) {
+  return guarded(c, [&] {
+    if (!F) throw Fail{SYMNMF_E_INVALID, "null output"};
+    if (c->l == 0 || !c->U) throw Fail{SYMNMF_E_STATE, "symnmf_lai has not run"};
+    c->ws.reset();
+    double* info = c->ws.dbl((size_t)2 * c->k + 2);
+    if (!info) throw Fail{SYMNMF_E_NOMEM, "workspace"};
+    LCHK(warm_features(c->U, c->n, c->l, c->k, c->lam, c->rowsum, c->d_scal + 1, F, info, c->ws, c->st));
+  });
+}
+
+int symnmf_warmstart(symnmf_ctx* c, const symnmf_mlp* net, double* beta_out) {
+  return guarded(c, [&] {
+    if (!net) throw Fail{SYMNMF_E_INVALID, "null network"};
+    if (c->l == 0 || !c->U) throw Fail{SYMNMF_E_STATE, "symnmf_lai has not run"};
+    const int n = c->n, k = c->k;
+    const int64_t nk = (int64_t)n * k;
+    symnmf_ctx::Timed tm(c, SYMNMF_PHASE_WARM);
+    float* F = dalloc<float>((size_t)nk * MLP_D_IN);
+    float* Htf = nullptr;
+    void* Ht = nullptr;
+    struct Temps {
+      std::vector<void*> p;
+      symnmf_ctx* c;
+      ~Temps() {
+        (void)hipStreamSynchronize(c->st);
+        for (void* q : p) dfree(q);
+      }
+    } temps{{F}, c};
+    Htf = dalloc<float>(nk);
+    temps.p.push_back(Htf);
+    Ht = dalloc<char>((size_t)nk * c->fsize());
+    temps.p.push_back(Ht);
+    c->ws.reset();
+    double* info = c->ws.dbl((size_t)2 * k + 2);
+    if (!info) throw Fail{SYMNMF_E_NOMEM, "workspace"};
+    LCHK(warm_features(c->U, n, c->l, k, c->lam, c->rowsum, c->d_scal + 1, F, info, c->ws, c->st));
+    LCHK(mlp_forward(net->p, F, nk, Htf, c->st));
+    LCHK(copy_convert(Htf, SYMNMF_F32, Ht, c->fdtype, nk, c->st));
+    // least-squares scale: beta^2 = tr(Ht^T X Ht) / ||Ht^T Ht||_F^2
+    c->product(Ht, c->fdtype, k, c->Y);
+    double* part = nullptr;
+    const int nb = dot_partials(Ht, c->Y, c->fdtype, nk, c->ws, &part, nullptr, c->st);
+    if (nb < 0) throw Fail{SYMNMF_E_DEVICE, "dot launch failed"};
+    sum_partials(part, nb, c->d_scal + 3, c->st);
+    double* ga = c->ws.dbl((size_t)k * k);
+    if (!ga) throw Fail{SYMNMF_E_NOMEM, "workspace"};
+    LCHK(gram(Ht, c->fdtype, k, k, Ht, c->fdtype, k, k, n, nullptr, nullptr, nullptr, 0, c->ws, ga, nullptr, 0, 0.0,
+              nullptr, c->st));
+    frob_dot(ga, ga, k * k, c->d_scal + 4, c->st);
+    LCHK(warm_apply(Htf, nk, c->d_scal + 3, c->d_scal + 4, info + 2 * k + 1, c->H, c->W, c->fdtype, c->d_scal + 5,
+                    c->st));
+    c->refresh_gram(c->W, c->G_W, c->Gh_W, c->Gi_W);
+    c->refresh_gram(c->H, c->G_H, c->Gh_H, c->Gi_H);
+    c->invalidate(SYMNMF_W);
+    c->invalidate(SYMNMF_H);
+    if (beta_out) *beta_out = c->readback(c->d_scal + 5, 1)[0];
   });
 }
 
