@@ -8,16 +8,20 @@ One step = one whole solve from the data resident in HBM: create (scalars
 pass, random init), then regularised HALS iterations until the normalised
 residual reaches r* = r_conv + 1e-3, where r_conv is the residual at which the
 plain random-init method stops under the paper's rule (no drop > 1e-4 for four
-iterations).  `value` is seconds per solve with the learned start (LAI basis
-l = k + 16, q = 2, the trained network of paper_2402_08134_amd/weights, the
-least-squares scale fit, then iterations on X); the plain random-start solve,
-the LAI method (Algorithm LAI-SymNMF followed by refinement on X) and the
-learned start followed by LAI iterations are reported beside it.
+iterations).  Four methods are timed: plain (random start, iterations on X),
+lai (Algorithm LAI-SymNMF from the random start until its own residual
+reaches r* or stalls, then refinement on X until the residual on X is r*), learned (the learned start -- LAI basis
+l = k + 16, q = 2, the trained network of paper_2402_08134_amd/weights and
+the least-squares scale fit -- then iterations on X) and learned_lai (the
+learned start, LAI iterations as in lai, then refinement on X).
+`value` is seconds per solve of learned_lai; every method's time, iteration
+counts, final residual and speed-up over plain are in `config.methods`.
 
-Also reported: the live roofline of the dominant kernel (the X H product,
-timed with HIP events on the solve stream inside the timed solves), the
-per-phase device time, and the FP64 CPU oracle timed on a bounded sample on
-the host cores.  `--pmc-probe` runs the short fixed workload the rocprofv3
+The timed solves replay their iterations from HIP graphs and record no
+events.  A second pass runs each method once more with HIP events around
+every phase's launches (eager launches): it gives the per-phase device time
+and the live roofline of the dominant kernel (the X H product).  Also
+reported: the FP64 CPU oracle timed on a bounded sample on the host cores.  `--pmc-probe` runs the short fixed workload the rocprofv3
 counter passes are taken on.
 """
 import argparse
@@ -71,7 +75,6 @@ def main():
     Xh, _ = workloads.gaussian_kernel(n, args.dim, args.comps, seed=0, dtype=np.float32)
     log(f"[bench] generated X n={n} in {time.time() - t0:.1f}s")
     X = torch.from_numpy(Xh).cuda()
-    stream = torch.cuda.current_stream()
     torch.cuda.synchronize()
 
     # Reference convergence level (untimed): plain random init, paper's rule.
@@ -83,104 +86,69 @@ def main():
     del ctx
     log(f"[bench] plain converged: {iters_conv} iterations, residual {r_conv:.6f}; r* = {r_star:.6f}")
 
-    def solve_plain(seed):
-        o = P.symnmf_default_options(stop_mode=P.STOP_TARGET, target=r_star, check_every=4, timing=1)
-        c = P.symnmf_create(X, k, 0.0, 0, seed, o)
-        it = P.symnmf_iterate(c, 4000)
-        return c, it
+    from paper_2402_08134_amd import warmstart as WSP
+    net = WSP.load(os.path.join(WSP.WEIGHTS_DIR, "warmstart_gk.npz"))
 
-    def solve_learned(seed, lai_first):
-        # learned start: LAI basis, network, scale fit; then (optionally LAI
-        # iterations until their own residual stalls, then) refinement on X
-        o = P.symnmf_default_options(stop_mode=P.STOP_STALL if lai_first else P.STOP_TARGET,
-                                     target=r_star, check_every=4, timing=1)
+    def solve(method, seed, timing):
+        """One solve to r*; returns (context, iterations, iterations on X)."""
+        lai_stage = method in ("lai", "learned_lai")
+        # LAI stage: until its own residual reaches r* or stalls, whichever
+        # comes first; then iterations on X until the residual on X is r*
+        o = P.symnmf_default_options(stop_mode=P.STOP_STALL_OR_TARGET if lai_stage else P.STOP_TARGET,
+                                     target=r_star, check_every=8 if lai_stage else 4, timing=timing)
         c = P.symnmf_create(X, k, 0.0, 0, seed, o)
+        if method == "plain":
+            it = P.symnmf_iterate(c, 4000)
+            return c, it, it
         P.symnmf_lai(c, l, q)
-        beta = P.symnmf_warmstart(c, net)
-        it = P.symnmf_iterate(c, 2000) if lai_first else 0
-        P.symnmf_refine(c, P.STOP_TARGET, r_star)
-        it2 = P.symnmf_iterate(c, 4000)
-        return c, it + it2, it2, beta
-
-    def solve_lai(seed):
-        # LAI phase until its own residual stalls, then refinement on X.
-        o = P.symnmf_default_options(stop_mode=P.STOP_STALL, check_every=8, timing=1)
-        c = P.symnmf_create(X, k, 0.0, 0, seed, o)
-        P.symnmf_lai(c, l, q)
-        it = P.symnmf_iterate(c, 2000)
+        if method in ("learned", "learned_lai"):
+            P.symnmf_warmstart(c, net, want_beta=False)
+        it = P.symnmf_iterate(c, 2000) if lai_stage else 0
         P.symnmf_refine(c, P.STOP_TARGET, r_star)
         it2 = P.symnmf_iterate(c, 4000)
         return c, it + it2, it2
 
-    from paper_2402_08134_amd import warmstart as WSP
-    net = WSP.load(os.path.join(WSP.WEIGHTS_DIR, "warmstart_gk.npz"))
-
+    methods = ["plain", "lai", "learned", "learned_lai"]
     for w in range(args.warmup):
-        solve_plain(100 + w)
-        solve_lai(100 + w)
-        solve_learned(100 + w, False)
-        solve_learned(100 + w, True)
+        for m in methods:
+            solve(m, 100 + w, 0)
     torch.cuda.synchronize()
 
-    # timed: plain
+    # Timed: whole solves, graphs on, no per-launch events.
     seeds = [1 + s for s in range(args.steps)]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    plain_iters = []
-    ctxs = []
-    for sd in seeds:
-        c, it = solve_plain(sd)
-        plain_iters.append(it)
-        ctxs.append(c)
-    torch.cuda.synchronize()
-    t_plain = (time.perf_counter() - t0) / args.steps
-    plain_res = [P.symnmf_residual(c, P.RESID_EXACT)[0] for c in ctxs]
-    plain_phases = phase_totals(P, ctxs)
-    del ctxs
-
-    # timed: LAI + refinement
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    lai_iters, lai_refine, ctxs = [], [], []
-    for sd in seeds:
-        c, it, it2 = solve_lai(sd)
-        lai_iters.append(it)
-        lai_refine.append(it2)
-        ctxs.append(c)
-    torch.cuda.synchronize()
-    t_lai = (time.perf_counter() - t0) / args.steps
-    lai_res = [P.symnmf_residual(c, P.RESID_EXACT)[0] for c in ctxs]
-    lai_phases = phase_totals(P, ctxs)
-    del ctxs
-    learned = {}
-    for lai_first in (False, True):
+    res = {}
+    for m in methods:
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        its, its2, betas, ctxs = [], [], [], []
+        its, its_x, ctxs = [], [], []
         for sd in seeds:
-            c, it, it2, beta = solve_learned(sd, lai_first)
+            c, it, itx = solve(m, sd, 0)
             its.append(it)
-            its2.append(it2)
-            betas.append(beta)
+            its_x.append(itx)
             ctxs.append(c)
         torch.cuda.synchronize()
         t = (time.perf_counter() - t0) / args.steps
-        res = [P.symnmf_residual(c, P.RESID_EXACT)[0] for c in ctxs]
-        ph = phase_totals(P, ctxs)
+        final = [P.symnmf_residual(c, P.RESID_EXACT)[0] for c in ctxs]
+        beta = [P.symnmf_get_stats(c).warm_beta for c in ctxs]
         del ctxs
-        name = "learned_then_lai" if lai_first else "learned"
-        learned[name] = {"s_per_solve": t, "iterations": its, "iterations_on_X": its2, "beta": betas,
-                         "final_residual": res, "speedup_vs_plain": None,
-                         "phases_ms_per_solve": {kk: v[0] / args.steps for kk, v in ph.items()}}
-        log(f"[bench] {name} {t * 1e3:.2f} ms/solve iters {its} (on X {its2}) res {res}")
-    log(f"[bench] plain {t_plain * 1e3:.2f} ms/solve iters {plain_iters} res {plain_res}")
-    log(f"[bench] lai   {t_lai * 1e3:.2f} ms/solve iters {lai_iters} (refine {lai_refine}) res {lai_res}")
+        res[m] = {"s_per_solve": t, "iterations": its, "iterations_on_X": its_x, "final_residual": final}
+        if m.startswith("learned"):
+            res[m]["warm_beta"] = beta
+        log(f"[bench] {m:12s} {t * 1e3:8.2f} ms/solve  iterations {its} (on X {its_x})  final residual "
+            f"{['%.6f' % v for v in final]}")
+    t_plain = res["plain"]["s_per_solve"]
+    for m in methods:
+        res[m]["speedup_vs_plain"] = t_plain / res[m]["s_per_solve"]
 
-    # Live roofline of the dominant kernel, the X H product of each
-    # half-iteration (one GEMM launch): its device time comes from the HIP
-    # events the library records around that launch on the solve stream
-    # during the timed plain solves above.
-    ms, calls = plain_phases["product"]
+    # Phase pass: the same solves once more with HIP events around every
+    # phase's launches (eager launches); the product kernel's average launch
+    # time gives the live roofline of the dominant kernel.
+    phases = {}
+    for m in methods:
+        c, _, _ = solve(m, seeds[0], 1)
+        phases[m] = phase_totals(P, [c])
+        del c
+    ms, calls = phases["plain"]["product"]
     t_prod = ms / 1e3 / calls
     alg_bytes = float(n) * n * 4 + 2.0 * n * k * 4
     achieved = alg_bytes / t_prod / 1e9
@@ -189,41 +157,34 @@ def main():
 
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(Xh, k, int(np.median(plain_iters)))
+        cpu = cpu_baseline(Xh, k, int(np.median(res["plain"]["iterations"])))
 
-    for v in learned.values():
-        v["speedup_vs_plain"] = t_plain / v["s_per_solve"]
-    t_learned = learned["learned"]["s_per_solve"]
+    t_val = res["learned_lai"]["s_per_solve"]
     out = {
         "metric": "SymNMF time-to-residual (s) and X*H GB/s or MFMA %, learned-init vs plain",
-        "value": t_learned,
+        "value": t_val,
         "unit": "s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": t_learned * 1e3,
+        "ms_per_step": t_val * 1e3,
         "higher_is_better": False,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": f"dense Gaussian-kernel similarity n={n} k={k} FP32 "
-                               f"(32-component GMM in R^64), HALS to r*=r_conv+1e-3; value: learned start "
-                               f"(LAI basis l={l}, q={q}, network, scale fit) then iterations on X",
-                   "n": n, "k": k, "r_conv": r_conv, "r_star": r_star,
-                   "plain": {"s_per_solve": t_plain, "iterations": plain_iters, "final_residual": plain_res},
-                   "learned_vs_plain": t_plain / t_learned,
-                   **learned,
-                   "plain_iterations": plain_iters,
-                   "lai": {"l": l, "q": q, "s_per_solve": t_lai, "iterations": lai_iters,
-                           "refine_iterations": lai_refine, "speedup_vs_plain": t_plain / t_lai}},
+        "config": {"workload": f"dense Gaussian-kernel similarity n={n} k={k} FP32 (32-component GMM in R^64), "
+                               f"HALS to r* = r_conv + 1e-3; value: learned start (LAI basis l={l}, q={q}, "
+                               f"trained network, scale fit), LAI iterations, refinement on X",
+                   "n": n, "k": k, "l": l, "q": q, "r_conv": r_conv, "r_star": r_star,
+                   "learned_vs_plain": t_plain / t_val,
+                   "methods": res},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": "k_gemm_mfma<float,2,4,true> (X H, one launch per half-iteration)",
                      "us_per_launch": t_prod * 1e6, "launches": calls,
                      "algorithmic_bytes_per_launch": alg_bytes},
-        "phases_ms_per_solve": {"plain": {kk: v[0] / args.steps for kk, v in plain_phases.items()},
-                                "lai": {kk: v[0] / args.steps for kk, v in lai_phases.items()}},
+        "phases_ms_per_solve": {m: {kk: v[0] for kk, v in ph.items()} for m, ph in phases.items()},
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
@@ -231,7 +192,8 @@ def main():
 
 def phase_totals(P, ctxs):
     """Summed (ms, launches) per phase over the contexts of a timed loop."""
-    names = {P.PHASE_PRODUCT: "product", P.PHASE_UPDATE: "update", P.PHASE_SAMPLE: "sample", P.PHASE_LAI: "lai"}
+    names = {P.PHASE_PRODUCT: "product", P.PHASE_UPDATE: "update", P.PHASE_SAMPLE: "sample", P.PHASE_LAI: "lai",
+             P.PHASE_WARM: "warm"}
     tot = {v: [0.0, 0] for v in names.values()}
     for c in ctxs:
         st = P.symnmf_get_stats(c)

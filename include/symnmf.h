@@ -65,6 +65,7 @@ extern "C" {
                                 stop_tol for stop_patience iterations
                                 (Section 6.1: 1e-4, four iterations)       */
 #define SYMNMF_STOP_TARGET 2 /* normalised residual <= target              */
+#define SYMNMF_STOP_STALL_OR_TARGET 3 /* whichever of the two comes first  */
 
 /* residual modes for symnmf_residual */
 #define SYMNMF_RESID_FAST 0  /* trace identity from the latest products
@@ -142,7 +143,14 @@ typedef struct symnmf_options {
                              events on the stream and accumulate their
                              durations into symnmf_stats.phase_ms (default 0;
                              adds two event records per timed launch)       */
-  int32_t reserved[5];
+  int32_t graphs;         /* 1 (default): once the operands of an iteration
+                             are in place, plain and LAI iterations are
+                             replayed from HIP graphs captured on the
+                             stream (blocks of check_every iterations, or 8
+                             without a stop rule); 0: every kernel is
+                             launched directly.  Not used with timing = 1
+                             or in LvS mode.  Same results either way.     */
+  int32_t reserved[4];
 } symnmf_options;
 
 typedef struct symnmf_stats {
@@ -163,9 +171,12 @@ typedef struct symnmf_stats {
   double theta_over_k;    /* LvS: deterministic leverage mass / k           */
   int32_t flags;          /* SYMNMF_FLAG_* */
   int32_t reserved[7];
+  double warm_beta;       /* scale of the last symnmf_warmstart (0: the
+                             random start was kept, or none ran)           */
   double phase_ms[SYMNMF_NUM_PHASES];     /* with options.timing: summed
                              device time of the timed launches per phase    */
   int64_t phase_calls[SYMNMF_NUM_PHASES]; /* timed launches per phase       */
+  int64_t graph_launches; /* iteration graphs replayed (options.graphs)     */
 } symnmf_stats;
 
 typedef struct symnmf_ctx symnmf_ctx;
@@ -277,8 +288,15 @@ int symnmf_get_stats(symnmf_ctx* ctx, symnmf_stats* out);
  * on the same context. */
 const char* symnmf_last_error(const symnmf_ctx* ctx);
 
-/* Free everything the context owns (never touches X).  NULL is a no-op. */
+/* Free everything the context owns (never touches X).  NULL is a no-op.
+ * Device blocks go back to the library's cache of device memory (per device
+ * and size, up to 16 GiB), from which later contexts and networks of the
+ * same sizes are served without hipMalloc. */
 void symnmf_destroy(symnmf_ctx* ctx);
+
+/* Return every cached device block to the HIP runtime (hipFree).  Call only
+ * when no context or network is being used by another thread. */
+int symnmf_trim_cache(void);
 
 /* ---- learned warm start ----------------------------------------------------
  * Not part of the paper's method: the paper starts from a random H (Section 6,

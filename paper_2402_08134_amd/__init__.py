@@ -16,7 +16,7 @@ OK, E_INVALID, E_UNSUPPORTED, E_NOMEM, E_DEVICE, E_NUMERIC, E_STATE = range(7)
 DENSE, CSR = 0, 1
 F64, F32, BF16 = 0, 1, 2
 RULE_HALS, RULE_BPP = 0, 1
-STOP_NONE, STOP_STALL, STOP_TARGET = 0, 1, 2
+STOP_NONE, STOP_STALL, STOP_TARGET, STOP_STALL_OR_TARGET = 0, 1, 2, 3
 RESID_FAST, RESID_EXACT, RESID_LAI = 0, 1, 2
 W, H = 0, 1
 MODE_PLAIN, MODE_LAI, MODE_LVS = 0, 1, 2
@@ -43,7 +43,7 @@ class Options(ctypes.Structure):
                 ("stop_mode", ctypes.c_int32), ("stop_tol", ctypes.c_double), ("stop_patience", ctypes.c_int32),
                 ("check_every", ctypes.c_int32), ("target", ctypes.c_double), ("tau", ctypes.c_double),
                 ("resid_every", ctypes.c_int32), ("max_history", ctypes.c_int32),
-                ("timing", ctypes.c_int32), ("reserved", ctypes.c_int32 * 5)]
+                ("timing", ctypes.c_int32), ("graphs", ctypes.c_int32), ("reserved", ctypes.c_int32 * 4)]
 
 
 class Stats(ctypes.Structure):
@@ -52,8 +52,8 @@ class Stats(ctypes.Structure):
                 ("alpha", ctypes.c_double), ("zeta", ctypes.c_double), ("normsq", ctypes.c_double),
                 ("maxval", ctypes.c_double), ("last_residual", ctypes.c_double), ("s_D", ctypes.c_int64),
                 ("sample_rows", ctypes.c_int64), ("theta_over_k", ctypes.c_double), ("flags", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 7), ("phase_ms", ctypes.c_double * 5),
-                ("phase_calls", ctypes.c_int64 * 5)]
+                ("reserved", ctypes.c_int32 * 7), ("warm_beta", ctypes.c_double), ("phase_ms", ctypes.c_double * 5),
+                ("phase_calls", ctypes.c_int64 * 5), ("graph_launches", ctypes.c_int64)]
 
 
 _VP = ctypes.c_void_p
@@ -78,6 +78,7 @@ _SIGS = {
     "symnmf_get_stats": (ctypes.c_int, [_VP, ctypes.POINTER(Stats)]),
     "symnmf_last_error": (ctypes.c_char_p, [_VP]),
     "symnmf_destroy": (None, [_VP]),
+    "symnmf_trim_cache": (ctypes.c_int, []),
     "symnmf_mlp_create": (ctypes.c_int, [ctypes.POINTER(_VP), ctypes.c_int32, ctypes.c_uint64, _VP]),
     "symnmf_mlp_num_params": (ctypes.c_int, [_VP, ctypes.POINTER(ctypes.c_int64)]),
     "symnmf_mlp_set_params": (ctypes.c_int, [_VP, _VP]),
@@ -248,6 +249,10 @@ def symnmf_get_stats(ctx):
     return st
 
 
+def symnmf_trim_cache():
+    _check(lib().symnmf_trim_cache())
+
+
 def symnmf_destroy(ctx):
     h, ctx.handle = ctx.handle, None
     if h:
@@ -328,7 +333,9 @@ def symnmf_warm_features(ctx, F):
     _check(lib().symnmf_warm_features(ctx.handle, F.data_ptr()), ctx.handle)
 
 
-def symnmf_warmstart(ctx, net):
+def symnmf_warmstart(ctx, net, want_beta=True):
+    """Returns beta (synchronises), or None with want_beta=False (stream-ordered;
+    the value is then in symnmf_get_stats(ctx).warm_beta)."""
     beta = ctypes.c_double()
-    _check(lib().symnmf_warmstart(ctx.handle, net.handle, ctypes.byref(beta)), ctx.handle)
-    return beta.value
+    _check(lib().symnmf_warmstart(ctx.handle, net.handle, ctypes.byref(beta) if want_beta else None), ctx.handle)
+    return beta.value if want_beta else None

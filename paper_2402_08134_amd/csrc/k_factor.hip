@@ -173,8 +173,11 @@ __global__ __launch_bounds__(256) void k_finish_iteration(const double* __restri
     st->prev = r;
     st->last = r;
     st->iter = t + 1;
-    if (rule.mode == SYMNMF_STOP_STALL && st->stall >= rule.patience) st->done = 1;
-    if (rule.mode == SYMNMF_STOP_TARGET && r <= rule.target) st->done = 1;
+    const bool stall = (rule.mode == SYMNMF_STOP_STALL || rule.mode == SYMNMF_STOP_STALL_OR_TARGET) &&
+                       st->stall >= rule.patience;
+    const bool hit = (rule.mode == SYMNMF_STOP_TARGET || rule.mode == SYMNMF_STOP_STALL_OR_TARGET) &&
+                     r <= rule.target;
+    if (stall || hit) st->done = 1;
   }
 }
 
@@ -280,6 +283,97 @@ __global__ __launch_bounds__(256) void k_chol_inverse(const double* __restrict__
   }
 }
 
+// Single-wavefront Cholesky and triangular inverse for k <= 64.  The matrix
+// lives in LDS (padded stride); lane c owns column c of every row update, so
+// each step is a sequence of wave-wide row operations whose iterations are
+// independent of one another (the loads pipeline), and no barrier beyond the
+// wavefront is needed: LDS operations of one wavefront complete in order, so
+// compiler fences suffice.  Factor: for pivot j, scale column j below it, then
+// for every trailing row r subtract L[r][j] L[c][j] from entry (r, c), c <= r.
+// Inverse: X = L^{-1} by row elimination of [L | I] (X[t] /= L[t][t], then
+// X[m] -= L[m][t] X[t] for m > t), lane c holding column c; R^{-1} = X^T.
+// Same shift retries and flags as the workgroup kernel.
+constexpr int CW_LD = 65;  // padded row stride of the LDS matrices (doubles)
+
+__global__ __launch_bounds__(64) void k_chol_wave(const double* __restrict__ G, int k, double* __restrict__ R,
+                                                  double* __restrict__ Rinv, int* d_flags, int flag_bit,
+                                                  int* d_fail) {
+  __shared__ double A[64 * CW_LD];
+  __shared__ double Xs[64 * CW_LD];
+  const int c = threadIdx.x;
+  const bool act = c < k;
+  // G into Xs (coalesced, independent loads), then the trace from LDS
+  const int kk = k * k;
+#pragma unroll 8
+  for (int e = c; e < kk; e += 64) {
+    const int r = e / k;
+    Xs[r * CW_LD + (e - r * k)] = G[e];
+  }
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  double trace = 0.0;
+  for (int t = 0; t < k; ++t) trace += Xs[t * CW_LD + t];
+  double shift = 0.0, grow = 1e-12 * fmax(trace, 1e-300) / k;
+  bool bad = true;
+  for (int attempt = 0; attempt < 6 && bad; ++attempt) {
+    if (attempt > 0) {
+      shift = grow;  // 1e-12, 1e-10, ... times tr(G) / k
+      grow *= 100.0;
+    }
+    if (act)
+      for (int r = 0; r < k; ++r) A[r * CW_LD + c] = Xs[r * CW_LD + c] + (r == c ? shift : 0.0);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    bad = false;
+    for (int j = 0; j < k; ++j) {
+      const double d = A[j * CW_LD + j];  // the same value in every lane
+      if (!(d > 0.0) || !isfinite(d)) {
+        bad = true;
+        break;
+      }
+      const double ljj = sqrt(d);
+      __builtin_amdgcn_wave_barrier();
+      if (c > j && act) A[c * CW_LD + j] /= ljj;  // column j below the pivot
+      if (c == j) A[j * CW_LD + j] = ljj;
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      if (c > j && act) {
+        const double lcj = A[c * CW_LD + j];
+#pragma unroll 4
+        for (int r = c; r < k; ++r) A[r * CW_LD + c] = fma(-A[r * CW_LD + j], lcj, A[r * CW_LD + c]);
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+    }
+  }
+  if (bad) {
+    if (c == 0) *d_fail = 1;
+    return;
+  }
+  if (c == 0 && shift > 0.0 && d_flags) atomicOr(d_flags, flag_bit);
+  // L is the lower triangle of A; R = L^T (row c of R = column c of L)
+  if (act)
+    for (int r = 0; r < k; ++r) R[c * k + r] = r >= c ? A[r * CW_LD + c] : 0.0;
+  // X = L^{-1}: lane c keeps column c
+  if (act)
+    for (int r = 0; r < k; ++r) Xs[r * CW_LD + c] = r == c ? 1.0 : 0.0;
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  for (int t = 0; t < k; ++t) {
+    if (act) {
+      const double xt = Xs[t * CW_LD + c] / A[t * CW_LD + t];
+      Xs[t * CW_LD + c] = xt;
+#pragma unroll 4
+      for (int m = t + 1; m < k; ++m) Xs[m * CW_LD + c] = fma(-A[m * CW_LD + t], xt, Xs[m * CW_LD + c]);
+    }
+  }
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  // R^{-1} = X^T: row c of R^{-1} = column c of X
+  if (act)
+    for (int r = 0; r < k; ++r) Rinv[c * k + r] = Xs[r * CW_LD + c];
+}
+
 // ---------------------------------------------------------------------------
 // Parallel cyclic Jacobi (round-robin pairing) on A = (T + T^T) / 2 in LDS;
 // V accumulated in LDS next to A, then columns sorted by descending
@@ -287,27 +381,30 @@ __global__ __launch_bounds__(256) void k_chol_inverse(const double* __restrict__
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_jacobi(const double* __restrict__ T, int l, double* __restrict__ V,
                                                 double* __restrict__ lam) {
-  extern __shared__ double A[];  // l x (l + 1) matrix, then l x (l + 1) eigenvectors
-  double* Vw = A + l * (l + 1);
-  __shared__ double cs[64], sn[64];
-  __shared__ int pp[64], qq[64];
+  // A: m x (m + 1) (m = l rounded up to even; the extra row and column are
+  // zero, so rotations that pair with them are the identity), then the
+  // eigenvectors V (m x (m + 1)).
+  extern __shared__ double A[];
+  const int m = l + (l & 1);
+  const int lda = m + 1;
+  double* Vw = A + m * lda;
+  __shared__ double cs[48], sn[48];
+  __shared__ int pp[48], qq[48];
   __shared__ double red[8];
-  __shared__ int order[128];
+  __shared__ int order[96];
   __shared__ int conv;
-  const int lda = l + 1;
   const int tid = threadIdx.x;
-  const int m = l + (l & 1);  // even; index l is a dummy when l is odd
   const int half = m / 2;
-  for (int e = tid; e < l * l; e += 256) {
-    const int p = e / l, q = e - p * l;
-    A[p * lda + q] = 0.5 * (T[p * l + q] + T[q * l + p]);
+  for (int e = tid; e < m * m; e += 256) {
+    const int p = e / m, q = e - p * m;
+    A[p * lda + q] = (p < l && q < l) ? 0.5 * (T[p * l + q] + T[q * l + p]) : 0.0;
     Vw[p * lda + q] = (p == q) ? 1.0 : 0.0;
   }
   __syncthreads();
   for (int sweep = 0; sweep < 40; ++sweep) {
     double off = 0.0, dg = 0.0;
-    for (int e = tid; e < l * l; e += 256) {
-      const int p = e / l, q = e - p * l;
+    for (int e = tid; e < m * m; e += 256) {
+      const int p = e / m, q = e - p * m;
       const double a = A[p * lda + q];
       if (p == q) dg += a * a; else off += a * a;
     }
@@ -319,51 +416,46 @@ __global__ __launch_bounds__(256) void k_jacobi(const double* __restrict__ T, in
     if (conv) break;
     for (int step = 0; step < m - 1; ++step) {
       // round-robin (circle) pairing: index 0 fixed, 1..m-1 rotate by `step`
-      for (int pr = tid; pr < half; pr += 256) {
-        int p = pr == 0 ? 0 : 1 + (pr - 1 + step) % (m - 1);
-        int q = 1 + (m - 2 - pr + step) % (m - 1);
+      if (tid < half) {
+        int p = tid == 0 ? 0 : 1 + (tid - 1 + step) % (m - 1);
+        int q = 1 + (m - 2 - tid + step) % (m - 1);
         if (p > q) { const int sw = p; p = q; q = sw; }
         double c = 1.0, s = 0.0;
-        if (q < l) {
-          const double apq = A[p * lda + q];
-          if (fabs(apq) > 1e-300) {
-            const double theta = (A[q * lda + q] - A[p * lda + p]) / (2.0 * apq);
-            const double t = (theta >= 0.0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(1.0 + theta * theta));
-            c = 1.0 / sqrt(1.0 + t * t);
-            s = t * c;
-          }
+        const double apq = A[p * lda + q];
+        if (fabs(apq) > 1e-300) {
+          const double theta = (A[q * lda + q] - A[p * lda + p]) / (2.0 * apq);
+          const double t = (theta >= 0.0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(1.0 + theta * theta));
+          c = 1.0 / sqrt(1.0 + t * t);
+          s = t * c;
         }
-        pp[pr] = p;
-        qq[pr] = q;
-        cs[pr] = c;
-        sn[pr] = s;
+        pp[tid] = p;
+        qq[tid] = q;
+        cs[tid] = c;
+        sn[tid] = s;
       }
       __syncthreads();
-      // columns p, q of A and V
-      for (int e = tid; e < half * l; e += 256) {
-        const int i = e / l, r = e - i * l;
-        const int p = pp[i], q = qq[i];
-        if (q < l && sn[i] != 0.0) {
-          const double c = cs[i], s = sn[i];
-          const double ap = A[r * lda + p], aq = A[r * lda + q];
-          A[r * lda + p] = c * ap - s * aq;
-          A[r * lda + q] = s * ap + c * aq;
-          const double vp = Vw[r * lda + p], vq = Vw[r * lda + q];
-          Vw[r * lda + p] = c * vp - s * vq;
-          Vw[r * lda + q] = s * vp + c * vq;
-        }
+      // every 2 x 2 block (rows of pair a, columns of pair b) from its own
+      // four entries: rotate its columns by pair b, then its rows by pair a
+      for (int e = tid; e < half * half; e += 256) {
+        const int a = e / half, b = e - a * half;
+        const int pa = pp[a], qa = qq[a], pb = pp[b], qb = qq[b];
+        const double ca = cs[a], sa = sn[a], cb = cs[b], sb = sn[b];
+        const double x00 = A[pa * lda + pb], x01 = A[pa * lda + qb];
+        const double x10 = A[qa * lda + pb], x11 = A[qa * lda + qb];
+        const double y00 = cb * x00 - sb * x01, y01 = sb * x00 + cb * x01;
+        const double y10 = cb * x10 - sb * x11, y11 = sb * x10 + cb * x11;
+        A[pa * lda + pb] = ca * y00 - sa * y10;
+        A[qa * lda + pb] = sa * y00 + ca * y10;
+        A[pa * lda + qb] = ca * y01 - sa * y11;
+        A[qa * lda + qb] = sa * y01 + ca * y11;
       }
-      __syncthreads();
-      // rows p, q of A
-      for (int e = tid; e < half * l; e += 256) {
-        const int i = e / l, r = e - i * l;
-        const int p = pp[i], q = qq[i];
-        if (q < l && sn[i] != 0.0) {
-          const double c = cs[i], s = sn[i];
-          const double ap = A[p * lda + r], aq = A[q * lda + r];
-          A[p * lda + r] = c * ap - s * aq;
-          A[q * lda + r] = s * ap + c * aq;
-        }
+      for (int e = tid; e < m * half; e += 256) {
+        const int r = e / half, b = e - r * half;
+        const int pb = pp[b], qb = qq[b];
+        const double cb = cs[b], sb = sn[b];
+        const double vp = Vw[r * lda + pb], vq = Vw[r * lda + qb];
+        Vw[r * lda + pb] = cb * vp - sb * vq;
+        Vw[r * lda + qb] = sb * vp + cb * vq;
       }
       __syncthreads();
     }
@@ -616,6 +708,10 @@ int rowmat(const void* A, int adtype, int64_t lda, int n, int l, const double* M
 
 int chol_inverse(const double* G, int k, double* R, double* Rinv, int* d_flags, int flag_bit, int* d_fail,
                  hipStream_t s) {
+  if (k >= 1 && k <= 64) {
+    k_chol_wave<<<1, 64, 0, s>>>(G, k, R, Rinv, d_flags, flag_bit, d_fail);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+  }
   const size_t lds = 2 * (size_t)k * (k + 1) * sizeof(double);
   if (k > 96) return -1;
   if (lds > 65536) {
@@ -629,7 +725,8 @@ int chol_inverse(const double* G, int k, double* R, double* Rinv, int* d_flags, 
 
 int jacobi_evd(const double* T, int l, double* V, double* lam, hipStream_t s) {
   if (l > 96) return -1;
-  const size_t lds = 2 * (size_t)l * (l + 1) * sizeof(double);
+  const int m = l + (l & 1);
+  const size_t lds = 2 * (size_t)m * (m + 1) * sizeof(double);
   if (lds > 65536) {
     if (hipFuncSetAttribute((const void*)k_jacobi, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
       return -1;

@@ -336,9 +336,12 @@ int dispatch_kp(const UpdateArgs& a, const UpdateRO& ro, int kp, int ymode, int 
 
 }  // namespace
 
+// 512 blocks of 16-row chunks (grid-stride beyond 8192 rows): measured at
+// n = 16384 against 128, 256 and 1024, it is the fastest update plus
+// partial-sum reduction (fewer partial rows to reduce, enough waves).
 int update_blocks(int n, int fdtype) {
   (void)fdtype;
-  return std::max(1, std::min(1024, ceil_div(n, 16)));
+  return std::max(1, std::min(512, ceil_div(n, 16)));
 }
 
 int fused_update(const UpdateArgs& a, const UpdateRO& ro, int kp, int ymode, int fdtype, int pdtype, int tdtype,

@@ -48,20 +48,31 @@ __global__ __launch_bounds__(256) void k_ws_colparts(const double* __restrict__ 
 }
 
 // info[0..k) = s_j, info[k..2k) = lam_j / lam_0, info[2k] = mean row sum,
-// info[2k+1] = 1 when lam_0 <= 0 (no usable spectrum).
-__global__ void k_ws_info(const double* __restrict__ part, int nb, int k, const double* __restrict__ lam,
-                          const double* __restrict__ total, int n, double* __restrict__ info) {
-  const int j = threadIdx.x;
+// info[2k+1] = 1 when lam_0 <= 0 (no usable spectrum).  One block: thread t
+// sums the partials b = t/64, t/64 + 4, ... of column t % 64; the four
+// phases are combined in a fixed order.
+__global__ __launch_bounds__(256) void k_ws_info(const double* __restrict__ part, int nb, int k,
+                                                 const double* __restrict__ lam, const double* __restrict__ total,
+                                                 int n, double* __restrict__ info) {
+  __shared__ double sp[4][64], sn[4][64];
+  const int j = threadIdx.x & 63, r = threadIdx.x >> 6;
+  double p = 0.0, q = 0.0;
   if (j < k) {
-    double p = 0.0, q = 0.0;
-    for (int b = 0; b < nb; ++b) {
+    for (int b = r; b < nb; b += 4) {
       p += part[(int64_t)b * 2 * k + j];
       q += part[(int64_t)b * 2 * k + k + j];
     }
-    info[j] = p >= q ? 1.0 : -1.0;
+  }
+  sp[r][j] = p;
+  sn[r][j] = q;
+  __syncthreads();
+  if (r == 0 && j < k) {
+    const double P = ((sp[0][j] + sp[1][j]) + sp[2][j]) + sp[3][j];
+    const double Q = ((sn[0][j] + sn[1][j]) + sn[2][j]) + sn[3][j];
+    info[j] = P >= Q ? 1.0 : -1.0;
     info[k + j] = lam[j] / lam[0];
   }
-  if (j == 0) {
+  if (threadIdx.x == 0) {
     info[2 * k] = *total / n;
     info[2 * k + 1] = lam[0] > 0.0 ? 0.0 : 1.0;
   }
@@ -128,12 +139,19 @@ __global__ __launch_bounds__(256) void k_mlp_forward(const float* __restrict__ P
                                                      float* __restrict__ h2, float* __restrict__ h3,
                                                      float* __restrict__ dz, double* __restrict__ loss_part) {
   using Lay = Layout<D, H>;
-  __shared__ float w[Lay::NP];
+  // The weights are the same for every lane: they are read straight from
+  // the (read-only) parameter array at wave-uniform addresses, which the
+  // compiler turns into scalar loads feeding the FMAs as SGPR operands.
   __shared__ double sc[8];
-  for (int e = threadIdx.x; e < Lay::NP; e += 256) w[e] = P[e];
-  __syncthreads();
   double lacc = 0.0;
   for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < rows; e += (int64_t)gridDim.x * 256) {
+    // An empty asm that claims to change a (scalar, zero) offset of the
+    // weights keeps the compiler from hoisting all 8833 weight loads out of
+    // the loop (they would not fit in scalar registers); it emits no
+    // instruction.
+    int woff = 0;
+    asm volatile("" : "+s"(woff));
+    const float* __restrict__ w = P + woff;
     float x[D], a[H], b[H];
 #pragma unroll
     for (int i = 0; i < D; ++i) x[i] = F[e * D + i];
@@ -175,10 +193,12 @@ __global__ __launch_bounds__(256) void k_mlp_backprop(const float* __restrict__ 
                                                       const float* __restrict__ dz_out,
                                                       const float* __restrict__ h_in, int64_t rows,
                                                       float* __restrict__ dz_in) {
-  __shared__ float w[IN * OUT];
-  for (int e = threadIdx.x; e < IN * OUT; e += 256) w[e] = P[woff + e];
-  __syncthreads();
   for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < rows; e += (int64_t)gridDim.x * 256) {
+    // wave-uniform weight reads (scalar loads), kept inside the loop as in
+    // the forward kernel
+    int zero = 0;
+    asm volatile("" : "+s"(zero));
+    const float* __restrict__ w = P + woff + zero;
     float d[OUT];
 #pragma unroll
     for (int o = 0; o < OUT; ++o) d[o] = dz_out[e * OUT + o];
@@ -361,11 +381,11 @@ int mlp_adam(float* p, const float* g, float* m, float* v, int np, double lr, in
 int warm_features(const double* U, int n, int l, int k, const double* lam, const double* rowsum,
                   const double* d_total, float* F, double* info, Workspace& ws, hipStream_t s) {
   if (k < 1 || k > 64 || k > l) return -1;
-  const int nb = std::max(1, std::min(256, ceil_div(n, 64)));
+  const int nb = std::max(1, std::min(64, ceil_div(n, 64)));
   double* part = ws.dbl((size_t)nb * 2 * k);
   if (!part) return -1;
   k_ws_colparts<<<nb, 256, 0, s>>>(U, n, l, k, part);
-  k_ws_info<<<1, 64, 0, s>>>(part, nb, k, lam, d_total, n, info);
+  k_ws_info<<<1, 256, 0, s>>>(part, nb, k, lam, d_total, n, info);
   k_ws_features<<<ceil_div(n, 256), 256, 0, s>>>(U, n, l, k, info, rowsum, F);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }

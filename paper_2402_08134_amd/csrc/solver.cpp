@@ -10,7 +10,10 @@
 #include <cstdio>
 #include <cstring>
 #include <functional>
+#include <map>
+#include <mutex>
 #include <new>
+#include <unordered_map>
 #include <string>
 #include <vector>
 
@@ -35,19 +38,140 @@ struct Fail {
     if ((expr) != 0) throw Fail{SYMNMF_E_DEVICE, std::string("launch failed: ") + #expr}; \
   } while (0)
 
+// Device memory cache.  Blocks a context releases are kept, per device and
+// size, and handed out again, so contexts of a shape seen before make no
+// hipMalloc / hipFree calls (both are slow and hipFree synchronises the
+// device).  Contexts release blocks only after synchronising their stream, so
+// a reused block has no pending work.  Above kCacheLimit cached bytes a
+// released block is freed for real; a failed hipMalloc first empties the
+// cache and tries again.  symnmf_trim_cache() frees every cached block.
+class DeviceCache {
+ public:
+  void* get(size_t bytes) {
+    bytes = round_up(bytes);
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    {
+      std::lock_guard<std::mutex> g(mu_);
+      auto it = free_.find({dev, bytes});
+      if (it != free_.end() && !it->second.empty()) {
+        void* p = it->second.back();
+        it->second.pop_back();
+        cached_ -= bytes;
+        live_[p] = {dev, bytes};
+        return p;
+      }
+    }
+    void* p = nullptr;
+    if (hipMalloc(&p, bytes) != hipSuccess) {
+      (void)hipGetLastError();
+      trim();
+      if (hipMalloc(&p, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        return nullptr;
+      }
+    }
+    std::lock_guard<std::mutex> g(mu_);
+    live_[p] = {dev, bytes};
+    return p;
+  }
+
+  void put(void* p) {
+    if (!p) return;
+    std::unique_lock<std::mutex> g(mu_);
+    auto it = live_.find(p);
+    if (it == live_.end()) {
+      g.unlock();
+      (void)hipFree(p);
+      return;
+    }
+    const auto key = it->second;
+    live_.erase(it);
+    if (cached_ + key.second > kCacheLimit) {
+      g.unlock();
+      (void)hipFree(p);
+      return;
+    }
+    free_[key].push_back(p);
+    cached_ += key.second;
+  }
+
+  void trim() {
+    std::vector<std::pair<int, void*>> drop;
+    {
+      std::lock_guard<std::mutex> g(mu_);
+      for (auto& kv : free_)
+        for (void* p : kv.second) drop.push_back({kv.first.first, p});
+      free_.clear();
+      cached_ = 0;
+    }
+    int cur = 0;
+    (void)hipGetDevice(&cur);
+    for (auto& d : drop) {
+      (void)hipSetDevice(d.first);
+      (void)hipFree(d.second);
+    }
+    (void)hipSetDevice(cur);
+  }
+
+ private:
+  static size_t round_up(size_t b) { return (std::max<size_t>(b, 1) + 255) & ~(size_t)255; }
+  static constexpr size_t kCacheLimit = (size_t)16 << 30;
+  std::mutex mu_;
+  std::map<std::pair<int, size_t>, std::vector<void*>> free_;
+  std::unordered_map<void*, std::pair<int, size_t>> live_;
+  size_t cached_ = 0;
+};
+
+DeviceCache& device_cache() {
+  static DeviceCache* c = new DeviceCache();  // never destroyed: blocks live until exit
+  return *c;
+}
+
+// Pinned host readback buffers of 64 doubles, kept for reuse (hipHostMalloc
+// is slow).
+class PinnedPool {
+ public:
+  double* get() {
+    {
+      std::lock_guard<std::mutex> g(mu_);
+      if (!free_.empty()) {
+        double* p = free_.back();
+        free_.pop_back();
+        return p;
+      }
+    }
+    void* p = nullptr;
+    if (hipHostMalloc(&p, 64 * sizeof(double), hipHostMallocDefault) != hipSuccess) {
+      (void)hipGetLastError();
+      return nullptr;
+    }
+    return (double*)p;
+  }
+  void put(double* p) {
+    if (!p) return;
+    std::lock_guard<std::mutex> g(mu_);
+    free_.push_back(p);
+  }
+
+ private:
+  std::mutex mu_;
+  std::vector<double*> free_;
+};
+
+PinnedPool& pinned_pool() {
+  static PinnedPool* p = new PinnedPool();
+  return *p;
+}
+
 template <typename T>
 T* dalloc(size_t count) {
-  void* p = nullptr;
   if (count == 0) count = 1;
-  if (hipMalloc(&p, count * sizeof(T)) != hipSuccess) {
-    (void)hipGetLastError();
-    throw Fail{SYMNMF_E_NOMEM, "device allocation of " + std::to_string(count * sizeof(T)) + " bytes failed"};
-  }
+  void* p = device_cache().get(count * sizeof(T));
+  if (!p) throw Fail{SYMNMF_E_NOMEM, "device allocation of " + std::to_string(count * sizeof(T)) + " bytes failed"};
   return (T*)p;
 }
-void dfree(void* p) {
-  if (p) (void)hipFree(p);
-}
+void dfree(void* p) { device_cache().put(p); }
 
 // k rounded up to the 16-column MFMA tile (the padded width of every k-wide
 // operand of the update).
@@ -102,7 +226,7 @@ struct symnmf_ctx {
   bool mW_ok = false, mH_ok = false;
   double *G_W = nullptr, *G_H = nullptr, *Gh_W = nullptr, *Gh_H = nullptr, *Gh_S = nullptr;
   double *Gi_W = nullptr, *Gi_H = nullptr, *Gi_S = nullptr;  // 1 / diag of the regularised Grams
-  double* d_scal = nullptr;  // [0] ||X||^2 [1] sum [2] max [3..7] scratch [8] ||Lambda||^2
+  double* d_scal = nullptr;  // [0] ||X||^2 [1] sum [2] max [3..7] scratch [8] ||Lambda||^2 [9] warm beta
   double* rowsum = nullptr;
   DevState* dstate = nullptr;
   double* hist = nullptr;
@@ -137,6 +261,21 @@ struct symnmf_ctx {
   std::vector<TimedPair> ev_pending;
   double phase_ms[SYMNMF_NUM_PHASES] = {};
   int64_t phase_calls[SYMNMF_NUM_PHASES] = {};
+  // HIP graphs of steady-state iterations: [0] one iteration, [1] a block of
+  // several; each valid while its generation and iteration count match (the
+  // generation is bumped whenever the launch sequence or its arguments change)
+  hipGraphExec_t graph_exec[2] = {nullptr, nullptr};
+  int64_t graph_gen_of[2] = {-1, -1};
+  int graph_count_of[2] = {0, 0};
+  int64_t gen = 0;
+  bool graphs_broken = false;
+  hipStream_t cap_stream = nullptr;  // private stream the graphs are captured on
+  int64_t graph_launches = 0;
+  // learned-start temporaries (allocated by the first symnmf_warmstart)
+  float* warm_F = nullptr;
+  float* warm_Htf = nullptr;
+  void* warm_Ht = nullptr;
+  bool warm_ran = false;  // d_scal[9] holds the scale of the last warm start
 
   ~symnmf_ctx() {
     if (st) (void)hipStreamSynchronize(st);
@@ -145,12 +284,90 @@ struct symnmf_ctx {
                     ws.base, Q, Q1, U, YQ, Tm, QT, Vw, lam, Rl, Rlinv, Z, sb.w, sb.prefix, sb.counts, sb.flags,
                     sb.info, sb.theta, rows, weights, seg_cnt, seg_ptr, seg_src, seg_val, lev, R, Rinv};
     for (void* p : ptrs) dfree(p);
-    if (hbuf) (void)hipHostFree(hbuf);
+    pinned_pool().put(hbuf);
     for (auto& t : ev_pending) {
       (void)hipEventDestroy(t.a);
       (void)hipEventDestroy(t.b);
     }
     for (hipEvent_t e : ev_free) (void)hipEventDestroy(e);
+    for (hipGraphExec_t& g : graph_exec)
+      if (g) (void)hipGraphExecDestroy(g);
+    if (cap_stream) (void)hipStreamDestroy(cap_stream);
+    dfree(warm_F);
+    dfree(warm_Htf);
+    dfree(warm_Ht);
+  }
+
+  // Any change of mode, options or operand state that alters the kernels of
+  // an iteration or their arguments.
+  void bump_generation() { ++gen; }
+
+  // Iterations whose launch sequence is fixed: plain (dense or CSR) and LAI
+  // with every product operand already up to date.
+  bool steady() const {
+    if (opt.timing || !opt.graphs || graphs_broken) return false;
+    if (mode == SYMNMF_MODE_LAI) return mW_ok && mH_ok;
+    if (mode == SYMNMF_MODE_PLAIN) return kind == SYMNMF_CSR || (btW_ok && btH_ok);
+    return false;
+  }
+
+  // Replay `count` iterations from graph `which`, capturing it
+  // first if needed.  Returns false (and stops using graphs) if capture or
+  // instantiation fails; the iterations are then not done.
+  bool graph_iterations(int which, int count) {
+    if (!graph_exec[which] || graph_gen_of[which] != gen || graph_count_of[which] != count) {
+      if (graph_exec[which]) {
+        HIPCHK(hipGraphExecDestroy(graph_exec[which]));
+        graph_exec[which] = nullptr;
+      }
+      // Capture on a private stream (the caller's may be the null stream,
+      // which cannot be captured); the graph is launched on the caller's.
+      if (!cap_stream && hipStreamCreateWithFlags(&cap_stream, hipStreamNonBlocking) != hipSuccess) {
+        (void)hipGetLastError();
+        cap_stream = nullptr;
+        graphs_broken = true;
+        return false;
+      }
+      if (hipStreamBeginCapture(cap_stream, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+        (void)hipGetLastError();
+        graphs_broken = true;
+        return false;
+      }
+      bool ok = true;
+      const int64_t saved = iter_host;
+      hipStream_t user = st;
+      st = cap_stream;
+      try {
+        for (int t = 0; t < count; ++t) one_iteration();
+      } catch (const Fail&) {
+        ok = false;
+      }
+      st = user;
+      iter_host = saved;
+      hipGraph_t g = nullptr;
+      const hipError_t e = hipStreamEndCapture(cap_stream, &g);
+      if (!ok || e != hipSuccess || !g) {
+        if (g) (void)hipGraphDestroy(g);
+        (void)hipGetLastError();
+        graphs_broken = true;
+        return false;
+      }
+      hipGraphExec_t ex = nullptr;
+      const hipError_t ei = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(g);
+      if (ei != hipSuccess) {
+        (void)hipGetLastError();
+        graphs_broken = true;
+        return false;
+      }
+      graph_exec[which] = ex;
+      graph_gen_of[which] = gen;
+      graph_count_of[which] = count;
+    }
+    HIPCHK(hipGraphLaunch(graph_exec[which], st));
+    iter_host += count;
+    ++graph_launches;
+    return true;
   }
 
   hipEvent_t take_event() {
@@ -527,7 +744,7 @@ struct symnmf_mlp {
     else (void)hipDeviceSynchronize();
     void* ptrs[] = {p, m, v, g, h1, h2, h3, dza, dzb, scratch, d_loss};
     for (void* q : ptrs) dfree(q);
-    if (hbuf) (void)hipHostFree(hbuf);
+    pinned_pool().put(hbuf);
   }
 
   void ensure(int64_t rows) {
@@ -620,6 +837,8 @@ int symnmf_default_options(symnmf_options* opt) {
   opt->tau = -1.0;
   opt->resid_every = 1;
   opt->max_history = 4096;
+  opt->timing = 0;
+  opt->graphs = 1;
   return SYMNMF_OK;
 }
 
@@ -646,6 +865,8 @@ int symnmf_create(symnmf_ctx** out, const symnmf_matrix* X, int32_t k, double al
     if (c->opt.check_every < 1) c->opt.check_every = 1;
     if (c->opt.max_history < 1) c->opt.max_history = 1;
     if (c->opt.rule != SYMNMF_RULE_HALS && c->opt.rule != SYMNMF_RULE_BPP) throw Fail{SYMNMF_E_INVALID, "rule"};
+    if (c->opt.stop_mode < SYMNMF_STOP_NONE || c->opt.stop_mode > SYMNMF_STOP_STALL_OR_TARGET)
+      throw Fail{SYMNMF_E_INVALID, "stop_mode"};
     c->st = (hipStream_t)hip_stream;
     c->kind = X->kind;
     c->xdtype = X->dtype;
@@ -746,7 +967,7 @@ int symnmf_create(symnmf_ctx** out, const symnmf_matrix* X, int32_t k, double al
     c->R = dalloc<double>((size_t)k * k);
     c->Rinv = dalloc<double>((size_t)k * k);
     c->lev = dalloc<double>(n);
-    if (hipHostMalloc((void**)&c->hbuf, 64 * sizeof(double), hipHostMallocDefault) != hipSuccess)
+    if (!(c->hbuf = pinned_pool().get()))
       throw Fail{SYMNMF_E_NOMEM, "pinned host buffer"};
     HIPCHK(hipMemsetAsync(c->dstate, 0, sizeof(DevState), c->st));
     HIPCHK(hipMemsetAsync(c->d_fail, 0, sizeof(int), c->st));
@@ -902,13 +1123,15 @@ int symnmf_lai(symnmf_ctx* c, int32_t l, int32_t q) {
     if (!(c->normsq_lai > 0.0)) throw Fail{SYMNMF_E_NUMERIC, "low-rank approximation is zero"};
     c->mode = SYMNMF_MODE_LAI;
     c->mW_ok = c->mH_ok = false;
+    c->bump_generation();
   });
 }
 
 int symnmf_refine(symnmf_ctx* c, int32_t stop_mode, double target) {
   return guarded(c, [&] {
     if (c->mode != SYMNMF_MODE_LAI) throw Fail{SYMNMF_E_STATE, "refinement needs a context in LAI mode"};
-    if (stop_mode < SYMNMF_STOP_NONE || stop_mode > SYMNMF_STOP_TARGET) throw Fail{SYMNMF_E_INVALID, "stop_mode"};
+    if (stop_mode < SYMNMF_STOP_NONE || stop_mode > SYMNMF_STOP_STALL_OR_TARGET)
+      throw Fail{SYMNMF_E_INVALID, "stop_mode"};
     DevState d = c->read_state();
     d.done = 0;
     d.stall = 0;
@@ -920,6 +1143,7 @@ int symnmf_refine(symnmf_ctx* c, int32_t stop_mode, double target) {
     c->opt.target = target;
     c->mode = SYMNMF_MODE_PLAIN;
     c->btW_ok = c->btH_ok = false;
+    c->bump_generation();
   });
 }
 
@@ -928,10 +1152,28 @@ int symnmf_iterate(symnmf_ctx* c, int32_t iters, int32_t* done) {
     if (iters < 0) throw Fail{SYMNMF_E_INVALID, "iters < 0"};
     const DevState before = c->read_state();
     if (!before.done) {
-      const int every = c->opt.stop_mode == SYMNMF_STOP_NONE ? iters : c->opt.check_every;
-      for (int t = 0; t < iters; ++t) {
-        c->one_iteration();
-        if (c->opt.stop_mode != SYMNMF_STOP_NONE && ((t + 1) % every) == 0 && t + 1 < iters) {
+      const bool polled = c->opt.stop_mode != SYMNMF_STOP_NONE;
+      const int every = polled ? std::max(1, c->opt.check_every) : iters;
+      const int block = polled ? std::min(every, 16) : 8;
+      int t = 0, since_poll = 0;
+      while (t < iters) {
+        int step = 0;
+        if (c->steady()) {
+          const bool whole_block = block > 1 && iters - t >= block && (!polled || every % block == 0);
+          if (whole_block) {
+            if (c->graph_iterations(1, block)) step = block;
+          } else if (c->graph_iterations(0, 1)) {
+            step = 1;
+          }
+        }
+        if (step == 0) {
+          c->one_iteration();
+          step = 1;
+        }
+        t += step;
+        since_poll += step;
+        if (polled && since_poll >= every && t < iters) {
+          since_poll = 0;
           if (c->read_state().done) break;
         }
       }
@@ -1062,6 +1304,8 @@ int symnmf_get_stats(symnmf_ctx* c, symnmf_stats* out) {
     out->maxval = c->maxval;
     out->last_residual = d.last;
     out->flags = d.flags;
+    out->warm_beta = c->warm_ran ? c->readback(c->d_scal + 9, 1)[0] : 0.0;
+    out->graph_launches = c->graph_launches;
     c->harvest_timers();
     for (int p = 0; p < SYMNMF_NUM_PHASES; ++p) {
       out->phase_ms[p] = c->phase_ms[p];
@@ -1101,7 +1345,7 @@ int symnmf_mlp_create(symnmf_mlp** out, int32_t hidden, uint64_t seed, void* hip
     net->v = dalloc<float>(net->np);
     net->g = dalloc<float>(net->np);
     net->d_loss = dalloc<double>(1);
-    if (hipHostMalloc((void**)&net->hbuf, 8 * sizeof(double), hipHostMallocDefault) != hipSuccess)
+    if (!(net->hbuf = pinned_pool().get()))
       throw Fail{SYMNMF_E_NOMEM, "pinned allocation failed"};
     LCHK(mlp_init(net->p, seed, net->st));
     HIPCHK(hipMemsetAsync(net->m, 0, sizeof(float) * net->np, net->st));
@@ -1186,22 +1430,15 @@ int symnmf_warmstart(symnmf_ctx* c, const symnmf_mlp* net, double* beta_out) {
     if (c->l == 0 || !c->U) throw Fail{SYMNMF_E_STATE, "symnmf_lai has not run"};
     const int n = c->n, k = c->k;
     const int64_t nk = (int64_t)n * k;
+    if (!c->warm_F) {
+      c->warm_F = dalloc<float>((size_t)nk * MLP_D_IN);
+      c->warm_Htf = dalloc<float>(nk);
+      c->warm_Ht = dalloc<char>((size_t)nk * c->fsize());
+    }
     symnmf_ctx::Timed tm(c, SYMNMF_PHASE_WARM);
-    float* F = dalloc<float>((size_t)nk * MLP_D_IN);
-    float* Htf = nullptr;
-    void* Ht = nullptr;
-    struct Temps {
-      std::vector<void*> p;
-      symnmf_ctx* c;
-      ~Temps() {
-        (void)hipStreamSynchronize(c->st);
-        for (void* q : p) dfree(q);
-      }
-    } temps{{F}, c};
-    Htf = dalloc<float>(nk);
-    temps.p.push_back(Htf);
-    Ht = dalloc<char>((size_t)nk * c->fsize());
-    temps.p.push_back(Ht);
+    float* F = c->warm_F;
+    float* Htf = c->warm_Htf;
+    void* Ht = c->warm_Ht;
     c->ws.reset();
     double* info = c->ws.dbl((size_t)2 * k + 2);
     if (!info) throw Fail{SYMNMF_E_NOMEM, "workspace"};
@@ -1219,14 +1456,20 @@ int symnmf_warmstart(symnmf_ctx* c, const symnmf_mlp* net, double* beta_out) {
     LCHK(gram(Ht, c->fdtype, k, k, Ht, c->fdtype, k, k, n, nullptr, nullptr, nullptr, 0, c->ws, ga, nullptr, 0, 0.0,
               nullptr, c->st));
     frob_dot(ga, ga, k * k, c->d_scal + 4, c->st);
-    LCHK(warm_apply(Htf, nk, c->d_scal + 3, c->d_scal + 4, info + 2 * k + 1, c->H, c->W, c->fdtype, c->d_scal + 5,
+    LCHK(warm_apply(Htf, nk, c->d_scal + 3, c->d_scal + 4, info + 2 * k + 1, c->H, c->W, c->fdtype, c->d_scal + 9,
                     c->st));
+    c->warm_ran = true;
     c->refresh_gram(c->W, c->G_W, c->Gh_W, c->Gi_W);
     c->refresh_gram(c->H, c->G_H, c->Gh_H, c->Gi_H);
     c->invalidate(SYMNMF_W);
     c->invalidate(SYMNMF_H);
-    if (beta_out) *beta_out = c->readback(c->d_scal + 5, 1)[0];
+    if (beta_out) *beta_out = c->readback(c->d_scal + 9, 1)[0];
   });
+}
+
+int symnmf_trim_cache(void) {
+  device_cache().trim();
+  return SYMNMF_OK;
 }
 
 const char* symnmf_last_error(const symnmf_ctx* c) { return c ? c->err.c_str() : g_create_error.c_str(); }

@@ -156,6 +156,13 @@ def test_stop_rules():
     h2 = np.array(P.symnmf_history(ctx))
     assert done <= 21 and len(h2) == done
     assert h2[-1] <= target and np.all(h2[:-1] > target)
+    # stall-or-target: the target when it comes first, else the stall rule
+    o = P.symnmf_default_options(stop_mode=P.STOP_STALL_OR_TARGET, target=target, check_every=5)
+    ctx = P.symnmf_create(dev(X), 6, 0.0, 0, 1, o)
+    assert P.symnmf_iterate(ctx, 500) == done
+    o = P.symnmf_default_options(stop_mode=P.STOP_STALL_OR_TARGET, target=0.0, check_every=3)
+    ctx = P.symnmf_create(dev(X), 6, 0.0, 0, 1, o)
+    assert P.symnmf_iterate(ctx, 500) == len(hist)
 
 
 def test_determinism_and_edge_sizes():
@@ -201,3 +208,48 @@ def test_invalid_arguments():
     with pytest.raises(P.SymNMFError) as e:
         P.symnmf_lai(ctx, 2, 1)                          # l < k
     assert e.value.code == P.E_INVALID
+
+
+@pytest.mark.parametrize("case", ["dense_f32", "dense_f64", "lai", "csr", "bpp", "stall"])
+def test_graph_replay_matches_eager(case):
+    """Iterations replayed from HIP graphs equal directly launched ones, bit
+    for bit, over several replays with other work and synchronisation in
+    between, and with iteration counts that are not multiples of a block."""
+    import scipy.sparse  # noqa: F401
+    if case == "csr":
+        Xs, _ = workloads.sbm(3000, 6, 20.0, 20.0, seed=3)
+        make = lambda o: P.symnmf_create(  # noqa: E731
+            (dev(Xs.indptr.astype(np.int32)), dev(Xs.indices.astype(np.int32)), dev(Xs.data), 3000), 8, 0.0, 0, 2, o)
+    else:
+        X, _ = workloads.gaussian_kernel(1300, 16, 8, seed=4, dtype=np.float64)
+        dt = torch.float64 if case == "dense_f64" else torch.float32
+        make = lambda o: P.symnmf_create(dev(X, dt), 12, 0.0, 0, 2, o)  # noqa: E731
+    kw = {}
+    if case == "bpp":
+        kw["rule"] = P.RULE_BPP
+    if case == "stall":
+        kw.update(stop_mode=P.STOP_STALL, check_every=4, stop_tol=1e-6)
+    a = make(P.symnmf_default_options(graphs=1, **kw))
+    b = make(P.symnmf_default_options(graphs=0, **kw))
+    if case == "lai":
+        P.symnmf_lai(a, 24, 1)
+        P.symnmf_lai(b, 24, 1)
+    done_a = done_b = 0
+    for chunk in (3, 8, 13, 8, 5, 16):
+        done_a += P.symnmf_iterate(a, chunk)
+        done_b += P.symnmf_iterate(b, chunk)
+        ra = P.symnmf_residual(a, P.RESID_FAST)
+        rb = P.symnmf_residual(b, P.RESID_FAST)
+        assert ra == rb
+        assert np.array_equal(factor(a, P.H), factor(b, P.H))
+        assert np.array_equal(factor(a, P.W), factor(b, P.W))
+    assert done_a == done_b
+    assert P.symnmf_history(a) == P.symnmf_history(b)
+    assert P.symnmf_get_stats(a).graph_launches > 0 and P.symnmf_get_stats(b).graph_launches == 0
+    if case == "lai":
+        # and after switching to X
+        P.symnmf_refine(a)
+        P.symnmf_refine(b)
+        P.symnmf_iterate(a, 11)
+        P.symnmf_iterate(b, 11)
+        assert np.array_equal(factor(a, P.H), factor(b, P.H))
