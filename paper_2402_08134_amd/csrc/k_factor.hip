@@ -332,14 +332,15 @@ __global__ __launch_bounds__(64) void k_chol_wave(const double* __restrict__ G, 
         break;
       }
       const double ljj = sqrt(d);
+      const double rl = 1.0 / ljj;
       __builtin_amdgcn_wave_barrier();
-      if (c > j && act) A[c * CW_LD + j] /= ljj;  // column j below the pivot
+      if (c > j && act) A[c * CW_LD + j] *= rl;  // column j below the pivot
       if (c == j) A[j * CW_LD + j] = ljj;
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
       __builtin_amdgcn_wave_barrier();
       if (c > j && act) {
         const double lcj = A[c * CW_LD + j];
-#pragma unroll 4
+#pragma unroll 8
         for (int r = c; r < k; ++r) A[r * CW_LD + c] = fma(-A[r * CW_LD + j], lcj, A[r * CW_LD + c]);
       }
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -363,7 +364,7 @@ __global__ __launch_bounds__(64) void k_chol_wave(const double* __restrict__ G, 
     if (act) {
       const double xt = Xs[t * CW_LD + c] / A[t * CW_LD + t];
       Xs[t * CW_LD + c] = xt;
-#pragma unroll 4
+#pragma unroll 8
       for (int m = t + 1; m < k; ++m) Xs[m * CW_LD + c] = fma(-A[m * CW_LD + t], xt, Xs[m * CW_LD + c]);
     }
   }

@@ -697,11 +697,19 @@ struct symnmf_ctx {
   }
 
   // CholeskyQR2: Qout (n x l, FP64) = orthonormal factor of Yin (n x l, fdtype).
-  void cholqr2(const void* Yin) {
+  // CholeskyQR of Yin into Q; `twice` repeats it on the result (CholeskyQR2,
+  // orthonormal to working precision).  One pass suffices between power
+  // iterations, where only the span matters: it keeps the basis well
+  // conditioned for the next product.
+  void cholqr(const void* Yin, bool twice) {
     ws.reset();
     LCHK(gram(Yin, fdtype, l, l, Yin, fdtype, l, l, n, nullptr, nullptr, nullptr, 0, ws, Tm, nullptr, 0, 0.0,
               nullptr, st));
     LCHK(chol_inverse(Tm, l, Rl, Rlinv, &dstate->flags, SYMNMF_FLAG_CHOLQR_SHIFT, d_fail, st));
+    if (!twice) {
+      LCHK(rowmat(Yin, fdtype, l, n, l, Rlinv, nullptr, l, Q, SYMNMF_F64, l, nullptr, st));
+      return;
+    }
     LCHK(rowmat(Yin, fdtype, l, n, l, Rlinv, nullptr, l, Q1, SYMNMF_F64, l, nullptr, st));
     ws.reset();
     LCHK(gram(Q1, SYMNMF_F64, l, l, Q1, SYMNMF_F64, l, l, n, nullptr, nullptr, nullptr, 0, ws, Tm, nullptr, 0, 0.0,
@@ -1094,13 +1102,14 @@ int symnmf_lai(symnmf_ctx* c, int32_t l, int32_t q) {
     }
     HIPCHK(hipMemsetAsync(c->d_fail, 0, sizeof(int), c->st));
     // Algorithm RRF: Omega Gaussian (Philox), then 2q+1 products each followed
-    // by CholeskyQR2 (re-orthonormalising after every product).
+    // by CholeskyQR (re-orthonormalising after every product; CholeskyQR2
+    // after the last one).
     {
       symnmf_ctx::Timed tm(c, SYMNMF_PHASE_LAI);
       LCHK(gen_gaussian(c->Q, (int64_t)n * l, c->seed, 0, TAG_OMEGA, c->st));
       for (int it = 0; it < 2 * q + 1; ++it) {
         c->product(c->Q, SYMNMF_F64, l, c->YQ);
-        c->cholqr2(c->YQ);
+        c->cholqr(c->YQ, it == 2 * q);
       }
       // Algorithm Apx-EVD: T = Q^T (X Q), T = Q_T Lambda Q_T^T, U = Q Q_T.
       c->product(c->Q, SYMNMF_F64, l, c->YQ);
