@@ -365,13 +365,15 @@ __global__ __launch_bounds__(256) void k_splitk_reduce(const TP* __restrict__ P,
   Y[(int64_t)r * ldy + j] = (TY)acc;
 }
 
+// One block per row (grid-stride over rows: a launch covers at most 65535
+// rows, since a dispatch counts its work-items in 32 bits per dimension).
 __global__ __launch_bounds__(256) void k_f32_to_bf16(const float* __restrict__ src, int64_t lds, __bf16* __restrict__ dst,
                                                      int64_t ldd, int n) {
-  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  const int64_t tot = (int64_t)n * n;
-  if (e >= tot) return;
-  const int64_t r = e / n, c = e - r * n;
-  dst[r * ldd + c] = (__bf16)src[r * lds + c];
+  for (int64_t r = blockIdx.x; r < n; r += gridDim.x) {
+    const float* sr = src + r * lds;
+    __bf16* dr = dst + r * ldd;
+    for (int c = threadIdx.x; c < n; c += 256) dr[c] = (__bf16)sr[c];
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -582,8 +584,7 @@ int dense_gemm(const void* X, int xdtype, int64_t ldx, const void* B, int bdtype
 }
 
 int convert_f32_bf16(const float* src, int64_t lds, void* dst, int64_t ldd, int n, hipStream_t s) {
-  const int64_t tot = (int64_t)n * n;
-  k_f32_to_bf16<<<(unsigned)ceil_div(tot, 256), 256, 0, s>>>(src, lds, (__bf16*)dst, ldd, n);
+  k_f32_to_bf16<<<std::max(1, std::min(n, 65535)), 256, 0, s>>>(src, lds, (__bf16*)dst, ldd, n);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 

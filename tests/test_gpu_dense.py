@@ -253,3 +253,20 @@ def test_graph_replay_matches_eager(case):
         P.symnmf_iterate(a, 11)
         P.symnmf_iterate(b, 11)
         assert np.array_equal(factor(a, P.H), factor(b, P.H))
+
+
+@pytest.mark.parametrize("compute", ["f32", "bf16"])
+def test_precision_k64_parity(compute):
+    # The precision sweep's shape at a size the oracle finishes quickly:
+    # 64-component mixture in R^128, k = 64, FP32 X, products in FP32 or BF16.
+    n, k, iters = 6000, 64, 10
+    X, _ = workloads.gaussian_kernel(n, 128, 64, seed=2, dtype=np.float32)
+    ctx = _ctx(X, k, torch.float32, seed=3, compute=(P.BF16 if compute == "bf16" else None))
+    P.symnmf_iterate(ctx, iters)
+    sc = O.data_scalars(X)
+    H0 = round_to(O.initial_factor(n, k, sc["zeta"], seed=3), torch.float32)
+    Wo, Ho, hist = O.plain_symnmf(X, k, sc["maxval"], H0, iters)
+    ro = O.residual_direct(X, Wo, Ho) / np.sqrt(sc["normsq"])
+    r = P.symnmf_residual(ctx, P.RESID_EXACT)[0]
+    log(f"precision k=64 {compute}: residual gpu {r:.8f} oracle {ro:.8f} rel {abs(r - ro) / ro:.2e}")
+    assert abs(r - ro) / ro <= (1e-4 if compute == "f32" else 1e-3)
