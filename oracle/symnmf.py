@@ -307,15 +307,43 @@ def rrf(X_apply, Omega, q):
     return Q
 
 
-def apx_evd(X_apply, Omega, q):
+def ada_rrf(X_apply, normsq, Omega, q_max, tol=1e-3):
+    """Algorithm Ada-RRF (appendix "Adaptive Randomized Range Finder") for a
+    symmetric X.  Q = qr(X Omega); then, while at most q_max rounds:
+    B^T = X^T Q (= X Q), the normalised QB residual
+    sqrt((||X||^2 - ||B||_F^2) / ||X||^2) (the trace identity of that
+    appendix), Q = qr(B^T); stop when the residual fell by less than `tol`
+    since the previous check (reading: absolute decrease, first check compared
+    with +infinity); otherwise Y = X Q and Q = qr(Y).
+    Returns (Q, number of completed rounds, residuals of the checks)."""
+    Q = _qr_positive(X_apply(Omega))
+    prev = np.inf
+    res = []
+    rounds = 0
+    for _ in range(q_max):
+        B = X_apply(Q)
+        r = np.sqrt(max(normsq - float(np.sum(B * B)), 0.0) / normsq)
+        res.append(r)
+        Q = _qr_positive(B)
+        if prev - r < tol:
+            break
+        prev = r
+        Q = _qr_positive(X_apply(Q))
+        rounds += 1
+    return Q, rounds, res
+
+
+def apx_evd(X_apply, Omega, q, Q=None):
     """Algorithm Apx-EVD: Q = RRF, T = Q^T X Q (one more product with X),
-    T = Q_T Lambda Q_T^T, U = Q Q_T.
+    T = Q_T Lambda Q_T^T, U = Q Q_T.  A basis Q computed elsewhere (Ada-RRF)
+    may be passed instead of running RRF with q.
 
     Readings: eigenvalues sorted descending and negative ones kept (the PSD
     projection is commented out in the source); each column of U is signed so
     that its entry of largest magnitude is positive (first such row on ties).
     """
-    Q = rrf(X_apply, Omega, q)
+    if Q is None:
+        Q = rrf(X_apply, Omega, q)
     T = Q.T @ X_apply(Q)
     T = 0.5 * (T + T.T)
     lam, V = np.linalg.eigh(T)

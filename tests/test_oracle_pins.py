@@ -311,6 +311,43 @@ def test_qb_residual_identity_and_bounds():
     assert qb >= np.sqrt(np.sum(d[l:] ** 2)) * (1 - 1e-12)
 
 
+def test_ada_rrf_checks_and_special_cases():
+    # Algorithm Ada-RRF: every reported check equals the QB residual formed
+    # directly; an infinite tolerance stops at the second check; a tolerance
+    # of -infinity runs q_max rounds and then spans the RRF basis with
+    # q = q_max; an exact rank-r input (r <= l) is captured at once.
+    rng = np.random.default_rng(12)
+    n, l = 300, 14
+    V, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    d = 0.9 ** np.arange(n)
+    X = (V * d) @ V.T
+    nx = float(np.sum(X * X))
+    Om = O.sketch_omega(n, l, 6)
+    # residual checks against the direct formation ||Q Q^T X - X|| / ||X||
+    Q0 = O._qr_positive(X @ Om)
+    Q, rounds, res = O.ada_rrf(lambda M: X @ M, nx, Om, q_max=1, tol=-np.inf)
+    assert rounds == 1 and len(res) == 1
+    assert res[0] == pytest.approx(np.linalg.norm(Q0 @ (Q0.T @ X) - X) / np.sqrt(nx), rel=1e-9)
+    # the first check is compared with +infinity, so even an infinite
+    # tolerance stops only at the second check
+    Q, rounds, res = O.ada_rrf(lambda M: X @ M, nx, Om, q_max=5, tol=np.inf)
+    assert rounds == 1 and len(res) == 2
+    Q, rounds, res = O.ada_rrf(lambda M: X @ M, nx, Om, q_max=3, tol=-np.inf)
+    Qr = O.rrf(lambda M: X @ M, Om, 3)
+    assert rounds == 3 and len(res) == 3
+    assert np.linalg.norm(Q @ Q.T - Qr @ Qr.T) <= 1e-9
+    # the residual of the best rank-l approximation bounds every check
+    assert min(res) >= np.sqrt(np.sum(d[l:] ** 2) / nx) * (1 - 1e-12)
+    # exact low rank: the first check is ~0, the second stops the loop
+    r = 9
+    Z = rng.random((n, r))
+    Xl = Z @ Z.T
+    nl = float(np.sum(Xl * Xl))
+    Q, rounds, res = O.ada_rrf(lambda M: Xl @ M, nl, Om, q_max=6, tol=1e-3)
+    assert rounds == 1 and len(res) == 2 and res[0] <= 1e-6
+    assert np.linalg.norm(Q @ (Q.T @ Xl) - Xl) <= 1e-10 * np.linalg.norm(Xl)
+
+
 def test_lai_equals_plain_when_input_is_low_rank():
     # X of exact rank <= l: U Lambda U^T = X, so LAI-SymNMF reproduces the
     # plain iteration.
