@@ -13,7 +13,9 @@ lai (Algorithm LAI-SymNMF from the random start until its own residual
 stalls, then refinement on X until the residual on X is r*), learned (the learned start -- LAI basis
 l = k + 16, q = 2, the trained network of paper_2402_08134_amd/weights and
 the least-squares scale fit -- then iterations on X) and learned_lai (the
-learned start, LAI iterations as in lai, then refinement on X).
+learned start, LAI iterations as in lai, then refinement on X); also
+learned_lai_ada, the same with the basis of Algorithm Ada-RRF (q chosen on
+the fly, tolerance 1e-3, at most 10 rounds) instead of q = 2.
 `value` is seconds per solve of learned_lai; every method's time, iteration
 counts, final residual and speed-up over plain are in `config.methods`.
 
@@ -106,7 +108,7 @@ def main():
 
     def solve(method, seed, timing):
         """One solve to r*; returns (context, iterations, iterations on X)."""
-        lai_stage = method in ("lai", "learned_lai")
+        lai_stage = method in ("lai", "learned_lai", "learned_lai_ada")
         # LAI stage until its own residual stalls (stopping it at r* instead
         # leaves the residual on X far above r*: measured slower); then
         # iterations on X until the residual on X is r*
@@ -116,15 +118,18 @@ def main():
         if method == "plain":
             it = P.symnmf_iterate(c, 4000)
             return c, it, it
-        P.symnmf_lai(c, l, q)
-        if method in ("learned", "learned_lai"):
+        if method.endswith("_ada"):
+            P.symnmf_lai_adaptive(c, l, 10, 1e-3)
+        else:
+            P.symnmf_lai(c, l, q)
+        if method.startswith("learned"):
             P.symnmf_warmstart(c, net, want_beta=False)
         it = P.symnmf_iterate(c, 2000) if lai_stage else 0
         P.symnmf_refine(c, P.STOP_TARGET, r_star)
         it2 = P.symnmf_iterate(c, 4000)
         return c, it + it2, it2
 
-    methods = ["plain", "lai", "learned", "learned_lai"]
+    methods = ["plain", "lai", "learned", "learned_lai", "learned_lai_ada"]
     for w in range(args.warmup):
         for m in methods:
             solve(m, 100 + w, 0)

@@ -205,12 +205,27 @@ int symnmf_create(symnmf_ctx** out, const symnmf_matrix* X, int32_t k, double al
 
 /* Build the low-rank approximate input X ~ U Lambda U^T with Algorithm
  * Apx-EVD (randomized range finder, Algorithm RRF, with 2q+1 products by X,
- * each followed by CholeskyQR2 in FP64; T = Q^T X Q; Jacobi EVD of T;
+ * each followed by CholeskyQR in FP64, CholeskyQR2 after the last one;
+ * T = Q^T X Q; Jacobi EVD of T;
  * U = Q Q_T) and switch the context to LAI mode (Algorithm LAI-SymNMF).
  * Requires dense X and no sampling.  l: k <= l <= min(n, 96).  q >= 0.
  * Errors: E_INVALID, E_UNSUPPORTED (CSR or s > 0), E_NUMERIC (CholeskyQR2
  * breakdown even with the shift), E_STATE. */
 int symnmf_lai(symnmf_ctx* ctx, int32_t l, int32_t q);
+
+/* Algorithm Ada-RRF (appendix "Adaptive Randomized Range Finder") followed
+ * by Apx-EVD, as symnmf_lai but with the number of power iterations chosen
+ * on the fly: Q = qr(X Omega); then up to q_max rounds of B^T = X Q, the
+ * normalised QB residual sqrt((||X||^2 - ||B||_F^2) / ||X||^2) (the trace
+ * identity of that appendix), Q = qr(B^T), stop when the residual fell by
+ * less than tol since the previous round (the paper uses 1e-3; the first
+ * round is compared with +infinity), otherwise Y = X Q, Q = qr(Y).
+ * *rounds (may be NULL): completed rounds (each one two products with X);
+ * *qb_residual (may be NULL): the last residual checked.  Synchronises once
+ * per round.  E_INVALID for q_max outside 1..64 or tol < 0; otherwise as
+ * symnmf_lai. */
+int symnmf_lai_adaptive(symnmf_ctx* ctx, int32_t l, int32_t q_max, double tol, int32_t* rounds,
+                        double* qb_residual);
 
 /* Iterative refinement (Section 3.3, "Iterative Refinement"): switch a
  * context in LAI mode back to the full X for the following iterations, keeping

@@ -63,6 +63,8 @@ _SIGS = {
                                      ctypes.c_int64, ctypes.c_uint64, ctypes.POINTER(Options), _VP]),
     "symnmf_lai": (ctypes.c_int, [_VP, ctypes.c_int32, ctypes.c_int32]),
     "symnmf_refine": (ctypes.c_int, [_VP, ctypes.c_int32, ctypes.c_double]),
+    "symnmf_lai_adaptive": (ctypes.c_int, [_VP, ctypes.c_int32, ctypes.c_int32, ctypes.c_double,
+                                           ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double)]),
     "symnmf_iterate": (ctypes.c_int, [_VP, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]),
     "symnmf_residual": (ctypes.c_int, [_VP, ctypes.c_int32, ctypes.POINTER(ctypes.c_double)]),
     "symnmf_set_factor": (ctypes.c_int, [_VP, ctypes.c_int32, _VP, ctypes.c_int32]),
@@ -181,6 +183,15 @@ def symnmf_create(X, k, alpha=0.0, s=0, seed=0, options=None, stream=None):
 
 def symnmf_lai(ctx, l, q):
     _check(lib().symnmf_lai(ctx.handle, int(l), int(q)), ctx.handle)
+
+
+def symnmf_lai_adaptive(ctx, l, q_max=10, tol=1e-3):
+    """Returns (completed rounds, last QB residual)."""
+    rounds = ctypes.c_int32()
+    res = ctypes.c_double()
+    _check(lib().symnmf_lai_adaptive(ctx.handle, int(l), int(q_max), float(tol), ctypes.byref(rounds),
+                                     ctypes.byref(res)), ctx.handle)
+    return rounds.value, res.value
 
 
 def symnmf_refine(ctx, stop_mode=STOP_NONE, target=0.0):

@@ -1057,50 +1057,89 @@ int symnmf_create(symnmf_ctx** out, const symnmf_matrix* X, int32_t k, double al
   return SYMNMF_OK;
 }
 
+namespace {
+
+// Validation and (re)allocation of the LAI buffers for rank l.
+void lai_prepare(symnmf_ctx* c, int l) {
+  if (c->kind != SYMNMF_DENSE) throw Fail{SYMNMF_E_UNSUPPORTED, "LAI needs dense X"};
+  if (c->mode == SYMNMF_MODE_LVS) throw Fail{SYMNMF_E_UNSUPPORTED, "LAI with sampling"};
+  if (l < c->k || l > 96 || l > c->n) throw Fail{SYMNMF_E_INVALID, "need k <= l <= min(n, 96)"};
+  const int n = c->n;
+  if (c->l != l) {
+    double** bufs[] = {&c->Q, &c->Q1, &c->U, &c->YQ, &c->Tm, &c->QT, &c->Vw, &c->lam, &c->Rl, &c->Rlinv, &c->Z};
+    c->sync();
+    for (double** b : bufs) {
+      dfree(*b);
+      *b = nullptr;
+    }
+    c->l = l;
+    c->Q = dalloc<double>((size_t)n * l);
+    c->Q1 = dalloc<double>((size_t)n * l);
+    c->U = dalloc<double>((size_t)n * l);
+    c->YQ = dalloc<double>((size_t)n * l);  // holds fdtype values
+    c->Tm = dalloc<double>((size_t)l * l);
+    c->QT = dalloc<double>((size_t)l * l);
+    c->Vw = dalloc<double>((size_t)l * l);
+    c->lam = dalloc<double>(l);
+    c->Rl = dalloc<double>((size_t)l * l);
+    c->Rlinv = dalloc<double>((size_t)l * l);
+    c->Z = dalloc<double>((size_t)l * c->k);
+    dfree(c->M_W);
+    dfree(c->M_H);
+    const size_t need = (size_t)c->k * c->k + (size_t)l * c->k;
+    if (need > c->pcap) {
+      dfree(c->part);
+      dfree(c->part_l1);
+      c->part = nullptr;
+      c->part_l1 = nullptr;
+      c->pcap = need;
+      c->part = dalloc<double>((size_t)c->nbu * c->pcap);
+      c->part_l1 = dalloc<double>((size_t)ceil_div(c->nbu, 32) * c->pcap);
+    }
+    c->M_W = dalloc<double>((size_t)l * c->kp);
+    c->M_H = dalloc<double>((size_t)l * c->kp);
+    HIPCHK(hipMemsetAsync(c->M_W, 0, sizeof(double) * l * c->kp, c->st));
+    HIPCHK(hipMemsetAsync(c->M_H, 0, sizeof(double) * l * c->kp, c->st));
+  }
+  HIPCHK(hipMemsetAsync(c->d_fail, 0, sizeof(int), c->st));
+}
+
+// Algorithm Apx-EVD on the basis in c->Q, then the switch to LAI mode.
+void lai_finish(symnmf_ctx* c) {
+  const int n = c->n, l = c->l;
+  {
+    symnmf_ctx::Timed tm(c, SYMNMF_PHASE_LAI);
+    // Algorithm Apx-EVD: T = Q^T (X Q), T = Q_T Lambda Q_T^T, U = Q Q_T.
+    c->product(c->Q, SYMNMF_F64, l, c->YQ);
+    c->ws.reset();
+    LCHK(gram(c->Q, SYMNMF_F64, l, l, c->YQ, c->fdtype, l, l, n, nullptr, nullptr, nullptr, 0, c->ws, c->Tm,
+            nullptr, 0, 0.0, nullptr, c->st));
+    LCHK(jacobi_evd(c->Tm, l, c->QT, c->lam, c->st));
+    LCHK(rowmat(c->Q, SYMNMF_F64, l, n, l, c->QT, nullptr, l, c->U, SYMNMF_F64, l, nullptr, c->st));
+    c->ws.reset();
+    LCHK(column_sign_fix(c->U, n, l, c->ws, c->st));
+    frob_dot(c->lam, c->lam, l, c->d_scal + 8, c->st);
+  }
+  HIPCHK(hipMemcpyAsync(c->hbuf, c->d_scal + 8, sizeof(double), hipMemcpyDeviceToHost, c->st));
+  HIPCHK(hipMemcpyAsync(c->hbuf + 1, c->d_fail, sizeof(int), hipMemcpyDeviceToHost, c->st));
+  c->sync();
+  c->normsq_lai = c->hbuf[0];
+  int failed = 0;
+  std::memcpy(&failed, c->hbuf + 1, sizeof(int));
+  if (failed) throw Fail{SYMNMF_E_NUMERIC, "CholeskyQR2 broke down"};
+  if (!(c->normsq_lai > 0.0)) throw Fail{SYMNMF_E_NUMERIC, "low-rank approximation is zero"};
+  c->mode = SYMNMF_MODE_LAI;
+  c->mW_ok = c->mH_ok = false;
+  c->bump_generation();
+}
+
+}  // namespace
+
 int symnmf_lai(symnmf_ctx* c, int32_t l, int32_t q) {
   return guarded(c, [&] {
-    if (c->kind != SYMNMF_DENSE) throw Fail{SYMNMF_E_UNSUPPORTED, "LAI needs dense X"};
-    if (c->mode == SYMNMF_MODE_LVS) throw Fail{SYMNMF_E_UNSUPPORTED, "LAI with sampling"};
-    if (l < c->k || l > 96 || l > c->n) throw Fail{SYMNMF_E_INVALID, "need k <= l <= min(n, 96)"};
     if (q < 0 || q > 64) throw Fail{SYMNMF_E_INVALID, "q out of range"};
+    lai_prepare(c, l);
     const int n = c->n;
-    if (c->l != l) {
-      double** bufs[] = {&c->Q, &c->Q1, &c->U, &c->YQ, &c->Tm, &c->QT, &c->Vw, &c->lam, &c->Rl, &c->Rlinv, &c->Z};
-      c->sync();
-      for (double** b : bufs) {
-        dfree(*b);
-        *b = nullptr;
-      }
-      c->l = l;
-      c->Q = dalloc<double>((size_t)n * l);
-      c->Q1 = dalloc<double>((size_t)n * l);
-      c->U = dalloc<double>((size_t)n * l);
-      c->YQ = dalloc<double>((size_t)n * l);  // holds fdtype values
-      c->Tm = dalloc<double>((size_t)l * l);
-      c->QT = dalloc<double>((size_t)l * l);
-      c->Vw = dalloc<double>((size_t)l * l);
-      c->lam = dalloc<double>(l);
-      c->Rl = dalloc<double>((size_t)l * l);
-      c->Rlinv = dalloc<double>((size_t)l * l);
-      c->Z = dalloc<double>((size_t)l * c->k);
-      dfree(c->M_W);
-      dfree(c->M_H);
-      const size_t need = (size_t)c->k * c->k + (size_t)l * c->k;
-      if (need > c->pcap) {
-        dfree(c->part);
-        dfree(c->part_l1);
-        c->part = nullptr;
-        c->part_l1 = nullptr;
-        c->pcap = need;
-        c->part = dalloc<double>((size_t)c->nbu * c->pcap);
-        c->part_l1 = dalloc<double>((size_t)ceil_div(c->nbu, 32) * c->pcap);
-      }
-      c->M_W = dalloc<double>((size_t)l * c->kp);
-      c->M_H = dalloc<double>((size_t)l * c->kp);
-      HIPCHK(hipMemsetAsync(c->M_W, 0, sizeof(double) * l * c->kp, c->st));
-      HIPCHK(hipMemsetAsync(c->M_H, 0, sizeof(double) * l * c->kp, c->st));
-    }
-    HIPCHK(hipMemsetAsync(c->d_fail, 0, sizeof(int), c->st));
     // Algorithm RRF: Omega Gaussian (Philox), then 2q+1 products each followed
     // by CholeskyQR (re-orthonormalising after every product; CholeskyQR2
     // after the last one).
@@ -1111,28 +1150,51 @@ int symnmf_lai(symnmf_ctx* c, int32_t l, int32_t q) {
         c->product(c->Q, SYMNMF_F64, l, c->YQ);
         c->cholqr(c->YQ, it == 2 * q);
       }
-      // Algorithm Apx-EVD: T = Q^T (X Q), T = Q_T Lambda Q_T^T, U = Q Q_T.
-      c->product(c->Q, SYMNMF_F64, l, c->YQ);
-      c->ws.reset();
-      LCHK(gram(c->Q, SYMNMF_F64, l, l, c->YQ, c->fdtype, l, l, n, nullptr, nullptr, nullptr, 0, c->ws, c->Tm,
-                nullptr, 0, 0.0, nullptr, c->st));
-      LCHK(jacobi_evd(c->Tm, l, c->QT, c->lam, c->st));
-      LCHK(rowmat(c->Q, SYMNMF_F64, l, n, l, c->QT, nullptr, l, c->U, SYMNMF_F64, l, nullptr, c->st));
-      c->ws.reset();
-      LCHK(column_sign_fix(c->U, n, l, c->ws, c->st));
-      frob_dot(c->lam, c->lam, l, c->d_scal + 8, c->st);
     }
-    HIPCHK(hipMemcpyAsync(c->hbuf, c->d_scal + 8, sizeof(double), hipMemcpyDeviceToHost, c->st));
-    HIPCHK(hipMemcpyAsync(c->hbuf + 1, c->d_fail, sizeof(int), hipMemcpyDeviceToHost, c->st));
-    c->sync();
-    c->normsq_lai = c->hbuf[0];
-    int failed = 0;
-    std::memcpy(&failed, c->hbuf + 1, sizeof(int));
-    if (failed) throw Fail{SYMNMF_E_NUMERIC, "CholeskyQR2 broke down"};
-    if (!(c->normsq_lai > 0.0)) throw Fail{SYMNMF_E_NUMERIC, "low-rank approximation is zero"};
-    c->mode = SYMNMF_MODE_LAI;
-    c->mW_ok = c->mH_ok = false;
-    c->bump_generation();
+    lai_finish(c);
+  });
+}
+
+int symnmf_lai_adaptive(symnmf_ctx* c, int32_t l, int32_t q_max, double tol, int32_t* rounds_out,
+                        double* qb_residual) {
+  return guarded(c, [&] {
+    if (q_max < 1 || q_max > 64) throw Fail{SYMNMF_E_INVALID, "q_max out of range"};
+    if (!(tol >= 0.0)) throw Fail{SYMNMF_E_INVALID, "tol must be >= 0"};
+    lai_prepare(c, l);
+    const int n = c->n;
+    const int64_t nl = (int64_t)n * l;
+    // Algorithm Ada-RRF: Q = qr(X Omega); each round B^T = X Q, the
+    // normalised QB residual sqrt((||X||^2 - ||B||_F^2) / ||X||^2) (trace
+    // identity), Q = qr(B^T); stop when the residual fell by less than tol,
+    // else Y = X Q, Q = qr(Y).  A basis that may be returned is made
+    // orthonormal to working precision (CholeskyQR2).
+    int rounds = 0;
+    double prev = INFINITY, r = 0.0;
+    {
+      symnmf_ctx::Timed tm(c, SYMNMF_PHASE_LAI);
+      LCHK(gen_gaussian(c->Q, nl, c->seed, 0, TAG_OMEGA, c->st));
+      c->product(c->Q, SYMNMF_F64, l, c->YQ);
+      c->cholqr(c->YQ, false);
+      for (int j = 0; j < q_max; ++j) {
+        c->product(c->Q, SYMNMF_F64, l, c->YQ);
+        c->ws.reset();
+        double* part = nullptr;
+        const int nb = dot_partials(c->YQ, c->YQ, c->fdtype, nl, c->ws, &part, nullptr, c->st);
+        if (nb < 0) throw Fail{SYMNMF_E_DEVICE, "dot launch failed"};
+        sum_partials(part, nb, c->d_scal + 5, c->st);
+        c->cholqr(c->YQ, true);
+        const double b2 = c->readback(c->d_scal + 5, 1)[0];
+        r = std::sqrt(std::fmax(c->normsq - b2, 0.0) / c->normsq);
+        if (prev - r < tol) break;
+        prev = r;
+        c->product(c->Q, SYMNMF_F64, l, c->YQ);
+        c->cholqr(c->YQ, j == q_max - 1);
+        ++rounds;
+      }
+    }
+    lai_finish(c);
+    if (rounds_out) *rounds_out = rounds;
+    if (qb_residual) *qb_residual = r;
   });
 }
 

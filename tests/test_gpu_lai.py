@@ -110,3 +110,28 @@ def test_lai_then_refinement_parity():
     with pytest.raises(P.SymNMFError) as e:
         P.symnmf_refine(ctx, P.STOP_NONE, 0.0)      # no longer in LAI mode
     assert e.value.code == P.E_STATE
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_ada_rrf_parity(dtype):
+    # Algorithm Ada-RRF: the same number of rounds as the oracle (its residual
+    # drops are 2.5e-2 then 6.2e-4 against the 1e-3 tolerance, far from a tie),
+    # the same last QB residual, and the same Apx-EVD of the resulting basis.
+    n, k, l, seed = 1500, 16, 32, 11
+    X, _ = workloads.gaussian_kernel(n, 32, 16, seed=7, dtype=np.float64)
+    tdt = torch.float64 if dtype == "f64" else torch.float32
+    Xo = round_to(X, tdt)
+    ctx = P.symnmf_create(dev(X, tdt), k, 0.0, 0, seed)
+    rounds, r = P.symnmf_lai_adaptive(ctx, l, 10, 1e-3)
+    nx = float(np.sum(Xo * Xo))
+    Qo, rounds_o, res = O.ada_rrf(lambda M: O.apply_x(Xo, M), nx, O.sketch_omega(n, l, seed), 10, 1e-3)
+    log(f"ada-rrf {dtype}: rounds gpu {rounds} oracle {rounds_o}; residual gpu {r:.8f} oracle {res[-1]:.8f}")
+    assert rounds == rounds_o == 2
+    assert abs(r - res[-1]) / res[-1] <= (1e-10 if dtype == "f64" else 1e-5)
+    Uo, lo = O.apx_evd(lambda M: O.apply_x(Xo, M), None, 0, Q=Qo)
+    lam = torch.empty(l, dtype=torch.float64, device="cuda")
+    P.symnmf_get_lai(ctx, None, lam)
+    assert rel(host(lam), lo) <= (1e-10 if dtype == "f64" else 2e-4)
+    with pytest.raises(P.SymNMFError) as e:
+        P.symnmf_lai_adaptive(ctx, l, 0, 1e-3)
+    assert e.value.code == P.E_INVALID
