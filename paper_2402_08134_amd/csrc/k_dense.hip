@@ -376,6 +376,159 @@ __global__ __launch_bounds__(256) void k_f32_to_bf16(const float* __restrict__ s
   }
 }
 
+// FP32 product on the BF16 matrix cores.  Every FP32 value x is split
+// exactly as x = hi + mid + lo with hi = bf16(x), mid = bf16(x - hi),
+// lo = bf16(x - hi - mid) (each subtraction is exact in FP32: the rounded
+// part shares the leading bits), so |x - hi - mid - lo| <= 2^-24 |x|.  The
+// product uses the six pairs of pieces whose weights reach 2^-16
+// (hh, hm, mh, hl, mm, lh) with FP32 accumulation; the dropped pairs weigh
+// 2^-24 and below, the size of FP32 rounding.  Six v_mfma_f32_16x16x32_bf16
+// replace the eight v_mfma_f32_16x16x4f32 of a 32-wide K step and take about
+// a third of their matrix-core time, but the splitting adds about five
+// vector instructions per loaded element (of X and of the B panel): on
+// MI355X at n = 16384, k = 32..64 and n = 65536, k = 64 the kernel runs at
+// the speed of the FP32 one (within 7%), with a smaller error (relative
+// 3e-7 against 5e-7).  Layout and pipelining follow k_gemm_mfma: LDS-free,
+// 16 * RT rows per wave, two register stages of raw FP32 loads; the
+// operand lanes follow the BF16 instruction (lane (li, lg) holds K elements
+// 8 lg .. 8 lg + 7 of row li of X and of row li of the B panel).
+__device__ __forceinline__ void split3(const floatx8& x, bf16x8& h, bf16x8& m, bf16x8& l) {
+  h = __builtin_convertvector(x, bf16x8);
+  const floatx8 r1 = x - __builtin_convertvector(h, floatx8);
+  m = __builtin_convertvector(r1, bf16x8);
+  const floatx8 r2 = r1 - __builtin_convertvector(m, floatx8);
+  l = __builtin_convertvector(r2, bf16x8);
+}
+
+__device__ __forceinline__ floatx4 mfma_x3(const bf16x8& ah, const bf16x8& am, const bf16x8& al, const bf16x8& bh,
+                                           const bf16x8& bm, const bf16x8& bl, floatx4 acc) {
+  // smallest terms first
+  acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh, acc, 0, 0, 0);
+  acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(am, bm, acc, 0, 0, 0);
+  acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl, acc, 0, 0, 0);
+  acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(am, bh, acc, 0, 0, 0);
+  acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bm, acc, 0, 0, 0);
+  acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, acc, 0, 0, 0);
+  return acc;
+}
+
+template <int NT, int RT, bool VEC>
+__global__ __launch_bounds__(256) void k_gemm_x3(const float* __restrict__ X, int64_t ldx, const float* __restrict__ Bt,
+                                                 int64_t ldt, int n, int kchunk, float* __restrict__ P, int cp,
+                                                 const DevState* __restrict__ st) {
+  if (stopped(st)) return;
+  constexpr int SS = GEMM_KT / 32;  // 32-wide K steps per tile
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int li = lane & 15, lg = lane >> 4;
+  const int row_base = (blockIdx.x * 4 + wave) * (16 * RT);
+  if (row_base >= n) return;
+  const int kb = blockIdx.y * kchunk;
+  const int ke = min(n, kb + kchunk);
+
+  floatx4 acc[RT][NT];
+#pragma unroll
+  for (int r = 0; r < RT; ++r)
+#pragma unroll
+    for (int t = 0; t < NT; ++t) acc[r][t] = floatx4{0, 0, 0, 0};
+
+  const float* xrow[RT];
+#pragma unroll
+  for (int r = 0; r < RT; ++r) xrow[r] = X + (int64_t)min(row_base + 16 * r + li, n - 1) * ldx + 8 * lg;
+  const float* brow[NT];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) brow[t] = Bt + (int64_t)(16 * t + li) * ldt + 8 * lg;
+
+  const int nfull = VEC ? (ke - kb) / GEMM_KT : 0;
+  floatx4 x0[RT][SS][2], b0[NT][SS][2], x1[RT][SS][2], b1[NT][SS][2];
+  auto load = [&](floatx4 (&xv)[RT][SS][2], floatx4 (&bv)[NT][SS][2], int k0) {
+#pragma unroll
+    for (int r = 0; r < RT; ++r)
+#pragma unroll
+      for (int ss = 0; ss < SS; ++ss)
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+          xv[r][ss][h] = __builtin_nontemporal_load((const floatx4*)(xrow[r] + k0 + 32 * ss + 4 * h));
+#pragma unroll
+    for (int ct = 0; ct < NT; ++ct)
+#pragma unroll
+      for (int ss = 0; ss < SS; ++ss)
+#pragma unroll
+        for (int h = 0; h < 2; ++h) bv[ct][ss][h] = *(const floatx4*)(brow[ct] + k0 + 32 * ss + 4 * h);
+  };
+  auto join = [](const floatx4& a, const floatx4& b) {
+    return floatx8{a[0], a[1], a[2], a[3], b[0], b[1], b[2], b[3]};
+  };
+  auto compute = [&](const floatx4 (&xv)[RT][SS][2], const floatx4 (&bv)[NT][SS][2]) {
+#pragma unroll
+    for (int ss = 0; ss < SS; ++ss) {
+      bf16x8 bh[NT], bm[NT], bl[NT];
+#pragma unroll
+      for (int ct = 0; ct < NT; ++ct) split3(join(bv[ct][ss][0], bv[ct][ss][1]), bh[ct], bm[ct], bl[ct]);
+#pragma unroll
+      for (int r = 0; r < RT; ++r) {
+        bf16x8 xh, xm, xl;
+        split3(join(xv[r][ss][0], xv[r][ss][1]), xh, xm, xl);
+#pragma unroll
+        for (int ct = 0; ct < NT; ++ct) acc[r][ct] = mfma_x3(xh, xm, xl, bh[ct], bm[ct], bl[ct], acc[r][ct]);
+      }
+    }
+  };
+  int t = 0;
+  if (nfull > 0) load(x0, b0, kb);
+  for (; t + 2 < nfull; t += 2) {
+    load(x1, b1, kb + (t + 1) * GEMM_KT);
+    compute(x0, b0);
+    load(x0, b0, kb + (t + 2) * GEMM_KT);
+    compute(x1, b1);
+  }
+  if (t + 1 < nfull) {
+    load(x1, b1, kb + (t + 1) * GEMM_KT);
+    compute(x0, b0);
+    compute(x1, b1);
+  } else if (t < nfull) {
+    compute(x0, b0);
+  }
+  // Remaining K (partial last tile, or all of it when X is not aligned for
+  // vector loads): guarded scalar loads of X; the B panel is zero padded.
+  for (int k0 = kb + nfull * GEMM_KT; k0 < ke; k0 += GEMM_KT) {
+#pragma unroll
+    for (int ss = 0; ss < SS; ++ss) {
+      floatx8 bs[NT];
+#pragma unroll
+      for (int ct = 0; ct < NT; ++ct)
+#pragma unroll
+        for (int u = 0; u < 8; ++u) bs[ct][u] = brow[ct][k0 + 32 * ss + u];
+      bf16x8 bh[NT], bm[NT], bl[NT];
+#pragma unroll
+      for (int ct = 0; ct < NT; ++ct) split3(bs[ct], bh[ct], bm[ct], bl[ct]);
+#pragma unroll
+      for (int r = 0; r < RT; ++r) {
+        floatx8 xs;
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const int col = k0 + 32 * ss + 8 * lg + u;
+          xs[u] = (col < ke) ? xrow[r][col - 8 * lg] : 0.0f;
+        }
+        bf16x8 xh, xm, xl;
+        split3(xs, xh, xm, xl);
+#pragma unroll
+        for (int ct = 0; ct < NT; ++ct) acc[r][ct] = mfma_x3(xh, xm, xl, bh[ct], bm[ct], bl[ct], acc[r][ct]);
+      }
+    }
+  }
+  float* out = P + (int64_t)blockIdx.y * n * cp;
+#pragma unroll
+  for (int r = 0; r < RT; ++r)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int row = row_base + 16 * r + 4 * lg + v;
+      if (row < n) {
+#pragma unroll
+        for (int ct = 0; ct < NT; ++ct) out[(int64_t)row * cp + 16 * ct + li] = acc[r][ct][v];
+      }
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Exact residual pass: sum over all (i, j) of (X_ij - w_i . h_j)^2 in FP64.
 // A 64 x 64 tile per workgroup; the factor rows of the tile are staged in LDS
@@ -478,6 +631,25 @@ int dispatch_mfma(int nt, int rt, const TX* X, int64_t ldx, bool vec, const TX* 
 #undef CASE
   return -1;
 }
+template <int NT, int RT>
+void launch_x3(const float* X, int64_t ldx, bool vec, const float* Bt, int64_t ldt, int n, const GemmPlan& p, float* P,
+               const DevState* st, hipStream_t s) {
+  dim3 g(ceil_div(n, 4 * 16 * RT), p.splits);
+  if (vec)
+    k_gemm_x3<NT, RT, true><<<g, 256, 0, s>>>(X, ldx, Bt, ldt, n, p.kchunk, P, p.cp, st);
+  else
+    k_gemm_x3<NT, RT, false><<<g, 256, 0, s>>>(X, ldx, Bt, ldt, n, p.kchunk, P, p.cp, st);
+}
+
+int dispatch_x3(int nt, int rt, const float* X, int64_t ldx, bool vec, const float* Bt, int64_t ldt, int n,
+                const GemmPlan& p, float* P, const DevState* st, hipStream_t s) {
+#define CASE(NT_, RT_) \
+  if (nt == NT_ && rt == RT_) { launch_x3<NT_, RT_>(X, ldx, vec, Bt, ldt, n, p, P, st, s); return 0; }
+  CASE(1, 4) CASE(2, 4) CASE(1, 2) CASE(2, 2) CASE(3, 2) CASE(4, 2) CASE(5, 2) CASE(6, 2)
+#undef CASE
+  return -1;
+}
+
 int dispatch_bf16(int nt, int rt, const __bf16* X, int64_t ldx, bool vec, const __bf16* Bt, int64_t ldt, int n,
                   const GemmPlan& p, float* P, const DevState* st, hipStream_t s) {
 #define CASE(NT_, RT_) \
@@ -490,6 +662,8 @@ int dispatch_bf16(int nt, int rt, const __bf16* X, int64_t ldx, bool vec, const 
 
 GemmPlan gemm_plan(int n, int c, int compute_dtype) {
   GemmPlan p;
+  p.split3 = compute_dtype == SYMNMF_F32X3;
+  if (p.split3) compute_dtype = SYMNMF_F32;
   p.cp = 16 * ceil_div(c, 16);
   p.rt = pick_rt(compute_dtype, p.cp / 16);
   const int kt = compute_dtype == SYMNMF_BF16 ? BF_KT : GEMM_KT;
@@ -517,7 +691,11 @@ int dense_gemm_bt(const void* X, int xdtype, int64_t ldx, const void* Bt, int n,
     rc = dispatch_mfma<double>(nt, p.rt, (const double*)X, ldx, vec, (const double*)Bt, p.ldt, n, p, (double*)P, st, s);
   } else if (xdtype == SYMNMF_F32) {
     const bool vec = (ldx % 4 == 0) && ((uintptr_t)X % 16 == 0);
-    rc = dispatch_mfma<float>(nt, p.rt, (const float*)X, ldx, vec, (const float*)Bt, p.ldt, n, p, (float*)P, st, s);
+    if (p.split3)
+      rc = dispatch_x3(nt, p.rt, (const float*)X, ldx, vec, (const float*)Bt, p.ldt, n, p, (float*)P, st, s);
+    else
+      rc = dispatch_mfma<float>(nt, p.rt, (const float*)X, ldx, vec, (const float*)Bt, p.ldt, n, p, (float*)P, st,
+                                s);
   } else {
     const bool vec = (ldx % 8 == 0) && ((uintptr_t)X % 16 == 0);
     rc = dispatch_bf16(nt, p.rt, (const __bf16*)X, ldx, vec, (const __bf16*)Bt, p.ldt, n, p, (float*)P, st, s);
@@ -561,8 +739,13 @@ int dense_gemm(const void* X, int xdtype, int64_t ldx, const void* B, int bdtype
     else
       k_transpose_pad<double, float><<<tg, 256, 0, s>>>((const double*)B, ldb, n, c, (float*)Bt, p.ldt, p.cp, st);
     const bool vec = (ldx % 4 == 0) && ((uintptr_t)X % 16 == 0);
-    if (dispatch_mfma<float>(nt, p.rt, (const float*)X, ldx, vec, (const float*)Bt, p.ldt, n, p, (float*)P, st, s))
+    if (p.split3) {
+      if (dispatch_x3(nt, p.rt, (const float*)X, ldx, vec, (const float*)Bt, p.ldt, n, p, (float*)P, st, s))
+        return -1;
+    } else if (dispatch_mfma<float>(nt, p.rt, (const float*)X, ldx, vec, (const float*)Bt, p.ldt, n, p, (float*)P,
+                                    st, s)) {
       return -1;
+    }
   } else {
     if (bdtype == SYMNMF_F32)
       k_transpose_pad<float, __bf16><<<tg, 256, 0, s>>>((const float*)B, ldb, n, c, (__bf16*)Bt, p.ldt, p.cp, st);

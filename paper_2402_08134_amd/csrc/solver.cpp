@@ -452,7 +452,7 @@ struct symnmf_ctx {
   void product(const void* B, int bdtype, int c, void* Yout) {
     if (kind == SYMNMF_DENSE) {
       const GemmPlan p = gemm_plan(n, c, cdtype);
-      LCHK(dense_gemm(Xc, cdtype, ldxc(), B, bdtype, c, n, c, p, Bt, P, Yout, fdtype, c, gate_, st));
+      LCHK(dense_gemm(Xc, opdtype(), ldxc(), B, bdtype, c, n, c, p, Bt, P, Yout, fdtype, c, gate_, st));
     } else {
       LCHK(csr_spmm(rp, ci, Xv, xdtype, n, B, bdtype, c, Yout, fdtype, gate_, st));
     }
@@ -494,7 +494,7 @@ struct symnmf_ctx {
       bool& ok = which == SYMNMF_W ? btW_ok : btH_ok;
       if (!ok) {
         const GemmPlan p = gemm_plan(n, k, cdtype);
-        LCHK(factor_transpose(F, fdtype, n, k, which == SYMNMF_W ? BtW : BtH, cdtype, p, nullptr, st));
+        LCHK(factor_transpose(F, fdtype, n, k, which == SYMNMF_W ? BtW : BtH, opdtype(), p, nullptr, st));
         ok = true;
       }
     }
@@ -554,7 +554,7 @@ struct symnmf_ctx {
       const GemmPlan p = gemm_plan(n, k, cdtype);
       {
         Timed tm(this, SYMNMF_PHASE_PRODUCT);
-        LCHK(dense_gemm_bt(Xc, cdtype, ldxc(), side == 0 ? BtH : BtW, n, k, p, P, gate_, st));
+        LCHK(dense_gemm_bt(Xc, opdtype(), ldxc(), side == 0 ? BtH : BtW, n, k, p, P, gate_, st));
       }
       a.P = P;
       a.splits = p.splits;
@@ -562,7 +562,7 @@ struct symnmf_ctx {
       a.Dt = side == 0 ? BtW : BtH;
       a.ldt = p.ldt;
       pdt = cdtype == SYMNMF_F64 ? SYMNMF_F64 : SYMNMF_F32;
-      tdt = cdtype;
+      tdt = opdtype();
     } else {
       {
         Timed tm(this, SYMNMF_PHASE_PRODUCT);
@@ -611,6 +611,9 @@ struct symnmf_ctx {
   }
 
   int64_t ldxc() const { return cdtype == SYMNMF_BF16 && xdtype != SYMNMF_BF16 ? n : ld; }
+  // element type of the product operands (X, B panel): the compute dtype,
+  // except that the three-piece BF16 products read FP32 operands
+  int opdtype() const { return cdtype == SYMNMF_F32X3 ? SYMNMF_F32 : cdtype; }
 
   struct Gate {
     symnmf_ctx* c;
@@ -896,10 +899,12 @@ int symnmf_create(symnmf_ctx** out, const symnmf_matrix* X, int32_t k, double al
       if (c->ld < c->n) throw Fail{SYMNMF_E_INVALID, "ld < n"};
       if (s > 0) throw Fail{SYMNMF_E_UNSUPPORTED, "leverage-score sampling needs CSR X"};
       int cd = c->opt.compute_dtype < 0 ? X->dtype : c->opt.compute_dtype;
+      if (cd == SYMNMF_F32X3 && X->dtype != SYMNMF_F32) throw Fail{SYMNMF_E_UNSUPPORTED, "F32X3 compute needs F32 X"};
       if (cd == SYMNMF_F64 && X->dtype != SYMNMF_F64) throw Fail{SYMNMF_E_UNSUPPORTED, "F64 compute needs F64 X"};
       if (X->dtype == SYMNMF_F64 && cd != SYMNMF_F64) throw Fail{SYMNMF_E_UNSUPPORTED, "F64 X needs F64 compute"};
       if (X->dtype == SYMNMF_BF16 && cd != SYMNMF_BF16) throw Fail{SYMNMF_E_UNSUPPORTED, "BF16 X needs BF16 compute"};
-      if (cd != SYMNMF_F64 && cd != SYMNMF_F32 && cd != SYMNMF_BF16) throw Fail{SYMNMF_E_INVALID, "compute dtype"};
+      if (cd != SYMNMF_F64 && cd != SYMNMF_F32 && cd != SYMNMF_BF16 && cd != SYMNMF_F32X3)
+        throw Fail{SYMNMF_E_INVALID, "compute dtype"};
       c->cdtype = cd;
       c->fdtype = cd == SYMNMF_F64 ? SYMNMF_F64 : SYMNMF_F32;
     } else if (c->kind == SYMNMF_CSR) {
