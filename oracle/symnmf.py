@@ -370,6 +370,95 @@ def lai_symnmf(U, lam, k, alpha, H0, iters, rule="hals", stop=None, target=None)
 
 
 # ----------------------------------------------------------------------------
+# Projected Gauss-Newton with conjugate gradients on the SymNMF objective
+# min_{H >= 0} ||X - H H^T||_F (Section 2.1.3, eq. symnmf_obj; Algorithm
+# LAI-PGNCG-SymNMF in the appendix on LAI-SymNMF).
+# ----------------------------------------------------------------------------
+
+def gn_gradient(XH, H):
+    """g = J^T r with r = vec(X - H H^T): g = -2 (X H - H (H^T H))
+    (Section 2.1.3; XH is the data product of H)."""
+    return -2.0 * (XH - H @ (H.T @ H))
+
+
+def gn_normal_apply(H, P):
+    """J^T J vec(P) for the Jacobian J = -(H kron I) - P_mm (H kron I) of
+    r(H) = vec(X - H H^T): 2 (P H^T H + H P^T H) (Section 2.1.3; the
+    CG product of Algorithm LAI-PGNCG-SymNMF)."""
+    return 2.0 * (P @ (H.T @ H) + H @ (P.T @ H))
+
+
+def gn_direction(XH, H, cg_iters):
+    """Z ~ (J^T J)^+ g by at most cg_iters conjugate-gradient steps from Z = 0
+    on the normal equations J^T J z = J^T r (Section 2.1.3).  The new factor
+    is max(H - Z, 0).
+
+    Readings (the printed pseudo-code updates neither the direction nor uses
+    a separate step name): standard CG, the step length a = e / <P, J^T J P>
+    with e = ||R||_F^2, then R <- R - a J^T J P, Z <- Z + a P and the
+    direction P <- R + (e_new / e) P.  CG stops early (its last Z kept) when
+    <P, J^T J P> is not positive: J^T J is singular along directions H S with
+    S skew-symmetric, and R = 0 at a stationary point."""
+    R = gn_gradient(XH, H)
+    P = R.copy()
+    Z = np.zeros_like(H)
+    e = float(np.sum(R * R))
+    for _ in range(cg_iters):
+        Y = gn_normal_apply(H, P)
+        pap = float(np.sum(P * Y))
+        if not pap > 0.0:
+            break
+        a = e / pap
+        Z = Z + a * P
+        R = R - a * Y
+        e_new = float(np.sum(R * R))
+        P = R + (e_new / e) * P
+        e = e_new
+    return Z
+
+
+def pgncg(X_apply, normsq, H0, iters, cg_iters, stop=None, target=None):
+    """PGNCG-SymNMF: H <- max(H - Z, 0) with Z from gn_direction, one data
+    product X H per iteration.  X_apply(B) is X @ B, or the LAI product
+    U (Lambda (U^T B)) for Algorithm LAI-PGNCG-SymNMF.
+
+    Reading (the paper gives no logging rule for this method): entry t of the
+    history is the normalised residual ||X - H_t H_t^T||_F / ||X||_F of the
+    factor iteration t starts from, by the trace identity with the product
+    that iteration computes anyway (Appendix "Fast residual evaluation");
+    the stop rule sees it before the step, so a stop keeps H_t.
+    Returns H and the history."""
+    H = np.array(H0, dtype=np.float64, copy=True)
+    nx = np.sqrt(normsq)
+    hist = []
+    for _ in range(iters):
+        XH = X_apply(H)
+        r = residual_trace(normsq, H, H, XH) / nx
+        hist.append(r)
+        if target is not None and r <= target:
+            break
+        if stop is not None and stop(r):
+            break
+        H = np.maximum(H - gn_direction(XH, H, cg_iters), 0.0)
+    return H, np.array(hist)
+
+
+def plain_pgncg(X, H0, iters, cg_iters, stop=None, target=None):
+    """PGNCG-SymNMF on the full X."""
+    sc = data_scalars(X)
+    return pgncg(lambda B: apply_x(X, B), sc["normsq"], H0, iters, cg_iters, stop=stop, target=target)
+
+
+def lai_pgncg(U, lam, H0, iters, cg_iters, stop=None, target=None):
+    """Algorithm LAI-PGNCG-SymNMF: X H replaced by U (Lambda (U^T H)), the
+    residual taken against U Lambda U^T (squared norm ||Lambda||^2)."""
+    U = np.asarray(U, dtype=np.float64)
+    lam = np.asarray(lam, dtype=np.float64)
+    return pgncg(lambda B: U @ (lam[:, None] * (U.T @ B)), float(lam @ lam), H0, iters, cg_iters,
+                 stop=stop, target=target)
+
+
+# ----------------------------------------------------------------------------
 # Leverage scores and hybrid sampling (Section 2.2.2 eq. lev_score_def and
 # lev_score_S; Section 4.2 hybrid sampling, eq. SH).
 # ----------------------------------------------------------------------------

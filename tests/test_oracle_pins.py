@@ -471,3 +471,97 @@ def test_sampled_nls_error_shrinks_with_samples():
         errs.append(np.median(e))
     assert errs[0] > errs[1] > errs[2]
     assert errs[2] < 0.05
+
+
+# --------------------------------------------------------------------------
+# PGNCG (Section 2.1.3; Algorithm LAI-PGNCG-SymNMF).
+# --------------------------------------------------------------------------
+
+def _vec(A):
+    return A.reshape(-1, order="F")
+
+
+def _explicit_jacobian(H):
+    """J = -(H kron I_n) - K (H kron I_n) with K the perfect shuffle
+    (K vec(A) = vec(A^T) for n x n A), as written in Section 2.1.3."""
+    n, k = H.shape
+    HI = np.kron(H, np.eye(n))
+    K = np.zeros((n * n, n * n))
+    for i in range(n):
+        for j in range(n):
+            K[j + n * i, i + n * j] = 1.0
+    return -HI - K @ HI
+
+
+def _sym(n, seed):
+    A = np.random.default_rng(seed).random((n, n))
+    return A + A.T
+
+
+def test_pgncg_operators_match_kronecker_jacobian_and_calculus():
+    # gn_normal_apply and gn_gradient against (a) the paper's Kronecker form of
+    # J and (b) central differences of r(H) = vec(X - H H^T), which are exact
+    # for a quadratic.  A dropped term (P^T H), a transposed Gram or a wrong
+    # sign in either fails.
+    n, k = 5, 3
+    rng = np.random.default_rng(0)
+    X = _sym(n, 1)
+    H = rng.random((n, k))
+    P = rng.standard_normal((n, k))
+    J = _explicit_jacobian(H)
+    h = 1e-3
+    Jfd = np.empty_like(J)
+    for c in range(n * k):
+        E = np.zeros(n * k)
+        E[c] = h
+        Ep = E.reshape((n, k), order="F")
+        Jfd[:, c] = (_vec(X - (H + Ep) @ (H + Ep).T) - _vec(X - (H - Ep) @ (H - Ep).T)) / (2 * h)
+    assert np.allclose(J, Jfd, rtol=0, atol=1e-10)
+    r = _vec(X - H @ H.T)
+    assert np.allclose(_vec(O.gn_normal_apply(H, P)), J.T @ (J @ _vec(P)), rtol=1e-12, atol=1e-12)
+    assert np.allclose(_vec(O.gn_gradient(X @ H, H)), J.T @ r, rtol=1e-12, atol=1e-12)
+
+
+def test_pgncg_direction_is_the_gauss_newton_step():
+    # With enough CG steps the direction is the minimum-norm least-squares
+    # solution of J z = r, i.e. the Gauss-Newton step -z of min ||J p + r||.
+    n, k = 6, 2
+    rng = np.random.default_rng(2)
+    X = _sym(n, 3)
+    H = rng.random((n, k)) + 0.2
+    J = _explicit_jacobian(H)
+    z = np.linalg.lstsq(J, _vec(X - H @ H.T), rcond=None)[0]
+    Z = O.gn_direction(X @ H, H, 60)
+    assert np.linalg.norm(_vec(Z) - z) <= 1e-8 * np.linalg.norm(z)
+    # one CG step is the steepest-descent step with the exact line search
+    g = O.gn_gradient(X @ H, H)
+    a = np.sum(g * g) / np.sum(g * O.gn_normal_apply(H, g))
+    assert np.allclose(O.gn_direction(X @ H, H, 1), a * g, rtol=1e-13, atol=0)
+
+
+def test_pgncg_zero_residual_converges_quadratically():
+    # X = H* H*^T with H* > 0: Gauss-Newton on a zero-residual problem
+    # converges quadratically from a nearby positive start, the projection
+    # inactive (the residual roughly squares each iteration).
+    n, k = 30, 3
+    rng = np.random.default_rng(4)
+    Hs = 0.5 + rng.random((n, k))
+    X = Hs @ Hs.T
+    H0 = Hs * (1.0 + 0.05 * rng.standard_normal((n, k)))
+    H, hist = O.plain_pgncg(X, H0, 3, 10)
+    rfin = O.residual_direct(X, H, H) / np.linalg.norm(X)
+    assert hist[0] > 1e-2 and hist[1] < 1e-3 and hist[2] < 1e-6 and rfin < 1e-10
+    # the logged entry t is the residual of the factor iteration t starts from
+    assert hist[0] == pytest.approx(O.residual_direct(X, H0, H0) / np.linalg.norm(X), rel=1e-10)
+
+
+def test_lai_pgncg_with_a_full_basis_is_plain_pgncg():
+    # U Lambda U^T = X exactly when U holds all n eigenvectors
+    n, k = 40, 3
+    X, _ = workloads.gaussian_kernel(n, 6, 3, seed=5, dtype=np.float64)
+    lam, U = np.linalg.eigh(X)
+    H0 = O.initial_factor(n, k, O.data_scalars(X)["zeta"], seed=6)
+    Hp, hp = O.plain_pgncg(X, H0, 6, 4)
+    Hl, hl = O.lai_pgncg(U, lam, H0, 6, 4)
+    assert np.allclose(Hl, Hp, rtol=1e-9, atol=1e-12) and np.allclose(hl, hp, rtol=1e-9)
+    assert hp[-1] < hp[0]
