@@ -58,11 +58,22 @@ extern "C" {
  * accumulated in FP32 (the dropped ones are below FP32 rounding) */
 #define SYMNMF_F32X3 3
 
-/* update rules (the NLS subproblems of eq. ANLS4symNMF, Section 2.1):
- *   HALS: one sweep of the regularised HALS rule (eq. symhals_update2)
- *   BPP:  the exact per-row NLS solution by block principal pivoting */
+/* update rules.  HALS and BPP solve the NLS subproblems of the regularised
+ * alternating scheme (eq. ANLS4symNMF, Section 2.1.1):
+ *   HALS:  one sweep of the regularised HALS rule (eq. symhals_update2)
+ *   BPP:   the exact per-row NLS solution by block principal pivoting
+ * PGNCG works on the SymNMF objective ||X - H H^T||_F itself (Section 2.1.3;
+ * Algorithm LAI-PGNCG-SymNMF in LAI mode; alpha is not used):
+ *   PGNCG: H <- max(H - Z, 0), Z from options.cg_iters conjugate-gradient
+ *          steps on the Gauss-Newton normal equations J^T J z = J^T r from
+ *          z = 0 (standard CG; it stops early when <P, J^T J P> is not
+ *          positive).  One product with X per iteration; W is kept equal
+ *          to H.  Residual log entry t: ||X - H_t H_t^T|| / ||X|| of the
+ *          factor iteration t starts from (the stop rule sees it before the
+ *          step).  Not available with sampling (s > 0). */
 #define SYMNMF_RULE_HALS 0
 #define SYMNMF_RULE_BPP 1
+#define SYMNMF_RULE_PGNCG 2
 
 /* stopping modes */
 #define SYMNMF_STOP_NONE 0   /* run exactly the requested iterations         */
@@ -129,7 +140,7 @@ typedef struct symnmf_matrix {
  * Defaults are the paper's settings (Section 6). */
 typedef struct symnmf_options {
   int32_t struct_size;    /* sizeof(symnmf_options)                         */
-  int32_t rule;           /* SYMNMF_RULE_HALS (default) or SYMNMF_RULE_BPP  */
+  int32_t rule;           /* SYMNMF_RULE_HALS (default), _BPP or _PGNCG     */
   int32_t compute_dtype;  /* dense products: F64 (needs F64 X), F32, BF16;
                              default: the dtype of X                         */
   int32_t stop_mode;      /* default SYMNMF_STOP_NONE                       */
@@ -155,7 +166,9 @@ typedef struct symnmf_options {
                              without a stop rule); 0: every kernel is
                              launched directly.  Not used with timing = 1
                              or in LvS mode.  Same results either way.     */
-  int32_t reserved[4];
+  int32_t cg_iters;       /* PGNCG: CG steps per iteration, 1..64 (default
+                             5; the paper does not state its value)        */
+  int32_t reserved[3];
 } symnmf_options;
 
 typedef struct symnmf_stats {

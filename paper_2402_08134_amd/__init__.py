@@ -15,7 +15,7 @@ LIB_PATH = os.path.join(_HERE, "libsymnmf.so")
 OK, E_INVALID, E_UNSUPPORTED, E_NOMEM, E_DEVICE, E_NUMERIC, E_STATE = range(7)
 DENSE, CSR = 0, 1
 F64, F32, BF16, F32X3 = 0, 1, 2, 3
-RULE_HALS, RULE_BPP = 0, 1
+RULE_HALS, RULE_BPP, RULE_PGNCG = 0, 1, 2
 STOP_NONE, STOP_STALL, STOP_TARGET, STOP_STALL_OR_TARGET = 0, 1, 2, 3
 RESID_FAST, RESID_EXACT, RESID_LAI = 0, 1, 2
 W, H = 0, 1
@@ -43,7 +43,8 @@ class Options(ctypes.Structure):
                 ("stop_mode", ctypes.c_int32), ("stop_tol", ctypes.c_double), ("stop_patience", ctypes.c_int32),
                 ("check_every", ctypes.c_int32), ("target", ctypes.c_double), ("tau", ctypes.c_double),
                 ("resid_every", ctypes.c_int32), ("max_history", ctypes.c_int32),
-                ("timing", ctypes.c_int32), ("graphs", ctypes.c_int32), ("reserved", ctypes.c_int32 * 4)]
+                ("timing", ctypes.c_int32), ("graphs", ctypes.c_int32), ("cg_iters", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 3)]
 
 
 class Stats(ctypes.Structure):

@@ -8,7 +8,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT_DIR = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libsymnmf.so")
-SOURCES = ["k_dense.hip", "k_sparse.hip", "k_factor.hip", "k_update.hip", "k_lvs.hip", "k_bpp.hip", "k_warm.hip", "solver.cpp"]
+SOURCES = ["k_dense.hip", "k_sparse.hip", "k_factor.hip", "k_update.hip", "k_lvs.hip", "k_bpp.hip", "k_warm.hip", "k_pgncg.hip", "solver.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-ffp-contract=fast",

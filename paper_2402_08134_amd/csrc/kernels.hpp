@@ -155,6 +155,39 @@ int pad_identity(double* Ghat, double* Ginv, int k, int kp, hipStream_t s);
 // M (l x kp, zero padded) = diag(lam) Z, Z l x k.
 int scale_rows(const double* Z, const double* lam, int l, int k, int kp, double* M, hipStream_t s);
 
+// ---- projected Gauss-Newton with conjugate gradients ------------------------
+// Operands of the row passes (k_pgncg.hip).  R, Pd, Z: n x kp FP64 CG
+// vectors (gradient residual, direction, accumulated step), zero padded.
+struct CgArgs {
+  int n = 0, k = 0, l = 0, splits = 1, cp = 0;
+  int64_t ldt = 0;
+  const void* P = nullptr;        // init, YMODE 0: product partials [splits][n][cp]
+  const double* U = nullptr;      // init YMODE 2 / final in LAI mode: U (n x l)
+  const double* Mlai = nullptr;   // init YMODE 2: Lambda U^T H (l x kp)
+  void* H = nullptr;              // the factor (read; replaced by the final pass)
+  void* W = nullptr;              // receives a copy of the new H (final pass)
+  void* Dt = nullptr;             // optional transposed panel of the new H (cp x ldt)
+  double* R = nullptr;
+  double* Pd = nullptr;
+  double* Z = nullptr;
+  double* part = nullptr;         // block partials
+  int pstride = 0;                // doubles per partial row (final pass)
+  double* dpart = nullptr;        // init: <h, y> per block
+  int first = 0;                  // step / final: the first CG step (no P_prev, Z)
+};
+int cg_blocks(int n);
+size_t cg_partial_doubles(int k);
+// pass 0: init (R = -2 (Y - H G), partials of the first step's scalars and
+// R^T H, residual dot); 1: one CG step; 2: last step and projected update.
+// pdtype: element type of a.P; tdtype: element type of a.Dt; G: k x k Gram
+// of H; cg: scalars and M (see cg_reduce).  Exactly nb blocks.
+int cg_pass(int pass, const CgArgs& a, int kp, int ymode, int fdtype, int pdtype, int tdtype, const double* G,
+            const double* cg, int nb, const DevState* st, hipStream_t s);
+// Reduce nb partial rows of init/step passes into cg = [e, beta, step, done,
+// 4 spare, M (k x k)]; l1: scratch of ceil(nb / 32) * cg_partial_doubles(k).
+int cg_reduce(const double* part, int nb, int k, double* l1, double* cg, bool init, const DevState* st,
+              hipStream_t s);
+
 // Exact NLS per row by block principal pivoting.  Yhat (n x kp FP64): the
 // regularised right-hand side on entry, the solution on exit.  Dst (n x k,
 // fdtype) is the current factor, whose support starts the pivoting.  Ghat:

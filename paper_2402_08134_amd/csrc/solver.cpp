@@ -276,6 +276,11 @@ struct symnmf_ctx {
   float* warm_Htf = nullptr;
   void* warm_Ht = nullptr;
   bool warm_ran = false;  // d_scal[9] holds the scale of the last warm start
+  // PGNCG: CG vectors (n x kp FP64), block partials, scalars [e, beta, step,
+  // done, 4 spare, M (k x k)]
+  double *cgR = nullptr, *cgP = nullptr, *cgZ = nullptr;
+  double *cg_part = nullptr, *cg_l1 = nullptr, *cg_sc = nullptr;
+  int nbc = 1;
 
   ~symnmf_ctx() {
     if (st) (void)hipStreamSynchronize(st);
@@ -296,6 +301,7 @@ struct symnmf_ctx {
     dfree(warm_F);
     dfree(warm_Htf);
     dfree(warm_Ht);
+    for (double* p : {cgR, cgP, cgZ, cg_part, cg_l1, cg_sc}) dfree(p);
   }
 
   // Any change of mode, options or operand state that alters the kernels of
@@ -306,6 +312,10 @@ struct symnmf_ctx {
   // with every product operand already up to date.
   bool steady() const {
     if (opt.timing || !opt.graphs || graphs_broken) return false;
+    if (opt.rule == SYMNMF_RULE_PGNCG) {
+      if (mode == SYMNMF_MODE_LAI) return mH_ok;
+      return kind == SYMNMF_CSR || btH_ok;
+    }
     if (mode == SYMNMF_MODE_LAI) return mW_ok && mH_ok;
     if (mode == SYMNMF_MODE_PLAIN) return kind == SYMNMF_CSR || (btW_ok && btH_ok);
     return false;
@@ -621,10 +631,78 @@ struct symnmf_ctx {
     ~Gate() { c->gate_ = nullptr; }
   };
 
+  // One PGNCG iteration (Section 2.1.3): Y = X H (or the LAI product), the
+  // gradient pass with the residual of H and the stop rule, cg_iters - 1 CG
+  // steps and the last step fused with H <- max(H - Z, 0), then the Gram of
+  // the new H (and Lambda U^T H in LAI mode) for the next iteration.
+  void pgncg_iteration(const double* nrm) {
+    ensure_operand(SYMNMF_H);
+    CgArgs a;
+    a.n = n;
+    a.k = k;
+    a.H = H;
+    a.W = W;
+    a.R = cgR;
+    a.Pd = cgP;
+    a.Z = cgZ;
+    a.part = cg_part;
+    a.dpart = dpart;
+    int ymode = 0, pdt = fdtype, tdt = fdtype;
+    if (mode == SYMNMF_MODE_LAI) {
+      a.U = U;
+      a.Mlai = M_H;
+      a.l = l;
+      ymode = 2;
+    } else if (kind == SYMNMF_DENSE) {
+      const GemmPlan p = gemm_plan(n, k, cdtype);
+      {
+        Timed tm(this, SYMNMF_PHASE_PRODUCT);
+        LCHK(dense_gemm_bt(Xc, opdtype(), ldxc(), BtH, n, k, p, P, gate_, st));
+      }
+      a.P = P;
+      a.splits = p.splits;
+      a.cp = p.cp;
+      a.Dt = BtH;
+      a.ldt = p.ldt;
+      pdt = cdtype == SYMNMF_F64 ? SYMNMF_F64 : SYMNMF_F32;
+      tdt = opdtype();
+    } else {
+      {
+        Timed tm(this, SYMNMF_PHASE_PRODUCT);
+        LCHK(csr_spmm(rp, ci, Xv, xdtype, n, H, fdtype, k, Yk, fdtype, gate_, st, kp));
+      }
+      a.P = Yk;
+      a.splits = 1;
+      a.cp = kp;
+    }
+    Timed tm(this, SYMNMF_PHASE_UPDATE);
+    LCHK(cg_pass(0, a, kp, ymode, fdtype, pdt, tdt, G_H, cg_sc, nbc, gate_, st));
+    finish_iteration(dpart, nbc, G_H, G_H, k, nrm, dstate, hist, rule(), st);
+    LCHK(cg_reduce(cg_part, nbc, k, cg_l1, cg_sc, true, gate_, st));
+    for (int j = 0; j + 1 < opt.cg_iters; ++j) {
+      a.first = j == 0;
+      LCHK(cg_pass(1, a, kp, ymode, fdtype, pdt, tdt, G_H, cg_sc, nbc, gate_, st));
+      LCHK(cg_reduce(cg_part, nbc, k, cg_l1, cg_sc, false, gate_, st));
+    }
+    a.first = opt.cg_iters == 1;
+    a.part = part;
+    a.pstride = k * k + (ymode == 2 ? l * k : 0);
+    LCHK(cg_pass(2, a, kp, ymode, fdtype, pdt, tdt, G_H, cg_sc, nbc, gate_, st));
+    LCHK(update_reduce(part, nbc, a.pstride, part_l1, k, l, kp, alpha, lam, G_H, Gh_H, Gi_H,
+                       ymode == 2 ? M_H : nullptr, gate_, st));
+    invalidate(SYMNMF_W);
+    if (ymode == 2) mH_ok = true;
+    if (a.Dt) btH_ok = true;
+  }
+
   void one_iteration() {
     Gate g(this);
     const int64_t t = iter_host++;
     const double* nrm = d_scal + (mode == SYMNMF_MODE_LAI ? 8 : 0);
+    if (opt.rule == SYMNMF_RULE_PGNCG) {
+      pgncg_iteration(nrm);
+      return;
+    }
     if (mode == SYMNMF_MODE_LVS) {
       half_step(0, 2 * t, false);
       half_step(1, 2 * t + 1, false);
@@ -850,6 +928,7 @@ int symnmf_default_options(symnmf_options* opt) {
   opt->max_history = 4096;
   opt->timing = 0;
   opt->graphs = 1;
+  opt->cg_iters = 5;
   return SYMNMF_OK;
 }
 
@@ -875,7 +954,12 @@ int symnmf_create(symnmf_ctx** out, const symnmf_matrix* X, int32_t k, double al
     }
     if (c->opt.check_every < 1) c->opt.check_every = 1;
     if (c->opt.max_history < 1) c->opt.max_history = 1;
-    if (c->opt.rule != SYMNMF_RULE_HALS && c->opt.rule != SYMNMF_RULE_BPP) throw Fail{SYMNMF_E_INVALID, "rule"};
+    if (c->opt.rule != SYMNMF_RULE_HALS && c->opt.rule != SYMNMF_RULE_BPP && c->opt.rule != SYMNMF_RULE_PGNCG)
+      throw Fail{SYMNMF_E_INVALID, "rule"};
+    if (c->opt.rule == SYMNMF_RULE_PGNCG) {
+      if (c->opt.cg_iters < 1 || c->opt.cg_iters > 64) throw Fail{SYMNMF_E_INVALID, "cg_iters must be in 1..64"};
+      if (s > 0) throw Fail{SYMNMF_E_UNSUPPORTED, "PGNCG with leverage-score sampling"};
+    }
     if (c->opt.stop_mode < SYMNMF_STOP_NONE || c->opt.stop_mode > SYMNMF_STOP_STALL_OR_TARGET)
       throw Fail{SYMNMF_E_INVALID, "stop_mode"};
     c->st = (hipStream_t)hip_stream;
@@ -956,6 +1040,16 @@ int symnmf_create(symnmf_ctx** out, const symnmf_matrix* X, int32_t k, double al
       HIPCHK(hipMemsetAsync(c->BtH, 0, gemm_bt_bytes(n, k), c->st));
     }
     if (c->opt.rule == SYMNMF_RULE_BPP) c->Yhat = dalloc<double>((size_t)n * c->kp);
+    if (c->opt.rule == SYMNMF_RULE_PGNCG) {
+      c->nbc = cg_blocks(n);
+      c->cgR = dalloc<double>((size_t)n * c->kp);
+      c->cgP = dalloc<double>((size_t)n * c->kp);
+      c->cgZ = dalloc<double>((size_t)n * c->kp);
+      c->cg_part = dalloc<double>((size_t)c->nbc * cg_partial_doubles(k));
+      c->cg_l1 = dalloc<double>((size_t)ceil_div(c->nbc, 32) * cg_partial_doubles(k));
+      c->cg_sc = dalloc<double>(8 + (size_t)k * k);
+      HIPCHK(hipMemsetAsync(c->cg_sc, 0, sizeof(double) * (8 + (size_t)k * k), c->st));
+    }
     c->G_W = dalloc<double>((size_t)k * k);
     c->G_H = dalloc<double>((size_t)k * k);
     c->Gh_W = dalloc<double>((size_t)c->kp * c->kp);
@@ -1320,6 +1414,7 @@ int symnmf_half_step(symnmf_ctx* c, int32_t side, int32_t half_iter) {
   return guarded(c, [&] {
     if (side != 0 && side != 1) throw Fail{SYMNMF_E_INVALID, "side"};
     if (half_iter < 0) throw Fail{SYMNMF_E_INVALID, "half_iter"};
+    if (c->opt.rule == SYMNMF_RULE_PGNCG) throw Fail{SYMNMF_E_UNSUPPORTED, "PGNCG has no half-steps"};
     c->half_step(side, half_iter, false);
   });
 }
