@@ -8,16 +8,20 @@ One step = one whole solve from the data resident in HBM: create (scalars
 pass, random init), then regularised HALS iterations until the normalised
 residual reaches r* = r_conv + 1e-3, where r_conv is the residual at which the
 plain random-init method stops under the paper's rule (no drop > 1e-4 for four
-iterations).  Four methods are timed: plain (random start, iterations on X),
+iterations).  The HALS methods timed: plain (random start, iterations on X),
 lai (Algorithm LAI-SymNMF from the random start until its own residual
 stalls, then refinement on X until the residual on X is r*), learned (the learned start -- LAI basis
 l = k + 16, q = 2, the trained network of paper_2402_08134_amd/weights and
 the least-squares scale fit -- then iterations on X) and learned_lai (the
 learned start, LAI iterations as in lai, then refinement on X); also
 learned_lai_ada, the same with the basis of Algorithm Ada-RRF (q chosen on
-the fly, tolerance 1e-3, at most 10 rounds) instead of q = 2.
-`value` is seconds per solve of learned_lai; every method's time, iteration
-counts, final residual and speed-up over plain are in `config.methods`.
+the fly, tolerance 1e-3, at most 10 rounds) instead of q = 2.  The PGNCG
+rows (Section 2.1.3) follow the paper's protocol instead -- iterate until the
+stall rule stops them, and report time and residual: pgncg (random start, on
+X), lai_pgncg (Algorithm LAI-PGNCG-SymNMF) and lai_pgncg_ir (then refinement
+on X).  `value` is seconds per solve of learned_lai; every method's time,
+iteration counts, final residuals and speed-up over plain are in
+`config.methods`.
 
 The timed solves replay their iterations from HIP graphs and record no
 events.  A second pass runs each method once more with HIP events around
@@ -107,7 +111,21 @@ def main():
     net = WSP.load(os.path.join(WSP.WEIGHTS_DIR, "warmstart_gk.npz"))
 
     def solve(method, seed, timing):
-        """One solve to r*; returns (context, iterations, iterations on X)."""
+        """One solve to r* (PGNCG methods: to the stall rule); returns
+        (context, iterations, iterations on X)."""
+        if "pgncg" in method:
+            o = P.symnmf_default_options(rule=P.RULE_PGNCG, stop_mode=P.STOP_STALL, check_every=8, timing=timing)
+            c = P.symnmf_create(X, k, 0.0, 0, seed, o)
+            if method == "pgncg":
+                it = P.symnmf_iterate(c, 4000)
+                return c, it, it
+            P.symnmf_lai(c, l, q)
+            it = P.symnmf_iterate(c, 2000)
+            if method == "lai_pgncg":
+                return c, it, 0
+            P.symnmf_refine(c, P.STOP_STALL)
+            it2 = P.symnmf_iterate(c, 4000)
+            return c, it + it2, it2
         lai_stage = method in ("lai", "learned_lai", "learned_lai_ada")
         # LAI stage until its own residual stalls (stopping it at r* instead
         # leaves the residual on X far above r*: measured slower); then
@@ -129,7 +147,7 @@ def main():
         it2 = P.symnmf_iterate(c, 4000)
         return c, it + it2, it2
 
-    methods = ["plain", "lai", "learned", "learned_lai", "learned_lai_ada"]
+    methods = ["plain", "lai", "learned", "learned_lai", "learned_lai_ada", "pgncg", "lai_pgncg", "lai_pgncg_ir"]
     for w in range(args.warmup):
         for m in methods:
             solve(m, 100 + w, 0)
@@ -149,10 +167,13 @@ def main():
             ctxs.append(c)
         torch.cuda.synchronize()
         t = (time.perf_counter() - t0) / args.steps
-        final = [P.symnmf_residual(c, P.RESID_EXACT)[0] for c in ctxs]
+        finals = [P.symnmf_residual(c, P.RESID_EXACT) for c in ctxs]
+        final = [float(v[0]) for v in finals]
         beta = [P.symnmf_get_stats(c).warm_beta for c in ctxs]
         del ctxs
-        res[m] = {"s_per_solve": t, "iterations": its, "iterations_on_X": its_x, "final_residual": final}
+        res[m] = {"s_per_solve": t, "iterations": its, "iterations_on_X": its_x, "final_residual": final,
+                  "final_residual_HHt": [float(v[1]) for v in finals],
+                  "stop": "stall rule" if "pgncg" in m else "r*"}
         if m.startswith("learned"):
             res[m]["warm_beta"] = beta
         log(f"[bench] {m:12s} {t * 1e3:8.2f} ms/solve  iterations {its} (on X {its_x})  final residual "
@@ -202,7 +223,7 @@ def main():
                    "methods": res},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": "k_gemm_mfma<float,2,4,true> (X H, one launch per half-iteration)",
+                     "kernel": "k_gemm_cols<2, 2, true> (X H read along rows of X, one launch per half-iteration)",
                      "us_per_launch": t_prod * 1e6, "launches": calls,
                      "algorithmic_bytes_per_launch": alg_bytes},
         "phases_ms_per_solve": {m: {kk: v[0] for kk, v in ph.items()} for m, ph in phases.items()},
@@ -475,7 +496,7 @@ def stored_traffic(n, k):
     rocprofv3 counter summary, or None when that summary is missing, was
     taken at another size, or the kernel source changed since."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", "k_gemm_mfma_f32_gk16384_k32_pmc.txt")
+    path = os.path.join(ROOT, "profiles", "k_gemm_cols_f32_gk16384_k32_pmc.txt")
     src = os.path.join(ROOT, "paper_2402_08134_amd", "csrc", "k_dense.hip")
     if not os.path.exists(path):
         return None

@@ -252,6 +252,103 @@ __global__ __launch_bounds__(256) void k_gemm_mfma(const TX* __restrict__ X, int
 }
 
 // ---------------------------------------------------------------------------
+// FP32 product read along rows of X: Y^T = B^T X, which is (X B)^T because X
+// is symmetric.  Each wave owns 64 * CT output rows j (a strip of X's
+// columns) and a range of X's rows i (split-K).  One K step takes 4 rows;
+// lane (ln, lq) = (lane % 16, lane / 16) holds X[i0 + 4 lq + s][j0 + 4 ln ..
+// + 3] for the steps s = 0..3 of a 16-row tile, so a wave's load instruction
+// covers 4 rows x 256 contiguous bytes (measured on MI355X: a pure read in
+// this pattern streams at about 6.7 TB/s, against 6.0 TB/s for 16 rows x 64
+// bytes).  v_mfma_f32_16x16x4f32 with A = the B panel (Bt[c][i], lane ->
+// (c = 16 t + ln, K = lq), one float4 of Bt per lane holds the tile's 4
+// steps) and B = X (lane -> (K = lq, column ln)); element u of the X float4
+// feeds the MFMA of the columns j0 + 4 ln + u.  Output lane (ln, lq), v ->
+// c = 16 t + 4 lq + v: one float4 store of 4 consecutive c per (t, u).
+// DS tiles are in flight (register ring, no LDS).  The partials land in
+// P[split][j][c] like those of k_gemm_mfma.
+template <int NT, int CT, bool VEC>
+__global__ __launch_bounds__(256) void k_gemm_cols(const float* __restrict__ X, int64_t ldx,
+                                                   const float* __restrict__ Bt, int64_t ldt, int n, int rchunk,
+                                                   float* __restrict__ P, int cp, const DevState* __restrict__ st) {
+  if (stopped(st)) return;
+  constexpr int DS = 4;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int ln = lane & 15, lq = lane >> 4;
+  const int j0 = (blockIdx.x * 4 + wave) * (64 * CT);
+  if (j0 >= n) return;
+  const int ib = blockIdx.y * rchunk;
+  const int ie = min(n, ib + rchunk);
+  const int ntile = (ie - ib + 15) / 16;
+  const bool full = VEC && (j0 + 64 * CT <= n);
+
+  floatx4 acc[NT][CT][4];
+#pragma unroll
+  for (int t = 0; t < NT; ++t)
+#pragma unroll
+    for (int ct = 0; ct < CT; ++ct)
+#pragma unroll
+      for (int u = 0; u < 4; ++u) acc[t][ct][u] = floatx4{0, 0, 0, 0};
+  const float* bp[NT];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) bp[t] = Bt + (int64_t)(16 * t + ln) * ldt + 4 * lq;
+
+  floatx4 xv[DS][CT][4], bv[DS][NT];
+  // Tile rows beyond n (last split only) read row n - 1 of X; the padded Bt
+  // is zero there, so they add nothing.
+  auto load = [&](floatx4 (&xd)[CT][4], floatx4 (&bd)[NT], int tile) {
+    const int i0 = ib + 16 * tile;
+#pragma unroll
+    for (int t = 0; t < NT; ++t) bd[t] = *(const floatx4*)(bp[t] + i0);
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const float* xr = X + (int64_t)min(i0 + 4 * lq + s, n - 1) * ldx + j0 + 4 * ln;
+#pragma unroll
+      for (int ct = 0; ct < CT; ++ct) {
+        if (full) {
+          xd[ct][s] = __builtin_nontemporal_load((const floatx4*)(xr + 64 * ct));
+        } else {
+#pragma unroll
+          for (int u = 0; u < 4; ++u) xd[ct][s][u] = (j0 + 64 * ct + 4 * ln + u < n) ? xr[64 * ct + u] : 0.0f;
+        }
+      }
+    }
+  };
+  auto compute = [&](const floatx4 (&xd)[CT][4], const floatx4 (&bd)[NT]) {
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+#pragma unroll
+      for (int t = 0; t < NT; ++t)
+#pragma unroll
+        for (int ct = 0; ct < CT; ++ct)
+#pragma unroll
+          for (int u = 0; u < 4; ++u)
+            acc[t][ct][u] = __builtin_amdgcn_mfma_f32_16x16x4f32(bd[t][s], xd[ct][s][u], acc[t][ct][u], 0, 0, 0);
+  };
+#pragma unroll
+  for (int d = 0; d < DS - 1; ++d)
+    if (d < ntile) load(xv[d], bv[d], d);
+  for (int tile = 0; tile < ntile; tile += DS) {
+#pragma unroll
+    for (int d = 0; d < DS; ++d) {
+      const int pre = tile + d + DS - 1;  // tile prefetched into slot (d + DS - 1) % DS
+      if (pre < ntile) load(xv[(d + DS - 1) % DS], bv[(d + DS - 1) % DS], pre);
+      if (tile + d < ntile) compute(xv[d], bv[d]);
+    }
+  }
+  float* out = P + (int64_t)blockIdx.y * n * cp;
+#pragma unroll
+  for (int ct = 0; ct < CT; ++ct)
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int j = j0 + 64 * ct + 4 * ln + u;
+      if (j < n) {
+#pragma unroll
+        for (int t = 0; t < NT; ++t) *(floatx4*)(out + (int64_t)j * cp + 16 * t + 4 * lq) = acc[t][ct][u];
+      }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // BF16 MFMA product (FP32 accumulate): v_mfma_f32_16x16x32_bf16.  Lane l
 // supplies 8 consecutive K values of A row l%16 and of B column l%16 (group
 // g = l/16 covers K offsets 8g..8g+7 of the 32-wide step); accumulator layout
@@ -650,6 +747,25 @@ int dispatch_x3(int nt, int rt, const float* X, int64_t ldx, bool vec, const flo
   return -1;
 }
 
+template <int NT, int CT>
+void launch_cols(const float* X, int64_t ldx, bool vec, const float* Bt, int64_t ldt, int n, const GemmPlan& p, float* P,
+                 const DevState* st, hipStream_t s) {
+  dim3 g(ceil_div(n, 4 * 64 * CT), p.splits);
+  if (vec)
+    k_gemm_cols<NT, CT, true><<<g, 256, 0, s>>>(X, ldx, Bt, ldt, n, p.kchunk, P, p.cp, st);
+  else
+    k_gemm_cols<NT, CT, false><<<g, 256, 0, s>>>(X, ldx, Bt, ldt, n, p.kchunk, P, p.cp, st);
+}
+
+int dispatch_cols(int nt, int ct, const float* X, int64_t ldx, bool vec, const float* Bt, int64_t ldt, int n,
+                  const GemmPlan& p, float* P, const DevState* st, hipStream_t s) {
+#define CASE(NT_, CT_) \
+  if (nt == NT_ && ct == CT_) { launch_cols<NT_, CT_>(X, ldx, vec, Bt, ldt, n, p, P, st, s); return 0; }
+  CASE(1, 2) CASE(2, 2) CASE(3, 1) CASE(4, 1) CASE(5, 1) CASE(6, 1)
+#undef CASE
+  return -1;
+}
+
 int dispatch_bf16(int nt, int rt, const __bf16* X, int64_t ldx, bool vec, const __bf16* Bt, int64_t ldt, int n,
                   const GemmPlan& p, float* P, const DevState* st, hipStream_t s) {
 #define CASE(NT_, RT_) \
@@ -663,8 +779,21 @@ int dispatch_bf16(int nt, int rt, const __bf16* X, int64_t ldx, bool vec, const 
 GemmPlan gemm_plan(int n, int c, int compute_dtype) {
   GemmPlan p;
   p.split3 = compute_dtype == SYMNMF_F32X3;
-  if (p.split3) compute_dtype = SYMNMF_F32;
   p.cp = 16 * ceil_div(c, 16);
+  p.ldt = (int64_t)BT_PAD * ceil_div(n, BT_PAD);
+  if (compute_dtype == SYMNMF_F32) {
+    // row-contiguous product: strips of 64 * ct columns, about one wave per
+    // SIMD in total, splits of at least 256 rows (multiples of 16)
+    p.cols = true;
+    p.ct = p.cp <= 32 ? 2 : 1;
+    const int strips = ceil_div(n, 64 * p.ct);
+    int splits = std::max(1, ceil_div(1024, strips));
+    splits = std::min(splits, std::max(1, n / 256));
+    p.kchunk = 16 * ceil_div(ceil_div(n, splits), 16);
+    p.splits = ceil_div(n, p.kchunk);
+    return p;
+  }
+  if (p.split3) compute_dtype = SYMNMF_F32;
   p.rt = pick_rt(compute_dtype, p.cp / 16);
   const int kt = compute_dtype == SYMNMF_BF16 ? BF_KT : GEMM_KT;
   const int waves = ceil_div(n, 16 * p.rt);
@@ -675,7 +804,6 @@ GemmPlan gemm_plan(int n, int c, int compute_dtype) {
   splits = std::min(splits, std::max(1, ceil_div(n, 4 * kt)));
   p.kchunk = kt * ceil_div(ceil_div(n, splits), kt);
   p.splits = ceil_div(n, p.kchunk);
-  p.ldt = (int64_t)BT_PAD * ceil_div(n, BT_PAD);
   return p;
 }
 
@@ -691,7 +819,9 @@ int dense_gemm_bt(const void* X, int xdtype, int64_t ldx, const void* Bt, int n,
     rc = dispatch_mfma<double>(nt, p.rt, (const double*)X, ldx, vec, (const double*)Bt, p.ldt, n, p, (double*)P, st, s);
   } else if (xdtype == SYMNMF_F32) {
     const bool vec = (ldx % 4 == 0) && ((uintptr_t)X % 16 == 0);
-    if (p.split3)
+    if (p.cols)
+      rc = dispatch_cols(nt, p.ct, (const float*)X, ldx, vec, (const float*)Bt, p.ldt, n, p, (float*)P, st, s);
+    else if (p.split3)
       rc = dispatch_x3(nt, p.rt, (const float*)X, ldx, vec, (const float*)Bt, p.ldt, n, p, (float*)P, st, s);
     else
       rc = dispatch_mfma<float>(nt, p.rt, (const float*)X, ldx, vec, (const float*)Bt, p.ldt, n, p, (float*)P, st,
@@ -739,7 +869,10 @@ int dense_gemm(const void* X, int xdtype, int64_t ldx, const void* B, int bdtype
     else
       k_transpose_pad<double, float><<<tg, 256, 0, s>>>((const double*)B, ldb, n, c, (float*)Bt, p.ldt, p.cp, st);
     const bool vec = (ldx % 4 == 0) && ((uintptr_t)X % 16 == 0);
-    if (p.split3) {
+    if (p.cols) {
+      if (dispatch_cols(nt, p.ct, (const float*)X, ldx, vec, (const float*)Bt, p.ldt, n, p, (float*)P, st, s))
+        return -1;
+    } else if (p.split3) {
       if (dispatch_x3(nt, p.rt, (const float*)X, ldx, vec, (const float*)Bt, p.ldt, n, p, (float*)P, st, s))
         return -1;
     } else if (dispatch_mfma<float>(nt, p.rt, (const float*)X, ldx, vec, (const float*)Bt, p.ldt, n, p, (float*)P,

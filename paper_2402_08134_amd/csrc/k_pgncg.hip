@@ -83,22 +83,42 @@ __device__ __forceinline__ void tile_gram(const double* A, const double* B, int 
   }
 }
 
-// Partial row of this block: [e, a1, a2, a3, K (k x k)].
+// Block sums of N values at once (fixed order: wave trees, then the four
+// waves in order); the totals land in v of thread 0.  sc: 4 * N doubles.
+template <int N>
+__device__ __forceinline__ void block_sums(double (&v)[N], double* sc) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1)
+#pragma unroll
+    for (int i = 0; i < N; ++i) v[i] += __shfl_xor(v[i], o, 64);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0)
+#pragma unroll
+    for (int i = 0; i < N; ++i) sc[w * N + i] = v[i];
+  __syncthreads();
+  if (threadIdx.x == 0)
+#pragma unroll
+    for (int i = 0; i < N; ++i) v[i] = ((sc[i] + sc[N + i]) + sc[2 * N + i]) + sc[3 * N + i];
+}
+
+// Partial row of this block: [e, a1, a2, a3, K (k x k)]; dpart (when given)
+// receives the block's residual dot.
 template <int KP>
 __device__ __forceinline__ void write_cg_partials(double* __restrict__ part, int k, double e, double a1, double a2,
-                                                  double a3, const double (&gacc)[KP / 16][KP / 16], double* sc) {
+                                                  double a3, const double (&gacc)[KP / 16][KP / 16], double* sc,
+                                                  double dot = 0.0, double* __restrict__ dpart = nullptr) {
   constexpr int CPL = KP / 16;
   const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
   double* gp = part + (int64_t)blockIdx.x * (CG_E0 + k * k);
-  const double s0 = block_sum(e, sc);
-  const double s1 = block_sum(a1, sc);
-  const double s2 = block_sum(a2, sc);
-  const double s3 = block_sum(a3, sc);
+  double v[5] = {e, a1, a2, a3, dot};
+  block_sums<5>(v, sc);
   if (threadIdx.x == 0) {
-    gp[0] = s0;
-    gp[1] = s1;
-    gp[2] = s2;
-    gp[3] = s3;
+    gp[0] = v[0];
+    gp[1] = v[1];
+    gp[2] = v[2];
+    gp[3] = v[3];
+    if (dpart) dpart[blockIdx.x] = v[4];
   }
 #pragma unroll
   for (int i = 0; i < CPL; ++i)
@@ -122,7 +142,7 @@ __global__ __launch_bounds__(256) void k_cg_init(CgArgs a, const double* __restr
   double* Gs = reinterpret_cast<double*>(smem);  // KP x KP
   double* T1 = Gs + KP * KP;                     // chunk rows of R
   double* T2 = T1 + CG_RPB * LW;                 // chunk rows of H
-  __shared__ double sc[8];
+  __shared__ double sc[20];
   const int tid = threadIdx.x, g = tid & 15, rg = tid >> 4;
   const int tx = tid & 15, ty = tid >> 4;
   const int n = a.n, k = a.k;
@@ -194,9 +214,7 @@ __global__ __launch_bounds__(256) void k_cg_init(CgArgs a, const double* __restr
     tile_gram<KP>(T1, T2, tx, ty, gacc);  // R^T H
     __syncthreads();
   }
-  write_cg_partials<KP>(a.part, k, e, a1, 0.0, 0.0, gacc, sc);
-  const double d = block_sum(dot, sc);
-  if (tid == 0) a.dpart[blockIdx.x] = d;
+  write_cg_partials<KP>(a.part, k, e, a1, 0.0, 0.0, gacc, sc, dot, a.dpart);
 }
 
 // One CG step.  cg: [0] e = ||R||^2, [1] beta, [2] step length, [3] done,
@@ -213,7 +231,7 @@ __global__ __launch_bounds__(256) void k_cg_step(CgArgs a, const double* __restr
   double* Ms = Gs + KP * KP;                     // KP x KP
   double* T1 = Ms + KP * KP;                     // chunk rows of P, then of R'
   double* T2 = T1 + CG_RPB * LW;                 // chunk rows of H
-  __shared__ double sc[8];
+  __shared__ double sc[20];
   const int tid = threadIdx.x, g = tid & 15, rg = tid >> 4;
   const int tx = tid & 15, ty = tid >> 4;
   const int n = a.n, k = a.k;
@@ -229,7 +247,7 @@ __global__ __launch_bounds__(256) void k_cg_step(CgArgs a, const double* __restr
     for (int j = 0; j < CPL; ++j) gacc[i][j] = 0.0;
   double e = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
   for (int base = blockIdx.x * CG_RPB; base < n; base += gridDim.x * CG_RPB) {
-    double r[CG_RPL][CPL], p[CG_RPL][CPL];
+    double r[CG_RPL][CPL], p[CG_RPL][CPL], zo[CG_RPL][CPL];
 #pragma unroll
     for (int j = 0; j < CG_RPL; ++j) {
       const int row = base + CG_RPL * rg + j;
@@ -241,6 +259,7 @@ __global__ __launch_bounds__(256) void k_cg_step(CgArgs a, const double* __restr
         const int64_t idx = (int64_t)rr * KP + q;
         const double rv = ok ? a.R[idx] : 0.0;
         const double pv = first ? 0.0 : (ok ? a.Pd[idx] : 0.0);
+        zo[j][c] = first ? 0.0 : a.Z[idx];  // loaded early; used after the products
         const double hv = (double)H[(int64_t)rr * k + (q < k ? q : k - 1)];
         r[j][c] = rv;
         p[j][c] = fma(beta, pv, rv);
@@ -261,8 +280,7 @@ __global__ __launch_bounds__(256) void k_cg_step(CgArgs a, const double* __restr
       for (int c = 0; c < CPL; ++c) {
         const int q = g + 16 * c;
         const int64_t idx = (int64_t)(ok ? row : n - 1) * KP + q;
-        const double zv = first ? 0.0 : (ok ? a.Z[idx] : 0.0);
-        const double z = fma(step, p[j][c], zv);
+        const double z = fma(step, p[j][c], zo[j][c]);
         const double y = 2.0 * (u[j][c] + v[j][c]);
         const double rn = fma(-step, y, r[j][c]);
         a2 = fma(rn, u[j][c], a2);
@@ -389,9 +407,18 @@ __global__ __launch_bounds__(256) void k_cg_final(CgArgs a, const double* __rest
 
 constexpr int CG_GROUP = 32;
 
+// Sum of nb values at stride `stride`, in order; loads issued 8 at a time.
 __device__ __forceinline__ double sum_rows(const double* __restrict__ p, int nb, int64_t stride) {
   double acc = 0.0;
-  for (int b = 0; b < nb; ++b) acc += p[(int64_t)b * stride];
+  int b = 0;
+  for (; b + 8 <= nb; b += 8) {
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = p[(int64_t)(b + u) * stride];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) acc += v[u];
+  }
+  for (; b < nb; ++b) acc += p[(int64_t)b * stride];
   return acc;
 }
 
@@ -413,25 +440,42 @@ __global__ __launch_bounds__(256) void k_cg_scalars(const double* __restrict__ p
                                                     double* __restrict__ cg, int init,
                                                     const DevState* __restrict__ st) {
   if (stopped(st)) return;
+  // tot: the CG_E0 scalars, then K (later M') with row stride k + 1 so that
+  // the transposed reads of tr(M' M') do not collide in LDS banks
   extern __shared__ __align__(16) unsigned char smem[];
   double* tot = reinterpret_cast<double*>(smem);
-  __shared__ double sc[8];
+  double* Ml = tot + CG_E0;
+  __shared__ double sc[20];
   const int E = CG_E0 + k * k, kk = k * k, tid = threadIdx.x;
-  for (int e = tid; e < E; e += 256) tot[e] = sum_rows(part + e, cnt, E);
+  for (int e = tid; e < E; e += 256) {
+    const double v = sum_rows(part + e, cnt, E);
+    if (e < CG_E0) {
+      tot[e] = v;
+    } else {
+      const int f = e - CG_E0, p = f / k, q = f - p * k;
+      Ml[p * (k + 1) + q] = v;
+    }
+  }
   const double e_old = cg[0];
   const bool done_old = !init && cg[3] != 0.0;
   __syncthreads();
   const double e_new = tot[0];
   const double beta = (init || done_old || !(e_old > 0.0)) ? 0.0 : e_new / e_old;
-  for (int e = tid; e < kk; e += 256) tot[CG_E0 + e] = init ? tot[CG_E0 + e] : fma(beta, cg[8 + e], tot[CG_E0 + e]);
+  if (!init)
+    for (int e = tid; e < kk; e += 256) {
+      const int p = e / k, q = e - p * k;
+      Ml[p * (k + 1) + q] = fma(beta, cg[8 + e], Ml[p * (k + 1) + q]);
+    }
   __syncthreads();
-  double tm = 0.0;
+  double tv[1] = {0.0};
   for (int e = tid; e < kk; e += 256) {
     const int p = e / k, q = e - p * k;
-    tm = fma(tot[CG_E0 + e], tot[CG_E0 + q * k + p], tm);
-    cg[8 + e] = tot[CG_E0 + e];
+    const double m = Ml[p * (k + 1) + q];
+    tv[0] = fma(m, Ml[q * (k + 1) + p], tv[0]);
+    cg[8 + e] = m;
   }
-  tm = block_sum(tm, sc);
+  block_sums<1>(tv, sc);
+  const double tm = tv[0];
   if (tid == 0) {
     const double pgp = fma(beta * beta, tot[3], fma(2.0 * beta, tot[2], tot[1]));
     const double pap = 2.0 * (pgp + tm);
@@ -543,7 +587,7 @@ int cg_reduce(const double* part, int nb, int k, double* l1, double* cg, bool in
     src = l1;
     cnt = groups;
   }
-  const size_t lds = 8 * (size_t)E;
+  const size_t lds = 8 * ((size_t)CG_E0 + (size_t)k * (k + 1));
   if (lds > 65536 &&
       hipFuncSetAttribute((const void*)k_cg_scalars, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) !=
           hipSuccess)
