@@ -626,6 +626,111 @@ __global__ __launch_bounds__(256) void k_gemm_x3(const float* __restrict__ X, in
     }
 }
 
+// BF16 product read along rows of X, the same scheme as k_gemm_cols with
+// v_mfma_f32_16x16x32_bf16 (B operand lane (ln, lq) -> K 8 lq .. 8 lq + 7 of
+// column ln).  One K step takes 32 rows: lane (ln, lq) loads 8 BF16 of each
+// of the rows i0 + 8 lq + e (e = 0..7) at columns j0 + 8 ln .. + 7 (a wave's
+// load instruction covers 4 rows x 256 contiguous bytes), transposes that
+// 8 x 8 block in registers (v_perm_b32, 4 per 16 loaded bytes), and feeds
+// column u of it to the MFMA of the columns j0 + 8 ln + u.  A = the BF16
+// B panel: one 16-byte load of Bt[16 t + ln][i0 + 8 lq ..] per K step.  A
+// wave owns 128 output rows j; output lane (ln, lq), v -> c = 16 t + 4 lq + v.
+__device__ __forceinline__ void transpose8_bf16(const uint32_t (&in)[8][4], uint32_t (&out)[8][4]) {
+  // out[u] dword d = {in[2d] element u, in[2d + 1] element u} (low, high half)
+#pragma unroll
+  for (int u = 0; u < 8; ++u)
+#pragma unroll
+    for (int d = 0; d < 4; ++d)
+      out[u][d] = __builtin_amdgcn_perm(in[2 * d + 1][u >> 1], in[2 * d][u >> 1], (u & 1) ? 0x07060302u : 0x05040100u);
+}
+
+template <int NT, bool VEC>
+__global__ __launch_bounds__(256) void k_gemm_cols_bf16(const __bf16* __restrict__ X, int64_t ldx,
+                                                        const __bf16* __restrict__ Bt, int64_t ldt, int n, int rchunk,
+                                                        float* __restrict__ P, int cp,
+                                                        const DevState* __restrict__ st) {
+  if (stopped(st)) return;
+  constexpr int DS = 4;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int ln = lane & 15, lq = lane >> 4;
+  const int j0 = (blockIdx.x * 4 + wave) * 128;
+  if (j0 >= n) return;
+  const int ib = blockIdx.y * rchunk;
+  const int ie = min(n, ib + rchunk);
+  const int nstep = (ie - ib + 31) / 32;
+  const bool full = VEC && (j0 + 128 <= n);
+  const unsigned short* Xs = reinterpret_cast<const unsigned short*>(X);
+
+  floatx4 acc[NT][8];
+#pragma unroll
+  for (int t = 0; t < NT; ++t)
+#pragma unroll
+    for (int u = 0; u < 8; ++u) acc[t][u] = floatx4{0, 0, 0, 0};
+  const __bf16* bp[NT];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) bp[t] = Bt + (int64_t)(16 * t + ln) * ldt + 8 * lq;
+
+  uint32_t xv[DS][8][4];
+  bf16x8 bv[DS][NT];
+  // Rows beyond n (last split only) read row n - 1; the padded Bt is zero there.
+  auto load = [&](uint32_t (&xd)[8][4], bf16x8 (&bd)[NT], int step) {
+    const int i0 = ib + 32 * step;
+#pragma unroll
+    for (int t = 0; t < NT; ++t) bd[t] = *(const bf16x8*)(bp[t] + i0);
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const int64_t ro = (int64_t)min(i0 + 8 * lq + e, n - 1) * ldx + j0 + 8 * ln;
+      if (full) {
+        typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+        const u32x4 v = __builtin_nontemporal_load((const u32x4*)(X + ro));
+        xd[e][0] = v[0];
+        xd[e][1] = v[1];
+        xd[e][2] = v[2];
+        xd[e][3] = v[3];
+      } else {
+#pragma unroll
+        for (int d = 0; d < 4; ++d) {
+          const int c0 = j0 + 8 * ln + 2 * d;
+          const uint32_t lo = (c0 < n) ? (uint32_t)Xs[ro + 2 * d] : 0u;
+          const uint32_t hi = (c0 + 1 < n) ? (uint32_t)Xs[ro + 2 * d + 1] : 0u;
+          xd[e][d] = lo | (hi << 16);
+        }
+      }
+    }
+  };
+  auto compute = [&](const uint32_t (&xd)[8][4], const bf16x8 (&bd)[NT]) {
+    uint32_t tr[8][4];
+    transpose8_bf16(xd, tr);
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      bf16x8 xb;
+      __builtin_memcpy(&xb, tr[u], 16);
+#pragma unroll
+      for (int t = 0; t < NT; ++t) acc[t][u] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bd[t], xb, acc[t][u], 0, 0, 0);
+    }
+  };
+#pragma unroll
+  for (int d = 0; d < DS - 1; ++d)
+    if (d < nstep) load(xv[d], bv[d], d);
+  for (int step = 0; step < nstep; step += DS) {
+#pragma unroll
+    for (int d = 0; d < DS; ++d) {
+      const int pre = step + d + DS - 1;
+      if (pre < nstep) load(xv[(d + DS - 1) % DS], bv[(d + DS - 1) % DS], pre);
+      if (step + d < nstep) compute(xv[d], bv[d]);
+    }
+  }
+  float* out = P + (int64_t)blockIdx.y * n * cp;
+#pragma unroll
+  for (int u = 0; u < 8; ++u) {
+    const int j = j0 + 8 * ln + u;
+    if (j < n) {
+#pragma unroll
+      for (int t = 0; t < NT; ++t) *(floatx4*)(out + (int64_t)j * cp + 16 * t + 4 * lq) = acc[t][u];
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Exact residual pass: sum over all (i, j) of (X_ij - w_i . h_j)^2 in FP64.
 // A 64 x 64 tile per workgroup; the factor rows of the tile are staged in LDS
@@ -766,6 +871,29 @@ int dispatch_cols(int nt, int ct, const float* X, int64_t ldx, bool vec, const f
   return -1;
 }
 
+template <int NT>
+void launch_cols_bf16(const __bf16* X, int64_t ldx, bool vec, const __bf16* Bt, int64_t ldt, int n,
+                      const GemmPlan& p, float* P, const DevState* st, hipStream_t s) {
+  dim3 g(ceil_div(n, 4 * 128), p.splits);
+  if (vec)
+    k_gemm_cols_bf16<NT, true><<<g, 256, 0, s>>>(X, ldx, Bt, ldt, n, p.kchunk, P, p.cp, st);
+  else
+    k_gemm_cols_bf16<NT, false><<<g, 256, 0, s>>>(X, ldx, Bt, ldt, n, p.kchunk, P, p.cp, st);
+}
+
+int dispatch_cols_bf16(int nt, const __bf16* X, int64_t ldx, bool vec, const __bf16* Bt, int64_t ldt, int n,
+                       const GemmPlan& p, float* P, const DevState* st, hipStream_t s) {
+  switch (nt) {
+    case 1: launch_cols_bf16<1>(X, ldx, vec, Bt, ldt, n, p, P, st, s); return 0;
+    case 2: launch_cols_bf16<2>(X, ldx, vec, Bt, ldt, n, p, P, st, s); return 0;
+    case 3: launch_cols_bf16<3>(X, ldx, vec, Bt, ldt, n, p, P, st, s); return 0;
+    case 4: launch_cols_bf16<4>(X, ldx, vec, Bt, ldt, n, p, P, st, s); return 0;
+    case 5: launch_cols_bf16<5>(X, ldx, vec, Bt, ldt, n, p, P, st, s); return 0;
+    case 6: launch_cols_bf16<6>(X, ldx, vec, Bt, ldt, n, p, P, st, s); return 0;
+    default: return -1;
+  }
+}
+
 int dispatch_bf16(int nt, int rt, const __bf16* X, int64_t ldx, bool vec, const __bf16* Bt, int64_t ldt, int n,
                   const GemmPlan& p, float* P, const DevState* st, hipStream_t s) {
 #define CASE(NT_, RT_) \
@@ -790,6 +918,16 @@ GemmPlan gemm_plan(int n, int c, int compute_dtype) {
     int splits = std::max(1, ceil_div(1024, strips));
     splits = std::min(splits, std::max(1, n / 256));
     p.kchunk = 16 * ceil_div(ceil_div(n, splits), 16);
+    p.splits = ceil_div(n, p.kchunk);
+    return p;
+  }
+  if (compute_dtype == SYMNMF_BF16) {
+    // the same for BF16: strips of 128 columns, splits in multiples of 32 rows
+    p.cols = true;
+    const int strips = ceil_div(n, 128);
+    int splits = std::max(1, ceil_div(1024, strips));
+    splits = std::min(splits, std::max(1, n / 256));
+    p.kchunk = 32 * ceil_div(ceil_div(n, splits), 32);
     p.splits = ceil_div(n, p.kchunk);
     return p;
   }
@@ -828,7 +966,8 @@ int dense_gemm_bt(const void* X, int xdtype, int64_t ldx, const void* Bt, int n,
                                 s);
   } else {
     const bool vec = (ldx % 8 == 0) && ((uintptr_t)X % 16 == 0);
-    rc = dispatch_bf16(nt, p.rt, (const __bf16*)X, ldx, vec, (const __bf16*)Bt, p.ldt, n, p, (float*)P, st, s);
+    rc = p.cols ? dispatch_cols_bf16(nt, (const __bf16*)X, ldx, vec, (const __bf16*)Bt, p.ldt, n, p, (float*)P, st, s)
+                : dispatch_bf16(nt, p.rt, (const __bf16*)X, ldx, vec, (const __bf16*)Bt, p.ldt, n, p, (float*)P, st, s);
   }
   if (rc) return rc;
   return hipGetLastError() == hipSuccess ? 0 : -1;
@@ -885,7 +1024,8 @@ int dense_gemm(const void* X, int xdtype, int64_t ldx, const void* B, int bdtype
     else
       k_transpose_pad<double, __bf16><<<tg, 256, 0, s>>>((const double*)B, ldb, n, c, (__bf16*)Bt, p.ldt, p.cp, st);
     const bool vec = (ldx % 8 == 0) && ((uintptr_t)X % 16 == 0);
-    if (dispatch_bf16(nt, p.rt, (const __bf16*)X, ldx, vec, (const __bf16*)Bt, p.ldt, n, p, (float*)P, st, s))
+    if (p.cols ? dispatch_cols_bf16(nt, (const __bf16*)X, ldx, vec, (const __bf16*)Bt, p.ldt, n, p, (float*)P, st, s)
+               : dispatch_bf16(nt, p.rt, (const __bf16*)X, ldx, vec, (const __bf16*)Bt, p.ldt, n, p, (float*)P, st, s))
       return -1;
   }
   if (xdtype != SYMNMF_F64) {
