@@ -1,14 +1,13 @@
 // Dense-X kernels: one-time scalars pass, the product Y = X B on MFMA
-// (FP64, FP32 and BF16 inputs), split-K reduction, FP32 -> BF16 conversion and
-// the exact residual pass.
+// (FP64, FP32 and BF16 inputs, and FP32 from three BF16 pieces), split-K
+// reduction, FP32 -> BF16 conversion and the exact residual pass.
 //
 // The product X B (B = H, W, the sketch Omega or the basis Q) is the main
 // cost of every iteration (Section 2.1.2: X H is reused by a whole HALS
-// sweep; Section 3.1 complexity).  X is streamed exactly once per product, so
-// the kernel is laid out for HBM streaming: each wave owns 16*RT rows of X
-// and reads them with 16-byte loads straight into MFMA A-operands; the B
-// panel of the current K tile is staged once per workgroup in LDS and shared
-// by its four waves.
+// sweep; Section 3.1 complexity).  X is streamed exactly once per product,
+// LDS-free, from HBM into registers.  FP32 and BF16 read X along its rows
+// (k_gemm_cols*: Y^T = B^T X, X symmetric); FP64 keeps the row-owner layout
+// (k_gemm_mfma).  The B operand is a transposed, zero-padded panel Bt.
 #include "kernels.hpp"
 
 namespace {
@@ -84,7 +83,7 @@ __global__ void k_scalars_final(int nb, const double* __restrict__ bpart, double
 }
 
 // ---------------------------------------------------------------------------
-// MFMA product P[split] = X[:, krange] B[krange, :].
+// Row-owner MFMA product P[split] = X[:, krange] B[krange, :] (FP64).
 //
 // The B operand is first written transposed and zero padded, Bt[q][j] =
 // B[j][q] (q < cp, j < npad), so a lane fetches its B values for four
@@ -123,7 +122,6 @@ template <> struct Vec4<float> { using type = floatx4; };
 template <> struct Vec4<double> { using type = doublex4; };
 
 constexpr int GEMM_KT = 64;   // K per tile, FP32 / FP64 (4 sub-steps of 16)
-constexpr int BF_KT = 128;    // K per tile, BF16 (4 sub-steps of 32)
 constexpr int BT_PAD = 128;   // Bt row length is n rounded up to this
 
 template <typename TB, typename TO>
@@ -348,106 +346,6 @@ __global__ __launch_bounds__(256) void k_gemm_cols(const float* __restrict__ X, 
     }
 }
 
-// ---------------------------------------------------------------------------
-// BF16 MFMA product (FP32 accumulate): v_mfma_f32_16x16x32_bf16.  Lane l
-// supplies 8 consecutive K values of A row l%16 and of B column l%16 (group
-// g = l/16 covers K offsets 8g..8g+7 of the 32-wide step); accumulator layout
-// as the f32 instruction.  Bt holds B rounded to BF16 (nearest even).
-// ---------------------------------------------------------------------------
-template <int NT, int RT, bool VEC>
-__global__ __launch_bounds__(256) void k_gemm_bf16(const __bf16* __restrict__ X, int64_t ldx,
-                                                   const __bf16* __restrict__ Bt, int64_t ldt, int n, int kchunk,
-                                                   float* __restrict__ P, int cp, const DevState* __restrict__ st) {
-  if (stopped(st)) return;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int li = lane & 15, lg = lane >> 4;
-  const int row_base = (blockIdx.x * 4 + wave) * (16 * RT);
-  if (row_base >= n) return;
-  const int kb = blockIdx.y * kchunk;
-  const int ke = min(n, kb + kchunk);
-
-  floatx4 acc[RT][NT];
-#pragma unroll
-  for (int r = 0; r < RT; ++r)
-#pragma unroll
-    for (int t = 0; t < NT; ++t) acc[r][t] = floatx4{0, 0, 0, 0};
-
-  const __bf16* xrow[RT];
-#pragma unroll
-  for (int r = 0; r < RT; ++r) xrow[r] = X + (int64_t)min(row_base + 16 * r + li, n - 1) * ldx + 8 * lg;
-  const __bf16* brow[NT];
-#pragma unroll
-  for (int t = 0; t < NT; ++t) brow[t] = Bt + (int64_t)(16 * t + li) * ldt + 8 * lg;
-
-  const int nfull = VEC ? (ke - kb) / BF_KT : 0;
-  bf16x8 x0[RT][4], b0[NT][4], x1[RT][4], b1[NT][4];
-  auto load = [&](bf16x8 (&xv)[RT][4], bf16x8 (&bv)[NT][4], int k0) {
-#pragma unroll
-    for (int r = 0; r < RT; ++r)
-#pragma unroll
-      for (int ss = 0; ss < 4; ++ss)
-        xv[r][ss] = __builtin_nontemporal_load((const bf16x8*)(xrow[r] + k0 + 32 * ss));
-#pragma unroll
-    for (int ct = 0; ct < NT; ++ct)
-#pragma unroll
-      for (int ss = 0; ss < 4; ++ss) bv[ct][ss] = *(const bf16x8*)(brow[ct] + k0 + 32 * ss);
-  };
-  auto compute = [&](const bf16x8 (&xv)[RT][4], const bf16x8 (&bv)[NT][4]) {
-#pragma unroll
-    for (int ss = 0; ss < 4; ++ss)
-#pragma unroll
-      for (int ct = 0; ct < NT; ++ct)
-#pragma unroll
-        for (int r = 0; r < RT; ++r)
-          acc[r][ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xv[r][ss], bv[ct][ss], acc[r][ct], 0, 0, 0);
-  };
-  int t = 0;
-  if (nfull > 0) load(x0, b0, kb);
-  for (; t + 2 < nfull; t += 2) {
-    load(x1, b1, kb + (t + 1) * BF_KT);
-    compute(x0, b0);
-    load(x0, b0, kb + (t + 2) * BF_KT);
-    compute(x1, b1);
-  }
-  if (t + 1 < nfull) {
-    load(x1, b1, kb + (t + 1) * BF_KT);
-    compute(x0, b0);
-    compute(x1, b1);
-  } else if (t < nfull) {
-    compute(x0, b0);
-  }
-  for (int k0 = kb + nfull * BF_KT; k0 < ke; k0 += BF_KT) {
-#pragma unroll
-    for (int ss = 0; ss < 4; ++ss) {
-      bf16x8 xs[RT], bs[NT];
-#pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const int col = k0 + 32 * ss + 8 * lg + u;
-#pragma unroll
-        for (int r = 0; r < RT; ++r) xs[r][u] = (col < ke) ? xrow[r][col - 8 * lg] : (__bf16)0.0f;
-#pragma unroll
-        for (int ct = 0; ct < NT; ++ct) bs[ct][u] = brow[ct][k0 + 32 * ss + u];
-      }
-#pragma unroll
-      for (int ct = 0; ct < NT; ++ct)
-#pragma unroll
-        for (int r = 0; r < RT; ++r)
-          acc[r][ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xs[r], bs[ct], acc[r][ct], 0, 0, 0);
-    }
-  }
-  float* out = P + (int64_t)blockIdx.y * n * cp;
-#pragma unroll
-  for (int r = 0; r < RT; ++r)
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int row = row_base + 16 * r + 4 * lg + v;
-      if (row < n) {
-#pragma unroll
-        for (int ct = 0; ct < NT; ++ct) out[(int64_t)row * cp + 16 * ct + li] = acc[r][ct][v];
-      }
-    }
-}
-
 // Y[r][j] = sum_s P[s][r][j], j < c, fixed order over s.
 template <typename TP, typename TY>
 __global__ __launch_bounds__(256) void k_splitk_reduce(const TP* __restrict__ P, int splits, int n, int c, int cp,
@@ -473,7 +371,8 @@ __global__ __launch_bounds__(256) void k_f32_to_bf16(const float* __restrict__ s
   }
 }
 
-// FP32 product on the BF16 matrix cores.  Every FP32 value x is split
+// FP32 products on the BF16 matrix cores (compute dtype F32X3).  Every FP32
+// value x is split
 // exactly as x = hi + mid + lo with hi = bf16(x), mid = bf16(x - hi),
 // lo = bf16(x - hi - mid) (each subtraction is exact in FP32: the rounded
 // part shares the leading bits), so |x - hi - mid - lo| <= 2^-24 |x|.  The
@@ -482,13 +381,10 @@ __global__ __launch_bounds__(256) void k_f32_to_bf16(const float* __restrict__ s
 // 2^-24 and below, the size of FP32 rounding.  Six v_mfma_f32_16x16x32_bf16
 // replace the eight v_mfma_f32_16x16x4f32 of a 32-wide K step and take about
 // a third of their matrix-core time, but the splitting adds about five
-// vector instructions per loaded element (of X and of the B panel): on
-// MI355X at n = 16384, k = 32..64 and n = 65536, k = 64 the kernel runs at
-// the speed of the FP32 one (within 7%), with a smaller error (relative
-// 3e-7 against 5e-7).  Layout and pipelining follow k_gemm_mfma: LDS-free,
-// 16 * RT rows per wave, two register stages of raw FP32 loads; the
-// operand lanes follow the BF16 instruction (lane (li, lg) holds K elements
-// 8 lg .. 8 lg + 7 of row li of X and of row li of the B panel).
+// vector instructions per element of X and of the B panel.  Measured on
+// MI355X against the FP32 MFMA kernel (k_gemm_cols): 8% slower at n = 16384,
+// k = 32 and 48, 3% faster at k = 64, 11% faster at n = 65536, k = 64, with
+// a smaller error (relative 3e-7 against 5e-7).
 __device__ __forceinline__ void split3(const floatx8& x, bf16x8& h, bf16x8& m, bf16x8& l) {
   h = __builtin_convertvector(x, bf16x8);
   const floatx8 r1 = x - __builtin_convertvector(h, floatx8);
@@ -509,119 +405,103 @@ __device__ __forceinline__ floatx4 mfma_x3(const bf16x8& ah, const bf16x8& am, c
   return acc;
 }
 
-template <int NT, int RT, bool VEC>
-__global__ __launch_bounds__(256) void k_gemm_x3(const float* __restrict__ X, int64_t ldx, const float* __restrict__ Bt,
-                                                 int64_t ldt, int n, int kchunk, float* __restrict__ P, int cp,
-                                                 const DevState* __restrict__ st) {
+// FP32 product from three BF16 pieces (split3 / mfma_x3 above), read along
+// rows of X like k_gemm_cols.  One K step takes 32 rows: lane (ln, lq) loads
+// the float4 at columns j0 + 64 ct + 4 ln of the rows i0 + 8 lq + e
+// (e = 0..7); column u of that 8 x 4 block is split into the BF16 pieces of
+// the B operand (K = 8 lq + e) of the MFMAs of column j0 + 64 ct + 4 ln + u.
+// A = the FP32 B panel, 8 consecutive K of Bt[16 t + ln] per lane, split the
+// same way.  Output as k_gemm_cols.
+template <int NT, int CT, bool VEC>
+__global__ __launch_bounds__(256) void k_gemm_cols_x3(const float* __restrict__ X, int64_t ldx,
+                                                      const float* __restrict__ Bt, int64_t ldt, int n, int rchunk,
+                                                      float* __restrict__ P, int cp,
+                                                      const DevState* __restrict__ st) {
   if (stopped(st)) return;
-  constexpr int SS = GEMM_KT / 32;  // 32-wide K steps per tile
+  constexpr int DS = 2;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int li = lane & 15, lg = lane >> 4;
-  const int row_base = (blockIdx.x * 4 + wave) * (16 * RT);
-  if (row_base >= n) return;
-  const int kb = blockIdx.y * kchunk;
-  const int ke = min(n, kb + kchunk);
+  const int ln = lane & 15, lq = lane >> 4;
+  const int j0 = (blockIdx.x * 4 + wave) * (64 * CT);
+  if (j0 >= n) return;
+  const int ib = blockIdx.y * rchunk;
+  const int ie = min(n, ib + rchunk);
+  const int nstep = (ie - ib + 31) / 32;
+  const bool full = VEC && (j0 + 64 * CT <= n);
 
-  floatx4 acc[RT][NT];
+  floatx4 acc[NT][CT][4];
 #pragma unroll
-  for (int r = 0; r < RT; ++r)
+  for (int t = 0; t < NT; ++t)
 #pragma unroll
-    for (int t = 0; t < NT; ++t) acc[r][t] = floatx4{0, 0, 0, 0};
+    for (int ct = 0; ct < CT; ++ct)
+#pragma unroll
+      for (int u = 0; u < 4; ++u) acc[t][ct][u] = floatx4{0, 0, 0, 0};
+  const float* bp[NT];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) bp[t] = Bt + (int64_t)(16 * t + ln) * ldt + 8 * lq;
 
-  const float* xrow[RT];
+  floatx4 xv[DS][CT][8], bv[DS][NT][2];
+  // Rows beyond n (last split only) read row n - 1; the padded Bt is zero there.
+  auto load = [&](floatx4 (&xd)[CT][8], floatx4 (&bd)[NT][2], int step) {
+    const int i0 = ib + 32 * step;
 #pragma unroll
-  for (int r = 0; r < RT; ++r) xrow[r] = X + (int64_t)min(row_base + 16 * r + li, n - 1) * ldx + 8 * lg;
-  const float* brow[NT];
+    for (int t = 0; t < NT; ++t) {
+      bd[t][0] = *(const floatx4*)(bp[t] + i0);
+      bd[t][1] = *(const floatx4*)(bp[t] + i0 + 4);
+    }
 #pragma unroll
-  for (int t = 0; t < NT; ++t) brow[t] = Bt + (int64_t)(16 * t + li) * ldt + 8 * lg;
-
-  const int nfull = VEC ? (ke - kb) / GEMM_KT : 0;
-  floatx4 x0[RT][SS][2], b0[NT][SS][2], x1[RT][SS][2], b1[NT][SS][2];
-  auto load = [&](floatx4 (&xv)[RT][SS][2], floatx4 (&bv)[NT][SS][2], int k0) {
+    for (int e = 0; e < 8; ++e) {
+      const float* xr = X + (int64_t)min(i0 + 8 * lq + e, n - 1) * ldx + j0 + 4 * ln;
 #pragma unroll
-    for (int r = 0; r < RT; ++r)
+      for (int ct = 0; ct < CT; ++ct) {
+        if (full) {
+          xd[ct][e] = __builtin_nontemporal_load((const floatx4*)(xr + 64 * ct));
+        } else {
 #pragma unroll
-      for (int ss = 0; ss < SS; ++ss)
-#pragma unroll
-        for (int h = 0; h < 2; ++h)
-          xv[r][ss][h] = __builtin_nontemporal_load((const floatx4*)(xrow[r] + k0 + 32 * ss + 4 * h));
-#pragma unroll
-    for (int ct = 0; ct < NT; ++ct)
-#pragma unroll
-      for (int ss = 0; ss < SS; ++ss)
-#pragma unroll
-        for (int h = 0; h < 2; ++h) bv[ct][ss][h] = *(const floatx4*)(brow[ct] + k0 + 32 * ss + 4 * h);
-  };
-  auto join = [](const floatx4& a, const floatx4& b) {
-    return floatx8{a[0], a[1], a[2], a[3], b[0], b[1], b[2], b[3]};
-  };
-  auto compute = [&](const floatx4 (&xv)[RT][SS][2], const floatx4 (&bv)[NT][SS][2]) {
-#pragma unroll
-    for (int ss = 0; ss < SS; ++ss) {
-      bf16x8 bh[NT], bm[NT], bl[NT];
-#pragma unroll
-      for (int ct = 0; ct < NT; ++ct) split3(join(bv[ct][ss][0], bv[ct][ss][1]), bh[ct], bm[ct], bl[ct]);
-#pragma unroll
-      for (int r = 0; r < RT; ++r) {
-        bf16x8 xh, xm, xl;
-        split3(join(xv[r][ss][0], xv[r][ss][1]), xh, xm, xl);
-#pragma unroll
-        for (int ct = 0; ct < NT; ++ct) acc[r][ct] = mfma_x3(xh, xm, xl, bh[ct], bm[ct], bl[ct], acc[r][ct]);
+          for (int u = 0; u < 4; ++u) xd[ct][e][u] = (j0 + 64 * ct + 4 * ln + u < n) ? xr[64 * ct + u] : 0.0f;
+        }
       }
     }
   };
-  int t = 0;
-  if (nfull > 0) load(x0, b0, kb);
-  for (; t + 2 < nfull; t += 2) {
-    load(x1, b1, kb + (t + 1) * GEMM_KT);
-    compute(x0, b0);
-    load(x0, b0, kb + (t + 2) * GEMM_KT);
-    compute(x1, b1);
-  }
-  if (t + 1 < nfull) {
-    load(x1, b1, kb + (t + 1) * GEMM_KT);
-    compute(x0, b0);
-    compute(x1, b1);
-  } else if (t < nfull) {
-    compute(x0, b0);
-  }
-  // Remaining K (partial last tile, or all of it when X is not aligned for
-  // vector loads): guarded scalar loads of X; the B panel is zero padded.
-  for (int k0 = kb + nfull * GEMM_KT; k0 < ke; k0 += GEMM_KT) {
+  auto compute = [&](const floatx4 (&xd)[CT][8], const floatx4 (&bd)[NT][2]) {
+    bf16x8 ah[NT], am[NT], al[NT];
 #pragma unroll
-    for (int ss = 0; ss < SS; ++ss) {
-      floatx8 bs[NT];
+    for (int t = 0; t < NT; ++t) {
+      const floatx8 b = {bd[t][0][0], bd[t][0][1], bd[t][0][2], bd[t][0][3],
+                         bd[t][1][0], bd[t][1][1], bd[t][1][2], bd[t][1][3]};
+      split3(b, ah[t], am[t], al[t]);
+    }
 #pragma unroll
-      for (int ct = 0; ct < NT; ++ct)
+    for (int ct = 0; ct < CT; ++ct)
 #pragma unroll
-        for (int u = 0; u < 8; ++u) bs[ct][u] = brow[ct][k0 + 32 * ss + u];
-      bf16x8 bh[NT], bm[NT], bl[NT];
-#pragma unroll
-      for (int ct = 0; ct < NT; ++ct) split3(bs[ct], bh[ct], bm[ct], bl[ct]);
-#pragma unroll
-      for (int r = 0; r < RT; ++r) {
-        floatx8 xs;
-#pragma unroll
-        for (int u = 0; u < 8; ++u) {
-          const int col = k0 + 32 * ss + 8 * lg + u;
-          xs[u] = (col < ke) ? xrow[r][col - 8 * lg] : 0.0f;
-        }
+      for (int u = 0; u < 4; ++u) {
+        const floatx8 xc = {xd[ct][0][u], xd[ct][1][u], xd[ct][2][u], xd[ct][3][u],
+                            xd[ct][4][u], xd[ct][5][u], xd[ct][6][u], xd[ct][7][u]};
         bf16x8 xh, xm, xl;
-        split3(xs, xh, xm, xl);
+        split3(xc, xh, xm, xl);
 #pragma unroll
-        for (int ct = 0; ct < NT; ++ct) acc[r][ct] = mfma_x3(xh, xm, xl, bh[ct], bm[ct], bl[ct], acc[r][ct]);
+        for (int t = 0; t < NT; ++t) acc[t][ct][u] = mfma_x3(ah[t], am[t], al[t], xh, xm, xl, acc[t][ct][u]);
       }
+  };
+#pragma unroll
+  for (int d = 0; d < DS - 1; ++d)
+    if (d < nstep) load(xv[d], bv[d], d);
+  for (int step = 0; step < nstep; step += DS) {
+#pragma unroll
+    for (int d = 0; d < DS; ++d) {
+      const int pre = step + d + DS - 1;
+      if (pre < nstep) load(xv[(d + DS - 1) % DS], bv[(d + DS - 1) % DS], pre);
+      if (step + d < nstep) compute(xv[d], bv[d]);
     }
   }
   float* out = P + (int64_t)blockIdx.y * n * cp;
 #pragma unroll
-  for (int r = 0; r < RT; ++r)
+  for (int ct = 0; ct < CT; ++ct)
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int row = row_base + 16 * r + 4 * lg + v;
-      if (row < n) {
+    for (int u = 0; u < 4; ++u) {
+      const int j = j0 + 64 * ct + 4 * ln + u;
+      if (j < n) {
 #pragma unroll
-        for (int ct = 0; ct < NT; ++ct) out[(int64_t)row * cp + 16 * ct + li] = acc[r][ct][v];
+        for (int t = 0; t < NT; ++t) *(floatx4*)(out + (int64_t)j * cp + 16 * t + 4 * lq) = acc[t][ct][u];
       }
     }
 }
@@ -806,52 +686,19 @@ void launch_mfma(const TX* X, int64_t ldx, bool vec, const TX* Bt, int64_t ldt, 
   else
     k_gemm_mfma<TX, NT, RT, false><<<g, 256, 0, s>>>(X, ldx, Bt, ldt, n, p.kchunk, P, p.cp, st);
 }
-template <int NT, int RT>
-void launch_bf16(const __bf16* X, int64_t ldx, bool vec, const __bf16* Bt, int64_t ldt, int n, const GemmPlan& p,
-                 float* P, const DevState* st, hipStream_t s) {
-  dim3 g(ceil_div(ceil_div(n, 16 * RT), 4), p.splits);
-  if (vec)
-    k_gemm_bf16<NT, RT, true><<<g, 256, 0, s>>>(X, ldx, Bt, ldt, n, p.kchunk, P, p.cp, st);
-  else
-    k_gemm_bf16<NT, RT, false><<<g, 256, 0, s>>>(X, ldx, Bt, ldt, n, p.kchunk, P, p.cp, st);
-}
-
-// Rows per wave (16 * RT) by operand width: more rows amortise the B loads,
-// fewer keep the registers of wide B panels in budget.
-int pick_rt(int compute_dtype, int nt) {
-  if (compute_dtype == SYMNMF_F64) return nt <= 2 ? 2 : 1;
-  return nt <= 2 ? 4 : 2;
-}
+// FP64 rows per wave (16 * RT) by operand width: more rows amortise the B
+// loads, fewer keep the registers of wide B panels in budget.
+int pick_rt_f64(int nt) { return nt <= 2 ? 2 : 1; }
 
 template <typename TX>
 int dispatch_mfma(int nt, int rt, const TX* X, int64_t ldx, bool vec, const TX* Bt, int64_t ldt, int n,
                   const GemmPlan& p, TX* P, const DevState* st, hipStream_t s) {
 #define CASE(NT_, RT_) \
   if (nt == NT_ && rt == RT_) { launch_mfma<TX, NT_, RT_>(X, ldx, vec, Bt, ldt, n, p, P, st, s); return 0; }
-  CASE(1, 4) CASE(2, 4) CASE(1, 2) CASE(2, 2) CASE(3, 2) CASE(4, 2) CASE(5, 2) CASE(6, 2)
-  CASE(1, 1) CASE(2, 1) CASE(3, 1) CASE(4, 1) CASE(5, 1) CASE(6, 1)
+  CASE(1, 2) CASE(2, 2) CASE(3, 1) CASE(4, 1) CASE(5, 1) CASE(6, 1)
 #undef CASE
   return -1;
 }
-template <int NT, int RT>
-void launch_x3(const float* X, int64_t ldx, bool vec, const float* Bt, int64_t ldt, int n, const GemmPlan& p, float* P,
-               const DevState* st, hipStream_t s) {
-  dim3 g(ceil_div(n, 4 * 16 * RT), p.splits);
-  if (vec)
-    k_gemm_x3<NT, RT, true><<<g, 256, 0, s>>>(X, ldx, Bt, ldt, n, p.kchunk, P, p.cp, st);
-  else
-    k_gemm_x3<NT, RT, false><<<g, 256, 0, s>>>(X, ldx, Bt, ldt, n, p.kchunk, P, p.cp, st);
-}
-
-int dispatch_x3(int nt, int rt, const float* X, int64_t ldx, bool vec, const float* Bt, int64_t ldt, int n,
-                const GemmPlan& p, float* P, const DevState* st, hipStream_t s) {
-#define CASE(NT_, RT_) \
-  if (nt == NT_ && rt == RT_) { launch_x3<NT_, RT_>(X, ldx, vec, Bt, ldt, n, p, P, st, s); return 0; }
-  CASE(1, 4) CASE(2, 4) CASE(1, 2) CASE(2, 2) CASE(3, 2) CASE(4, 2) CASE(5, 2) CASE(6, 2)
-#undef CASE
-  return -1;
-}
-
 template <int NT, int CT>
 void launch_cols(const float* X, int64_t ldx, bool vec, const float* Bt, int64_t ldt, int n, const GemmPlan& p, float* P,
                  const DevState* st, hipStream_t s) {
@@ -866,6 +713,25 @@ int dispatch_cols(int nt, int ct, const float* X, int64_t ldx, bool vec, const f
                   const GemmPlan& p, float* P, const DevState* st, hipStream_t s) {
 #define CASE(NT_, CT_) \
   if (nt == NT_ && ct == CT_) { launch_cols<NT_, CT_>(X, ldx, vec, Bt, ldt, n, p, P, st, s); return 0; }
+  CASE(1, 2) CASE(2, 2) CASE(3, 1) CASE(4, 1) CASE(5, 1) CASE(6, 1)
+#undef CASE
+  return -1;
+}
+
+template <int NT, int CT>
+void launch_cols_x3(const float* X, int64_t ldx, bool vec, const float* Bt, int64_t ldt, int n, const GemmPlan& p,
+                    float* P, const DevState* st, hipStream_t s) {
+  dim3 g(ceil_div(n, 4 * 64 * CT), p.splits);
+  if (vec)
+    k_gemm_cols_x3<NT, CT, true><<<g, 256, 0, s>>>(X, ldx, Bt, ldt, n, p.kchunk, P, p.cp, st);
+  else
+    k_gemm_cols_x3<NT, CT, false><<<g, 256, 0, s>>>(X, ldx, Bt, ldt, n, p.kchunk, P, p.cp, st);
+}
+
+int dispatch_cols_x3(int nt, int ct, const float* X, int64_t ldx, bool vec, const float* Bt, int64_t ldt, int n,
+                     const GemmPlan& p, float* P, const DevState* st, hipStream_t s) {
+#define CASE(NT_, CT_) \
+  if (nt == NT_ && ct == CT_) { launch_cols_x3<NT_, CT_>(X, ldx, vec, Bt, ldt, n, p, P, st, s); return 0; }
   CASE(1, 2) CASE(2, 2) CASE(3, 1) CASE(4, 1) CASE(5, 1) CASE(6, 1)
 #undef CASE
   return -1;
@@ -894,14 +760,6 @@ int dispatch_cols_bf16(int nt, const __bf16* X, int64_t ldx, bool vec, const __b
   }
 }
 
-int dispatch_bf16(int nt, int rt, const __bf16* X, int64_t ldx, bool vec, const __bf16* Bt, int64_t ldt, int n,
-                  const GemmPlan& p, float* P, const DevState* st, hipStream_t s) {
-#define CASE(NT_, RT_) \
-  if (nt == NT_ && rt == RT_) { launch_bf16<NT_, RT_>(X, ldx, vec, Bt, ldt, n, p, P, st, s); return 0; }
-  CASE(1, 4) CASE(2, 4) CASE(3, 2) CASE(4, 2) CASE(5, 2) CASE(6, 2)
-#undef CASE
-  return -1;
-}
 }  // namespace
 
 GemmPlan gemm_plan(int n, int c, int compute_dtype) {
@@ -909,15 +767,17 @@ GemmPlan gemm_plan(int n, int c, int compute_dtype) {
   p.split3 = compute_dtype == SYMNMF_F32X3;
   p.cp = 16 * ceil_div(c, 16);
   p.ldt = (int64_t)BT_PAD * ceil_div(n, BT_PAD);
-  if (compute_dtype == SYMNMF_F32) {
+  if (compute_dtype == SYMNMF_F32 || compute_dtype == SYMNMF_F32X3) {
     // row-contiguous product: strips of 64 * ct columns, about one wave per
-    // SIMD in total, splits of at least 256 rows (multiples of 16)
+    // SIMD in total, splits of at least 256 rows (multiples of the K step:
+    // 16 rows for FP32 MFMA, 32 for the BF16 pieces)
     p.cols = true;
     p.ct = p.cp <= 32 ? 2 : 1;
+    const int step = p.split3 ? 32 : 16;
     const int strips = ceil_div(n, 64 * p.ct);
     int splits = std::max(1, ceil_div(1024, strips));
     splits = std::min(splits, std::max(1, n / 256));
-    p.kchunk = 16 * ceil_div(ceil_div(n, splits), 16);
+    p.kchunk = step * ceil_div(ceil_div(n, splits), step);
     p.splits = ceil_div(n, p.kchunk);
     return p;
   }
@@ -931,14 +791,11 @@ GemmPlan gemm_plan(int n, int c, int compute_dtype) {
     p.splits = ceil_div(n, p.kchunk);
     return p;
   }
-  if (p.split3) compute_dtype = SYMNMF_F32;
-  p.rt = pick_rt(compute_dtype, p.cp / 16);
-  const int kt = compute_dtype == SYMNMF_BF16 ? BF_KT : GEMM_KT;
+  // FP64: the row-owner kernel, about two waves per SIMD (256 CUs x 4 SIMDs)
+  p.rt = pick_rt_f64(p.cp / 16);
+  const int kt = GEMM_KT;
   const int waves = ceil_div(n, 16 * p.rt);
-  // Measured on MI355X: the software-pipelined schedule runs best with about
-  // one wave per SIMD at 64 rows per wave, two at 32 rows (256 CUs x 4 SIMDs).
-  const int target = p.rt >= 4 ? 1024 : 2048;
-  int splits = std::max(1, ceil_div(target, waves));
+  int splits = std::max(1, ceil_div(2048, waves));
   splits = std::min(splits, std::max(1, ceil_div(n, 4 * kt)));
   p.kchunk = kt * ceil_div(ceil_div(n, splits), kt);
   p.splits = ceil_div(n, p.kchunk);
@@ -957,17 +814,12 @@ int dense_gemm_bt(const void* X, int xdtype, int64_t ldx, const void* Bt, int n,
     rc = dispatch_mfma<double>(nt, p.rt, (const double*)X, ldx, vec, (const double*)Bt, p.ldt, n, p, (double*)P, st, s);
   } else if (xdtype == SYMNMF_F32) {
     const bool vec = (ldx % 4 == 0) && ((uintptr_t)X % 16 == 0);
-    if (p.cols)
-      rc = dispatch_cols(nt, p.ct, (const float*)X, ldx, vec, (const float*)Bt, p.ldt, n, p, (float*)P, st, s);
-    else if (p.split3)
-      rc = dispatch_x3(nt, p.rt, (const float*)X, ldx, vec, (const float*)Bt, p.ldt, n, p, (float*)P, st, s);
-    else
-      rc = dispatch_mfma<float>(nt, p.rt, (const float*)X, ldx, vec, (const float*)Bt, p.ldt, n, p, (float*)P, st,
-                                s);
+    rc = p.split3
+             ? dispatch_cols_x3(nt, p.ct, (const float*)X, ldx, vec, (const float*)Bt, p.ldt, n, p, (float*)P, st, s)
+             : dispatch_cols(nt, p.ct, (const float*)X, ldx, vec, (const float*)Bt, p.ldt, n, p, (float*)P, st, s);
   } else {
     const bool vec = (ldx % 8 == 0) && ((uintptr_t)X % 16 == 0);
-    rc = p.cols ? dispatch_cols_bf16(nt, (const __bf16*)X, ldx, vec, (const __bf16*)Bt, p.ldt, n, p, (float*)P, st, s)
-                : dispatch_bf16(nt, p.rt, (const __bf16*)X, ldx, vec, (const __bf16*)Bt, p.ldt, n, p, (float*)P, st, s);
+    rc = dispatch_cols_bf16(nt, (const __bf16*)X, ldx, vec, (const __bf16*)Bt, p.ldt, n, p, (float*)P, st, s);
   }
   if (rc) return rc;
   return hipGetLastError() == hipSuccess ? 0 : -1;
@@ -1008,24 +860,17 @@ int dense_gemm(const void* X, int xdtype, int64_t ldx, const void* B, int bdtype
     else
       k_transpose_pad<double, float><<<tg, 256, 0, s>>>((const double*)B, ldb, n, c, (float*)Bt, p.ldt, p.cp, st);
     const bool vec = (ldx % 4 == 0) && ((uintptr_t)X % 16 == 0);
-    if (p.cols) {
-      if (dispatch_cols(nt, p.ct, (const float*)X, ldx, vec, (const float*)Bt, p.ldt, n, p, (float*)P, st, s))
-        return -1;
-    } else if (p.split3) {
-      if (dispatch_x3(nt, p.rt, (const float*)X, ldx, vec, (const float*)Bt, p.ldt, n, p, (float*)P, st, s))
-        return -1;
-    } else if (dispatch_mfma<float>(nt, p.rt, (const float*)X, ldx, vec, (const float*)Bt, p.ldt, n, p, (float*)P,
-                                    st, s)) {
+    if (p.split3 ? dispatch_cols_x3(nt, p.ct, (const float*)X, ldx, vec, (const float*)Bt, p.ldt, n, p, (float*)P,
+                                    st, s)
+                 : dispatch_cols(nt, p.ct, (const float*)X, ldx, vec, (const float*)Bt, p.ldt, n, p, (float*)P, st, s))
       return -1;
-    }
   } else {
     if (bdtype == SYMNMF_F32)
       k_transpose_pad<float, __bf16><<<tg, 256, 0, s>>>((const float*)B, ldb, n, c, (__bf16*)Bt, p.ldt, p.cp, st);
     else
       k_transpose_pad<double, __bf16><<<tg, 256, 0, s>>>((const double*)B, ldb, n, c, (__bf16*)Bt, p.ldt, p.cp, st);
     const bool vec = (ldx % 8 == 0) && ((uintptr_t)X % 16 == 0);
-    if (p.cols ? dispatch_cols_bf16(nt, (const __bf16*)X, ldx, vec, (const __bf16*)Bt, p.ldt, n, p, (float*)P, st, s)
-               : dispatch_bf16(nt, p.rt, (const __bf16*)X, ldx, vec, (const __bf16*)Bt, p.ldt, n, p, (float*)P, st, s))
+    if (dispatch_cols_bf16(nt, (const __bf16*)X, ldx, vec, (const __bf16*)Bt, p.ldt, n, p, (float*)P, st, s))
       return -1;
   }
   if (xdtype != SYMNMF_F64) {

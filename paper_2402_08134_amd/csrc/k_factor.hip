@@ -376,6 +376,94 @@ __global__ __launch_bounds__(64) void k_chol_wave(const double* __restrict__ G, 
 }
 
 // ---------------------------------------------------------------------------
+// Cholesky G + shift I = L L^T and L^{-1} in the registers of one wavefront:
+// lane r holds row r (KM doubles, KM = k rounded up to 16; rows and columns
+// beyond k are the identity).  Step j of the factorisation takes the pivot
+// from lane j, scales column j in every lane, then broadcasts column j
+// (v_readlane, one per entry) for the rank-one update of the trailing rows;
+// the inverse is built row by row the same way (row t of L^{-1} is final
+// after step t, broadcast, and subtracted from the rows below).  With all
+// loops unrolled every register index is static; only the lower triangle is
+// meaningful.  Retries with the same growing shifts as the LDS kernels.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double lane_value(double v, int lane) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
+  return __hiloint2double(hi, lo);
+}
+
+template <int KM>
+__global__ __launch_bounds__(64) void k_chol_regs(const double* __restrict__ G, int k, double* __restrict__ R,
+                                                  double* __restrict__ Rinv, int* d_flags, int flag_bit,
+                                                  int* d_fail) {
+  const int r = threadIdx.x;
+  const bool act = r < k;
+  double g[KM];
+#pragma unroll
+  for (int c = 0; c < KM; ++c) g[c] = (act && c < k) ? G[r * k + c] : (c == r ? 1.0 : 0.0);
+  double tr = act ? G[r * k + r] : 0.0;
+  tr = wave_sum(tr);
+  double shift = 0.0, grow = 1e-12 * fmax(tr, 1e-300) / k;
+  double a[KM];
+  bool ok = false;
+  for (int attempt = 0; attempt < 6 && !ok; ++attempt) {
+    if (attempt > 0) {
+      shift = grow;  // 1e-12, 1e-10, ... times tr(G) / k
+      grow *= 100.0;
+    }
+#pragma unroll
+    for (int c = 0; c < KM; ++c) a[c] = g[c] + ((act && c == r) ? shift : 0.0);
+    ok = true;
+#pragma unroll
+    for (int j = 0; j < KM; ++j) {
+      if (ok) {
+        const double d = lane_value(a[j], j);
+        if (!(d > 0.0) || !isfinite(d)) {
+          ok = false;
+        } else {
+          const double ljj = sqrt(d);
+          const double rl = 1.0 / ljj;
+          a[j] = r > j ? a[j] * rl : (r == j ? ljj : a[j]);
+#pragma unroll
+          for (int c = j + 1; c < KM; ++c) a[c] = fma(-a[j], lane_value(a[j], c), a[c]);
+        }
+      }
+    }
+  }
+  if (!ok) {
+    if (r == 0) *d_fail = 1;
+    return;
+  }
+  if (r == 0 && shift > 0.0 && d_flags) atomicOr(d_flags, flag_bit);
+  // R = L^T: R[c][r] = L[r][c]
+  if (act) {
+#pragma unroll
+    for (int c = 0; c < KM; ++c)
+      if (c < k) R[c * k + r] = c <= r ? a[c] : 0.0;
+  }
+  double x[KM];
+#pragma unroll
+  for (int c = 0; c < KM; ++c) x[c] = c == r ? 1.0 : 0.0;
+#pragma unroll
+  for (int t = 0; t < KM; ++t) {
+    const double rt = 1.0 / lane_value(a[t], t);
+#pragma unroll
+    for (int c = 0; c <= t; ++c) x[c] = r == t ? x[c] * rt : x[c];
+#pragma unroll
+    for (int c = 0; c <= t; ++c) {
+      const double xt = lane_value(x[c], t);
+      x[c] = r > t ? fma(-a[t], xt, x[c]) : x[c];
+    }
+  }
+  // R^{-1} = (L^{-1})^T: Rinv[c][r] = X[r][c]
+  if (act) {
+#pragma unroll
+    for (int c = 0; c < KM; ++c)
+      if (c < k) Rinv[c * k + r] = x[c];
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Parallel cyclic Jacobi (round-robin pairing) on A = (T + T^T) / 2 in LDS;
 // V accumulated in LDS next to A, then columns sorted by descending
 // eigenvalue into V.
@@ -710,7 +798,12 @@ int rowmat(const void* A, int adtype, int64_t lda, int n, int l, const double* M
 int chol_inverse(const double* G, int k, double* R, double* Rinv, int* d_flags, int flag_bit, int* d_fail,
                  hipStream_t s) {
   if (k >= 1 && k <= 64) {
-    k_chol_wave<<<1, 64, 0, s>>>(G, k, R, Rinv, d_flags, flag_bit, d_fail);
+    switch (16 * ceil_div(k, 16)) {
+      case 16: k_chol_regs<16><<<1, 64, 0, s>>>(G, k, R, Rinv, d_flags, flag_bit, d_fail); break;
+      case 32: k_chol_regs<32><<<1, 64, 0, s>>>(G, k, R, Rinv, d_flags, flag_bit, d_fail); break;
+      case 48: k_chol_regs<48><<<1, 64, 0, s>>>(G, k, R, Rinv, d_flags, flag_bit, d_fail); break;
+      default: k_chol_regs<64><<<1, 64, 0, s>>>(G, k, R, Rinv, d_flags, flag_bit, d_fail); break;
+    }
     return hipGetLastError() == hipSuccess ? 0 : -1;
   }
   const size_t lds = 2 * (size_t)k * (k + 1) * sizeof(double);
