@@ -62,21 +62,40 @@ __global__ __launch_bounds__(256) void k_gram(const TA* __restrict__ A, int64_t 
   for (int i = 0; i < T; ++i)
 #pragma unroll
     for (int j = 0; j < T; ++j) acc[i][j] = 0.0;
-  for (int rb = r0; rb < r1; rb += RB) {
-    __syncthreads();
-    for (int e = tid; e < RB * CM; e += 256) {
+  // Each thread stages EPT entries of the 16-row chunk; the next chunk's
+  // values are loaded into registers while the current one is multiplied.
+  constexpr int EPT = (RB * CM + 255) / 256;
+  double na[EPT], nbv[EPT];
+  auto fetch = [&](int rb) {
+#pragma unroll
+    for (int u = 0; u < EPT; ++u) {
+      const int e = tid + 256 * u;
       const int rr = e / CM, q = e - rr * CM;
       const int r = rb + rr;
       double a = 0.0, b = 0.0;
-      if (r < r1) {
+      if (e < RB * CM && r < r1) {
         const int src = rows ? rows[r] : r;
         if (q < ca) a = (double)A[(int64_t)src * lda + q] * (w ? w[r] : 1.0);
         if (q < cb) b = (double)B[(int64_t)src * ldb + q];
       }
-      As[rr][q] = a;
-      Bs[rr][q] = b;
+      na[u] = a;
+      nbv[u] = b;
+    }
+  };
+  if (r0 < r1) fetch(r0);
+  for (int rb = r0; rb < r1; rb += RB) {
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < EPT; ++u) {
+      const int e = tid + 256 * u;
+      if (e < RB * CM) {
+        const int rr = e / CM, q = e - rr * CM;
+        As[rr][q] = na[u];
+        Bs[rr][q] = nbv[u];
+      }
     }
     __syncthreads();
+    if (rb + RB < r1) fetch(rb + RB);
 #pragma unroll 4
     for (int rr = 0; rr < RB; ++rr) {
       double bv[T];
@@ -109,8 +128,18 @@ __global__ __launch_bounds__(256) void k_gram_reduce(const double* __restrict__ 
   const int tot = (Ghat ? kp * kp : ca * cb);
   if (e >= max(tot, ca * cb)) return;
   if (e < ca * cb) {
+    // fixed order, loads issued 8 at a time
+    const int64_t stride = (int64_t)ca * cb;
     double acc = 0.0;
-    for (int b = 0; b < nb; ++b) acc += part[(int64_t)b * ca * cb + e];
+    int b = 0;
+    for (; b + 8 <= nb; b += 8) {
+      double v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = part[(int64_t)(b + u) * stride + e];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) acc += v[u];
+    }
+    for (; b < nb; ++b) acc += part[(int64_t)b * stride + e];
     if (G) G[e] = acc;
     if (Ghat) {
       const int p = e / cb, q = e - p * cb;
@@ -191,11 +220,19 @@ __global__ __launch_bounds__(256) void k_rowmat(const TA* __restrict__ A, int64_
   const int j = (int)(e / c), q = (int)(e - (int64_t)j * c);
   const TA* a = A + (int64_t)j * lda;
   double acc = 0.0;
-  if (scale) {
-    for (int p = 0; p < l; ++p) acc = fma((double)a[p] * scale[p], M[p * c + q], acc);
-  } else {
-    for (int p = 0; p < l; ++p) acc = fma((double)a[p], M[p * c + q], acc);
+  // loads of 8 terms issued together, summed in order
+  int p = 0;
+  for (; p + 8 <= l; p += 8) {
+    double av[8], mv[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      av[u] = (double)a[p + u] * (scale ? scale[p + u] : 1.0);
+      mv[u] = M[(p + u) * c + q];
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) acc = fma(av[u], mv[u], acc);
   }
+  for (; p < l; ++p) acc = fma((double)a[p] * (scale ? scale[p] : 1.0), M[p * c + q], acc);
   out[(int64_t)j * ldo + q] = (TO)acc;
 }
 
@@ -739,7 +776,9 @@ int gram(const void* A, int adtype, int64_t lda, int ca, const void* B, int bdty
   if (ca > 96 || cb > 96 || ca < 1 || cb < 1) return -1;
   const int t = ceil_div(std::max(ca, cb), 16);
   const int nrows = rows ? max_rows : n;
-  const int nb = std::max(1, std::min(256, ceil_div(std::max(nrows, 1), 256)));
+  // 64 rows per block (256 blocks at n = 16384; more rows per block chain
+  // more load latencies)
+  const int nb = std::max(1, std::min(256, ceil_div(std::max(nrows, 1), 64)));
   const int rpb = 16 * ceil_div(ceil_div(std::max(nrows, 1), nb), 16);
   double* part = ws.dbl((size_t)nb * ca * cb);
   if (!part) return -1;
