@@ -26,7 +26,19 @@ __global__ __launch_bounds__(256) void k_dense_colstats(const TX* __restrict__ X
   const int r0 = c * rows_per_chunk;
   const int r1 = min(n, r0 + rows_per_chunk);
   double s = 0.0, q = 0.0, m = -INFINITY;
-  for (int r = r0; r < r1; ++r) {
+  int r = r0;
+  for (; r + 8 <= r1; r += 8) {  // 8 loads in flight, summed in row order
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = to_f64(X[(int64_t)(r + u) * ld + j]);
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      s += v[u];
+      q += v[u] * v[u];
+      m = fmax(m, v[u]);
+    }
+  }
+  for (; r < r1; ++r) {
     const double v = to_f64(X[(int64_t)r * ld + j]);
     s += v;
     q += v * v;
@@ -35,6 +47,43 @@ __global__ __launch_bounds__(256) void k_dense_colstats(const TX* __restrict__ X
   psum[(int64_t)c * n + j] = s;
   psq[(int64_t)c * n + j] = q;
   pmax[(int64_t)c * n + j] = m;
+}
+
+// The same for FP32 X with 16-byte loads: thread owns columns 4 t .. 4 t + 3
+// (same per-column order of the sums as above).
+__global__ __launch_bounds__(256) void k_dense_colstats_f4(const float* __restrict__ X, int64_t ld, int n,
+                                                           int rows_per_chunk, double* __restrict__ psum,
+                                                           double* __restrict__ psq, double* __restrict__ pmax) {
+  const int j = 4 * (blockIdx.x * 256 + threadIdx.x);
+  const int c = blockIdx.y;
+  if (j >= n) return;
+  const int r0 = c * rows_per_chunk;
+  const int r1 = min(n, r0 + rows_per_chunk);
+  double s[4] = {0, 0, 0, 0}, q[4] = {0, 0, 0, 0}, m[4] = {-INFINITY, -INFINITY, -INFINITY, -INFINITY};
+  auto add = [&](const floatx4& v) {
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const double d = (double)v[t];
+      s[t] += d;
+      q[t] += d * d;
+      m[t] = fmax(m[t], d);
+    }
+  };
+  int r = r0;
+  for (; r + 8 <= r1; r += 8) {
+    floatx4 v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = __builtin_nontemporal_load((const floatx4*)(X + (int64_t)(r + u) * ld + j));
+#pragma unroll
+    for (int u = 0; u < 8; ++u) add(v[u]);
+  }
+  for (; r < r1; ++r) add(*(const floatx4*)(X + (int64_t)r * ld + j));
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    psum[(int64_t)c * n + j + t] = s[t];
+    psq[(int64_t)c * n + j + t] = q[t];
+    pmax[(int64_t)c * n + j + t] = m[t];
+  }
 }
 
 __global__ __launch_bounds__(256) void k_colstats_combine(int n, int chunks, const double* __restrict__ psum,
@@ -666,6 +715,8 @@ int dense_scalars(const void* X, int dtype, int64_t ld, int n, Workspace& ws, do
   dim3 g(ceil_div(n, 256), chunks);
   if (dtype == SYMNMF_F64)
     k_dense_colstats<double><<<g, 256, 0, s>>>((const double*)X, ld, n, rpc, psum, psq, pmax);
+  else if (dtype == SYMNMF_F32 && n % 4 == 0 && ld % 4 == 0 && (uintptr_t)X % 16 == 0)
+    k_dense_colstats_f4<<<dim3(ceil_div(n, 1024), chunks), 256, 0, s>>>((const float*)X, ld, n, rpc, psum, psq, pmax);
   else if (dtype == SYMNMF_F32)
     k_dense_colstats<float><<<g, 256, 0, s>>>((const float*)X, ld, n, rpc, psum, psq, pmax);
   else
