@@ -10,7 +10,15 @@ namespace {
 __global__ __launch_bounds__(256) void k_sum_partials(const double* __restrict__ part, int nb, double* __restrict__ out) {
   __shared__ double sc[8];
   double v = 0.0;
-  for (int i = threadIdx.x; i < nb; i += 256) v += part[i];
+  int i = threadIdx.x;
+  for (; i + 7 * 256 < nb; i += 8 * 256) {  // 8 loads in flight, added in order
+    double u[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) u[q] = part[i + q * 256];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) v += u[q];
+  }
+  for (; i < nb; i += 256) v += part[i];
   const double t = block_sum(v, sc);
   if (threadIdx.x == 0) out[0] = t;
 }
