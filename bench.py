@@ -320,42 +320,6 @@ def bench_sparse(args):
     print(json.dumps(out), flush=True)
 
 
-def gpu_gaussian_kernel(n, dim, comps, seed):
-    """The Gaussian-kernel similarity of workloads.gaussian_kernel (same
-    points, same sampled-pairs median for n > 16384), formed on the GPU in
-    FP64 blocks and stored as FP32, bitwise symmetric, zero diagonal."""
-    import numpy as np
-    import torch
-    import workloads
-    Pp, _ = workloads.gmm_points(n, dim, comps, seed)
-    rng = np.random.default_rng(seed + 1)
-    i = rng.integers(0, n, size=1 << 22)
-    j = rng.integers(0, n, size=1 << 22)
-    keep = i != j
-    d2 = np.maximum(np.sum((Pp[i[keep]] - Pp[j[keep]]) ** 2, axis=1), 0.0)
-    m = (d2.shape[0] - 1) // 2
-    med2 = float(np.partition(d2, m)[m])
-    Pd = torch.from_numpy(Pp).cuda()
-    sq = (Pd * Pd).sum(1)
-    X = torch.empty((n, n), dtype=torch.float32, device="cuda")
-    B = 8192
-    for i0 in range(0, n, B):
-        i1 = min(i0 + B, n)
-        for j0 in range(i0, n, B):
-            j1 = min(j0 + B, n)
-            blk = sq[i0:i1, None] + sq[None, j0:j1] - 2.0 * (Pd[i0:i1] @ Pd[j0:j1].T)
-            blk = torch.exp(-blk.clamp_min(0.0) / med2).float()
-            if j0 == i0:
-                up = torch.triu(blk)
-                blk = up + torch.triu(blk, 1).T
-            X[i0:i1, j0:j1] = blk
-            if j0 != i0:
-                X[j0:j1, i0:i1] = blk.T
-    X.fill_diagonal_(0.0)
-    torch.cuda.synchronize()
-    return X
-
-
 def bench_precision(args):
     """Precision sweep at n = 65536, k = 64 (64-component mixture in R^128):
     the products X H and X Omega in FP32 and in BF16 (X converted once, FP32
@@ -370,10 +334,11 @@ def bench_precision(args):
     import torch
     import paper_2402_08134_amd as P
     from paper_2402_08134_amd import warmstart as WSP
+    import workloads
     n, k = args.precision_n, 64
     l, q = k + 16, 2
     t0 = time.time()
-    X = gpu_gaussian_kernel(n, 128, 64, seed=0)
+    X = workloads.gpu_gaussian_kernel(n, 128, 64, seed=0)
     log(f"[bench] generated X n={n} on the GPU in {time.time() - t0:.1f}s")
     net = WSP.load(os.path.join(WSP.WEIGHTS_DIR, "warmstart_gk.npz"))
     o = P.symnmf_default_options(stop_mode=P.STOP_STALL, check_every=8)

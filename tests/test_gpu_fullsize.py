@@ -1,0 +1,122 @@
+"""Parity at the benchmark sizes, in the launch configurations bench.py
+times: the dense similarity n = 16384, k = 32 (FP32), the precision sweep
+n = 65536, k = 64 (FP32 and BF16 products) and the sparse graph n = 2^20,
+k = 64.  The FP64 oracle computes sampled output rows one by one (a row of
+X H, a row of the HALS update given the exact Gram) or, at n = 16384, whole
+plain iterations; at n = 2^20 a property that holds at any size is checked
+too (leverage scores sum to k)."""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+from oracle import symnmf as O
+import workloads
+
+from gpu_common import P, torch, require_gpu, dev, host, rel, factor, round_to, csr_dev, log
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    require_gpu()
+
+
+def _rows(n, count, seed):
+    return np.sort(np.random.default_rng(seed).choice(n, size=count, replace=False))
+
+
+@pytest.fixture(scope="module")
+def dense16k():
+    X, _ = workloads.gaussian_kernel(16384, 64, 32, seed=0, dtype=np.float32)
+    return X
+
+
+def test_dense_16384_product_and_half_step(dense16k):
+    X = dense16k
+    n, k = X.shape[0], 32
+    ctx = P.symnmf_create(dev(X), k, 0.0, 0, 1)
+    alpha = P.symnmf_get_stats(ctx).alpha
+    H = factor(ctx, P.H)
+    W0 = factor(ctx, P.W)
+    S = _rows(n, 128, 1)
+    XS = X[S].astype(np.float64)
+    # the product in the benchmark's configuration (k_gemm_cols, 8 row splits)
+    Y = torch.empty((n, k), dtype=torch.float32, device="cuda")
+    P.symnmf_apply_x(ctx, dev(H, torch.float32), Y)
+    Yo = XS @ H
+    e = rel(host(Y)[S], Yo)
+    log(f"n=16384 X H sampled rows: rel {e:.2e}")
+    assert e <= 2e-6
+    # one W half-step: sampled rows of the HALS sweep with the exact Gram
+    P.symnmf_half_step(ctx, 0, 0)
+    G = H.T @ H + alpha * np.eye(k)
+    Wo = O.hals_gy(G, Yo + alpha * H[S], W0[S])
+    e = rel(factor(ctx, P.W)[S], Wo)
+    log(f"n=16384 W half-step sampled rows: rel {e:.2e}")
+    assert e <= 1e-5
+
+
+def test_dense_16384_three_iterations(dense16k):
+    X = dense16k
+    n, k, iters = X.shape[0], 32, 3
+    ctx = P.symnmf_create(dev(X), k, 0.0, 0, 5)
+    P.symnmf_iterate(ctx, iters)
+    sc = O.data_scalars(X)
+    H0 = round_to(O.initial_factor(n, k, sc["zeta"], seed=5), torch.float32)
+    Wo, Ho, hist = O.plain_symnmf(X, k, sc["maxval"], H0, iters)
+    hg = np.array(P.symnmf_history(ctx))
+    log(f"n=16384 three iterations: history gpu {hg} oracle {hist}")
+    assert np.max(np.abs(hg - hist) / hist) <= 1e-4
+    assert rel(factor(ctx, P.H), Ho) <= 1e-4
+
+
+@pytest.mark.parametrize("compute", ["f32", "bf16"])
+def test_precision_65536_products(compute):
+    n, k = 65536, 64
+    X = workloads.gpu_gaussian_kernel(n, 128, 64, seed=0)
+    o = P.symnmf_default_options()
+    if compute == "bf16":
+        o.compute_dtype = P.BF16
+    ctx = P.symnmf_create(X, k, 0.0, 0, 1, o)
+    H = factor(ctx, P.H)
+    Y = torch.empty((n, k), dtype=torch.float32, device="cuda")
+    P.symnmf_apply_x(ctx, dev(H, torch.float32), Y)
+    S = _rows(n, 64, 2)
+    XS = host(X[torch.from_numpy(S).cuda()])
+    del ctx, X
+    torch.cuda.empty_cache()
+    Yg = host(Y)[S]
+    if compute == "f32":
+        e = rel(Yg, XS @ H)
+        log(f"n=65536 FP32 X H sampled rows: rel {e:.2e}")
+        assert e <= 1e-5
+    else:
+        e = rel(Yg, round_to(XS, torch.bfloat16) @ round_to(H, torch.bfloat16))
+        e2 = rel(Yg, XS @ H)
+        log(f"n=65536 BF16 X H sampled rows: rel {e:.2e} (vs FP32 data {e2:.2e})")
+        assert e <= 1e-5 and e2 <= 1e-2
+
+
+def test_sparse_2pow20_spmm_and_leverage():
+    X, _ = workloads.sbm(1 << 20, 64, 32.0, 20.0, seed=0)
+    n, k = X.shape[0], 64
+    ctx = P.symnmf_create(csr_dev(X), k, 0.0, 0, 1)
+    H = factor(ctx, P.H)
+    Y = torch.empty((n, k), dtype=torch.float32, device="cuda")
+    P.symnmf_apply_x(ctx, dev(H, torch.float32), Y)
+    S = _rows(n, 256, 3)
+    X64 = sp.csr_matrix((X.data.astype(np.float64), X.indices, X.indptr), shape=X.shape)
+    e = rel(host(Y)[S], X64[S] @ H)
+    log(f"n=2^20 SpMM sampled rows: rel {e:.2e}")
+    assert e <= 1e-6
+    lev = torch.empty(n, dtype=torch.float64, device="cuda")
+    P.symnmf_leverage(ctx, P.H, lev)
+    lg = host(lev)
+    tot = float(lg.sum())
+    log(f"n=2^20 leverage scores of H: sum {tot:.10f} (k = {k})")
+    assert abs(tot - k) <= 1e-8 * k
+    # sampled rows: l_i = h_i (H^T H)^-1 h_i^T with the exact FP64 Gram
+    Gi = np.linalg.inv(H.T @ H)
+    lo = np.einsum("ij,jk,ik->i", H[S], Gi, H[S])
+    assert rel(lg[S], lo) <= 1e-9

@@ -91,6 +91,41 @@ def gaussian_kernel(n=16384, dim=64, comps=32, seed=0, dtype=np.float32, median_
     return X, lab
 
 
+def gpu_gaussian_kernel(n, dim, comps, seed):
+    """The Gaussian-kernel similarity of gaussian_kernel (same points, same
+    sampled-pairs median for n > 16384), formed on the GPU in FP64 blocks
+    and stored as FP32 (a torch tensor on the GPU), bitwise symmetric, zero
+    diagonal.  For sizes whose host copy would be too large."""
+    import torch
+    Pp, _ = gmm_points(n, dim, comps, seed)
+    rng = np.random.default_rng(seed + 1)
+    i = rng.integers(0, n, size=1 << 22)
+    j = rng.integers(0, n, size=1 << 22)
+    keep = i != j
+    d2 = np.maximum(np.sum((Pp[i[keep]] - Pp[j[keep]]) ** 2, axis=1), 0.0)
+    m = (d2.shape[0] - 1) // 2
+    med2 = float(np.partition(d2, m)[m])
+    Pd = torch.from_numpy(Pp).cuda()
+    sq = (Pd * Pd).sum(1)
+    X = torch.empty((n, n), dtype=torch.float32, device="cuda")
+    B = 8192
+    for i0 in range(0, n, B):
+        i1 = min(i0 + B, n)
+        for j0 in range(i0, n, B):
+            j1 = min(j0 + B, n)
+            blk = sq[i0:i1, None] + sq[None, j0:j1] - 2.0 * (Pd[i0:i1] @ Pd[j0:j1].T)
+            blk = torch.exp(-blk.clamp_min(0.0) / med2).float()
+            if j0 == i0:
+                up = torch.triu(blk)
+                blk = up + torch.triu(blk, 1).T
+            X[i0:i1, j0:j1] = blk
+            if j0 != i0:
+                X[j0:j1, i0:i1] = blk.T
+    X.fill_diagonal_(0.0)
+    torch.cuda.synchronize()
+    return X
+
+
 def sbm(n=1 << 20, blocks=64, avg_degree=32.0, ratio=20.0, seed=0):
     """Stochastic block model, equal contiguous blocks, simple undirected graph
     without self loops, X = D^-1/2 A D^-1/2 as CSR (int32 indices, FP32
