@@ -15,6 +15,11 @@
 
 namespace {
 
+// Rows per block chunk: 32 rows x 16 lanes = 512 threads (measured on
+// MI355X at n = 16384: a LAI iteration 68 us with 16-row, 256-thread blocks,
+// 62 us with 32, 67 us with 64; the same 512 blocks in each case).
+constexpr int UPD_RPB = 32;
+
 // Sum of a double over the 16 lanes of a DPP row, every lane receiving the
 // total: quad_perm [1,0,3,2] and [2,3,0,1] (pairs, quads), then
 // row_half_mirror and row_mirror (halves, full row).  DPP moves are plain
@@ -33,16 +38,16 @@ __device__ __forceinline__ double row16_sum(double v) {
   return v;
 }
 
-// 16 lanes per row, 16 rows per 256-thread block.  Lane g of a row owns the
+// 16 lanes per row, UPD_RPB rows per block.  Lane g of a row owns the
 // columns q = g + 16 c (c < KP / 16).  The HALS sweep over column i sums
 // w_q Ghat[i][q] over the row's lanes (a DPP row) and the lane owning column
 // i applies the update.
 template <int KP, int LP, typename TF, typename TP, typename TT, int YMODE>
-__global__ __launch_bounds__(256) void k_update(UpdateArgs a, const double* __restrict__ Gh,
+__global__ __launch_bounds__(16 * UPD_RPB) void k_update(UpdateArgs a, const double* __restrict__ Gh,
                                                 const double* __restrict__ Ginv, const double* __restrict__ M,
                                                 const TF* __restrict__ Src, const DevState* __restrict__ st) {
   if (stopped(st)) return;
-  constexpr int NTH = 256, RPB = 16;
+  constexpr int NTH = 16 * UPD_RPB, RPB = UPD_RPB;
   constexpr int CPL = KP / 16;
   constexpr int ZI = LP > 0 ? LP / 16 : 1;
   constexpr int LW = KP + 1;
@@ -172,7 +177,7 @@ __global__ __launch_bounds__(256) void k_update(UpdateArgs a, const double* __re
     __syncthreads();
     // block partials of F^T F and (LAI) U^T F over this chunk (none when
     // only the right-hand side is written)
-    if (a.rule != 1) {
+    if (a.rule != 1 && tid < 256) {  // a 16 x 16 tile of threads over all the chunk's rows
 #pragma unroll
       for (int r = 0; r < RPB; ++r) {
         double bv[CPL];
@@ -204,9 +209,9 @@ __global__ __launch_bounds__(256) void k_update(UpdateArgs a, const double* __re
 #pragma unroll
     for (int j = 0; j < CPL; ++j) {
       const int p = ty + 16 * i, q = tx + 16 * j;
-      if (p < k && q < k) gp[p * k + q] = gacc[i][j];
+      if (tid < 256 && p < k && q < k) gp[p * k + q] = gacc[i][j];
     }
-  if (LP > 0) {
+  if (LP > 0 && tid < 256) {
     double* zp = gp + k * k;
 #pragma unroll
     for (int i = 0; i < ZI; ++i)
@@ -295,14 +300,14 @@ __global__ __launch_bounds__(256) void k_pad_identity(double* __restrict__ Ghat,
 
 template <int KP, int LP, typename TF, typename TP, typename TT, int YMODE>
 int launch_update(const UpdateArgs& a, const UpdateRO& ro, int nb, const DevState* st, hipStream_t s) {
-  const size_t lds = 8 * (size_t)KP * (KP + 1 + LP) + sizeof(TF) * 16 * ((KP + 1) + (LP > 0 ? LP + 1 : 0));
+  const size_t lds = 8 * (size_t)KP * (KP + 1 + LP) + sizeof(TF) * UPD_RPB * ((KP + 1) + (LP > 0 ? LP + 1 : 0));
   auto kern = k_update<KP, LP, TF, TP, TT, YMODE>;
   if (lds > 65536 &&
       hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
     return -1;
   // exactly nb blocks (the reduction reads nb partials); rows beyond
   // 16 * nb are covered by the grid-stride loop
-  kern<<<nb, 256, lds, s>>>(a, ro.Ghat, ro.Ginv, ro.M, (const TF*)a.Src, st);
+  kern<<<nb, 16 * UPD_RPB, lds, s>>>(a, ro.Ghat, ro.Ginv, ro.M, (const TF*)a.Src, st);
   return 0;
 }
 
@@ -336,12 +341,12 @@ int dispatch_kp(const UpdateArgs& a, const UpdateRO& ro, int kp, int ymode, int 
 
 }  // namespace
 
-// 512 blocks of 16-row chunks (grid-stride beyond 8192 rows): measured at
-// n = 16384 against 128, 256 and 1024, it is the fastest update plus
-// partial-sum reduction (fewer partial rows to reduce, enough waves).
+// At most 512 blocks (grid-stride beyond 512 chunks): measured at n = 16384
+// against 128, 256, 768 and 1024, it is the fastest update plus partial-sum
+// reduction (fewer partial rows to reduce, enough waves).
 int update_blocks(int n, int fdtype) {
   (void)fdtype;
-  return std::max(1, std::min(512, ceil_div(n, 16)));
+  return std::max(1, std::min(512, ceil_div(n, UPD_RPB)));
 }
 
 int fused_update(const UpdateArgs& a, const UpdateRO& ro, int kp, int ymode, int fdtype, int pdtype, int tdtype,
