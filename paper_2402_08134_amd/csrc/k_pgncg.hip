@@ -142,11 +142,14 @@ __global__ __launch_bounds__(256) void k_cg_init(CgArgs a, const double* __restr
   double* Gs = reinterpret_cast<double*>(smem);  // KP x KP
   double* T1 = Gs + KP * KP;                     // chunk rows of R
   double* T2 = T1 + CG_RPB * LW;                 // chunk rows of H
+  double* Ml = T2 + CG_RPB * LW;                 // YMODE 2: Lambda U^T H (l x KP)
   __shared__ double sc[20];
   const int tid = threadIdx.x, g = tid & 15, rg = tid >> 4;
   const int tx = tid & 15, ty = tid >> 4;
   const int n = a.n, k = a.k;
   stage_square<KP>(Gs, G, k);
+  if (YMODE == 2)
+    for (int e = tid; e < a.l * KP; e += 256) Ml[e] = a.Mlai[e];
   __syncthreads();
   double gacc[CPL][CPL];
 #pragma unroll
@@ -157,25 +160,44 @@ __global__ __launch_bounds__(256) void k_cg_init(CgArgs a, const double* __restr
   for (int base = blockIdx.x * CG_RPB; base < n; base += gridDim.x * CG_RPB) {
     double y[CG_RPL][CPL];
 #pragma unroll
+    for (int j = 0; j < CG_RPL; ++j)
+#pragma unroll
+      for (int c = 0; c < CPL; ++c) y[j][c] = 0.0;
+    if (YMODE == 2) {
+      // y = U[row, :] M for the group's 4 rows: 8 terms of U per row loaded
+      // together, M from LDS
+      const double* u[CG_RPL];
+#pragma unroll
+      for (int j = 0; j < CG_RPL; ++j) u[j] = a.U + (int64_t)min(base + CG_RPL * rg + j, n - 1) * a.l;
+      for (int p0 = 0; p0 < a.l; p0 += 8) {
+        double uv[CG_RPL][8];
+#pragma unroll
+        for (int j = 0; j < CG_RPL; ++j)
+#pragma unroll
+          for (int w = 0; w < 8; ++w) uv[j][w] = p0 + w < a.l ? u[j][p0 + w] : 0.0;
+#pragma unroll
+        for (int w = 0; w < 8; ++w) {
+          const int p = min(p0 + w, a.l - 1);
+#pragma unroll
+          for (int c = 0; c < CPL; ++c) {
+            const double mv = Ml[p * KP + g + 16 * c];
+#pragma unroll
+            for (int j = 0; j < CG_RPL; ++j) y[j][c] = fma(uv[j][w], mv, y[j][c]);
+          }
+        }
+      }
+    }
+#pragma unroll
     for (int j = 0; j < CG_RPL; ++j) {
       const int row = base + CG_RPL * rg + j;
       const int rr = min(row, n - 1);
       const bool ok = row < n;
-#pragma unroll
-      for (int c = 0; c < CPL; ++c) y[j][c] = 0.0;
       if (YMODE == 0) {
         const TP* pr = (const TP*)a.P + (int64_t)rr * a.cp + g;
         const int64_t sstride = (int64_t)n * a.cp;
         for (int sp = 0; sp < a.splits; ++sp) {
 #pragma unroll
           for (int c = 0; c < CPL; ++c) y[j][c] += (double)pr[sp * sstride + 16 * c];
-        }
-      } else {
-        const double* u = a.U + (int64_t)rr * a.l;
-        for (int p = 0; p < a.l; ++p) {
-          const double up = u[p];
-#pragma unroll
-          for (int c = 0; c < CPL; ++c) y[j][c] = fma(up, a.Mlai[p * KP + g + 16 * c], y[j][c]);
         }
       }
 #pragma unroll
@@ -320,8 +342,10 @@ __global__ __launch_bounds__(256) void k_cg_final(CgArgs a, const double* __rest
   if (stopped(st)) return;
   constexpr int CPL = KP / 16, LW = cg_lw<KP>();
   constexpr int ZI = LP > 0 ? LP / 16 : 1;
+  constexpr int LU = LP + 1;
   extern __shared__ __align__(16) unsigned char smem[];
   double* T1 = reinterpret_cast<double*>(smem);  // chunk rows of the new H
+  double* Us = T1 + CG_RPB * LW;                 // LAI: chunk rows of U (CG_RPB x LU)
   const int tid = threadIdx.x, g = tid & 15, rg = tid >> 4;
   const int tx = tid & 15, ty = tid >> 4;
   const int n = a.n, k = a.k, l = a.l;
@@ -364,18 +388,22 @@ __global__ __launch_bounds__(256) void k_cg_final(CgArgs a, const double* __rest
         }
       }
     }
+    if (LP > 0)
+      for (int e = tid; e < CG_RPB * LP; e += 256) {
+        const int r = e / LP, p = e - r * LP;
+        Us[r * LU + p] = (base + r < n && p < l) ? a.U[(int64_t)(base + r) * l + p] : 0.0;
+      }
     __syncthreads();
     tile_gram<KP>(T1, T1, tx, ty, gacc);
     if (LP > 0) {
+#pragma unroll 4
       for (int r = 0; r < CG_RPB; ++r) {
-        const int row = base + r;
         double bv[CPL];
 #pragma unroll
         for (int j = 0; j < CPL; ++j) bv[j] = T1[r * LW + tx + 16 * j];
 #pragma unroll
         for (int i = 0; i < ZI; ++i) {
-          const int p = ty + 16 * i;
-          const double uv = (row < n && p < l) ? a.U[(int64_t)row * l + p] : 0.0;
+          const double uv = Us[r * LU + ty + 16 * i];
 #pragma unroll
           for (int j = 0; j < CPL; ++j) zacc[i][j] = fma(uv, bv[j], zacc[i][j]);
         }
@@ -494,7 +522,7 @@ int set_lds(const void* kern, size_t lds) {
 
 template <int KP, typename TF, typename TP>
 int launch_init(const CgArgs& a, int ymode, const double* G, int nb, const DevState* st, hipStream_t s) {
-  const size_t lds = 8 * ((size_t)KP * KP + 2 * CG_RPB * cg_lw<KP>());
+  const size_t lds = 8 * ((size_t)KP * KP + 2 * CG_RPB * cg_lw<KP>() + (ymode == 2 ? (size_t)a.l * KP : 0));
   if (ymode == 0) {
     auto kern = k_cg_init<KP, TF, TP, 0>;
     if (set_lds((const void*)kern, lds)) return -1;
@@ -518,8 +546,10 @@ int launch_step(const CgArgs& a, const double* G, const double* cg, int nb, cons
 
 template <int KP, int LP, typename TF, typename TT>
 int launch_final(const CgArgs& a, const double* cg, int nb, const DevState* st, hipStream_t s) {
-  const size_t lds = 8 * (size_t)CG_RPB * cg_lw<KP>();
-  k_cg_final<KP, LP, TF, TT><<<nb, 256, lds, s>>>(a, cg, st);
+  const size_t lds = 8 * (size_t)CG_RPB * (cg_lw<KP>() + (LP > 0 ? LP + 1 : 0));
+  auto kern = k_cg_final<KP, LP, TF, TT>;
+  if (set_lds((const void*)kern, lds)) return -1;
+  kern<<<nb, 256, lds, s>>>(a, cg, st);
   return 0;
 }
 
