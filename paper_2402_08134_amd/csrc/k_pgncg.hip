@@ -15,9 +15,10 @@
 // forms and the k x k matrix R'^T H, and the next pass applies the direction
 // update on the fly.  The CG vectors R, P, Z are FP64, n x KP (zero padded).
 //
-// Thread layout (all passes): 256 threads = 16 row groups of 16 lanes; a
-// group owns 4 consecutive rows of a 64-row chunk and lane g of it the
-// columns q = g + 16 c.  Row products with a k x k matrix (P G, H M, R' G)
+// Thread layout (all passes): 512 threads = 32 row groups of 16 lanes; a
+// group owns 2 consecutive rows of a 64-row chunk and lane g of it the
+// columns q = g + 16 c (measured at n = 16384, k = 32: with 256 threads and
+// 4 rows per lane a CG step took 16 us).  Row products with a k x k matrix (P G, H M, R' G)
 // read the group's rows from LDS (one broadcast per row and i) and the
 // matrix from LDS; the k x k block partials use the 16 x 16 thread tile of
 // the fused update.
@@ -25,8 +26,9 @@
 
 namespace {
 
-constexpr int CG_RPL = 4;            // rows per lane
-constexpr int CG_RPB = 16 * CG_RPL;  // rows per chunk
+constexpr int CG_RPL = 2;                        // rows per lane
+constexpr int CG_NT = 512;                       // threads of a row pass
+constexpr int CG_RPB = (CG_NT / 16) * CG_RPL;    // rows per chunk (64)
 constexpr int CG_E0 = 4;             // scalars ahead of the k x k block in a partial row
 
 template <int KP> constexpr int cg_lw() { return KP + 2; }
@@ -34,7 +36,7 @@ template <int KP> constexpr int cg_lw() { return KP + 2; }
 // KP x KP copy of a k x k row-major matrix, zero padded.
 template <int KP>
 __device__ __forceinline__ void stage_square(double* S, const double* __restrict__ A, int k) {
-  for (int e = threadIdx.x; e < KP * KP; e += 256) {
+  for (int e = threadIdx.x; e < KP * KP; e += CG_NT) {
     const int p = e / KP, q = e - p * KP;
     S[e] = (p < k && q < k) ? A[p * k + q] : 0.0;
   }
@@ -83,15 +85,15 @@ __device__ __forceinline__ void tile_gram(const double* A, const double* B, int 
   }
 }
 
-// Block sums of N values at once (fixed order: wave trees, then the four
-// waves in order); the totals land in v of thread 0.  sc: 4 * N doubles.
+// Block sums of N values at once (fixed order: wave trees, then the waves
+// in order); the totals land in v of thread 0.  sc: (waves) * N doubles.
 template <int N>
 __device__ __forceinline__ void block_sums(double (&v)[N], double* sc) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1)
 #pragma unroll
     for (int i = 0; i < N; ++i) v[i] += __shfl_xor(v[i], o, 64);
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
   __syncthreads();
   if (lane == 0)
 #pragma unroll
@@ -99,7 +101,11 @@ __device__ __forceinline__ void block_sums(double (&v)[N], double* sc) {
   __syncthreads();
   if (threadIdx.x == 0)
 #pragma unroll
-    for (int i = 0; i < N; ++i) v[i] = ((sc[i] + sc[N + i]) + sc[2 * N + i]) + sc[3 * N + i];
+    for (int i = 0; i < N; ++i) {
+      double t = sc[i];
+      for (int q = 1; q < nw; ++q) t += sc[q * N + i];
+      v[i] = t;
+    }
 }
 
 // Partial row of this block: [e, a1, a2, a3, K (k x k)]; dpart (when given)
@@ -120,13 +126,14 @@ __device__ __forceinline__ void write_cg_partials(double* __restrict__ part, int
     gp[3] = v[3];
     if (dpart) dpart[blockIdx.x] = v[4];
   }
+  if (threadIdx.x < 256)
 #pragma unroll
-  for (int i = 0; i < CPL; ++i)
+    for (int i = 0; i < CPL; ++i)
 #pragma unroll
-    for (int j = 0; j < CPL; ++j) {
-      const int p = ty + 16 * i, q = tx + 16 * j;
-      if (p < k && q < k) gp[CG_E0 + p * k + q] = gacc[i][j];
-    }
+      for (int j = 0; j < CPL; ++j) {
+        const int p = ty + 16 * i, q = tx + 16 * j;
+        if (p < k && q < k) gp[CG_E0 + p * k + q] = gacc[i][j];
+      }
 }
 
 // First pass of an iteration: R = -2 (Y - H G) (the gradient J^T r), the
@@ -134,7 +141,7 @@ __device__ __forceinline__ void write_cg_partials(double* __restrict__ part, int
 // the fused update: YMODE 0 split-K partials of X H (or the CSR product),
 // YMODE 2 U[j,:] M with M = Lambda U^T H.
 template <int KP, typename TF, typename TP, int YMODE>
-__global__ __launch_bounds__(256) void k_cg_init(CgArgs a, const double* __restrict__ G, const TF* __restrict__ H,
+__global__ __launch_bounds__(CG_NT) void k_cg_init(CgArgs a, const double* __restrict__ G, const TF* __restrict__ H,
                                                  const DevState* __restrict__ st) {
   if (stopped(st)) return;
   constexpr int CPL = KP / 16, LW = cg_lw<KP>();
@@ -143,13 +150,13 @@ __global__ __launch_bounds__(256) void k_cg_init(CgArgs a, const double* __restr
   double* T1 = Gs + KP * KP;                     // chunk rows of R
   double* T2 = T1 + CG_RPB * LW;                 // chunk rows of H
   double* Ml = T2 + CG_RPB * LW;                 // YMODE 2: Lambda U^T H (l x KP)
-  __shared__ double sc[20];
+  __shared__ double sc[40];
   const int tid = threadIdx.x, g = tid & 15, rg = tid >> 4;
   const int tx = tid & 15, ty = tid >> 4;
   const int n = a.n, k = a.k;
   stage_square<KP>(Gs, G, k);
   if (YMODE == 2)
-    for (int e = tid; e < a.l * KP; e += 256) Ml[e] = a.Mlai[e];
+    for (int e = tid; e < a.l * KP; e += CG_NT) Ml[e] = a.Mlai[e];
   __syncthreads();
   double gacc[CPL][CPL];
 #pragma unroll
@@ -233,7 +240,7 @@ __global__ __launch_bounds__(256) void k_cg_init(CgArgs a, const double* __restr
     for (int j = 0; j < CG_RPL; ++j)
 #pragma unroll
       for (int c = 0; c < CPL; ++c) a1 = fma(y[j][c], t[j][c], a1);
-    tile_gram<KP>(T1, T2, tx, ty, gacc);  // R^T H
+    if (tid < 256) tile_gram<KP>(T1, T2, tx, ty, gacc);  // R^T H
     __syncthreads();
   }
   write_cg_partials<KP>(a.part, k, e, a1, 0.0, 0.0, gacc, sc, dot, a.dpart);
@@ -243,7 +250,7 @@ __global__ __launch_bounds__(256) void k_cg_init(CgArgs a, const double* __restr
 // then M = P^T H (k x k) at offset 8, for the direction P = R + beta P_prev
 // of this step (P_prev and Z are not read on the first step).
 template <int KP, typename TF>
-__global__ __launch_bounds__(256) void k_cg_step(CgArgs a, const double* __restrict__ G,
+__global__ __launch_bounds__(CG_NT) void k_cg_step(CgArgs a, const double* __restrict__ G,
                                                  const double* __restrict__ cg, const TF* __restrict__ H,
                                                  const DevState* __restrict__ st) {
   if (stopped(st)) return;
@@ -253,7 +260,7 @@ __global__ __launch_bounds__(256) void k_cg_step(CgArgs a, const double* __restr
   double* Ms = Gs + KP * KP;                     // KP x KP
   double* T1 = Ms + KP * KP;                     // chunk rows of P, then of R'
   double* T2 = T1 + CG_RPB * LW;                 // chunk rows of H
-  __shared__ double sc[20];
+  __shared__ double sc[40];
   const int tid = threadIdx.x, g = tid & 15, rg = tid >> 4;
   const int tx = tid & 15, ty = tid >> 4;
   const int n = a.n, k = a.k;
@@ -326,7 +333,7 @@ __global__ __launch_bounds__(256) void k_cg_step(CgArgs a, const double* __restr
     for (int j = 0; j < CG_RPL; ++j)
 #pragma unroll
       for (int c = 0; c < CPL; ++c) a1 = fma(r[j][c], u[j][c], a1);
-    tile_gram<KP>(T1, T2, tx, ty, gacc);  // R'^T H
+    if (tid < 256) tile_gram<KP>(T1, T2, tx, ty, gacc);  // R'^T H
     __syncthreads();
   }
   write_cg_partials<KP>(a.part, k, e, a1, a2, a3, gacc, sc);
@@ -337,7 +344,7 @@ __global__ __launch_bounds__(256) void k_cg_step(CgArgs a, const double* __restr
 // transposed panel, with the block partials of the new Gram H^T H and, in
 // LAI mode, of U^T H (the layout the update reduction expects).
 template <int KP, int LP, typename TF, typename TT>
-__global__ __launch_bounds__(256) void k_cg_final(CgArgs a, const double* __restrict__ cg,
+__global__ __launch_bounds__(CG_NT) void k_cg_final(CgArgs a, const double* __restrict__ cg,
                                                   const DevState* __restrict__ st) {
   if (stopped(st)) return;
   constexpr int CPL = KP / 16, LW = cg_lw<KP>();
@@ -389,13 +396,13 @@ __global__ __launch_bounds__(256) void k_cg_final(CgArgs a, const double* __rest
       }
     }
     if (LP > 0)
-      for (int e = tid; e < CG_RPB * LP; e += 256) {
+      for (int e = tid; e < CG_RPB * LP; e += CG_NT) {
         const int r = e / LP, p = e - r * LP;
         Us[r * LU + p] = (base + r < n && p < l) ? a.U[(int64_t)(base + r) * l + p] : 0.0;
       }
     __syncthreads();
-    tile_gram<KP>(T1, T1, tx, ty, gacc);
-    if (LP > 0) {
+    if (tid < 256) tile_gram<KP>(T1, T1, tx, ty, gacc);
+    if (LP > 0 && tid < 256) {
 #pragma unroll 4
       for (int r = 0; r < CG_RPB; ++r) {
         double bv[CPL];
@@ -411,6 +418,7 @@ __global__ __launch_bounds__(256) void k_cg_final(CgArgs a, const double* __rest
     }
     __syncthreads();
   }
+  if (tid >= 256) return;
   double* gp = a.part + (int64_t)blockIdx.x * a.pstride;
 #pragma unroll
   for (int i = 0; i < CPL; ++i)
@@ -473,7 +481,7 @@ __global__ __launch_bounds__(256) void k_cg_scalars(const double* __restrict__ p
   extern __shared__ __align__(16) unsigned char smem[];
   double* tot = reinterpret_cast<double*>(smem);
   double* Ml = tot + CG_E0;
-  __shared__ double sc[20];
+  __shared__ double sc[40];
   const int E = CG_E0 + k * k, kk = k * k, tid = threadIdx.x;
   for (int e = tid; e < E; e += 256) {
     const double v = sum_rows(part + e, cnt, E);
@@ -526,11 +534,11 @@ int launch_init(const CgArgs& a, int ymode, const double* G, int nb, const DevSt
   if (ymode == 0) {
     auto kern = k_cg_init<KP, TF, TP, 0>;
     if (set_lds((const void*)kern, lds)) return -1;
-    kern<<<nb, 256, lds, s>>>(a, G, (const TF*)a.H, st);
+    kern<<<nb, CG_NT, lds, s>>>(a, G, (const TF*)a.H, st);
   } else {
     auto kern = k_cg_init<KP, TF, TP, 2>;
     if (set_lds((const void*)kern, lds)) return -1;
-    kern<<<nb, 256, lds, s>>>(a, G, (const TF*)a.H, st);
+    kern<<<nb, CG_NT, lds, s>>>(a, G, (const TF*)a.H, st);
   }
   return 0;
 }
@@ -540,7 +548,7 @@ int launch_step(const CgArgs& a, const double* G, const double* cg, int nb, cons
   const size_t lds = 8 * (2 * (size_t)KP * KP + 2 * CG_RPB * cg_lw<KP>());
   auto kern = k_cg_step<KP, TF>;
   if (set_lds((const void*)kern, lds)) return -1;
-  kern<<<nb, 256, lds, s>>>(a, G, cg, (const TF*)a.H, st);
+  kern<<<nb, CG_NT, lds, s>>>(a, G, cg, (const TF*)a.H, st);
   return 0;
 }
 
@@ -549,7 +557,7 @@ int launch_final(const CgArgs& a, const double* cg, int nb, const DevState* st, 
   const size_t lds = 8 * (size_t)CG_RPB * (cg_lw<KP>() + (LP > 0 ? LP + 1 : 0));
   auto kern = k_cg_final<KP, LP, TF, TT>;
   if (set_lds((const void*)kern, lds)) return -1;
-  kern<<<nb, 256, lds, s>>>(a, cg, st);
+  kern<<<nb, CG_NT, lds, s>>>(a, cg, st);
   return 0;
 }
 
