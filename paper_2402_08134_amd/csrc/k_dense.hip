@@ -764,7 +764,7 @@ int dispatch_cols(int nt, int ct, const float* X, int64_t ldx, bool vec, const f
                   const GemmPlan& p, float* P, const DevState* st, hipStream_t s) {
 #define CASE(NT_, CT_) \
   if (nt == NT_ && ct == CT_) { launch_cols<NT_, CT_>(X, ldx, vec, Bt, ldt, n, p, P, st, s); return 0; }
-  CASE(1, 2) CASE(2, 2) CASE(3, 1) CASE(4, 1) CASE(5, 1) CASE(6, 1)
+  CASE(1, 2) CASE(2, 2) CASE(3, 2) CASE(4, 2) CASE(5, 1) CASE(6, 1)
 #undef CASE
   return -1;
 }
@@ -823,7 +823,11 @@ GemmPlan gemm_plan(int n, int c, int compute_dtype) {
     // SIMD in total, splits of at least 256 rows (multiples of the K step:
     // 16 rows for FP32 MFMA, 32 for the BF16 pieces)
     p.cols = true;
-    p.ct = p.cp <= 32 ? 2 : 1;
+    // two 64-column blocks per wave up to 64 output columns for FP32 MFMA
+    // (measured at n = 16384: X Q at l = 48 317 -> 290 us, k = 64 361 ->
+    // 338 us; at n = 65536, k = 64 5.14 -> 4.48 ms); the BF16-piece kernel
+    // keeps registers for its splitting beyond 32
+    p.ct = (p.cp <= 64 && !p.split3) || p.cp <= 32 ? 2 : 1;
     const int step = p.split3 ? 32 : 16;
     const int strips = ceil_div(n, 64 * p.ct);
     int splits = std::max(1, ceil_div(1024, strips));
