@@ -40,6 +40,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+FP32_MFMA_PEAK_TFLOPS = 157.3
 
 
 def log(msg):
@@ -225,7 +226,11 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": "k_gemm_cols<2, 2, true> (X H read along rows of X, one launch per half-iteration)",
                      "us_per_launch": t_prod * 1e6, "launches": calls,
-                     "algorithmic_bytes_per_launch": alg_bytes},
+                     "algorithmic_bytes_per_launch": alg_bytes,
+                     # the same launches against the FP32 matrix-core peak
+                     # (2 n^2 k flop per product)
+                     "mfma_tflops": 2.0 * n * n * k / t_prod / 1e12,
+                     "mfma_frac": 2.0 * n * n * k / t_prod / 1e12 / FP32_MFMA_PEAK_TFLOPS},
         "phases_ms_per_solve": {m: {kk: v[0] for kk, v in ph.items()} for m, ph in phases.items()},
         "cpu_baseline": cpu,
     }
