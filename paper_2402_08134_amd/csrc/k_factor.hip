@@ -443,9 +443,6 @@ __global__ __launch_bounds__(64) void k_chol_regs(const double* __restrict__ G, 
                                                   int* d_fail) {
   const int r = threadIdx.x;
   const bool act = r < k;
-  double g[KM];
-#pragma unroll
-  for (int c = 0; c < KM; ++c) g[c] = (act && c < k) ? G[r * k + c] : (c == r ? 1.0 : 0.0);
   double tr = act ? G[r * k + r] : 0.0;
   tr = wave_sum(tr);
   double shift = 0.0, grow = 1e-12 * fmax(tr, 1e-300) / k;
@@ -456,8 +453,10 @@ __global__ __launch_bounds__(64) void k_chol_regs(const double* __restrict__ G, 
       shift = grow;  // 1e-12, 1e-10, ... times tr(G) / k
       grow *= 100.0;
     }
+    // row r of G (identity rows and columns beyond k), reloaded for a retry
 #pragma unroll
-    for (int c = 0; c < KM; ++c) a[c] = g[c] + ((act && c == r) ? shift : 0.0);
+    for (int c = 0; c < KM; ++c)
+      a[c] = ((act && c < k) ? G[r * k + c] : (c == r ? 1.0 : 0.0)) + ((act && c == r) ? shift : 0.0);
     ok = true;
 #pragma unroll
     for (int j = 0; j < KM; ++j) {
@@ -690,15 +689,22 @@ __global__ __launch_bounds__(256) void k_scan_blocks(const T* __restrict__ in, i
 }
 
 template <typename T>
-__global__ void k_scan_totals(T* bsum, int nb, T* grand) {
-  if (threadIdx.x != 0) return;
-  T acc = 0;
-  for (int b = 0; b < nb; ++b) {
+__global__ __launch_bounds__(256) void k_scan_totals(T* bsum, int nb, T* grand) {
+  // exclusive scan of the nb block sums in one workgroup: each thread scans
+  // a contiguous chunk, the chunk totals are scanned across the block
+  __shared__ T ws[4];
+  const int per = (nb + 255) / 256;
+  const int b0 = min(nb, (int)threadIdx.x * per), b1 = min(nb, b0 + per);
+  T sum = 0;
+  for (int b = b0; b < b1; ++b) sum += bsum[b];
+  T total;
+  T run = block_exclusive_scan<T>(sum, ws, total);
+  for (int b = b0; b < b1; ++b) {
     const T v = bsum[b];
-    bsum[b] = acc;
-    acc += v;
+    bsum[b] = run;
+    run += v;
   }
-  if (grand) *grand = acc;
+  if (grand && threadIdx.x == 0) *grand = total;
 }
 
 template <typename T, bool INCLUSIVE>
@@ -894,7 +900,7 @@ int exclusive_scan_i32(const int* in, int* out, int n, Workspace& ws, hipStream_
   int* bsum = ws.i32(nb);
   if (!bsum) return -1;
   k_scan_blocks<int><<<nb, 256, 0, s>>>(in, n, bsum);
-  k_scan_totals<int><<<1, 64, 0, s>>>(bsum, nb, out + n);
+  k_scan_totals<int><<<1, 256, 0, s>>>(bsum, nb, out + n);
   k_scan_apply<int, false><<<nb, 256, 0, s>>>(in, n, bsum, out);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
@@ -904,7 +910,7 @@ int inclusive_scan_u64(const uint64_t* in, uint64_t* out, int n, Workspace& ws, 
   uint64_t* bsum = ws.u64(nb);
   if (!bsum) return -1;
   k_scan_blocks<uint64_t><<<nb, 256, 0, s>>>(in, n, bsum);
-  k_scan_totals<uint64_t><<<1, 64, 0, s>>>(bsum, nb, (uint64_t*)nullptr);
+  k_scan_totals<uint64_t><<<1, 256, 0, s>>>(bsum, nb, (uint64_t*)nullptr);
   k_scan_apply<uint64_t, true><<<nb, 256, 0, s>>>(in, n, bsum, out);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }

@@ -24,11 +24,20 @@
 
 namespace {
 
+// Thread per row; R^{-1} (upper triangular) staged once per 256-row block
+// in LDS and read as broadcasts.
 template <int KP, typename TF>
-__global__ __launch_bounds__(64) void k_leverage(const TF* __restrict__ F, int n, int k, const double* __restrict__ Rinv,
-                                                 double* __restrict__ lev, const DevState* __restrict__ st) {
+__global__ __launch_bounds__(256) void k_leverage(const TF* __restrict__ F, int n, int k,
+                                                  const double* __restrict__ Rinv, double* __restrict__ lev,
+                                                  const DevState* __restrict__ st) {
   if (stopped(st)) return;
-  const int j = blockIdx.x * 64 + threadIdx.x;
+  __shared__ double Rs[KP * KP];
+  for (int e = threadIdx.x; e < KP * KP; e += 256) {
+    const int p = e / KP, i = e - p * KP;
+    Rs[e] = (p < k && i < k) ? Rinv[p * k + i] : 0.0;
+  }
+  __syncthreads();
+  const int j = blockIdx.x * 256 + threadIdx.x;
   if (j >= n) return;
   double h[KP];
 #pragma unroll
@@ -42,7 +51,7 @@ __global__ __launch_bounds__(64) void k_leverage(const TF* __restrict__ F, int n
     if (i < k) {
       double q = 0.0;
 #pragma unroll
-      for (int p = 0; p <= i; ++p) q = fma(h[p], Rinv[p * k + i], q);
+      for (int p = 0; p <= i; ++p) q = fma(h[p], Rs[p * KP + i], q);
       acc = fma(q, q, acc);
     }
   }
@@ -197,7 +206,7 @@ __global__ __launch_bounds__(256) void k_slab_sort(const int* __restrict__ seg_p
 
 template <int KP, typename TF>
 void lev_launch(const void* F, int n, int k, const double* Rinv, double* lev, const DevState* st, hipStream_t s) {
-  k_leverage<KP, TF><<<ceil_div(n, 64), 64, 0, s>>>((const TF*)F, n, k, Rinv, lev, st);
+  k_leverage<KP, TF><<<ceil_div(n, 256), 256, 0, s>>>((const TF*)F, n, k, Rinv, lev, st);
 }
 
 }  // namespace
