@@ -94,7 +94,7 @@ __global__ __launch_bounds__(16 * UPD_RPB) void k_update(UpdateArgs a, const dou
     }
     if (row < n) {
       const int64_t rb = (int64_t)row * k;
-      double y[CPL], w[CPL], sv[CPL];
+      double y[CPL], w[CPL];
 #pragma unroll
       for (int c = 0; c < CPL; ++c) y[c] = 0.0;
       // Loads are never guarded by a branch (a branch per element makes the
@@ -133,9 +133,8 @@ __global__ __launch_bounds__(16 * UPD_RPB) void k_update(UpdateArgs a, const dou
         const int qc = q < k ? q : k - 1;
         const double xs = (double)Src[rb + qc];
         const double xd = (double)Dst[rb + qc];
-        sv[c] = q < k ? xs : 0.0;
         w[c] = q < k ? xd : 0.0;
-        y[c] = fma(alpha, sv[c], y[c]);   // HALS target y + alpha src
+        y[c] = fma(alpha, q < k ? xs : 0.0, y[c]);   // HALS target y + alpha src
       }
       if (a.rule == 1) {
 #pragma unroll
@@ -162,7 +161,10 @@ __global__ __launch_bounds__(16 * UPD_RPB) void k_update(UpdateArgs a, const dou
         for (int c = 0; c < CPL; ++c) {
           const int q = g + 16 * c;
           const TF wt = (TF)w[c];
-          dot = fma((double)wt, fma(-alpha, sv[c], y[c]), dot);   // product part of the target
+          if (a.dpart) {  // product part of the target (src reloaded: fewer live registers)
+            const double xs = q < k ? (double)Src[rb + (q < k ? q : k - 1)] : 0.0;
+            dot = fma((double)wt, fma(-alpha, xs, y[c]), dot);
+          }
           wl[rs * LW + q] = wt;
           if (q < k) {
             Dst[rb + q] = wt;

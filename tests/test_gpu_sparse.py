@@ -137,3 +137,32 @@ def test_lvs_tau_zero_matches_plain():
     P.symnmf_iterate(a, 5)
     P.symnmf_iterate(b, 5)
     assert rel(factor(a, P.H), factor(b, P.H)) <= 1e-5
+
+
+@pytest.mark.parametrize("case", [(66_001, 64, 0, np.float32), (66_001, 64, 6000, np.float32),
+                                  (65_600, 10, 0, np.float32), (65_600, 40, 3000, np.float32),
+                                  (65_551, 33, 0, np.float64), (65_551, 64, 4000, np.float64)])
+def test_long_factor_half_step(case):
+    # n >= 65536: every one of the update's blocks walks several row chunks
+    # (grid stride) and n is ragged against the chunk; every padded width
+    n, k, s, vt = case
+    log(f"long factor half step n={n} k={k} s={s} {np.dtype(vt).name}")
+    X = _sbm(n, 32, 16.0, seed=n + k)
+    X = sp.csr_matrix((X.data.astype(vt), X.indices, X.indptr), shape=X.shape)
+    ctx = P.symnmf_create(csr_dev(X), k, 0.0, s, 3)
+    alpha = P.symnmf_get_stats(ctx).alpha
+    H = workloads.random_factor(n, k, seed=8, scale=0.2)
+    W = workloads.random_factor(n, k, seed=9, scale=0.2)
+    td = torch.float64 if vt == np.float64 else torch.float32
+    P.symnmf_set_factor(ctx, P.H, dev(H))
+    P.symnmf_set_factor(ctx, P.W, dev(W))
+    Hr, Wr = round_to(H, td), round_to(W, td)
+    P.symnmf_half_step(ctx, 0, 2)
+    X64 = _X64(X)
+    if s:
+        Wo, _ = O.lvs_half_step(X64, Hr, Wr, alpha, s, 1.0 / s, 3, 2)
+    else:
+        Wo = O.hals_gy(Hr.T @ Hr + alpha * np.eye(k), X64 @ Hr + alpha * Hr, Wr)
+    e = rel(factor(ctx, P.W), Wo)
+    log(f"   W rel {e:.2e}")
+    assert e <= (1e-12 if vt == np.float64 else 1e-5)
