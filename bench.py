@@ -237,6 +237,11 @@ def main():
     print(json.dumps(out), flush=True)
 
 
+def nnz_gb_bf16(nnz, k):
+    """Bytes of BF16 factor rows gathered by one CSR product."""
+    return nnz * k * 2.0
+
+
 def bench_sparse(args):
     """Sparse graph workload: X = D^-1/2 A D^-1/2 of a stochastic block model
     (64 equal blocks, average degree 32, p_in / p_out = 20) in CSR int32 /
@@ -246,9 +251,10 @@ def bench_sparse(args):
     and the plain method stalls within a few iterations near residual 1: a
     time-to-residual figure says little here.  Reported instead: seconds per
     iteration and the residual after a fixed number of iterations for plain
-    HALS with the CSR product and for leverage-score sampled HALS (s rows,
-    tau = 1/s), the per-phase device time, and the live roofline of the SpMM.
-    `value` is seconds per LvS iteration."""
+    HALS with the CSR product, for the same with BF16 gathers of the factor
+    rows (the precision option of the CSR product) and for leverage-score
+    sampled HALS (s rows, tau = 1/s), the per-phase device time, and the live
+    roofline of the SpMM.  `value` is seconds per LvS iteration."""
     import numpy as np
     import torch
     import paper_2402_08134_amd as P
@@ -264,11 +270,13 @@ def bench_sparse(args):
 
     def run(method, seed, timing, count):
         o = P.symnmf_default_options(timing=timing, resid_every=iters)
+        if method == "plain_bf16":
+            o.compute_dtype = P.BF16
         c = P.symnmf_create(Xd, k, 0.0, s_rows if method == "lvs" else 0, seed, o)
         P.symnmf_iterate(c, count)
         return c
 
-    methods = ["plain", "lvs"]
+    methods = ["plain", "plain_bf16", "lvs"]
     for m in methods:
         run(m, 100, 0, 2)
     torch.cuda.synchronize()
@@ -287,7 +295,9 @@ def bench_sparse(args):
             res[m].update({"s": s_rows, "deterministic_rows": int(st.s_D), "sampled_rows": int(st.sample_rows),
                            "theta_over_k": st.theta_over_k})
         del c
-        log(f"[bench] {m:6s} {t * 1e3:8.3f} ms/iteration  residual after {iters + 1} iterations {r[0]:.6f}")
+        log(f"[bench] {m:10s} {t * 1e3:8.3f} ms/iteration  residual after {iters + 1} iterations {r[0]:.6f}")
+    rb, rf = res["plain_bf16"]["residual"], res["plain"]["residual"]
+    res["plain_bf16"]["residual_rel_diff_vs_fp32"] = abs(rb - rf) / rf
     phases = {}
     for m in methods:
         c = run(m, 1, 1, iters)
@@ -295,7 +305,14 @@ def bench_sparse(args):
         if m == "plain":
             ph = phase_totals(P, [c])
             ms, calls = ph["product"]
+        if m == "plain_bf16":
+            msb, callsb = phase_totals(P, [c])["product"]
         del c
+    t_bf = msb / 1e3 / callsb
+    res["plain_bf16"]["spmm_us_per_launch"] = t_bf * 1e6
+    log(f"[bench] SpMM with BF16 gathers {t_bf * 1e6:.1f} us per launch "
+        f"({nnz_gb_bf16(Xs.nnz, k) / t_bf / 1e9:.0f} GB/s of BF16 row gathers); residual after {iters + 1} "
+        f"iterations differs from FP32 by {res['plain_bf16']['residual_rel_diff_vs_fp32']:.1e} (relative)")
     t_prod = ms / 1e3 / calls
     nnz = Xs.nnz
     alg_bytes = nnz * 8.0 + 4.0 * (n + 1) + 2.0 * n * k * 4
@@ -316,7 +333,7 @@ def bench_sparse(args):
                        res["plain"]["s_per_iteration"] / t_val, "methods": res},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "k_csr_spmm<float,float,float,64,1> (X H, one launch per half-iteration)",
+                     "kernel": "k_csr_spmm_vec<float, float, float, 16, 4> (X H, one launch per half-iteration)",
                      "us_per_launch": t_prod * 1e6, "launches": calls, "algorithmic_bytes_per_launch": alg_bytes,
                      "row_gather_bytes_per_launch": gather},
         "phases_ms_per_iteration": phases,
@@ -406,7 +423,7 @@ def bench_precision(args):
                    "n": n, "k": k, "l": l, "q": q, "r_conv_fp32": r_conv, "r_star": r_star, "methods": res},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "k_gemm_bf16 (X H in BF16, one launch per half-iteration)",
+                     "kernel": "k_gemm_cols_bf16<NT, VEC> (X H in BF16, one launch per half-iteration)",
                      "us_per_launch": t_prod * 1e6, "launches": calls, "algorithmic_bytes_per_launch": alg_bytes},
         "cpu_baseline": cpu,
     }

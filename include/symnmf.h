@@ -142,6 +142,10 @@ typedef struct symnmf_options {
   int32_t struct_size;    /* sizeof(symnmf_options)                         */
   int32_t rule;           /* SYMNMF_RULE_HALS (default), _BPP or _PGNCG     */
   int32_t compute_dtype;  /* dense products: F64 (needs F64 X), F32, BF16;
+                             CSR products: the dtype of X, or BF16 with FP32
+                             values -- the iteration products then gather a
+                             BF16 copy of the factor rows (FP32 values, FP64
+                             sums; HALS and BPP rules only);
                              default: the dtype of X                         */
   int32_t stop_mode;      /* default SYMNMF_STOP_NONE                       */
   double stop_tol;        /* default 1e-4                                   */

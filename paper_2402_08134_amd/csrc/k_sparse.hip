@@ -119,6 +119,96 @@ __global__ __launch_bounds__(256) void k_csr_spmm(const int* __restrict__ rp, co
   }
 }
 
+__global__ __launch_bounds__(256) void k_to_bf16(const float* __restrict__ F, int64_t count, __bf16* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < count) out[i] = (__bf16)F[i];
+}
+
+// The same product with 16-byte row pieces: VEC adjacent columns per lane
+// (4 FP32 or 8 BF16), CW = ceil(c / VEC) lanes per group, so one load
+// instruction of the wave gathers 64 / CW factor rows and each group keeps UN
+// of them in flight.  Needs c % VEC == 0 and 16-byte aligned rows of B.
+template <typename TB>
+struct Piece;
+template <>
+struct Piece<float> {
+  static constexpr int VEC = 4;
+  __device__ static void load(const float* p, double (&x)[4]) {
+    const float4 v = *reinterpret_cast<const float4*>(p);
+    x[0] = v.x;
+    x[1] = v.y;
+    x[2] = v.z;
+    x[3] = v.w;
+  }
+};
+template <>
+struct Piece<__bf16> {
+  static constexpr int VEC = 8;
+  __device__ static void load(const __bf16* p, double (&x)[8]) {
+    const uint4 v = *reinterpret_cast<const uint4*>(p);
+    const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      x[2 * u] = (double)__uint_as_float(w[u] << 16);
+      x[2 * u + 1] = (double)__uint_as_float(w[u] & 0xffff0000u);
+    }
+  }
+};
+
+template <typename TV, typename TB, typename TY, int CW, int UN>
+__global__ __launch_bounds__(256) void k_csr_spmm_vec(const int* __restrict__ rp, const int* __restrict__ ci,
+                                                      const TV* __restrict__ val, int n, const TB* __restrict__ B,
+                                                      int c, TY* __restrict__ Y, int64_t ldy,
+                                                      const DevState* __restrict__ st) {
+  if (stopped(st)) return;
+  constexpr int VEC = Piece<TB>::VEC, G = 64 / CW;
+  const int lane = threadIdx.x & 63;
+  const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (row >= n) return;
+  const int g = lane / CW, li = lane - g * CW;
+  const int col0 = li * VEC;
+  const bool live = col0 < c;
+  const int off = live ? col0 : c - VEC;  // clamped piece, masked below
+  double acc[VEC];
+#pragma unroll
+  for (int u = 0; u < VEC; ++u) acc[u] = 0.0;
+  const int e0 = rp[row], e1 = rp[row + 1];
+  int e = e0 + g;
+  for (; e + (UN - 1) * G < e1; e += UN * G) {
+    int j[UN];
+    double v[UN];
+#pragma unroll
+    for (int u = 0; u < UN; ++u) {
+      j[u] = ci[e + u * G];
+      v[u] = live ? (double)val[e + u * G] : 0.0;
+    }
+    double x[UN][VEC];
+#pragma unroll
+    for (int u = 0; u < UN; ++u) Piece<TB>::load(B + (int64_t)j[u] * c + off, x[u]);
+#pragma unroll
+    for (int u = 0; u < UN; ++u)
+#pragma unroll
+      for (int q = 0; q < VEC; ++q) acc[q] = fma(v[u], x[u][q], acc[q]);
+  }
+  for (; e < e1; e += G) {
+    const int j = ci[e];
+    const double v = live ? (double)val[e] : 0.0;
+    double x[VEC];
+    Piece<TB>::load(B + (int64_t)j * c + off, x);
+#pragma unroll
+    for (int q = 0; q < VEC; ++q) acc[q] = fma(v, x[q], acc[q]);
+  }
+#pragma unroll
+  for (int q = 0; q < VEC; ++q) {
+#pragma unroll
+    for (int o = CW; o < 64; o <<= 1) acc[q] += __shfl_xor(acc[q], o, 64);
+  }
+  if (g == 0 && live) {
+#pragma unroll
+    for (int q = 0; q < VEC; ++q) Y[(int64_t)row * ldy + col0 + q] = (TY)acc[q];
+  }
+}
+
 // sum over stored (i, j) of X_ij (w_i . h_j); wave per row, lane per column.
 template <typename TV, typename TF>
 __global__ __launch_bounds__(256) void k_csr_cross(const int* __restrict__ rp, const int* __restrict__ ci,
@@ -140,6 +230,19 @@ template <typename TV, typename TB, typename TY>
 void spmm_dispatch(const int* rp, const int* ci, const TV* val, int n, const TB* B, int c, TY* Y, int64_t ldy,
                    const DevState* st, hipStream_t s) {
   const int nb = ceil_div(n, 4);
+  if constexpr (!std::is_same<TB, double>::value) {
+    constexpr int VEC = Piece<TB>::VEC;
+    if (c % VEC == 0 && (reinterpret_cast<uintptr_t>(B) & 15) == 0 && c <= 16 * VEC) {
+      const int cw = ceil_div(c, VEC);
+      if (cw <= 4)
+        k_csr_spmm_vec<TV, TB, TY, 4, 2><<<nb, 256, 0, s>>>(rp, ci, val, n, B, c, Y, ldy, st);
+      else if (cw <= 8)
+        k_csr_spmm_vec<TV, TB, TY, 8, 2><<<nb, 256, 0, s>>>(rp, ci, val, n, B, c, Y, ldy, st);
+      else
+        k_csr_spmm_vec<TV, TB, TY, 16, 4><<<nb, 256, 0, s>>>(rp, ci, val, n, B, c, Y, ldy, st);
+      return;
+    }
+  }
   if (c <= 16)
     k_csr_spmm<TV, TB, TY, 16, 1><<<nb, 256, 0, s>>>(rp, ci, val, n, B, c, Y, ldy, st);
   else if (c <= 32)
@@ -176,11 +279,19 @@ int csr_spmm(const int* rp, const int* ci, const void* val, int vdtype, int n, c
   } else {
     if (bdtype == SYMNMF_F32 && ydtype == SYMNMF_F32)
       spmm_dispatch<float, float, float>(rp, ci, (const float*)val, n, (const float*)B, c, (float*)Y, ldy, st, s);
+    else if (bdtype == SYMNMF_BF16 && ydtype == SYMNMF_F32)
+      spmm_dispatch<float, __bf16, float>(rp, ci, (const float*)val, n, (const __bf16*)B, c, (float*)Y, ldy, st, s);
     else if (bdtype == SYMNMF_F64 && ydtype == SYMNMF_F64)
       spmm_dispatch<float, double, double>(rp, ci, (const float*)val, n, (const double*)B, c, (double*)Y, ldy, st, s);
     else
       return -1;
   }
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int to_bf16(const float* F, int64_t count, void* out, hipStream_t s) {
+  if (count <= 0) return 0;
+  k_to_bf16<<<(unsigned)((count + 255) / 256), 256, 0, s>>>(F, count, (__bf16*)out);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 

@@ -168,7 +168,10 @@ __global__ __launch_bounds__(16 * UPD_RPB) void k_update(UpdateArgs a, const dou
           wl[rs * LW + q] = wt;
           if (q < k) {
             Dst[rb + q] = wt;
-            if (a.Dt) ((TT*)a.Dt)[(int64_t)q * a.ldt + row] = (TT)wt;
+            if (a.Dt) {
+              if (a.dt_rows) ((TT*)a.Dt)[(int64_t)row * a.ldt + q] = (TT)wt;
+              else ((TT*)a.Dt)[(int64_t)q * a.ldt + row] = (TT)wt;
+            }
           }
         }
       }

@@ -74,6 +74,8 @@ int csr_scalars(const int* rp, const void* val, int vdtype, int n, int64_t nnz, 
 // Y = X B (B n x c of bdtype, Y n x c of ydtype, c <= 128).
 int csr_spmm(const int* rp, const int* ci, const void* val, int vdtype, int n, const void* B, int bdtype, int c,
              void* Y, int ydtype, const DevState* st, hipStream_t s, int64_t ldy = 0);
+// out[i] = BF16(F[i]) (round to nearest even) for count FP32 values.
+int to_bf16(const float* F, int64_t count, void* out, hipStream_t s);
 // d_sum = sum over stored (i, j) of X_ij (w_i . h_j).
 int csr_resid_cross(const int* rp, const int* ci, const void* val, int vdtype, int n, int k, const void* W,
                     const void* H, int fdtype, Workspace& ws, double* d_sum, hipStream_t s);
@@ -125,7 +127,8 @@ struct UpdateArgs {
   const double* M = nullptr;
   const void* Src = nullptr;         // the fixed factor (alpha term, YMODE 1 rows)
   void* Dst = nullptr;               // the factor being updated (in place)
-  void* Dt = nullptr;                // optional transposed copy of Dst (cp x ldt)
+  void* Dt = nullptr;                // optional copy of Dst: transposed (cp x ldt) or,
+  int dt_rows = 0;                   // when dt_rows, row-major (n x ldt)
   const double* Ghat = nullptr;      // G + alpha I padded to kp x kp
   double alpha = 0.0;
   double* part = nullptr;            // [nb][pstride]: F^T F (k*k) then U^T F (l*k, YMODE 2)

@@ -213,8 +213,8 @@ struct symnmf_ctx {
   void* Yk = nullptr;  // CSR product in the update's padded layout (n x kp)
   void* P = nullptr;
   void* Bt = nullptr;
-  void* BtW = nullptr;  // transposed factor panels for the dense product
-  void* BtH = nullptr;
+  void* BtW = nullptr;  // transposed factor panels for the dense product, or
+  void* BtH = nullptr;  // row-major BF16 copies for the BF16-gather CSR product
   bool btW_ok = false, btH_ok = false;
   double* Yhat = nullptr;   // BPP: right-hand sides, then solutions (n x kp FP64)
   double* part = nullptr;   // fused-update block partials (nbu x pcap)
@@ -317,7 +317,7 @@ struct symnmf_ctx {
       return kind == SYMNMF_CSR || btH_ok;
     }
     if (mode == SYMNMF_MODE_LAI) return mW_ok && mH_ok;
-    if (mode == SYMNMF_MODE_PLAIN) return kind == SYMNMF_CSR || (btW_ok && btH_ok);
+    if (mode == SYMNMF_MODE_PLAIN) return (kind == SYMNMF_CSR && cdtype != SYMNMF_BF16) || (btW_ok && btH_ok);
     return false;
   }
 
@@ -507,6 +507,12 @@ struct symnmf_ctx {
         LCHK(factor_transpose(F, fdtype, n, k, which == SYMNMF_W ? BtW : BtH, opdtype(), p, nullptr, st));
         ok = true;
       }
+    } else if (mode == SYMNMF_MODE_PLAIN && kind == SYMNMF_CSR && cdtype == SYMNMF_BF16) {
+      bool& ok = which == SYMNMF_W ? btW_ok : btH_ok;
+      if (!ok) {
+        LCHK(to_bf16((const float*)F, (int64_t)n * k, which == SYMNMF_W ? BtW : BtH, st));
+        ok = true;
+      }
     }
   }
 
@@ -573,6 +579,19 @@ struct symnmf_ctx {
       a.ldt = p.ldt;
       pdt = cdtype == SYMNMF_F64 ? SYMNMF_F64 : SYMNMF_F32;
       tdt = opdtype();
+    } else if (cdtype == SYMNMF_BF16) {
+      // gathers of the BF16 copy of Src; the update writes the copy of Dst
+      {
+        Timed tm(this, SYMNMF_PHASE_PRODUCT);
+        LCHK(csr_spmm(rp, ci, Xv, xdtype, n, side == 0 ? BtH : BtW, SYMNMF_BF16, k, Yk, fdtype, gate_, st, kp));
+      }
+      a.P = Yk;
+      a.splits = 1;
+      a.cp = kp;
+      a.Dt = side == 0 ? BtW : BtH;
+      a.dt_rows = 1;
+      a.ldt = k;
+      tdt = SYMNMF_BF16;
     } else {
       {
         Timed tm(this, SYMNMF_PHASE_PRODUCT);
@@ -1000,6 +1019,14 @@ int symnmf_create(symnmf_ctx** out, const symnmf_matrix* X, int32_t k, double al
       c->ci = X->col_idx;
       c->cdtype = X->dtype;
       c->fdtype = X->dtype;
+      const int cd = c->opt.compute_dtype;
+      if (cd == SYMNMF_BF16) {
+        if (X->dtype != SYMNMF_F32) throw Fail{SYMNMF_E_UNSUPPORTED, "BF16 gathers need FP32 CSR values"};
+        if (c->opt.rule == SYMNMF_RULE_PGNCG) throw Fail{SYMNMF_E_UNSUPPORTED, "BF16 gathers with PGNCG"};
+        c->cdtype = SYMNMF_BF16;
+      } else if (cd >= 0 && cd != X->dtype) {
+        throw Fail{SYMNMF_E_UNSUPPORTED, "CSR compute dtype"};
+      }
     } else {
       throw Fail{SYMNMF_E_INVALID, "matrix kind"};
     }
@@ -1023,6 +1050,10 @@ int symnmf_create(symnmf_ctx** out, const symnmf_matrix* X, int32_t k, double al
     if (c->kind == SYMNMF_CSR) {
       c->Yk = dalloc<char>((size_t)n * c->kp * fs);
       HIPCHK(hipMemsetAsync(c->Yk, 0, (size_t)n * c->kp * fs, c->st));
+      if (c->cdtype == SYMNMF_BF16) {
+        c->BtW = dalloc<char>((size_t)n * k * 2);
+        c->BtH = dalloc<char>((size_t)n * k * 2);
+      }
     }
     if (c->kind == SYMNMF_DENSE) {
       // partials buffer: the largest splits * cp over every product width

@@ -166,3 +166,74 @@ def test_long_factor_half_step(case):
     e = rel(factor(ctx, P.W), Wo)
     log(f"   W rel {e:.2e}")
     assert e <= (1e-12 if vt == np.float64 else 1e-5)
+
+
+def _bf16_opts(**kw):
+    o = P.symnmf_default_options(**kw)
+    o.compute_dtype = P.BF16
+    return o
+
+
+@pytest.mark.parametrize("k", [16, 33, 64])
+def test_bf16_gather_half_steps(k):
+    # the product gathers a BF16 copy of the source rows (FP32 values, FP64
+    # sums); both half-steps, so the copy written by the update is used too
+    X = _sbm(6007, 12, 24.0, seed=k)
+    n = X.shape[0]
+    log(f"bf16 gathers n={n} k={k}")
+    ctx = P.symnmf_create(csr_dev(X), k, 0.0, 0, 4, _bf16_opts())
+    alpha = P.symnmf_get_stats(ctx).alpha
+    H = round_to(workloads.random_factor(n, k, seed=10, scale=0.2), torch.float32)
+    W = round_to(workloads.random_factor(n, k, seed=11, scale=0.2), torch.float32)
+    P.symnmf_set_factor(ctx, P.H, dev(H))
+    P.symnmf_set_factor(ctx, P.W, dev(W))
+    X64 = _X64(X)
+    P.symnmf_half_step(ctx, 0, 0)
+    Wo = O.hals_gy(H.T @ H + alpha * np.eye(k), X64 @ round_to(H, torch.bfloat16) + alpha * H, W)
+    e = rel(factor(ctx, P.W), Wo)
+    log(f"   W rel {e:.2e}")
+    assert e <= 1e-5
+    P.symnmf_half_step(ctx, 1, 1)
+    Wr = round_to(Wo, torch.float32)
+    Ho = O.hals_gy(Wr.T @ Wr + alpha * np.eye(k), X64 @ round_to(Wr, torch.bfloat16) + alpha * Wr, H)
+    e = rel(factor(ctx, P.H), Ho)
+    log(f"   H rel {e:.2e}")
+    assert e <= 1e-4
+
+
+def test_bf16_gather_run_residual_and_graphs():
+    # against the FP64 oracle on FP32 data: the relative residual within 1e-3;
+    # graph replay bit-identical to eager launches
+    X = _sbm(5000, 10, 20.0, seed=12)
+    n, k, iters = X.shape[0], 20, 12
+    out = []
+    for graphs in (0, 1):
+        ctx = P.symnmf_create(csr_dev(X), k, 0.0, 0, 8, _bf16_opts(graphs=graphs))
+        P.symnmf_iterate(ctx, iters)
+        out.append((factor(ctx, P.H), P.symnmf_residual(ctx, P.RESID_EXACT)[0],
+                    P.symnmf_get_stats(ctx).graph_launches))
+    assert out[0][2] == 0 and out[1][2] > 0
+    assert np.array_equal(out[0][0], out[1][0])
+    X64 = _X64(X)
+    sc = O.data_scalars(X64)
+    H0 = round_to(O.initial_factor(n, k, sc["zeta"], 8), torch.float32)
+    Wo, Ho, hist = O.plain_symnmf(X64, k, sc["maxval"], H0, iters)
+    ro = O.residual_direct(X64, Wo, Ho) / np.sqrt(sc["normsq"])
+    log(f"bf16 gathers: residual gpu {out[0][1]:.6f} oracle {ro:.6f}")
+    assert abs(out[0][1] - ro) / ro <= 1e-3
+
+
+def test_bf16_gather_unsupported():
+    X = _sbm(2000, 4, 20.0, seed=1)
+    with pytest.raises(P.SymNMFError) as e:
+        P.symnmf_create(csr_dev(X), 4, 0.0, 0, 0, _bf16_opts(rule=P.RULE_PGNCG))
+    assert e.value.code == P.E_UNSUPPORTED
+    X64 = _X64(X)
+    with pytest.raises(P.SymNMFError) as e:
+        P.symnmf_create(csr_dev(X64), 4, 0.0, 0, 0, _bf16_opts())
+    assert e.value.code == P.E_UNSUPPORTED
+    o = P.symnmf_default_options()
+    o.compute_dtype = P.F64
+    with pytest.raises(P.SymNMFError) as e:
+        P.symnmf_create(csr_dev(X), 4, 0.0, 0, 0, o)
+    assert e.value.code == P.E_UNSUPPORTED
