@@ -231,49 +231,49 @@ __global__ __launch_bounds__(16 * UPD_RPB) void k_update(UpdateArgs a, const dou
     if (tid == 0) a.dpart[blockIdx.x] = t;
   }
 }
-
 // Fixed-order reduction of the block partials (unified rows of E = k*k
-// [+ l*k] doubles): G (k x k), Ghat = G + alpha I (k x k part of the kp x kp
-// padded matrix; the padding is set once), the reciprocals of its diagonal,
-// and, for the LAI path, M = diag(lam) Z (l x kp, zero padded) with Z the
-// reduced U^T F.  Large partial counts go through a first level that sums
-// fixed groups of 32 rows.
-__device__ __forceinline__ double sum_strided(const double* __restrict__ p, int nb, int64_t stride) {
+// [+ l*k] doubles) in one kernel: G (k x k), Ghat = G + alpha I (k x k part of
+// the kp x kp padded matrix; the padding is set once), the reciprocals of its
+// diagonal, and, for the LAI path, M = diag(lam) Z (l x kp, zero padded) with
+// Z the reduced U^T F.  A block takes 16 entries; its 16 slices of threads
+// each sum a contiguous run of partial rows (16 loads in flight), the slice
+// sums are added in slice order and the epilogue is applied per entry.  One
+// launch instead of a level over groups of 32 rows plus a final level: a LAI
+// iteration at n = 16384, k = 32, l = 48 measured 61.9 -> 56.8 us.
+constexpr int RED_SLICES = 16, RED_COLS = 16;
+
+__device__ __forceinline__ double sum_rows16(const double* __restrict__ p, int cnt, int64_t stride) {
   double acc = 0.0;
   int b = 0;
-  for (; b + 8 <= nb; b += 8) {
-    double v[8];
+  for (; b + 16 <= cnt; b += 16) {
+    double v[16];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) v[u] = p[(int64_t)(b + u) * stride];
+    for (int u = 0; u < 16; ++u) v[u] = p[(int64_t)(b + u) * stride];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) acc += v[u];
+    for (int u = 0; u < 16; ++u) acc += v[u];
   }
-  for (; b < nb; ++b) acc += p[(int64_t)b * stride];
+  for (; b < cnt; ++b) acc += p[(int64_t)b * stride];
   return acc;
 }
 
-constexpr int REDUCE_GROUP = 32;
-
-__global__ __launch_bounds__(256) void k_reduce_level1(const double* __restrict__ part, int nb, int E,
-                                                       double* __restrict__ out, const DevState* __restrict__ st) {
+__global__ __launch_bounds__(RED_SLICES * RED_COLS) void k_update_reduce(
+    const double* __restrict__ part, int nb, int E, int k, int l, int kp, double alpha,
+    const double* __restrict__ lam, double* __restrict__ G, double* __restrict__ Ghat, double* __restrict__ Ginv,
+    double* __restrict__ M, const DevState* __restrict__ st) {
   if (stopped(st)) return;
-  const int e = blockIdx.x * 256 + threadIdx.x;
-  if (e >= E) return;
-  const int b0 = blockIdx.y * REDUCE_GROUP;
-  const int cnt = min(REDUCE_GROUP, nb - b0);
-  out[(int64_t)blockIdx.y * E + e] = sum_strided(part + (int64_t)b0 * E + e, cnt, E);
-}
-
-__global__ __launch_bounds__(256) void k_update_reduce(const double* __restrict__ part, int nb, int E, int k, int l,
-                                                       int kp, double alpha, const double* __restrict__ lam,
-                                                       double* __restrict__ G, double* __restrict__ Ghat,
-                                                       double* __restrict__ Ginv, double* __restrict__ M,
-                                                       const DevState* __restrict__ st) {
-  if (stopped(st)) return;
-  const int e = blockIdx.x * 256 + threadIdx.x;
+  __shared__ double ps[RED_SLICES][RED_COLS + 1];
+  const int c = threadIdx.x % RED_COLS, sl = threadIdx.x / RED_COLS;
+  const int e = blockIdx.x * RED_COLS + c;
+  const int per = (nb + RED_SLICES - 1) / RED_SLICES;
+  const int b0 = sl * per;
+  const int cnt = max(0, min(per, nb - b0));
+  ps[sl][c] = e < E ? sum_rows16(part + (int64_t)b0 * E + e, cnt, E) : 0.0;
+  __syncthreads();
+  if (sl != 0 || e >= E) return;
+  double acc = 0.0;
+#pragma unroll
+  for (int j = 0; j < RED_SLICES; ++j) acc += ps[j][c];
   const int kk = k * k;
-  if (e >= E) return;
-  const double acc = sum_strided(part + e, nb, E);
   if (e < kk) {
     const int p = e / k, q = e - p * k;
     if (G) G[e] = acc;
@@ -370,19 +370,10 @@ int fused_update(const UpdateArgs& a, const UpdateRO& ro, int kp, int ymode, int
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
-int update_reduce(const double* part, int nb, int E, double* l1, int k, int l, int kp, double alpha,
-                  const double* lam, double* G, double* Ghat, double* Ginv, double* M, const DevState* st,
-                  hipStream_t s) {
-  const double* src = part;
-  int cnt = nb;
-  if (nb > REDUCE_GROUP) {
-    const int groups = ceil_div(nb, REDUCE_GROUP);
-    dim3 g1(ceil_div(E, 256), groups);
-    k_reduce_level1<<<g1, 256, 0, s>>>(part, nb, E, l1, st);
-    src = l1;
-    cnt = groups;
-  }
-  k_update_reduce<<<ceil_div(E, 256), 256, 0, s>>>(src, cnt, E, k, l, kp, alpha, lam, G, Ghat, Ginv, M, st);
+int update_reduce(const double* part, int nb, int E, int k, int l, int kp, double alpha, const double* lam,
+                  double* G, double* Ghat, double* Ginv, double* M, const DevState* st, hipStream_t s) {
+  k_update_reduce<<<ceil_div(E, RED_COLS), RED_SLICES * RED_COLS, 0, s>>>(part, nb, E, k, l, kp, alpha, lam, G, Ghat,
+                                                                          Ginv, M, st);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 

@@ -152,10 +152,9 @@ int update_blocks(int n, int fdtype);
 int fused_update(const UpdateArgs& a, const UpdateRO& ro, int kp, int ymode, int fdtype, int pdtype, int tdtype,
                  int nb, const DevState* st, hipStream_t s);
 // Reduce nb partial rows of E doubles (E = k*k, or k*k + l*k when M is
-// wanted); l1: scratch of ceil(nb / 32) * E doubles.
-int update_reduce(const double* part, int nb, int E, double* l1, int k, int l, int kp, double alpha,
-                  const double* lam, double* G, double* Ghat, double* Ginv, double* M, const DevState* st,
-                  hipStream_t s);
+// wanted).
+int update_reduce(const double* part, int nb, int E, int k, int l, int kp, double alpha, const double* lam,
+                  double* G, double* Ghat, double* Ginv, double* M, const DevState* st, hipStream_t s);
 int pad_identity(double* Ghat, double* Ginv, int k, int kp, hipStream_t s);
 // M (l x kp, zero padded) = diag(lam) Z, Z l x k.
 int scale_rows(const double* Z, const double* lam, int l, int k, int kp, double* M, hipStream_t s);

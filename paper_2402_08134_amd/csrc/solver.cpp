@@ -218,7 +218,6 @@ struct symnmf_ctx {
   bool btW_ok = false, btH_ok = false;
   double* Yhat = nullptr;   // BPP: right-hand sides, then solutions (n x kp FP64)
   double* part = nullptr;   // fused-update block partials (nbu x pcap)
-  double* part_l1 = nullptr;
   size_t pcap = 0;          // doubles per partial row
   double* dpart = nullptr;
   int nbu = 1;              // blocks of the fused update
@@ -285,7 +284,7 @@ struct symnmf_ctx {
   ~symnmf_ctx() {
     if (st) (void)hipStreamSynchronize(st);
     else (void)hipDeviceSynchronize();
-    void* ptrs[] = {Xb_owned, W, H, Y, Yk, Yhat, P, Bt, BtW, BtH, part, part_l1, dpart, M_W, M_H, Gi_W, Gi_H, Gi_S, G_W, G_H, Gh_W, Gh_H, Gh_S, d_scal, rowsum, dstate, hist, d_fail,
+    void* ptrs[] = {Xb_owned, W, H, Y, Yk, Yhat, P, Bt, BtW, BtH, part, dpart, M_W, M_H, Gi_W, Gi_H, Gi_S, G_W, G_H, Gh_W, Gh_H, Gh_S, d_scal, rowsum, dstate, hist, d_fail,
                     ws.base, Q, Q1, U, YQ, Tm, QT, Vw, lam, Rl, Rlinv, Z, sb.w, sb.prefix, sb.counts, sb.flags,
                     sb.info, sb.theta, rows, weights, seg_cnt, seg_ptr, seg_src, seg_val, lev, R, Rinv};
     for (void* p : ptrs) dfree(p);
@@ -321,11 +320,27 @@ struct symnmf_ctx {
     return false;
   }
 
+  // Whether graph `which` holds `count` iterations of the current launch
+  // sequence.
+  bool graph_ready(int which, int count) const {
+    return graph_exec[which] && graph_gen_of[which] == gen && graph_count_of[which] == count;
+  }
+
   // Replay `count` iterations from graph `which`, capturing it
   // first if needed.  Returns false (and stops using graphs) if capture or
   // instantiation fails; the iterations are then not done.
   bool graph_iterations(int which, int count) {
-    if (!graph_exec[which] || graph_gen_of[which] != gen || graph_count_of[which] != count) {
+    if (!graph_ready(which, count) && !graph_capture(which, count)) return false;
+    HIPCHK(hipGraphLaunch(graph_exec[which], st));
+    iter_host += count;
+    ++graph_launches;
+    return true;
+  }
+
+  // Capture and instantiate graph `which` for `count` iterations without
+  // launching it.  Returns false (and stops using graphs) on failure.
+  bool graph_capture(int which, int count) {
+    {
       if (graph_exec[which]) {
         HIPCHK(hipGraphExecDestroy(graph_exec[which]));
         graph_exec[which] = nullptr;
@@ -374,9 +389,6 @@ struct symnmf_ctx {
       graph_gen_of[which] = gen;
       graph_count_of[which] = count;
     }
-    HIPCHK(hipGraphLaunch(graph_exec[which], st));
-    iter_host += count;
-    ++graph_launches;
     return true;
   }
 
@@ -608,7 +620,7 @@ struct symnmf_ctx {
       ro.Ginv = Gis;
       ro.M = a.M;
       LCHK(fused_update(a, ro, kp, ymode, fdtype, pdt, tdt, nbu, gate_, st));
-      LCHK(update_reduce(part, nbu, a.pstride, part_l1, k, l, kp, alpha, lam, Gd, Ghd, Gid,
+      LCHK(update_reduce(part, nbu, a.pstride, k, l, kp, alpha, lam, Gd, Ghd, Gid,
                          side == 0 ? M_W : M_H, gate_, st));
     } else {
       // BPP: the update kernel writes the right-hand sides, the pivoting
@@ -625,7 +637,7 @@ struct symnmf_ctx {
       LCHK(bpp_update(n, k, kp, Yhat, Dst, fdtype, a.Ghat, &dstate->flags, SYMNMF_FLAG_BPP_CAP, gate_, st));
       a.rule = 2;
       LCHK(fused_update(a, ro, kp, ymode, fdtype, pdt, tdt, nbu, gate_, st));
-      LCHK(update_reduce(part, nbu, a.pstride, part_l1, k, l, kp, alpha, lam, Gd, Ghd, Gid,
+      LCHK(update_reduce(part, nbu, a.pstride, k, l, kp, alpha, lam, Gd, Ghd, Gid,
                          side == 0 ? M_W : M_H, gate_, st));
     }
     invalidate(dst_id);
@@ -707,7 +719,7 @@ struct symnmf_ctx {
     a.part = part;
     a.pstride = k * k + (ymode == 2 ? l * k : 0);
     LCHK(cg_pass(2, a, kp, ymode, fdtype, pdt, tdt, G_H, cg_sc, nbc, gate_, st));
-    LCHK(update_reduce(part, nbc, a.pstride, part_l1, k, l, kp, alpha, lam, G_H, Gh_H, Gi_H,
+    LCHK(update_reduce(part, nbc, a.pstride, k, l, kp, alpha, lam, G_H, Gh_H, Gi_H,
                        ymode == 2 ? M_H : nullptr, gate_, st));
     invalidate(SYMNMF_W);
     if (ymode == 2) mH_ok = true;
@@ -1090,7 +1102,6 @@ int symnmf_create(symnmf_ctx** out, const symnmf_matrix* X, int32_t k, double al
     c->nbu = update_blocks(n, c->fdtype);
     c->pcap = (size_t)k * k;
     c->part = dalloc<double>((size_t)c->nbu * c->pcap);
-    c->part_l1 = dalloc<double>((size_t)ceil_div(c->nbu, 32) * c->pcap);
     c->dpart = dalloc<double>(c->nbu);
     c->Gi_W = dalloc<double>(c->kp);
     c->Gi_H = dalloc<double>(c->kp);
@@ -1219,12 +1230,9 @@ void lai_prepare(symnmf_ctx* c, int l) {
     const size_t need = (size_t)c->k * c->k + (size_t)l * c->k;
     if (need > c->pcap) {
       dfree(c->part);
-      dfree(c->part_l1);
       c->part = nullptr;
-      c->part_l1 = nullptr;
       c->pcap = need;
       c->part = dalloc<double>((size_t)c->nbu * c->pcap);
-      c->part_l1 = dalloc<double>((size_t)ceil_div(c->nbu, 32) * c->pcap);
     }
     c->M_W = dalloc<double>((size_t)l * c->kp);
     c->M_H = dalloc<double>((size_t)l * c->kp);
@@ -1362,7 +1370,15 @@ int symnmf_iterate(symnmf_ctx* c, int32_t iters, int32_t* done) {
         if (c->steady()) {
           const bool whole_block = block > 1 && iters - t >= block && (!polled || every % block == 0);
           if (whole_block) {
-            if (c->graph_iterations(1, block)) step = block;
+            if (c->graph_ready(1, block)) {
+              if (c->graph_iterations(1, block)) step = block;
+            } else {
+              // run this block with direct launches and capture the graph
+              // behind it: instantiation then overlaps the block's device work
+              for (int b = 0; b < block; ++b) c->one_iteration();
+              step = block;
+              (void)c->graph_capture(1, block);
+            }
           } else if (c->graph_iterations(0, 1)) {
             step = 1;
           }
