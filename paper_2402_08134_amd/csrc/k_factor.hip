@@ -346,115 +346,6 @@ __global__ __launch_bounds__(256) void k_chol_inverse(const double* __restrict__
   }
 }
 
-// Single-wavefront Cholesky and triangular inverse for k <= 64.  The matrix
-// lives in LDS (padded stride); lane c owns column c of every row update, so
-// each step is a sequence of wave-wide row operations whose iterations are
-// independent of one another (the loads pipeline), and no barrier beyond the
-// wavefront is needed: LDS operations of one wavefront complete in order, so
-// compiler fences suffice.  Factor: for pivot j, scale column j below it, then
-// for every trailing row r subtract L[r][j] L[c][j] from entry (r, c), c <= r.
-// Inverse: X = L^{-1} by row elimination of [L | I] (X[t] /= L[t][t], then
-// X[m] -= L[m][t] X[t] for m > t), lane c holding column c; R^{-1} = X^T.
-// Same shift retries and flags as the workgroup kernel.
-constexpr int CW_LD = 65;  // padded row stride of the LDS matrices (doubles)
-
-__global__ __launch_bounds__(64) void k_chol_wave(const double* __restrict__ G, int k, double* __restrict__ R,
-                                                  double* __restrict__ Rinv, int* d_flags, int flag_bit,
-                                                  int* d_fail) {
-  __shared__ double A[64 * CW_LD];
-  __shared__ double Xs[64 * CW_LD];
-  const int c = threadIdx.x;
-  const bool act = c < k;
-  // G into Xs (coalesced, independent loads), then the trace from LDS
-  const int kk = k * k;
-#pragma unroll 8
-  for (int e = c; e < kk; e += 64) {
-    const int r = e / k;
-    Xs[r * CW_LD + (e - r * k)] = G[e];
-  }
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  double trace = 0.0;
-  for (int t = 0; t < k; ++t) trace += Xs[t * CW_LD + t];
-  double shift = 0.0, grow = 1e-12 * fmax(trace, 1e-300) / k;
-  bool bad = true;
-  for (int attempt = 0; attempt < 6 && bad; ++attempt) {
-    if (attempt > 0) {
-      shift = grow;  // 1e-12, 1e-10, ... times tr(G) / k
-      grow *= 100.0;
-    }
-    if (act)
-      for (int r = 0; r < k; ++r) A[r * CW_LD + c] = Xs[r * CW_LD + c] + (r == c ? shift : 0.0);
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    bad = false;
-    for (int j = 0; j < k; ++j) {
-      const double d = A[j * CW_LD + j];  // the same value in every lane
-      if (!(d > 0.0) || !isfinite(d)) {
-        bad = true;
-        break;
-      }
-      const double ljj = sqrt(d);
-      const double rl = 1.0 / ljj;
-      __builtin_amdgcn_wave_barrier();
-      if (c > j && act) A[c * CW_LD + j] *= rl;  // column j below the pivot
-      if (c == j) A[j * CW_LD + j] = ljj;
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-      __builtin_amdgcn_wave_barrier();
-      if (c > j && act) {
-        const double lcj = A[c * CW_LD + j];
-#pragma unroll 8
-        for (int r = c; r < k; ++r) A[r * CW_LD + c] = fma(-A[r * CW_LD + j], lcj, A[r * CW_LD + c]);
-      }
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-      __builtin_amdgcn_wave_barrier();
-    }
-  }
-  if (bad) {
-    if (c == 0) *d_fail = 1;
-    return;
-  }
-  if (c == 0 && shift > 0.0 && d_flags) atomicOr(d_flags, flag_bit);
-  // L is the lower triangle of A; R = L^T (row c of R = column c of L)
-  if (act)
-    for (int r = 0; r < k; ++r) R[c * k + r] = r >= c ? A[r * CW_LD + c] : 0.0;
-  // X = L^{-1}: lane c keeps column c
-  if (act)
-    for (int r = 0; r < k; ++r) Xs[r * CW_LD + c] = r == c ? 1.0 : 0.0;
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  for (int t = 0; t < k; ++t) {
-    if (act) {
-      const double xt = Xs[t * CW_LD + c] / A[t * CW_LD + t];
-      Xs[t * CW_LD + c] = xt;
-#pragma unroll 8
-      for (int m = t + 1; m < k; ++m) Xs[m * CW_LD + c] = fma(-A[m * CW_LD + t], xt, Xs[m * CW_LD + c]);
-    }
-  }
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  // R^{-1} = X^T: row c of R^{-1} = column c of X
-  if (act)
-    for (int r = 0; r < k; ++r) Rinv[c * k + r] = Xs[r * CW_LD + c];
-}
-
-// ---------------------------------------------------------------------------
-// Cholesky G + shift I = L L^T and L^{-1} in the registers of one wavefront:
-// lane r holds row r (KM doubles, KM = k rounded up to 16; rows and columns
-// beyond k are the identity).  Step j of the factorisation takes the pivot
-// from lane j, scales column j in every lane, then broadcasts column j
-// (v_readlane, one per entry) for the rank-one update of the trailing rows;
-// the inverse is built row by row the same way (row t of L^{-1} is final
-// after step t, broadcast, and subtracted from the rows below).  With all
-// loops unrolled every register index is static; only the lower triangle is
-// meaningful.  Retries with the same growing shifts as the LDS kernels.
-// ---------------------------------------------------------------------------
-__device__ __forceinline__ double lane_value(double v, int lane) {
-  const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
-  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
-  return __hiloint2double(hi, lo);
-}
-
 template <int KM>
 __global__ __launch_bounds__(64) void k_chol_regs(const double* __restrict__ G, int k, double* __restrict__ R,
                                                   double* __restrict__ Rinv, int* d_flags, int flag_bit,
