@@ -346,6 +346,23 @@ __global__ __launch_bounds__(256) void k_chol_inverse(const double* __restrict__
   }
 }
 
+// ---------------------------------------------------------------------------
+// Cholesky G + shift I = L L^T and L^{-1} in the registers of one wavefront:
+// lane r holds row r (KM doubles, KM = k rounded up to 16; rows and columns
+// beyond k are the identity).  Step j of the factorisation takes the pivot
+// from lane j, scales column j in every lane, then broadcasts column j
+// (v_readlane, one per entry) for the rank-one update of the trailing rows;
+// the inverse is built row by row the same way (row t of L^{-1} is final
+// after step t, broadcast, and subtracted from the rows below).  With all
+// loops unrolled every register index is static; only the lower triangle is
+// meaningful.  Retries with the same growing shifts as the workgroup kernel.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double lane_value(double v, int lane) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
+  return __hiloint2double(hi, lo);
+}
+
 template <int KM>
 __global__ __launch_bounds__(64) void k_chol_regs(const double* __restrict__ G, int k, double* __restrict__ R,
                                                   double* __restrict__ Rinv, int* d_flags, int flag_bit,
