@@ -443,6 +443,19 @@ constexpr int JACOBI_NT = 1024;
 // V accumulated in LDS next to A, then columns sorted by descending
 // eigenvalue into V.
 // ---------------------------------------------------------------------------
+// Pair `t` of round-robin step `step` over m (even) indices: index 0 fixed,
+// 1..m-1 rotated by the step; returned with p < q.
+__device__ __forceinline__ void jacobi_pair(int t, int step, int m, int& p, int& q) {
+  // both sums are below 2 (m - 1): one conditional subtraction each, no
+  // integer division
+  int x = t - 1 + step, y = m - 2 - t + step;
+  x -= x >= m - 1 ? m - 1 : 0;
+  y -= y >= m - 1 ? m - 1 : 0;
+  const int a = t == 0 ? 0 : 1 + x, b = 1 + y;
+  p = a < b ? a : b;
+  q = a < b ? b : a;
+}
+
 __global__ __launch_bounds__(JACOBI_NT) void k_jacobi(const double* __restrict__ T, int l, double* __restrict__ V,
                                                 double* __restrict__ lam) {
   // A: m x (m + 1) (m = l rounded up to even; the extra row and column are
@@ -452,8 +465,7 @@ __global__ __launch_bounds__(JACOBI_NT) void k_jacobi(const double* __restrict__
   const int m = l + (l & 1);
   const int lda = m + 1;
   double* Vw = A + m * lda;
-  __shared__ double cs[48], sn[48];
-  __shared__ int pp[48], qq[48];
+  __shared__ double2 rot[48];  // (c, s) of each pair of the step
   __shared__ double red[JACOBI_NT / 64];
   __shared__ int order[96];
   __shared__ int conv;
@@ -481,9 +493,8 @@ __global__ __launch_bounds__(JACOBI_NT) void k_jacobi(const double* __restrict__
     for (int step = 0; step < m - 1; ++step) {
       // round-robin (circle) pairing: index 0 fixed, 1..m-1 rotate by `step`
       if (tid < half) {
-        int p = tid == 0 ? 0 : 1 + (tid - 1 + step) % (m - 1);
-        int q = 1 + (m - 2 - tid + step) % (m - 1);
-        if (p > q) { const int sw = p; p = q; q = sw; }
+        int p, q;
+        jacobi_pair(tid, step, m, p, q);
         double c = 1.0, s = 0.0;
         const double apq = A[p * lda + q];
         if (fabs(apq) > 1e-300) {
@@ -492,34 +503,36 @@ __global__ __launch_bounds__(JACOBI_NT) void k_jacobi(const double* __restrict__
           c = 1.0 / sqrt(1.0 + t * t);
           s = t * c;
         }
-        pp[tid] = p;
-        qq[tid] = q;
-        cs[tid] = c;
-        sn[tid] = s;
+        rot[tid] = make_double2(c, s);
       }
       __syncthreads();
-      // every 2 x 2 block (rows of pair a, columns of pair b) from its own
-      // four entries: rotate its columns by pair b, then its rows by pair a
+      // one task per (pair a, pair b): the 2 x 2 block of A on the rows of
+      // pair a and the columns of pair b (its columns rotated by pair b, then
+      // its rows by pair a), and rows 2a, 2a + 1 of V on the columns of pair
+      // b.  Pair indices are recomputed, so every read of a task is issued at
+      // once; the tasks touch disjoint entries.
       for (int e = tid; e < half * half; e += JACOBI_NT) {
         const int a = e / half, b = e - a * half;
-        const int pa = pp[a], qa = qq[a], pb = pp[b], qb = qq[b];
-        const double ca = cs[a], sa = sn[a], cb = cs[b], sb = sn[b];
+        int pa, qa, pb, qb;
+        jacobi_pair(a, step, m, pa, qa);
+        jacobi_pair(b, step, m, pb, qb);
+        const double2 ra = rot[a], rb = rot[b];
         const double x00 = A[pa * lda + pb], x01 = A[pa * lda + qb];
         const double x10 = A[qa * lda + pb], x11 = A[qa * lda + qb];
+        const int r0 = 2 * a;
+        const double v0p = Vw[r0 * lda + pb], v0q = Vw[r0 * lda + qb];
+        const double v1p = Vw[(r0 + 1) * lda + pb], v1q = Vw[(r0 + 1) * lda + qb];
+        const double ca = ra.x, sa = ra.y, cb = rb.x, sb = rb.y;
         const double y00 = cb * x00 - sb * x01, y01 = sb * x00 + cb * x01;
         const double y10 = cb * x10 - sb * x11, y11 = sb * x10 + cb * x11;
         A[pa * lda + pb] = ca * y00 - sa * y10;
         A[qa * lda + pb] = sa * y00 + ca * y10;
         A[pa * lda + qb] = ca * y01 - sa * y11;
         A[qa * lda + qb] = sa * y01 + ca * y11;
-      }
-      for (int e = tid; e < m * half; e += JACOBI_NT) {
-        const int r = e / half, b = e - r * half;
-        const int pb = pp[b], qb = qq[b];
-        const double cb = cs[b], sb = sn[b];
-        const double vp = Vw[r * lda + pb], vq = Vw[r * lda + qb];
-        Vw[r * lda + pb] = cb * vp - sb * vq;
-        Vw[r * lda + qb] = sb * vp + cb * vq;
+        Vw[r0 * lda + pb] = cb * v0p - sb * v0q;
+        Vw[r0 * lda + qb] = sb * v0p + cb * v0q;
+        Vw[(r0 + 1) * lda + pb] = cb * v1p - sb * v1q;
+        Vw[(r0 + 1) * lda + qb] = sb * v1p + cb * v1q;
       }
       __syncthreads();
     }
