@@ -38,17 +38,40 @@ __device__ __forceinline__ double row16_sum(double v) {
   return v;
 }
 
-// 16 lanes per row, UPD_RPB rows per block.  Lane g of a row owns the
-// columns q = g + 16 c (c < KP / 16).  The HALS sweep over column i sums
-// w_q Ghat[i][q] over the row's lanes (a DPP row) and the lane owning column
-// i applies the update.
-template <int KP, int LP, typename TF, typename TP, typename TT, int YMODE>
+// Column held in slot c by lane g of a row: with 16 lanes per row the
+// columns interleave (g + 16 c); with 8 lanes each lane holds runs of 4
+// adjacent columns (32 (c / 4) + 4 g + c mod 4), so the 8 lanes of a row read
+// 32 adjacent values per step.
+template <int LPR>
+__device__ __forceinline__ constexpr int col_of(int g, int c) {
+  return LPR == 8 ? 32 * (c >> 2) + 4 * g + (c & 3) : g + 16 * c;
+}
+// Sum over the LPR lanes of a row: 8 lanes are half a DPP row (pairs, quads,
+// then row_half_mirror), 16 a full row.
+template <int LPR>
+__device__ __forceinline__ double lanes_sum(double v) {
+  if (LPR == 8) {
+    v += dpp_double<0xB1>(v);
+    v += dpp_double<0x4E>(v);
+    v += dpp_double<0x141>(v);
+    return v;
+  }
+  return row16_sum(v);
+}
+
+// LPR lanes per row (16, or 8 for long factors with KP a multiple of 32:
+// three DPP steps per column sum instead of four and half as many lanes per
+// row), 512 threads per block.  Lane g of a row owns the KP / LPR columns
+// col_of(g, c).  The HALS sweep over column i sums w_q Ghat[i][q] over the
+// row's lanes and the lane owning column i applies the update.
+template <int KP, int LP, typename TF, typename TP, typename TT, int YMODE, int LPR>
 __global__ __launch_bounds__(16 * UPD_RPB) void k_update(UpdateArgs a, const double* __restrict__ Gh,
                                                 const double* __restrict__ Ginv, const double* __restrict__ M,
                                                 const TF* __restrict__ Src, const DevState* __restrict__ st) {
   if (stopped(st)) return;
-  constexpr int NTH = 16 * UPD_RPB, RPB = UPD_RPB;
-  constexpr int CPL = KP / 16;
+  constexpr int NTH = 16 * UPD_RPB, RPB = NTH / LPR;
+  constexpr int CPL = KP / LPR;   // HALS columns per lane
+  constexpr int TCPL = KP / 16;   // entries per thread of the 16 x 16 partial tile
   constexpr int ZI = LP > 0 ? LP / 16 : 1;
   constexpr int LW = KP + 1;
   constexpr int LU = LP + 1;
@@ -60,7 +83,7 @@ __global__ __launch_bounds__(16 * UPD_RPB) void k_update(UpdateArgs a, const dou
   TF* us = wl + RPB * LW;                                         // RPB x LU (LAI)
   __shared__ double sc[8];
   const int tid = threadIdx.x;
-  const int g = tid & 15, rs = tid >> 4;       // lane in row, row slot
+  const int g = tid % LPR, rs = tid / LPR;     // lane in row, row slot
   const int tx = tid & 15, ty = tid >> 4;      // Gram / U^T F tile coordinates
   const int n = a.n, k = a.k, l = a.l;
   TF* __restrict__ Dst = (TF*)a.Dst;
@@ -71,16 +94,16 @@ __global__ __launch_bounds__(16 * UPD_RPB) void k_update(UpdateArgs a, const dou
     for (int e = tid; e < l * KP; e += NTH) ms[e] = M[e];
   __syncthreads();
 
-  double gacc[CPL][CPL];
-  double zacc[ZI][CPL];
+  double gacc[TCPL][TCPL];
+  double zacc[ZI][TCPL];
 #pragma unroll
-  for (int i = 0; i < CPL; ++i)
+  for (int i = 0; i < TCPL; ++i)
 #pragma unroll
-    for (int j = 0; j < CPL; ++j) gacc[i][j] = 0.0;
+    for (int j = 0; j < TCPL; ++j) gacc[i][j] = 0.0;
 #pragma unroll
   for (int i = 0; i < ZI; ++i)
 #pragma unroll
-    for (int j = 0; j < CPL; ++j) zacc[i][j] = 0.0;
+    for (int j = 0; j < TCPL; ++j) zacc[i][j] = 0.0;
   double dot = 0.0;
 
   for (int base = blockIdx.x * RPB; base < n; base += gridDim.x * RPB) {
@@ -101,11 +124,11 @@ __global__ __launch_bounds__(16 * UPD_RPB) void k_update(UpdateArgs a, const dou
       // compiler wait for each load in turn): padded buffers are read in
       // full, factor rows with a clamped column index and a zero mask.
       if (YMODE == 0) {
-        const TP* pr = (const TP*)a.P + (int64_t)row * a.cp + g;  // cp == KP, zero padded
+        const TP* pr = (const TP*)a.P + (int64_t)row * a.cp;  // cp == KP, zero padded
         const int64_t sstride = (int64_t)n * a.cp;
         for (int sp = 0; sp < a.splits; ++sp) {
 #pragma unroll
-          for (int c = 0; c < CPL; ++c) y[c] += (double)pr[sp * sstride + 16 * c];
+          for (int c = 0; c < CPL; ++c) y[c] += (double)pr[sp * sstride + col_of<LPR>(g, c)];
         }
       } else if (YMODE == 1) {
         const int e1 = a.seg_ptr[row + 1];
@@ -114,7 +137,7 @@ __global__ __launch_bounds__(16 * UPD_RPB) void k_update(UpdateArgs a, const dou
           const TF* sr = Src + (int64_t)a.seg_src[e] * k;
 #pragma unroll
           for (int c = 0; c < CPL; ++c) {
-            const int q = g + 16 * c;
+            const int q = col_of<LPR>(g, c);
             const double x = (double)sr[q < k ? q : k - 1];
             y[c] = fma(v, q < k ? x : 0.0, y[c]);
           }
@@ -124,12 +147,12 @@ __global__ __launch_bounds__(16 * UPD_RPB) void k_update(UpdateArgs a, const dou
         for (int p = 0; p < l; ++p) {
           const double up = (double)u[p];
 #pragma unroll
-          for (int c = 0; c < CPL; ++c) y[c] = fma(up, ms[p * KP + g + 16 * c], y[c]);
+          for (int c = 0; c < CPL; ++c) y[c] = fma(up, ms[p * KP + col_of<LPR>(g, c)], y[c]);
         }
       }
 #pragma unroll
       for (int c = 0; c < CPL; ++c) {
-        const int q = g + 16 * c;
+        const int q = col_of<LPR>(g, c);
         const int qc = q < k ? q : k - 1;
         const double xs = (double)Src[rb + qc];
         const double xd = (double)Dst[rb + qc];
@@ -138,10 +161,10 @@ __global__ __launch_bounds__(16 * UPD_RPB) void k_update(UpdateArgs a, const dou
       }
       if (a.rule == 1) {
 #pragma unroll
-        for (int c = 0; c < CPL; ++c) a.Yhat[(int64_t)row * KP + g + 16 * c] = y[c];
+        for (int c = 0; c < CPL; ++c) a.Yhat[(int64_t)row * KP + col_of<LPR>(g, c)] = y[c];
       } else if (a.rule == 2) {
 #pragma unroll
-        for (int c = 0; c < CPL; ++c) w[c] = a.Yhat[(int64_t)row * KP + g + 16 * c];
+        for (int c = 0; c < CPL; ++c) w[c] = a.Yhat[(int64_t)row * KP + col_of<LPR>(g, c)];
       } else {
         // Regularised HALS sweep over the KP columns in order.  Padded columns
         // have Ghat = identity, zero target and zero start, so they stay zero.
@@ -149,17 +172,19 @@ __global__ __launch_bounds__(16 * UPD_RPB) void k_update(UpdateArgs a, const dou
         for (int i = 0; i < KP; ++i) {
           double part = 0.0;
 #pragma unroll
-          for (int c = 0; c < CPL; ++c) part = fma(w[c], gs[i * KP + g + 16 * c], part);
-          part = row16_sum(part);
-          const int ci = i >> 4;
+          for (int c = 0; c < CPL; ++c) part = fma(w[c], gs[i * KP + col_of<LPR>(g, c)], part);
+          part = lanes_sum<LPR>(part);
+          // slot and owning lane of column i
+          const int ci = LPR == 8 ? 4 * (i >> 5) + (i & 3) : i >> 4;
+          const int own = LPR == 8 ? (i >> 2) & 7 : i & 15;
           const double cand = fmax(0.0, fma(y[ci] - part, gi[i], w[ci]));
-          w[ci] = (g == (i & 15)) ? cand : w[ci];
+          w[ci] = (g == own) ? cand : w[ci];
         }
       }
       if (a.rule != 1) {
 #pragma unroll
         for (int c = 0; c < CPL; ++c) {
-          const int q = g + 16 * c;
+          const int q = col_of<LPR>(g, c);
           const TF wt = (TF)w[c];
           if (a.dpart) {  // product part of the target (src reloaded: fewer live registers)
             const double xs = q < k ? (double)Src[rb + (q < k ? q : k - 1)] : 0.0;
@@ -177,29 +202,29 @@ __global__ __launch_bounds__(16 * UPD_RPB) void k_update(UpdateArgs a, const dou
       }
     } else {
 #pragma unroll
-      for (int c = 0; c < CPL; ++c) wl[rs * LW + g + 16 * c] = (TF)0;
+      for (int c = 0; c < CPL; ++c) wl[rs * LW + col_of<LPR>(g, c)] = (TF)0;
     }
     __syncthreads();
     // block partials of F^T F and (LAI) U^T F over this chunk (none when
     // only the right-hand side is written)
     if (a.rule != 1 && tid < 256) {  // a 16 x 16 tile of threads over all the chunk's rows
-#pragma unroll
+#pragma unroll 4
       for (int r = 0; r < RPB; ++r) {
-        double bv[CPL];
+        double bv[TCPL];
 #pragma unroll
-        for (int j = 0; j < CPL; ++j) bv[j] = (double)wl[r * LW + tx + 16 * j];
+        for (int j = 0; j < TCPL; ++j) bv[j] = (double)wl[r * LW + tx + 16 * j];
 #pragma unroll
-        for (int i = 0; i < CPL; ++i) {
+        for (int i = 0; i < TCPL; ++i) {
           const double av = (double)wl[r * LW + ty + 16 * i];
 #pragma unroll
-          for (int j = 0; j < CPL; ++j) gacc[i][j] = fma(av, bv[j], gacc[i][j]);
+          for (int j = 0; j < TCPL; ++j) gacc[i][j] = fma(av, bv[j], gacc[i][j]);
         }
         if (LP > 0) {
 #pragma unroll
           for (int i = 0; i < ZI; ++i) {
             const double uv = (double)us[r * LU + ty + 16 * i];
 #pragma unroll
-            for (int j = 0; j < CPL; ++j) zacc[i][j] = fma(uv, bv[j], zacc[i][j]);
+            for (int j = 0; j < TCPL; ++j) zacc[i][j] = fma(uv, bv[j], zacc[i][j]);
           }
         }
       }
@@ -210,9 +235,9 @@ __global__ __launch_bounds__(16 * UPD_RPB) void k_update(UpdateArgs a, const dou
   // unified partial row of this block: [F^T F (k x k) | U^T F (l x k)]
   double* gp = a.part + (int64_t)blockIdx.x * a.pstride;
 #pragma unroll
-  for (int i = 0; i < CPL; ++i)
+  for (int i = 0; i < TCPL; ++i)
 #pragma unroll
-    for (int j = 0; j < CPL; ++j) {
+    for (int j = 0; j < TCPL; ++j) {
       const int p = ty + 16 * i, q = tx + 16 * j;
       if (tid < 256 && p < k && q < k) gp[p * k + q] = gacc[i][j];
     }
@@ -221,7 +246,7 @@ __global__ __launch_bounds__(16 * UPD_RPB) void k_update(UpdateArgs a, const dou
 #pragma unroll
     for (int i = 0; i < ZI; ++i)
 #pragma unroll
-      for (int j = 0; j < CPL; ++j) {
+      for (int j = 0; j < TCPL; ++j) {
         const int p = ty + 16 * i, q = tx + 16 * j;
         if (p < l && q < k) zp[p * k + q] = zacc[i][j];
       }
@@ -303,17 +328,31 @@ __global__ __launch_bounds__(256) void k_pad_identity(double* __restrict__ Ghat,
   if (Ginv && e < kp && e >= k) Ginv[e] = 1.0;
 }
 
-template <int KP, int LP, typename TF, typename TP, typename TT, int YMODE>
-int launch_update(const UpdateArgs& a, const UpdateRO& ro, int nb, const DevState* st, hipStream_t s) {
-  const size_t lds = 8 * (size_t)KP * (KP + 1 + LP) + sizeof(TF) * UPD_RPB * ((KP + 1) + (LP > 0 ? LP + 1 : 0));
-  auto kern = k_update<KP, LP, TF, TP, TT, YMODE>;
+template <int KP, int LP, typename TF, typename TP, typename TT, int YMODE, int LPR>
+int launch_update_lpr(const UpdateArgs& a, const UpdateRO& ro, int nb, const DevState* st, hipStream_t s) {
+  constexpr int RPB = 16 * UPD_RPB / LPR;
+  const size_t lds = 8 * (size_t)KP * (KP + 1 + LP) + sizeof(TF) * RPB * ((KP + 1) + (LP > 0 ? LP + 1 : 0));
+  auto kern = k_update<KP, LP, TF, TP, TT, YMODE, LPR>;
   if (lds > 65536 &&
       hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
     return -1;
   // exactly nb blocks (the reduction reads nb partials); rows beyond
-  // 16 * nb are covered by the grid-stride loop
+  // RPB * nb are covered by the grid-stride loop
   kern<<<nb, 16 * UPD_RPB, lds, s>>>(a, ro.Ghat, ro.Ginv, ro.M, (const TF*)a.Src, st);
   return 0;
+}
+
+// 8 lanes per row (64-row chunks) for the right-hand sides from the product
+// or the sampled slab once every one of the 512 blocks has a full chunk
+// (the block count is then 512 with either layout) and KP is a multiple of 32.
+constexpr int LPR8_MIN_ROWS = 512 * 64;
+
+template <int KP, int LP, typename TF, typename TP, typename TT, int YMODE>
+int launch_update(const UpdateArgs& a, const UpdateRO& ro, int nb, const DevState* st, hipStream_t s) {
+  if constexpr (LP == 0 && KP % 32 == 0) {
+    if (a.n >= LPR8_MIN_ROWS) return launch_update_lpr<KP, LP, TF, TP, TT, YMODE, 8>(a, ro, nb, st, s);
+  }
+  return launch_update_lpr<KP, LP, TF, TP, TT, YMODE, 16>(a, ro, nb, st, s);
 }
 
 template <int KP, typename TF, typename TP, typename TT>

@@ -141,10 +141,12 @@ def test_lvs_tau_zero_matches_plain():
 
 @pytest.mark.parametrize("case", [(66_001, 64, 0, np.float32), (66_001, 64, 6000, np.float32),
                                   (65_600, 10, 0, np.float32), (65_600, 40, 3000, np.float32),
-                                  (65_551, 33, 0, np.float64), (65_551, 64, 4000, np.float64)])
+                                  (65_551, 33, 0, np.float64), (65_551, 64, 4000, np.float64),
+                                  (40_003, 32, 0, np.float32), (40_003, 20, 3000, np.float32)])
 def test_long_factor_half_step(case):
-    # n >= 65536: every one of the update's blocks walks several row chunks
-    # (grid stride) and n is ragged against the chunk; every padded width
+    # long factors: every one of the update's blocks walks several row chunks
+    # (grid stride), the 8-lanes-per-row layout where the padded width is a
+    # multiple of 32, and n is ragged against the chunk; every padded width
     n, k, s, vt = case
     log(f"long factor half step n={n} k={k} s={s} {np.dtype(vt).name}")
     X = _sbm(n, 32, 16.0, seed=n + k)
