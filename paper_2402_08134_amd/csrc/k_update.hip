@@ -342,15 +342,10 @@ int launch_update_lpr(const UpdateArgs& a, const UpdateRO& ro, int nb, const Dev
   return 0;
 }
 
-// 8 lanes per row (64-row chunks) for the right-hand sides from the product
-// or the sampled slab once every one of the 512 blocks has a full chunk
-// (the block count is then 512 with either layout) and KP is a multiple of 32.
-constexpr int LPR8_MIN_ROWS = 512 * 64;
-
 template <int KP, int LP, typename TF, typename TP, typename TT, int YMODE>
 int launch_update(const UpdateArgs& a, const UpdateRO& ro, int nb, const DevState* st, hipStream_t s) {
-  if constexpr (LP == 0 && KP % 32 == 0) {
-    if (a.n >= LPR8_MIN_ROWS) return launch_update_lpr<KP, LP, TF, TP, TT, YMODE, 8>(a, ro, nb, st, s);
+  if constexpr (KP % 32 == 0) {
+    if (update_lpr8(a.n, KP, LP, sizeof(TF))) return launch_update_lpr<KP, LP, TF, TP, TT, YMODE, 8>(a, ro, nb, st, s);
   }
   return launch_update_lpr<KP, LP, TF, TP, TT, YMODE, 16>(a, ro, nb, st, s);
 }
@@ -385,13 +380,27 @@ int dispatch_kp(const UpdateArgs& a, const UpdateRO& ro, int kp, int ymode, int 
 
 }  // namespace
 
-// At most 512 blocks (grid-stride beyond 512 chunks): measured at n = 16384
-// against 128, 256, 768 and 1024, it is the fastest update plus partial-sum
-// reduction (fewer partial rows to reduce, enough waves).
-int update_blocks(int n, int fdtype) {
-  (void)fdtype;
-  return std::max(1, std::min(512, ceil_div(n, UPD_RPB)));
+// 8 lanes per row (64-row chunks) where the padded width is a multiple of
+// 32 and the staging fits in LDS: for the LAI right-hand side at any n (LAI
+// iteration at n = 16384, k = 32, l = 48: 56.6 -> 49.9 us, with 256 blocks of
+// 64 rows), for the product or the sampled slab once every one of the 512
+// blocks has a full chunk (the block count is then 512 with either layout).
+bool update_lpr8(int n, int kp, int lp, int tf_bytes) {
+  if (kp % 32 != 0) return false;
+  const size_t lds = 8 * (size_t)kp * (kp + 1 + lp) + (size_t)tf_bytes * 64 * ((kp + 1) + (lp > 0 ? lp + 1 : 0));
+  if (lds > (size_t)160 * 1024) return false;
+  return lp > 0 || n >= 512 * 64;
 }
+
+// One block per chunk, at most 512 (grid-stride beyond 512 chunks): with
+// 16 lanes per row, measured at n = 16384 against 128, 256, 768 and 1024, it
+// is the fastest update plus partial-sum reduction.  lp: padded l (LAI), else 0.
+int update_blocks(int n, int kp, int lp, int fdtype) {
+  const int rpb = update_lpr8(n, kp, lp, fdtype == SYMNMF_F64 ? 8 : 4) ? 2 * UPD_RPB : UPD_RPB;
+  return std::max(1, std::min(512, ceil_div(n, rpb)));
+}
+
+int update_blocks_max(int n) { return std::max(1, std::min(512, ceil_div(n, UPD_RPB))); }
 
 int fused_update(const UpdateArgs& a, const UpdateRO& ro, int kp, int ymode, int fdtype, int pdtype, int tdtype,
                  int nb, const DevState* st, hipStream_t s) {

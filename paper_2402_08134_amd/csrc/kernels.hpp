@@ -147,7 +147,11 @@ struct UpdateRO {
   const double* Ginv = nullptr;  // kp reciprocals of diag(Ghat)
   const double* M = nullptr;     // YMODE 2
 };
-int update_blocks(int n, int fdtype);
+// Blocks of the fused update for n rows, padded width kp and padded LAI
+// width lp (0 without LAI); update_blocks_max(n) bounds it over every mode.
+int update_blocks(int n, int kp, int lp, int fdtype);
+int update_blocks_max(int n);
+bool update_lpr8(int n, int kp, int lp, int tf_bytes);
 // pdtype: element type of P (F32 or F64); tdtype: element type of Dt.
 int fused_update(const UpdateArgs& a, const UpdateRO& ro, int kp, int ymode, int fdtype, int pdtype, int tdtype,
                  int nb, const DevState* st, hipStream_t s);

@@ -220,7 +220,8 @@ struct symnmf_ctx {
   double* part = nullptr;   // fused-update block partials (nbu x pcap)
   size_t pcap = 0;          // doubles per partial row
   double* dpart = nullptr;
-  int nbu = 1;              // blocks of the fused update
+  int nbu = 1;              // capacity in blocks of the fused update's partials
+  int nb_dot = 1;           // blocks of the update that wrote dpart last
   double *M_W = nullptr, *M_H = nullptr;  // LAI: Lambda U^T W, Lambda U^T H
   bool mW_ok = false, mH_ok = false;
   double *G_W = nullptr, *G_H = nullptr, *Gh_W = nullptr, *Gh_H = nullptr, *Gh_S = nullptr;
@@ -613,14 +614,16 @@ struct symnmf_ctx {
       a.splits = 1;
       a.cp = kp;
     }
+    const int nb = update_blocks(n, kp, ymode == 2 ? 16 * ceil_div(l, 16) : 0, fdtype);
+    if (want_dot) nb_dot = nb;
     if (opt.rule == SYMNMF_RULE_HALS) {
       Timed tm(this, SYMNMF_PHASE_UPDATE);
       UpdateRO ro;
       ro.Ghat = a.Ghat;
       ro.Ginv = Gis;
       ro.M = a.M;
-      LCHK(fused_update(a, ro, kp, ymode, fdtype, pdt, tdt, nbu, gate_, st));
-      LCHK(update_reduce(part, nbu, a.pstride, k, l, kp, alpha, lam, Gd, Ghd, Gid,
+      LCHK(fused_update(a, ro, kp, ymode, fdtype, pdt, tdt, nb, gate_, st));
+      LCHK(update_reduce(part, nb, a.pstride, k, l, kp, alpha, lam, Gd, Ghd, Gid,
                          side == 0 ? M_W : M_H, gate_, st));
     } else {
       // BPP: the update kernel writes the right-hand sides, the pivoting
@@ -633,11 +636,11 @@ struct symnmf_ctx {
       ro.M = a.M;
       a.Yhat = Yhat;
       a.rule = 1;
-      LCHK(fused_update(a, ro, kp, ymode, fdtype, pdt, tdt, nbu, gate_, st));
+      LCHK(fused_update(a, ro, kp, ymode, fdtype, pdt, tdt, nb, gate_, st));
       LCHK(bpp_update(n, k, kp, Yhat, Dst, fdtype, a.Ghat, &dstate->flags, SYMNMF_FLAG_BPP_CAP, gate_, st));
       a.rule = 2;
-      LCHK(fused_update(a, ro, kp, ymode, fdtype, pdt, tdt, nbu, gate_, st));
-      LCHK(update_reduce(part, nbu, a.pstride, k, l, kp, alpha, lam, Gd, Ghd, Gid,
+      LCHK(fused_update(a, ro, kp, ymode, fdtype, pdt, tdt, nb, gate_, st));
+      LCHK(update_reduce(part, nb, a.pstride, k, l, kp, alpha, lam, Gd, Ghd, Gid,
                          side == 0 ? M_W : M_H, gate_, st));
     }
     invalidate(dst_id);
@@ -755,7 +758,7 @@ struct symnmf_ctx {
     }
     half_step(0, 2 * t, false);
     half_step(1, 2 * t + 1, true);
-    finish_iteration(dpart, nbu, G_W, G_H, k, nrm, dstate, hist, rule(), st);
+    finish_iteration(dpart, nb_dot, G_W, G_H, k, nrm, dstate, hist, rule(), st);
   }
 
   DevState read_state() {
@@ -1099,7 +1102,7 @@ int symnmf_create(symnmf_ctx** out, const symnmf_matrix* X, int32_t k, double al
     c->Gh_H = dalloc<double>((size_t)c->kp * c->kp);
     c->Gh_S = dalloc<double>((size_t)c->kp * c->kp);
     c->d_scal = dalloc<double>(16);
-    c->nbu = update_blocks(n, c->fdtype);
+    c->nbu = update_blocks_max(n);
     c->pcap = (size_t)k * k;
     c->part = dalloc<double>((size_t)c->nbu * c->pcap);
     c->dpart = dalloc<double>(c->nbu);
