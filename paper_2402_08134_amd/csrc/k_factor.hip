@@ -414,16 +414,18 @@ __global__ __launch_bounds__(64) void k_chol_regs(const double* __restrict__ G, 
   double x[KM];
 #pragma unroll
   for (int c = 0; c < KM; ++c) x[c] = c == r ? 1.0 : 0.0;
+  // per step one scale and one multiplier per lane instead of a select per
+  // entry: lane t scales its row by 1 / L[t][t] (the others by 1, exactly),
+  // rows below t subtract L[r][t] times row t (the others 0, exactly)
 #pragma unroll
   for (int t = 0; t < KM; ++t) {
     const double rt = 1.0 / lane_value(a[t], t);
+    const double sc = r == t ? rt : 1.0;
+    const double mt = r > t ? a[t] : 0.0;
 #pragma unroll
-    for (int c = 0; c <= t; ++c) x[c] = r == t ? x[c] * rt : x[c];
+    for (int c = 0; c <= t; ++c) x[c] *= sc;
 #pragma unroll
-    for (int c = 0; c <= t; ++c) {
-      const double xt = lane_value(x[c], t);
-      x[c] = r > t ? fma(-a[t], xt, x[c]) : x[c];
-    }
+    for (int c = 0; c <= t; ++c) x[c] = fma(-mt, lane_value(x[c], t), x[c]);
   }
   // R^{-1} = (L^{-1})^T: Rinv[c][r] = X[r][c]
   if (act) {
