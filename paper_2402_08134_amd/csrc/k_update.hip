@@ -84,7 +84,9 @@ __global__ __launch_bounds__(16 * UPD_RPB) void k_update(UpdateArgs a, const dou
   __shared__ double sc[8];
   const int tid = threadIdx.x;
   const int g = tid % LPR, rs = tid / LPR;     // lane in row, row slot
-  const int tx = tid & 15, ty = tid >> 4;      // Gram / U^T F tile coordinates
+  // Gram / U^T F tile: two 16 x 16 tiles of threads, each over half of the
+  // chunk's rows, added together at the end
+  const int th = tid >> 8, tx = tid & 15, ty = (tid & 255) >> 4;
   const int n = a.n, k = a.k, l = a.l;
   TF* __restrict__ Dst = (TF*)a.Dst;
   const double alpha = a.alpha;
@@ -207,9 +209,10 @@ __global__ __launch_bounds__(16 * UPD_RPB) void k_update(UpdateArgs a, const dou
     __syncthreads();
     // block partials of F^T F and (LAI) U^T F over this chunk (none when
     // only the right-hand side is written)
-    if (a.rule != 1 && tid < 256) {  // a 16 x 16 tile of threads over all the chunk's rows
+    if (a.rule != 1) {
 #pragma unroll 4
-      for (int r = 0; r < RPB; ++r) {
+      for (int rr = 0; rr < RPB / 2; ++rr) {
+        const int r = th * (RPB / 2) + rr;
         double bv[TCPL];
 #pragma unroll
         for (int j = 0; j < TCPL; ++j) bv[j] = (double)wl[r * LW + tx + 16 * j];
@@ -232,6 +235,37 @@ __global__ __launch_bounds__(16 * UPD_RPB) void k_update(UpdateArgs a, const dou
     __syncthreads();
   }
   if (a.rule == 1) return;
+  // the second tile's sums onto the first's, through the staging area (free
+  // now: it holds at least KP (KP + LP) doubles, the size of both tiles)
+  {
+    double* cmb = reinterpret_cast<double*>(smem);
+    const int t8 = tid & 255;
+    if (th == 1) {
+#pragma unroll
+      for (int i = 0; i < TCPL; ++i)
+#pragma unroll
+        for (int j = 0; j < TCPL; ++j) cmb[(i * TCPL + j) * 256 + t8] = gacc[i][j];
+      if (LP > 0) {
+#pragma unroll
+        for (int i = 0; i < ZI; ++i)
+#pragma unroll
+          for (int j = 0; j < TCPL; ++j) cmb[(TCPL * TCPL + i * TCPL + j) * 256 + t8] = zacc[i][j];
+      }
+    }
+    __syncthreads();
+    if (th == 0) {
+#pragma unroll
+      for (int i = 0; i < TCPL; ++i)
+#pragma unroll
+        for (int j = 0; j < TCPL; ++j) gacc[i][j] += cmb[(i * TCPL + j) * 256 + t8];
+      if (LP > 0) {
+#pragma unroll
+        for (int i = 0; i < ZI; ++i)
+#pragma unroll
+          for (int j = 0; j < TCPL; ++j) zacc[i][j] += cmb[(TCPL * TCPL + i * TCPL + j) * 256 + t8];
+      }
+    }
+  }
   // unified partial row of this block: [F^T F (k x k) | U^T F (l x k)]
   double* gp = a.part + (int64_t)blockIdx.x * a.pstride;
 #pragma unroll
