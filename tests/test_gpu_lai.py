@@ -61,6 +61,33 @@ def test_lai_parity(dtype, compute):
     assert abs(re[0] - ro) / ro <= rtol
 
 
+@pytest.mark.parametrize("case", [(1500, 32, 48, "f32"), (1500, 64, 80, "f32"), (1333, 30, 46, "f64"),
+                                  (1333, 64, 96, "f64"), (1100, 40, 56, "f32")])
+def test_lai_wide_parity(case):
+    # wider factors and bases: padded widths 32 and 64 take the update layout
+    # with 8 lanes per row and 64-row chunks (n ragged against the chunk);
+    # k = 64 with l = 96 in FP64 (staging too large for LDS) and width 48
+    # keep 16 lanes per row
+    n, k, l, dtype = case
+    log(f"lai wide n={n} k={k} l={l} {dtype}")
+    q, seed, iters = 1, 3, 10
+    X, _ = workloads.gaussian_kernel(n, 2 * k, k, seed=k + l, dtype=np.float64)
+    tdt = torch.float64 if dtype == "f64" else torch.float32
+    ctx = P.symnmf_create(dev(X, tdt), k, 0.0, 0, seed)
+    P.symnmf_lai(ctx, l, q)
+    P.symnmf_iterate(ctx, iters)
+    Xo = round_to(X, tdt)
+    Uo, lo = O.apx_evd(lambda M: O.apply_x(Xo, M), O.sketch_omega(n, l, seed), q)
+    sc = O.data_scalars(Xo)
+    H0 = round_to(O.initial_factor(n, k, sc["zeta"], seed), tdt)
+    Wo, Ho, hist = O.lai_symnmf(Uo, lo, k, sc["maxval"], H0, iters)
+    hg = np.array(P.symnmf_history(ctx))
+    rtol = 1e-8 if dtype == "f64" else 1e-4
+    log(f"   history max rel {np.max(np.abs(hg - hist) / hist):.2e}, H rel {rel(factor(ctx, P.H), Ho):.2e}")
+    assert np.max(np.abs(hg - hist) / hist) <= rtol
+    assert rel(factor(ctx, P.H), Ho) <= (1e-6 if dtype == "f64" else 1e-2)
+
+
 def test_lai_exact_low_rank_input():
     # X of rank r <= l: the LAI reproduces X, so the LAI residual against
     # U Lambda U^T equals the residual against X.
