@@ -27,8 +27,9 @@ The timed solves replay their iterations from HIP graphs and record no
 events.  A second pass runs each method once more with HIP events around
 every phase's launches (eager launches): it gives the per-phase device time
 and the live roofline of the dominant kernel (the X H product).  Also
-reported: the FP64 CPU oracle timed on a bounded sample on the host cores.  `--pmc-probe` runs the short fixed workload the rocprofv3
-counter passes are taken on.
+reported: the FP64 CPU oracle timed on a bounded sample on the host cores.
+`--pmc-probe` runs the short fixed workload the rocprofv3 counter passes are
+taken on (with `--workload sparse`: the CSR product's).
 """
 import argparse
 import json
@@ -73,15 +74,17 @@ def main():
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(run with --gpus 1)", file=sys.stderr)
         sys.exit(2)
+    if args.pmc_probe:
+        if args.workload == "sparse":
+            pmc_probe_sparse(args)
+        else:
+            pmc_probe(args)
+        return
     if args.workload == "sparse":
         bench_sparse(args)
         return
     if args.workload == "precision":
         bench_precision(args)
-        return
-
-    if args.pmc_probe:
-        pmc_probe(args)
         return
 
     import numpy as np
@@ -527,6 +530,37 @@ def pmc_probe(args):
     P.symnmf_iterate(c, 10)
     torch.cuda.synchronize()
     log("[pmc-probe] 10 plain iterations done")
+
+
+def pmc_probe_sparse(args):
+    """Counter-collection workload for the CSR product: the SBM of the sparse
+    bench, three 1 GiB device copies (the calibration kernel of known
+    traffic), then three plain HALS iterations with the FP32 product and three
+    with BF16 gathers of the factor rows."""
+    import numpy as np
+    import torch
+    import paper_2402_08134_amd as P
+    import workloads
+    n, k = args.sparse_n, args.sparse_k
+    Xs, _ = workloads.sbm(n, 64, 32.0, 20.0, seed=0)
+    Xd = (torch.from_numpy(Xs.indptr.astype(np.int32)).cuda(), torch.from_numpy(Xs.indices.astype(np.int32)).cuda(),
+          torch.from_numpy(Xs.data.astype(np.float32)).cuda(), n)
+    a = torch.empty(1 << 28, dtype=torch.float32, device="cuda").fill_(1.0)
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    log("[pmc-probe] copies done (3 x 1 GiB read + 1 GiB write)")
+    for bf in (False, True):
+        o = P.symnmf_default_options(resid_every=100)
+        if bf:
+            o.compute_dtype = P.BF16
+        c = P.symnmf_create(Xd, k, 0.0, 0, 1, o)
+        P.symnmf_iterate(c, 3)
+        torch.cuda.synchronize()
+        log(f"[pmc-probe] 3 plain iterations done ({'BF16' if bf else 'FP32'} gathers)")
+        del c
 
 
 def cpu_baseline(Xh, k, iters_gpu):
