@@ -172,9 +172,14 @@ __global__ __launch_bounds__(16 * UPD_RPB) void k_update(UpdateArgs a, const dou
         // have Ghat = identity, zero target and zero start, so they stay zero.
 #pragma unroll
         for (int i = 0; i < KP; ++i) {
+          // slot changed by column i - 1 goes last: the other terms of the
+          // dot product do not wait for that column's result
+          const int cp = i == 0 ? -1 : (LPR == 8 ? 4 * ((i - 1) >> 5) + ((i - 1) & 3) : (i - 1) >> 4);
           double part = 0.0;
 #pragma unroll
-          for (int c = 0; c < CPL; ++c) part = fma(w[c], gs[i * KP + col_of<LPR>(g, c)], part);
+          for (int c = 0; c < CPL; ++c)
+            if (c != cp) part = fma(w[c], gs[i * KP + col_of<LPR>(g, c)], part);
+          if (cp >= 0) part = fma(w[cp], gs[i * KP + col_of<LPR>(g, cp)], part);
           part = lanes_sum<LPR>(part);
           // slot and owning lane of column i
           const int ci = LPR == 8 ? 4 * (i >> 5) + (i & 3) : i >> 4;
