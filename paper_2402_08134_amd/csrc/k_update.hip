@@ -64,8 +64,15 @@ __device__ __forceinline__ double lanes_sum(double v) {
 // row), 512 threads per block.  Lane g of a row owns the KP / LPR columns
 // col_of(g, c).  The HALS sweep over column i sums w_q Ghat[i][q] over the
 // row's lanes and the lane owning column i applies the update.
+// Waves per SIMD the register allocation must leave room for: the long-factor
+// update without a LAI term (KP = 64) otherwise takes more than 128 VGPRs and
+// runs one 512-thread block per CU.
+template <int KP, int LP>
+constexpr int upd_waves() { return KP == 64 && LP == 0 ? 4 : 1; }
+
 template <int KP, int LP, typename TF, typename TP, typename TT, int YMODE, int LPR>
-__global__ __launch_bounds__(16 * UPD_RPB) void k_update(UpdateArgs a, const double* __restrict__ Gh,
+__global__ __launch_bounds__(16 * UPD_RPB) __attribute__((amdgpu_waves_per_eu(upd_waves<KP, LP>())))
+void k_update(UpdateArgs a, const double* __restrict__ Gh,
                                                 const double* __restrict__ Ginv, const double* __restrict__ M,
                                                 const TF* __restrict__ Src, const DevState* __restrict__ st) {
   if (stopped(st)) return;
@@ -90,6 +97,22 @@ __global__ __launch_bounds__(16 * UPD_RPB) void k_update(UpdateArgs a, const dou
   const int n = a.n, k = a.k, l = a.l;
   TF* __restrict__ Dst = (TF*)a.Dst;
   const double alpha = a.alpha;
+  // LAI: this thread's share of a chunk's U rows, held in registers; the
+  // first chunk's loads are issued with the staging loads below and each
+  // next chunk's while the current one is processed.  Clamped index, masked
+  // value: every load stays inside U.
+  constexpr int UPT = LP > 0 ? (RPB * LP + NTH - 1) / NTH : 1;
+  TF ureg[UPT];
+  auto load_u = [&](int b) {
+#pragma unroll
+    for (int t = 0; t < UPT; ++t) {
+      const int e = tid + t * NTH, r = e / l, p = e - r * l;
+      const bool ok = e < RPB * l && b + r < n;
+      const TF v = (TF)a.U[ok ? (int64_t)(b + r) * l + p : 0];
+      ureg[t] = ok ? v : (TF)0;
+    }
+  };
+  if (LP > 0 && l > 0) load_u(blockIdx.x * RPB);
   for (int e = tid; e < KP * KP; e += NTH) gs[e] = Gh[e];
   for (int e = tid; e < KP; e += NTH) gi[e] = Ginv[e];
   if (LP > 0)
@@ -111,15 +134,30 @@ __global__ __launch_bounds__(16 * UPD_RPB) void k_update(UpdateArgs a, const dou
   for (int base = blockIdx.x * RPB; base < n; base += gridDim.x * RPB) {
     const int row = base + rs;
     if (LP > 0) {
-      for (int e = tid; e < RPB * l; e += NTH) {
-        const int r = e / l, p = e - r * l;
-        us[r * LU + p] = (base + r < n) ? (TF)a.U[(int64_t)(base + r) * l + p] : (TF)0;
+#pragma unroll
+      for (int t = 0; t < UPT; ++t) {
+        const int e = tid + t * NTH;
+        if (e < RPB * l) {
+          const int r = e / l, p = e - r * l;
+          us[r * LU + p] = ureg[t];
+        }
       }
       __syncthreads();
+      if (l > 0 && base + gridDim.x * RPB < n) load_u(base + gridDim.x * RPB);
     }
     if (row < n) {
       const int64_t rb = (int64_t)row * k;
       double y[CPL], w[CPL];
+      // this row's old factor and the source of the alpha term, issued
+      // before the right-hand side so their latency overlaps it
+      TF xs_r[CPL], xd_r[CPL];
+#pragma unroll
+      for (int c = 0; c < CPL; ++c) {
+        const int q = col_of<LPR>(g, c);
+        const int qc = q < k ? q : k - 1;
+        xs_r[c] = Src[rb + qc];
+        xd_r[c] = Dst[rb + qc];
+      }
 #pragma unroll
       for (int c = 0; c < CPL; ++c) y[c] = 0.0;
       // Loads are never guarded by a branch (a branch per element makes the
@@ -155,9 +193,8 @@ __global__ __launch_bounds__(16 * UPD_RPB) void k_update(UpdateArgs a, const dou
 #pragma unroll
       for (int c = 0; c < CPL; ++c) {
         const int q = col_of<LPR>(g, c);
-        const int qc = q < k ? q : k - 1;
-        const double xs = (double)Src[rb + qc];
-        const double xd = (double)Dst[rb + qc];
+        const double xs = (double)xs_r[c];
+        const double xd = (double)xd_r[c];
         w[c] = q < k ? xd : 0.0;
         y[c] = fma(alpha, q < k ? xs : 0.0, y[c]);   // HALS target y + alpha src
       }
