@@ -59,17 +59,17 @@ __device__ __forceinline__ double lanes_sum(double v) {
   return row16_sum(v);
 }
 
-// LPR lanes per row (16, or 8 for long factors with KP a multiple of 32:
-// three DPP steps per column sum instead of four and half as many lanes per
-// row), 512 threads per block.  Lane g of a row owns the KP / LPR columns
-// col_of(g, c).  The HALS sweep over column i sums w_q Ghat[i][q] over the
-// row's lanes and the lane owning column i applies the update.
 // Waves per SIMD the register allocation must leave room for: the long-factor
 // update without a LAI term (KP = 64) otherwise takes more than 128 VGPRs and
 // runs one 512-thread block per CU.
 template <int KP, int LP>
 constexpr int upd_waves() { return KP == 64 && LP == 0 ? 4 : 1; }
 
+// LPR lanes per row (16, or 8 for long factors with KP a multiple of 32:
+// three DPP steps per column sum instead of four and half as many lanes per
+// row), 512 threads per block.  Lane g of a row owns the KP / LPR columns
+// col_of(g, c).  The HALS sweep over column i sums w_q Ghat[i][q] over the
+// row's lanes and the lane owning column i applies the update.
 template <int KP, int LP, typename TF, typename TP, typename TT, int YMODE, int LPR>
 __global__ __launch_bounds__(16 * UPD_RPB) __attribute__((amdgpu_waves_per_eu(upd_waves<KP, LP>())))
 void k_update(UpdateArgs a, const double* __restrict__ Gh,
@@ -97,11 +97,17 @@ void k_update(UpdateArgs a, const double* __restrict__ Gh,
   const int n = a.n, k = a.k, l = a.l;
   TF* __restrict__ Dst = (TF*)a.Dst;
   const double alpha = a.alpha;
-  // LAI: this thread's share of a chunk's U rows, held in registers; the
-  // first chunk's loads are issued with the staging loads below and each
-  // next chunk's while the current one is processed.  Clamped index, masked
-  // value: every load stays inside U.
-  constexpr int UPT = LP > 0 ? (RPB * LP + NTH - 1) / NTH : 1;
+  // LAI with KP <= 32: this thread's share of a chunk's U rows, held in
+  // registers; the first chunk's loads are issued with the staging loads
+  // below and each next chunk's while the current one is processed.  Clamped
+  // index, masked value: every load stays inside U.  The factor rows of the
+  // HALS target are likewise loaded before the right-hand side (EARLY).  At
+  // KP = 64 with a LAI term the extra live registers made the kernel slower
+  // (127 -> 155 us at n = 65536, l = 80), so there the loads stay where they
+  // are used.
+  constexpr bool UREG = LP > 0 && KP <= 32;
+  constexpr bool EARLY = LP == 0 || KP <= 32;
+  constexpr int UPT = UREG ? (RPB * LP + NTH - 1) / NTH : 1;
   TF ureg[UPT];
   auto load_u = [&](int b) {
 #pragma unroll
@@ -112,7 +118,7 @@ void k_update(UpdateArgs a, const double* __restrict__ Gh,
       ureg[t] = ok ? v : (TF)0;
     }
   };
-  if (LP > 0 && l > 0) load_u(blockIdx.x * RPB);
+  if (UREG && l > 0) load_u(blockIdx.x * RPB);
   for (int e = tid; e < KP * KP; e += NTH) gs[e] = Gh[e];
   for (int e = tid; e < KP; e += NTH) gi[e] = Ginv[e];
   if (LP > 0)
@@ -134,16 +140,23 @@ void k_update(UpdateArgs a, const double* __restrict__ Gh,
   for (int base = blockIdx.x * RPB; base < n; base += gridDim.x * RPB) {
     const int row = base + rs;
     if (LP > 0) {
+      if (UREG) {
 #pragma unroll
-      for (int t = 0; t < UPT; ++t) {
-        const int e = tid + t * NTH;
-        if (e < RPB * l) {
+        for (int t = 0; t < UPT; ++t) {
+          const int e = tid + t * NTH;
+          if (e < RPB * l) {
+            const int r = e / l, p = e - r * l;
+            us[r * LU + p] = ureg[t];
+          }
+        }
+      } else {
+        for (int e = tid; e < RPB * l; e += NTH) {
           const int r = e / l, p = e - r * l;
-          us[r * LU + p] = ureg[t];
+          us[r * LU + p] = (base + r < n) ? (TF)a.U[(int64_t)(base + r) * l + p] : (TF)0;
         }
       }
       __syncthreads();
-      if (l > 0 && base + gridDim.x * RPB < n) load_u(base + gridDim.x * RPB);
+      if (UREG && l > 0 && base + gridDim.x * RPB < n) load_u(base + gridDim.x * RPB);
     }
     if (row < n) {
       const int64_t rb = (int64_t)row * k;
@@ -151,12 +164,14 @@ void k_update(UpdateArgs a, const double* __restrict__ Gh,
       // this row's old factor and the source of the alpha term, issued
       // before the right-hand side so their latency overlaps it
       TF xs_r[CPL], xd_r[CPL];
+      if (EARLY) {
 #pragma unroll
-      for (int c = 0; c < CPL; ++c) {
-        const int q = col_of<LPR>(g, c);
-        const int qc = q < k ? q : k - 1;
-        xs_r[c] = Src[rb + qc];
-        xd_r[c] = Dst[rb + qc];
+        for (int c = 0; c < CPL; ++c) {
+          const int q = col_of<LPR>(g, c);
+          const int qc = q < k ? q : k - 1;
+          xs_r[c] = Src[rb + qc];
+          xd_r[c] = Dst[rb + qc];
+        }
       }
 #pragma unroll
       for (int c = 0; c < CPL; ++c) y[c] = 0.0;
@@ -193,8 +208,9 @@ void k_update(UpdateArgs a, const double* __restrict__ Gh,
 #pragma unroll
       for (int c = 0; c < CPL; ++c) {
         const int q = col_of<LPR>(g, c);
-        const double xs = (double)xs_r[c];
-        const double xd = (double)xd_r[c];
+        const int qc = q < k ? q : k - 1;
+        const double xs = EARLY ? (double)xs_r[c] : (double)Src[rb + qc];
+        const double xd = EARLY ? (double)xd_r[c] : (double)Dst[rb + qc];
         w[c] = q < k ? xd : 0.0;
         y[c] = fma(alpha, q < k ? xs : 0.0, y[c]);   // HALS target y + alpha src
       }
