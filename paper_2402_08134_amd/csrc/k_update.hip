@@ -125,6 +125,13 @@ void k_update(UpdateArgs a, const double* __restrict__ Gh,
     for (int e = tid; e < l * KP; e += NTH) ms[e] = M[e];
   __syncthreads();
 
+  // Without a LAI term at KP = 64 the Gram partial runs on the FP64 matrix
+  // cores: wave w accumulates the 16 x 16 tiles (w / 2, 2 (w % 2)) and
+  // (w / 2, 2 (w % 2) + 1) of F^T F, four chunk rows per instruction.
+  constexpr bool GMF = LP == 0 && KP == 64;
+  doublex4 gm[2];
+  gm[0] = doublex4{0.0, 0.0, 0.0, 0.0};
+  gm[1] = gm[0];
   double gacc[TCPL][TCPL];
   double zacc[ZI][TCPL];
 #pragma unroll
@@ -267,7 +274,19 @@ void k_update(UpdateArgs a, const double* __restrict__ Gh,
     __syncthreads();
     // block partials of F^T F and (LAI) U^T F over this chunk (none when
     // only the right-hand side is written)
-    if (a.rule != 1) {
+    if (GMF && a.rule != 1) {
+      // lane l supplies A[l % 16][l / 16] = F[r0 + l / 16][16 (w / 2) + l % 16]
+      // and B[l / 16][l % 16] = F[r0 + l / 16][16 tb + l % 16]
+      const int wid = tid >> 6, li = tid & 15, lg = (tid & 63) >> 4;
+      const int ca = 16 * (wid >> 1) + li, cb = 32 * (wid & 1) + li;
+#pragma unroll 4
+      for (int s4 = 0; s4 < RPB / 4; ++s4) {
+        const TF* wr = wl + (4 * s4 + lg) * LW;
+        const double av = (double)wr[ca];
+        gm[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, (double)wr[cb], gm[0], 0, 0, 0);
+        gm[1] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, (double)wr[cb + 16], gm[1], 0, 0, 0);
+      }
+    } else if (a.rule != 1) {
 #pragma unroll 4
       for (int rr = 0; rr < RPB / 2; ++rr) {
         const int r = th * (RPB / 2) + rr;
@@ -295,7 +314,7 @@ void k_update(UpdateArgs a, const double* __restrict__ Gh,
   if (a.rule == 1) return;
   // the second tile's sums onto the first's, through the staging area (free
   // now: it holds at least KP (KP + LP) doubles, the size of both tiles)
-  {
+  if (!GMF) {
     double* cmb = reinterpret_cast<double*>(smem);
     const int t8 = tid & 255;
     if (th == 1) {
@@ -326,13 +345,25 @@ void k_update(UpdateArgs a, const double* __restrict__ Gh,
   }
   // unified partial row of this block: [F^T F (k x k) | U^T F (l x k)]
   double* gp = a.part + (int64_t)blockIdx.x * a.pstride;
+  if (GMF) {
+    // accumulator element v of lane l: row l / 16 + 4 v, column l % 16
+    const int wid = tid >> 6, li = tid & 15, lg = (tid & 63) >> 4;
 #pragma unroll
-  for (int i = 0; i < TCPL; ++i)
+    for (int h = 0; h < 2; ++h)
 #pragma unroll
-    for (int j = 0; j < TCPL; ++j) {
-      const int p = ty + 16 * i, q = tx + 16 * j;
-      if (tid < 256 && p < k && q < k) gp[p * k + q] = gacc[i][j];
-    }
+      for (int v = 0; v < 4; ++v) {
+        const int p = 16 * (wid >> 1) + lg + 4 * v, q = 32 * (wid & 1) + 16 * h + li;
+        if (p < k && q < k) gp[p * k + q] = gm[h][v];
+      }
+  } else {
+#pragma unroll
+    for (int i = 0; i < TCPL; ++i)
+#pragma unroll
+      for (int j = 0; j < TCPL; ++j) {
+        const int p = ty + 16 * i, q = tx + 16 * j;
+        if (tid < 256 && p < k && q < k) gp[p * k + q] = gacc[i][j];
+      }
+  }
   if (LP > 0 && tid < 256) {
     double* zp = gp + k * k;
 #pragma unroll
