@@ -129,6 +129,12 @@ void k_update(UpdateArgs a, const double* __restrict__ Gh,
   // cores: wave w accumulates the 16 x 16 tiles (w / 2, 2 (w % 2)) and
   // (w / 2, 2 (w % 2) + 1) of F^T F, four chunk rows per instruction.
   constexpr bool GMF = LP == 0 && KP == 64;
+  // With a LAI term at KP = 32 both partials run there: tile t (t < NGT) is
+  // F^T F tile (t / 2, t % 2), tile NGT + z is U^T F tile (z / 2, z % 2);
+  // wave w takes tiles w and w + 8.
+  constexpr bool GMZ = LP > 0 && KP == 32;
+  constexpr int NGT = 4, NTT = NGT + (LP / 16) * 2;
+  static_assert(!GMZ || NTT <= 16, "two tiles per wave");
   doublex4 gm[2];
   gm[0] = doublex4{0.0, 0.0, 0.0, 0.0};
   gm[1] = gm[0];
@@ -274,7 +280,24 @@ void k_update(UpdateArgs a, const double* __restrict__ Gh,
     __syncthreads();
     // block partials of F^T F and (LAI) U^T F over this chunk (none when
     // only the right-hand side is written)
-    if (GMF && a.rule != 1) {
+    if (GMZ && a.rule != 1) {
+      const int wid = tid >> 6, li = tid & 15, lg = (tid & 63) >> 4;
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int t = wid + 8 * h;
+        if (t < NTT) {   // the same for the whole wave
+          const bool zt = t >= NGT;
+          const int tt = zt ? t - NGT : t;
+          const int ca = 16 * (tt >> 1) + li, cb = 16 * (tt & 1) + li;
+#pragma unroll 4
+          for (int s4 = 0; s4 < RPB / 4; ++s4) {
+            const int r = 4 * s4 + lg;
+            const double av = zt ? (double)us[r * LU + ca] : (double)wl[r * LW + ca];
+            gm[h] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, (double)wl[r * LW + cb], gm[h], 0, 0, 0);
+          }
+        }
+      }
+    } else if (GMF && a.rule != 1) {
       // lane l supplies A[l % 16][l / 16] = F[r0 + l / 16][16 (w / 2) + l % 16]
       // and B[l / 16][l % 16] = F[r0 + l / 16][16 tb + l % 16]
       const int wid = tid >> 6, li = tid & 15, lg = (tid & 63) >> 4;
@@ -314,7 +337,7 @@ void k_update(UpdateArgs a, const double* __restrict__ Gh,
   if (a.rule == 1) return;
   // the second tile's sums onto the first's, through the staging area (free
   // now: it holds at least KP (KP + LP) doubles, the size of both tiles)
-  if (!GMF) {
+  if (!GMF && !GMZ) {
     double* cmb = reinterpret_cast<double*>(smem);
     const int t8 = tid & 255;
     if (th == 1) {
@@ -355,6 +378,22 @@ void k_update(UpdateArgs a, const double* __restrict__ Gh,
         const int p = 16 * (wid >> 1) + lg + 4 * v, q = 32 * (wid & 1) + 16 * h + li;
         if (p < k && q < k) gp[p * k + q] = gm[h][v];
       }
+  } else if (GMZ) {
+    const int wid = tid >> 6, li = tid & 15, lg = (tid & 63) >> 4;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int t = wid + 8 * h;
+      if (t < NTT) {
+        const bool zt = t >= NGT;
+        const int tt = zt ? t - NGT : t;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int p = 16 * (tt >> 1) + lg + 4 * v, q = 16 * (tt & 1) + li;
+          if (!zt && p < k && q < k) gp[p * k + q] = gm[h][v];
+          if (zt && p < l && q < k) gp[k * k + p * k + q] = gm[h][v];
+        }
+      }
+    }
   } else {
 #pragma unroll
     for (int i = 0; i < TCPL; ++i)
@@ -364,7 +403,7 @@ void k_update(UpdateArgs a, const double* __restrict__ Gh,
         if (tid < 256 && p < k && q < k) gp[p * k + q] = gacc[i][j];
       }
   }
-  if (LP > 0 && tid < 256) {
+  if (LP > 0 && !GMZ && tid < 256) {
     double* zp = gp + k * k;
 #pragma unroll
     for (int i = 0; i < ZI; ++i)
