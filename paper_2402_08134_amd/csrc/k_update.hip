@@ -129,15 +129,17 @@ void k_update(UpdateArgs a, const double* __restrict__ Gh,
   // cores: wave w accumulates the 16 x 16 tiles (w / 2, 2 (w % 2)) and
   // (w / 2, 2 (w % 2) + 1) of F^T F, four chunk rows per instruction.
   constexpr bool GMF = LP == 0 && KP == 64;
-  // With a LAI term at KP = 32 both partials run there: tile t (t < NGT) is
-  // F^T F tile (t / 2, t % 2), tile NGT + z is U^T F tile (z / 2, z % 2);
-  // wave w takes tiles w and w + 8.
+  // With a LAI term both partials run there: with KT = KP / 16 tiles per
+  // row, tile t (t < NGT = KT^2) is F^T F tile (t / KT, t % KT) and tile
+  // NGT + z is U^T F tile (z / KT, z % KT); wave w takes tiles w, w + 8, ...
+  // Only at KP = 32: at KP = 64 (five tiles per wave) the LAI iteration at
+  // n = 65536, l = 80 measured 289 -> 335 us, so there the VALU tile stays.
   constexpr bool GMZ = LP > 0 && KP == 32;
-  constexpr int NGT = 4, NTT = NGT + (LP / 16) * 2;
-  static_assert(!GMZ || NTT <= 16, "two tiles per wave");
-  doublex4 gm[2];
-  gm[0] = doublex4{0.0, 0.0, 0.0, 0.0};
-  gm[1] = gm[0];
+  constexpr int KT = KP / 16, NGT = KT * KT, NTT = NGT + (LP / 16) * KT;
+  constexpr int TPW = GMZ ? (NTT + 7) / 8 : 2;
+  doublex4 gm[TPW > 2 ? TPW : 2];
+#pragma unroll
+  for (int h = 0; h < (TPW > 2 ? TPW : 2); ++h) gm[h] = doublex4{0.0, 0.0, 0.0, 0.0};
   double gacc[TCPL][TCPL];
   double zacc[ZI][TCPL];
 #pragma unroll
@@ -283,12 +285,12 @@ void k_update(UpdateArgs a, const double* __restrict__ Gh,
     if (GMZ && a.rule != 1) {
       const int wid = tid >> 6, li = tid & 15, lg = (tid & 63) >> 4;
 #pragma unroll
-      for (int h = 0; h < 2; ++h) {
+      for (int h = 0; h < TPW; ++h) {
         const int t = wid + 8 * h;
         if (t < NTT) {   // the same for the whole wave
           const bool zt = t >= NGT;
           const int tt = zt ? t - NGT : t;
-          const int ca = 16 * (tt >> 1) + li, cb = 16 * (tt & 1) + li;
+          const int ca = 16 * (tt / KT) + li, cb = 16 * (tt % KT) + li;
 #pragma unroll 4
           for (int s4 = 0; s4 < RPB / 4; ++s4) {
             const int r = 4 * s4 + lg;
@@ -381,14 +383,14 @@ void k_update(UpdateArgs a, const double* __restrict__ Gh,
   } else if (GMZ) {
     const int wid = tid >> 6, li = tid & 15, lg = (tid & 63) >> 4;
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
+    for (int h = 0; h < TPW; ++h) {
       const int t = wid + 8 * h;
       if (t < NTT) {
         const bool zt = t >= NGT;
         const int tt = zt ? t - NGT : t;
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-          const int p = 16 * (tt >> 1) + lg + 4 * v, q = 16 * (tt & 1) + li;
+          const int p = 16 * (tt / KT) + lg + 4 * v, q = 16 * (tt % KT) + li;
           if (!zt && p < k && q < k) gp[p * k + q] = gm[h][v];
           if (zt && p < l && q < k) gp[k * k + p * k + q] = gm[h][v];
         }
