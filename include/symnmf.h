@@ -79,7 +79,7 @@ extern "C" {
 #define SYMNMF_STOP_NONE 0   /* run exactly the requested iterations         */
 #define SYMNMF_STOP_STALL 1  /* normalised residual fails to drop by more than
                                 stop_tol for stop_patience iterations
-                                (Section 6.1: 1e-4, four iterations)       */
+                                (Section 5.1: 1e-4, four iterations)       */
 #define SYMNMF_STOP_TARGET 2 /* normalised residual <= target              */
 #define SYMNMF_STOP_STALL_OR_TARGET 3 /* whichever of the two comes first  */
 
@@ -137,7 +137,7 @@ typedef struct symnmf_matrix {
 } symnmf_matrix;
 
 /* Options; fill with symnmf_default_options() and then override fields.
- * Defaults are the paper's settings (Section 6). */
+ * Defaults are the paper's settings (Section 5). */
 typedef struct symnmf_options {
   int32_t struct_size;    /* sizeof(symnmf_options)                         */
   int32_t rule;           /* SYMNMF_RULE_HALS (default), _BPP or _PGNCG     */
@@ -154,7 +154,7 @@ typedef struct symnmf_options {
                              (default 8); iterations after a stop are skipped
                              on the device                                  */
   double target;          /* residual target for SYMNMF_STOP_TARGET         */
-  double tau;             /* hybrid threshold; < 0 means 1/s (Section 6.2)  */
+  double tau;             /* hybrid threshold; < 0 means 1/s (Section 5.2)  */
   int32_t resid_every;    /* LvS: evaluate the residual every this many
                              iterations (needs a full product); default 1   */
   int32_t max_history;    /* capacity of the per-iteration residual log
@@ -206,12 +206,12 @@ typedef struct symnmf_ctx symnmf_ctx;
 /* Fill *opt with the defaults listed above.  Host pointer. */
 int symnmf_default_options(symnmf_options* opt);
 
-/* Create a solver context (Section 2.1.1; initialisation of Section 6).
+/* Create a solver context (Section 2.1.1; initialisation of Section 5).
  *   out:   host pointer receiving the new context (owned by the caller, freed
  *          with symnmf_destroy).
  *   X:     host pointer to the matrix descriptor (device data, borrowed).
  *   k:     rank, 1..64.
- *   alpha: regulariser; alpha <= 0 selects alpha = max(X) (Section 6.1).
+ *   alpha: regulariser; alpha <= 0 selects alpha = max(X) (Section 5.1).
  *   s:     number of leverage-score samples per half-iteration; 0 = no
  *          sampling, s > 0 selects LvS mode (CSR X only, else E_UNSUPPORTED).
  *   seed:  Philox-4x32-10 key for the random initial H, the sketch and the
@@ -336,7 +336,7 @@ void symnmf_destroy(symnmf_ctx* ctx);
 int symnmf_trim_cache(void);
 
 /* ---- learned warm start ----------------------------------------------------
- * Not part of the paper's method: the paper starts from a random H (Section 6,
+ * Not part of the paper's method: the paper starts from a random H (Section 5,
  * experimental setup) and mentions SVD-based starts as the alternative.  This
  * start builds on the LAI basis of Section 3.  For every entry (i, j), j < k,
  * of H, six features are taken from the embedding (c_j = sqrt(n) U[:, j],

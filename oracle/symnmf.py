@@ -43,7 +43,7 @@ def data_scalars(X):
     """One-time scalars of X used by the method.
 
     ||X||_F^2 (= tr(X^T X), computed once, Appendix "Fast residual evaluation"),
-    the mean zeta of all n^2 entries and max(X) (Section 6: the random
+    the mean zeta of all n^2 entries and max(X) (Section 5: the random
     initialisation scales by zeta; alpha = max(X)), and the row sums.
     """
     if sp.issparse(X):
@@ -70,7 +70,7 @@ def data_scalars(X):
 
 
 # ----------------------------------------------------------------------------
-# Initialisation (Section 6, experimental setup): entries uniform on [0, 1),
+# Initialisation (Section 5, experimental setup): entries uniform on [0, 1),
 # scaled by 2*sqrt(zeta/k), zeta the average of all entries of X.
 # Reading: the starting W of the HALS sweeps equals H.
 # ----------------------------------------------------------------------------
@@ -214,7 +214,7 @@ def projected_gradient_norm(XH, XW, W, H, alpha):
 
 class StallRule:
     """Stop once the normalised residual has failed to drop by more than
-    `tol` for `patience` consecutive iterations (Section 6.1 setup: 1e-4,
+    `tol` for `patience` consecutive iterations (Section 5.1 setup: 1e-4,
     four iterations).  Reading: the drop is the absolute difference of
     consecutive normalised residuals."""
 
@@ -543,6 +543,8 @@ def lvs_half_step(X, src, dst, alpha, s, tau, seed, half_iter, rule="hals"):
     info["lev"] = lev
     info["rows"] = rows
     info["weights"] = wts
+    info["G"] = G
+    info["Y"] = Y
     return new, info
 
 

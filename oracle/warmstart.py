@@ -1,6 +1,6 @@
 """FP64 oracle of the learned warm start (test infrastructure only).
 
-The paper starts every run from a random H (Section 6, experimental setup)
+The paper starts every run from a random H (Section 5, experimental setup)
 and names SVD-based starts only as an alternative.  This project adds a
 learned start built on the LAI basis of Section 3: a small MLP maps features
 of each entry of H, taken from the spectral embedding of its row and column

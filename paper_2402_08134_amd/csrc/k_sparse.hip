@@ -1,6 +1,6 @@
 // CSR-X kernels: scalars pass, SpMM Y = X B and the cross term of the exact
 // residual.  The sparse product is the "MM" cost of the sparse experiments
-// (Section 6.2); a wavefront owns one row, its lanes own the output columns
+// (Section 5.2); a wavefront owns one row, its lanes own the output columns
 // (so every B-row gather is one contiguous 64..512-byte read) and, for narrow
 // B, several lane groups walk different nonzeros of the row and are combined
 // by a fixed shuffle tree.

@@ -1,7 +1,7 @@
 // Learned warm start: entry features from the LAI basis, and the small
 // column-shared network (inference, and training: forward, backward, weight
 // gradients, Adam).  Not part of the paper's method, which starts from a
-// random H (Section 6); the start built here feeds the same iterations.
+// random H (Section 5); the start built here feeds the same iterations.
 //
 // Features of entry (i, j), j < k (c_j = sqrt(n) U[:, j], s_j the sign whose
 // part of c_j has the larger norm, a_ij = s_j c_ij, r_i the norm of row i of

@@ -1152,7 +1152,7 @@ int symnmf_create(symnmf_ctx** out, const symnmf_matrix* X, int32_t k, double al
     if (!(c->zeta > 0.0)) throw Fail{SYMNMF_E_INVALID, "mean of X is not positive"};
     c->tau = c->opt.tau >= 0.0 ? c->opt.tau : (s > 0 ? 1.0 / (double)s : 0.0);
 
-    // H0 = U[0,1) * 2 sqrt(zeta / k), W0 = H0 (Section 6 initialisation)
+    // H0 = U[0,1) * 2 sqrt(zeta / k), W0 = H0 (Section 5 initialisation)
     LCHK(init_uniform_factor(c->H, c->fdtype, n, k, 2.0 * std::sqrt(c->zeta / k), seed, c->st));
     HIPCHK(hipMemcpyAsync(c->W, c->H, (size_t)n * k * fs, hipMemcpyDeviceToDevice, c->st));
     c->refresh_gram(c->H, c->G_H, c->Gh_H, c->Gi_H);

@@ -44,7 +44,7 @@ def test_default_options_match_the_paper():
     o = P.symnmf_default_options()
     assert o.struct_size == ctypes.sizeof(P.Options)
     assert o.stop_tol == 1e-4 and o.stop_patience == 4 and o.rule == P.RULE_HALS
-    assert o.tau < 0  # tau = 1/s (Section 6.2)
+    assert o.tau < 0  # tau = 1/s (Section 5.2)
 
 
 def test_struct_layouts_match_header(tmp_path):

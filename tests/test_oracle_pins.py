@@ -417,7 +417,7 @@ def test_hybrid_sample_distribution_chi2():
 
 @pytest.mark.slow
 def test_hybrid_sample_unbiased_gram():
-    # E[H^T S^T S H] = H^T H over the random part (Section 6.2 uses
+    # E[H^T S^T S H] = H^T H over the random part (Section 5.2 uses
     # E||S H||^2 = ||H||^2 to justify the same alpha).
     rng = np.random.default_rng(16)
     n, k, s = 300, 3, 60
@@ -448,6 +448,63 @@ def test_lvs_with_tau_zero_is_plain():
     W2, H2, h2 = O.lvs_symnmf(Xs, 4, alpha, Hi, 5, s=60, tau=0.0, seed=1)
     assert np.allclose(H1, H2, rtol=1e-12, atol=1e-13)
     assert np.allclose(h1, h2, rtol=1e-10)
+
+
+def test_lvs_sampled_operands_match_an_explicit_sketch():
+    # Algorithm LvS-SymNMF with the hybrid S of Section 4.2 (eq. SH), built
+    # here row by row from the draw list: one row e_i^T for each deterministic
+    # row (p_i = l_i / k >= tau) and one row e_r^T / sqrt(s_R p_r) for every
+    # random draw r (eq. lev_score_S, p_r = l_r / (k - theta)).  The sampled
+    # NLS operands are G = H^T S^T S H + alpha I and Y = X S^T S H + alpha H,
+    # and the new factor is the HALS sweep on them.  tau = 1/s gives both
+    # kinds of rows and weights far from 1.
+    rng = np.random.default_rng(21)
+    n, k, s = 90, 4, 30
+    H = rng.uniform(0.1, 1.0, size=(n, k)) ** 2
+    H[[3, 17, 50, 71]] *= 9.0
+    B = rng.uniform(size=(n, n))
+    X = B + B.T
+    W = rng.uniform(size=(n, k))
+    alpha, tau = 0.7, 1.0 / s
+    new, info = O.lvs_half_step(X, H, W, alpha, s, tau, seed=9, half_iter=5)
+    # leverage scores from the SVD (eq. lev_score_def), not from a QR
+    Uh = np.linalg.svd(H, full_matrices=False)[0]
+    lev = np.sum(Uh * Uh, axis=1)
+    assert np.allclose(info["lev"], lev, rtol=1e-12, atol=1e-15)
+    lev = info["lev"]                 # the exact bits the draws were made from
+    det = lev / k >= tau
+    s_D = int(det.sum())
+    assert 0 < s_D < s
+    theta = float(lev[det].sum())
+    s_R = s - s_D
+    # draw j: r = floor(v_j W_R / 2^64) on the integer weights w_i =
+    # floor(l_i 2^40) of the random rows; the row is the first whose running
+    # sum of w exceeds r (linear scan)
+    w = [0 if det[i] else int(np.floor(lev[i] * 2.0 ** 40)) for i in range(n)]
+    W_R = sum(w)
+    v = philox.u64_stream(9, s_R, 5, philox.TAG_SAMPLE)
+    drawn = []
+    for x in v:
+        r = (int(x) * W_R) >> 64
+        acc = 0
+        for i in range(n):
+            acc += w[i]
+            if acc > r:
+                drawn.append(i)
+                break
+    assert len(drawn) == s_R
+    S = np.zeros((s_D + s_R, n))
+    for j, i in enumerate(np.nonzero(det)[0]):
+        S[j, i] = 1.0
+    for j, i in enumerate(drawn):
+        S[s_D + j, i] = 1.0 / np.sqrt(s_R * lev[i] / (k - theta))
+    SH = S @ H
+    G = SH.T @ SH + alpha * np.eye(k)
+    Y = X @ (S.T @ SH) + alpha * H
+    assert np.abs(np.diag(S.T @ S) - 1.0).max() > 0.5       # weights really differ from 1
+    assert np.linalg.norm(info["G"] - G) <= 1e-8 * np.linalg.norm(G)
+    assert np.linalg.norm(info["Y"] - Y) <= 1e-8 * np.linalg.norm(Y)
+    assert np.allclose(new, O.hals_gy(G, Y, W), rtol=1e-8, atol=1e-10)
 
 
 def test_sampled_nls_error_shrinks_with_samples():

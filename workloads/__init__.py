@@ -5,10 +5,10 @@ vectors).  It holds none of the factorisation's arithmetic and is shared by
 the tests, the oracle checks and the benchmark.
 
 Stand-ins (the paper's datasets are not available):
-* dense similarity (the Web of Science hypergraph adjacency of Section 6.1 is
+* dense similarity (the Web of Science hypergraph adjacency of Section 5.1 is
   a dense symmetric nonnegative similarity matrix): a Gaussian-kernel matrix
   of points drawn from a Gaussian mixture, zero diagonal;
-* sparse graph (the normalised, zero-diagonal citation graph of Section 6.2):
+* sparse graph (the normalised, zero-diagonal citation graph of Section 5.2):
   a stochastic block model, symmetrically normalised D^-1/2 A D^-1/2;
 * planted: X = H0 H0^T + small symmetric noise with a block-dominant H0.
 """
