@@ -283,6 +283,20 @@ int symnmf_get_factor(symnmf_ctx* ctx, int32_t which, void* dst, int32_t dtype);
  * (device, l FP64, descending).  Either may be NULL.  Errors: E_STATE. */
 int symnmf_get_lai(symnmf_ctx* ctx, void* U, void* lambda);
 
+/* Parity hook: the Gaussian sketch Omega of Algorithm RRF (Section 2.2.1)
+ * that symnmf_lai and symnmf_lai_adaptive draw for rank l, into caller-owned
+ * device memory (n x l FP64, row-major).  Entry (i, j) is Gaussian number
+ * i l + j of the Philox-4x32-10 stream (key = seed, sub-stream 0, tag 2):
+ * block e gives two 64-bit words v0, v1, and the value is
+ * sqrt(-2 ln x) cos(2 pi b 2^-53) with x = 1 - (v0 >> 11) 2^-53 and
+ * b = v1 >> 11 (Box-Muller).  The logarithm (atanh series after reduction to
+ * [sqrt(1/2), sqrt(2)), ln 2 split in two) and the cosine (quarter-turn
+ * reduction done exactly on b, Taylor series of sin and cos) are the
+ * library's own, each step one correctly rounded FP64 operation in a fixed
+ * order with nothing fused, so the values are fixed bit for bit.
+ * 1 <= l <= n.  Stream-ordered.  Errors: E_INVALID. */
+int symnmf_get_sketch(symnmf_ctx* ctx, int32_t l, void* Omega);
+
 /* Y = X * B with the context's product kernel (dense GEMM in the compute
  * dtype, or CSR SpMM).  B: device, n x c (c <= 96) of the factor dtype
  * (F64 when the compute dtype is F64, else F32); Y: device, n x c of the same

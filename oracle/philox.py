@@ -16,11 +16,15 @@ agree on the *stream layout* below, which is this project's convention:
   value e of a stream is v[e mod 2] of block e div 2.
 
 Conversions: uniform u = (v >> 11) * 2^-53 in [0, 1) (exact in FP64);
-Gaussian value e uses both words of block e:  u1, u2 from v0, v1 and
-z = sqrt(-2 ln(1 - u1)) * cos(2 pi u2)  (Box-Muller; libm on each side, so the
-Gaussians agree to a few ulps, not bitwise);  a draw in [0, W) is the high
-64 bits of v * W (exact integer arithmetic).
+a draw in [0, W) is the high 64 bits of v * W (exact integer arithmetic);
+Gaussian value e uses both words of block e (Box-Muller):
+z = sqrt(-2 ln(1 - u1)) * cos(2 pi u2), u1, u2 from v0, v1, with the logarithm
+and cosine below (`log_unit`, `cos_turn`) instead of a math library, so that
+every value is fixed bit for bit by this definition: each step is one
+correctly rounded FP64 operation (+, -, *, /, sqrt) in the order written, and
+numpy performs exactly those (it fuses no multiply-add).
 """
+import math
 import numpy as np
 
 _M0 = np.uint64(0xD2511F53)
@@ -88,12 +92,77 @@ def uniform(seed, count, sub, tag):
     return (v >> np.uint64(11)).astype(np.float64) * (2.0 ** -53)
 
 
+# ln 2 = LN2_HI + LN2_LO: LN2_HI keeps 32 fraction bits, so e * LN2_HI is
+# exact for the exponents that occur (Cody and Waite's split of the constant);
+# both are derived here from a 60-digit ln 2.
+def _ln2_split():
+    from decimal import Decimal, getcontext
+    getcontext().prec = 60
+    ln2 = Decimal(2).ln()
+    hi = Decimal(int(ln2 * (1 << 32))) / Decimal(1 << 32)
+    return float(hi), float(ln2 - hi)
+
+
+LN2_HI, LN2_LO = _ln2_split()
+SQRT_HALF = math.sqrt(0.5)
+HALF_PI = math.pi / 2.0      # the double nearest pi/2 (math.pi is the double nearest pi)
+
+
+def log_unit(a):
+    """ln x for x = (2^53 - a) 2^-53 in (0, 1], a: uint64 array of 53-bit integers.
+
+    x = m 2^e with m in [sqrt(1/2), sqrt(2)); with s = (m - 1)/(m + 1),
+    ln m = 2 atanh(s) = 2 s (1 + s^2/3 + s^4/5 + ...), summed by Horner up to
+    the s^22/23 term (|s| <= 0.1716, so the rest is below 2^-62 relative);
+    ln x = e LN2_HI + (e LN2_LO + ln m).
+    """
+    x = ((np.uint64(1) << np.uint64(53)) - np.asarray(a, dtype=np.uint64)).astype(np.float64) * 2.0 ** -53
+    m, e = np.frexp(x)                       # m in [1/2, 1), exact
+    low = m < SQRT_HALF
+    m = np.where(low, m * 2.0, m)
+    e = np.where(low, e - 1, e).astype(np.float64)
+    s = (m - 1.0) / (m + 1.0)
+    z = s * s
+    p = np.full_like(s, 1.0 / 23.0)
+    for j in range(10, -1, -1):
+        p = 1.0 / float(2 * j + 1) + z * p
+    lnm = (s + s) * p
+    return e * LN2_HI + (e * LN2_LO + lnm)
+
+
+def cos_turn(b):
+    """cos(2 pi b 2^-53) for b: uint64 array of 53-bit integers.
+
+    The angle is q quarter turns plus theta = f pi/2 with q the nearest
+    integer to b / 2^51 and f = (b - q 2^51) 2^-51 in [-1/2, 1/2] (both exact);
+    sin and cos of theta by their Taylor series up to theta^17/17! and
+    theta^18/18! (the rest is below 2^-62 relative for |theta| <= pi/4), each
+    coefficient the double nearest +-1/n!; q mod 4 = 0..3 selects cos, -sin,
+    -cos, sin.
+    """
+    b = np.asarray(b, dtype=np.uint64)
+    q = (b + (np.uint64(1) << np.uint64(50))) >> np.uint64(51)
+    f = (b.astype(np.int64) - (q << np.uint64(51)).astype(np.int64)).astype(np.float64) * 2.0 ** -51
+    theta = f * HALF_PI
+    t = theta * theta
+    S = np.full_like(t, 1.0 / float(math.factorial(17)))
+    for j in range(7, 0, -1):
+        S = (-1.0) ** j / float(math.factorial(2 * j + 1)) + t * S
+    C = np.full_like(t, -1.0 / float(math.factorial(18)))
+    for j in range(8, 0, -1):
+        C = (-1.0) ** j / float(math.factorial(2 * j)) + t * C
+    sn = theta + (theta * t) * S
+    cs = 1.0 + t * C
+    qm = (q & np.uint64(3)).astype(np.int64)
+    return np.choose(qm, [cs, -sn, -cs, sn])
+
+
 def gaussian(seed, count, sub, tag):
-    """Standard normal FP64 numbers by Box-Muller, one per block."""
+    """Standard normal FP64 numbers by Box-Muller, one per block:
+    sqrt(-2 ln(1 - u1)) * cos(2 pi u2) with the log and cosine above."""
     v0, v1 = _blocks(seed, 0, count, sub, tag)
-    u1 = (v0 >> np.uint64(11)).astype(np.float64) * (2.0 ** -53)
-    u2 = (v1 >> np.uint64(11)).astype(np.float64) * (2.0 ** -53)
-    return np.sqrt(-2.0 * np.log(1.0 - u1)) * np.cos(2.0 * np.pi * u2)
+    r2 = -2.0 * log_unit(v0 >> np.uint64(11))
+    return np.sqrt(r2) * cos_turn(v1 >> np.uint64(11))
 
 
 def draws(seed, count, sub, tag, bound):

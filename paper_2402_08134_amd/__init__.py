@@ -72,6 +72,7 @@ _SIGS = {
     "symnmf_get_factor": (ctypes.c_int, [_VP, ctypes.c_int32, _VP, ctypes.c_int32]),
     "symnmf_get_lai": (ctypes.c_int, [_VP, _VP, _VP]),
     "symnmf_apply_x": (ctypes.c_int, [_VP, _VP, ctypes.c_int32, _VP]),
+    "symnmf_get_sketch": (ctypes.c_int, [_VP, ctypes.c_int32, _VP]),
     "symnmf_half_step": (ctypes.c_int, [_VP, ctypes.c_int32, ctypes.c_int32]),
     "symnmf_leverage": (ctypes.c_int, [_VP, ctypes.c_int32, _VP]),
     "symnmf_sample": (ctypes.c_int, [_VP, _VP, ctypes.c_int32, _VP, _VP, ctypes.c_int64,
@@ -229,6 +230,12 @@ def symnmf_get_lai(ctx, U=None, lam=None):
 def symnmf_apply_x(ctx, B, Y):
     assert B.is_contiguous() and Y.is_contiguous() and B.shape == Y.shape and B.shape[0] == ctx.n
     _check(lib().symnmf_apply_x(ctx.handle, B.data_ptr(), int(B.shape[1]), Y.data_ptr()), ctx.handle)
+
+
+def symnmf_get_sketch(ctx, l, Omega):
+    import torch
+    assert Omega.is_contiguous() and Omega.dtype == torch.float64 and Omega.numel() == ctx.n * l
+    _check(lib().symnmf_get_sketch(ctx.handle, int(l), Omega.data_ptr()), ctx.handle)
 
 
 def symnmf_half_step(ctx, side, half_iter=0):

@@ -8,18 +8,22 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT_DIR = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libsymnmf.so")
-SOURCES = ["k_dense.hip", "k_sparse.hip", "k_factor.hip", "k_update.hip", "k_lvs.hip", "k_bpp.hip", "k_warm.hip", "k_pgncg.hip", "solver.cpp"]
+SOURCES = ["k_dense.hip", "k_sparse.hip", "k_factor.hip", "k_sketch.hip", "k_update.hip", "k_lvs.hip", "k_bpp.hip",
+           "k_warm.hip", "k_pgncg.hip", "solver.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-ffp-contract=fast",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wno-unused-result",
 ]
+# The sketch's values are fixed bit for bit by their definition: every FP64
+# operation rounded on its own, none fused.
+FILE_FLAGS = {"k_sketch.hip": ["-ffp-contract=off"]}
 
 
 def _compile(src):
     obj = os.path.join(OUT_DIR, os.path.splitext(src)[0] + ".o")
-    cmd = [HIPCC] + FLAGS + ["-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj]
+    cmd = [HIPCC] + FLAGS + FILE_FLAGS.get(src, []) + ["-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     msgs = "\n".join(l for l in (r.stdout + r.stderr).splitlines()
                      if "packed-fp32-ops' is not a recognized feature" not in l)

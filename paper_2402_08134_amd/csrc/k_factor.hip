@@ -30,16 +30,6 @@ __global__ __launch_bounds__(256) void k_init_uniform(TF* __restrict__ F, int64_
   F[e] = (TF)(u53(philox_value(seed, (uint64_t)e, 0, TAG_H0)) * scale);
 }
 
-__global__ __launch_bounds__(256) void k_gaussian(double* __restrict__ out, int64_t count, uint64_t seed, uint32_t sub,
-                                                  uint32_t tag) {
-  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (e >= count) return;
-  uint64_t v0, v1;
-  philox_block(seed, (uint64_t)e, sub, tag, v0, v1);
-  const double a = u53(v0), b = u53(v1);
-  out[e] = sqrt(-2.0 * log(1.0 - a)) * cos(6.283185307179586 * b);
-}
-
 template <typename TS, typename TD>
 __global__ __launch_bounds__(256) void k_convert(const TS* __restrict__ src, TD* __restrict__ dst, int64_t count) {
   const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
@@ -707,11 +697,6 @@ int init_uniform_factor(void* F, int fdtype, int n, int k, double scale, uint64_
     k_init_uniform<double><<<ceil_div(cnt, 256), 256, 0, s>>>((double*)F, cnt, scale, seed);
   else
     k_init_uniform<float><<<ceil_div(cnt, 256), 256, 0, s>>>((float*)F, cnt, scale, seed);
-  return hipGetLastError() == hipSuccess ? 0 : -1;
-}
-
-int gen_gaussian(double* out, int64_t count, uint64_t seed, uint32_t sub, uint32_t tag, hipStream_t s) {
-  k_gaussian<<<ceil_div(count, 256), 256, 0, s>>>(out, count, seed, sub, tag);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 

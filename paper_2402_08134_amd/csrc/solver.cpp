@@ -1452,6 +1452,14 @@ int symnmf_get_lai(symnmf_ctx* c, void* U, void* lambda) {
   });
 }
 
+int symnmf_get_sketch(symnmf_ctx* c, int32_t l, void* Omega) {
+  return guarded(c, [&] {
+    if (!Omega) throw Fail{SYMNMF_E_INVALID, "null output"};
+    if (l < 1 || l > c->n) throw Fail{SYMNMF_E_INVALID, "l must be in 1..n"};
+    LCHK(gen_gaussian((double*)Omega, (int64_t)c->n * l, c->seed, 0, TAG_OMEGA, c->st));
+  });
+}
+
 int symnmf_apply_x(symnmf_ctx* c, const void* B, int32_t cols, void* Yout) {
   return guarded(c, [&] {
     if (!B || !Yout || cols < 1 || cols > CMAX) throw Fail{SYMNMF_E_INVALID, "argument"};

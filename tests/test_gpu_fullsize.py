@@ -1,10 +1,14 @@
 """Parity at the benchmark sizes, in the launch configurations bench.py
-times: the dense similarity n = 16384, k = 32 (FP32), the precision sweep
+times: the dense similarity n = 16384, k = 32 (FP32; plain iterations, and
+the LAI basis l = 48, q = 2 with the learned start and LAI iterations), a
+LAI run past n = 32768 (the update's U prefetch), the precision sweep
 n = 65536, k = 64 (FP32 and BF16 products) and the sparse graph n = 2^20,
 k = 64.  The FP64 oracle computes sampled output rows one by one (a row of
 X H, a row of the HALS update given the exact Gram) or, at n = 16384, whole
 plain iterations; at n = 2^20 a property that holds at any size is checked
 too (leverage scores sum to k)."""
+import os
+
 import numpy as np
 import pytest
 import scipy.sparse as sp
@@ -69,6 +73,96 @@ def test_dense_16384_three_iterations(dense16k):
     log(f"n=16384 three iterations: history gpu {hg} oracle {hist}")
     assert np.max(np.abs(hg - hist) / hist) <= 1e-4
     assert rel(factor(ctx, P.H), Ho) <= 1e-4
+
+
+def test_dense_16384_lai_learned_start_and_iterations(dense16k):
+    """The benchmark's value path at its size: RRF + Apx-EVD (l = 48, q = 2;
+    the sketch is bit-identical on both sides) against the oracle's
+    Householder / eigh version; then, from the device's basis, the learned
+    start's features, network and scale fit, and LAI iterations."""
+    from oracle import warmstart as WS
+    from paper_2402_08134_amd import warmstart as WSP
+    X = dense16k
+    n, k, l, q, seed = X.shape[0], 32, 48, 2, 1
+    X64 = X.astype(np.float64)
+    ctx = P.symnmf_create(dev(X), k, 0.0, 0, seed)
+    P.symnmf_lai(ctx, l, q)
+    U = torch.empty((n, l), dtype=torch.float64, device="cuda")
+    lam = torch.empty(l, dtype=torch.float64, device="cuda")
+    P.symnmf_get_lai(ctx, U, lam)
+    Ug, lg = host(U), host(lam)
+    Uo, lo = O.apx_evd(lambda M: X64 @ M, O.sketch_omega(n, l, seed), q)
+    S = _rows(n, 96, 4)
+    e_lam = rel(lg, lo)
+    e_xl = rel((Ug[S] * lg) @ Ug.T, (Uo[S] * lo) @ Uo.T)
+    log(f"n=16384 l=48 q=2: lambda rel {e_lam:.2e}, sampled rows of U Lambda U^T rel {e_xl:.2e}, "
+        f"|U^T U - I| {np.abs(Ug.T @ Ug - np.eye(l)).max():.1e}")
+    assert np.abs(Ug.T @ Ug - np.eye(l)).max() <= 1e-12
+    assert e_lam <= 1e-4 and e_xl <= 1e-3
+    # learned start from the device's basis
+    rowsum = O.data_scalars(X64)["rowsum"]
+    F = torch.empty((n * k, P.MLP_FEATURES), dtype=torch.float32, device="cuda")
+    P.symnmf_warm_features(ctx, F)
+    Fo = WS.features(Ug, lg, rowsum, k)
+    Fg = host(F)
+    e_f = max(rel(Fg[:, c], Fo[:, c]) for c in range(P.MLP_FEATURES))
+    net = WSP.load(os.path.join(WSP.WEIGHTS_DIR, "warmstart_gk.npz"))
+    p = torch.empty(P.symnmf_mlp_num_params(net), dtype=torch.float32, device="cuda")
+    P.symnmf_mlp_get_params(net, p)
+    ps = []
+    v, o_ = host(p), 0
+    for a, b in zip(WS.layer_sizes()[:-1], WS.layer_sizes()[1:]):
+        ps.append((v[o_:o_ + a * b].reshape(a, b), v[o_ + a * b:o_ + a * b + b]))
+        o_ += a * b + b
+    beta = P.symnmf_warmstart(ctx, net)
+    H0g = factor(ctx, P.H)
+    H0o = WS.warm_start(ps, Ug, lg, rowsum, k, lambda B: X64 @ B)
+    e_h0 = rel(H0g, H0o)
+    log(f"n=16384 learned start: features max rel {e_f:.2e}, beta {beta:.6f}, H0 rel {e_h0:.2e}")
+    assert e_f <= 1e-5 and e_h0 <= 1e-5
+    # LAI iterations from that start, against the oracle on the same basis
+    iters = 5
+    P.symnmf_iterate(ctx, iters)
+    Wo, Ho, hist = O.lai_symnmf(Ug, lg, k, O.data_scalars(X64)["maxval"], H0g, iters)
+    hg = np.array(P.symnmf_history(ctx))
+    e_hist = float(np.max(np.abs(hg - hist) / hist))
+    log(f"n=16384 {iters} LAI iterations: history max rel {e_hist:.2e}, H rel {rel(factor(ctx, P.H), Ho):.2e}")
+    assert e_hist <= 1e-4 and rel(factor(ctx, P.H), Ho) <= 1e-4
+
+
+def test_lai_iterations_past_32768_rows():
+    """LAI iterations at n = 40000, k = 16 (padded width 16, 16 lanes per row,
+    each block prefetching its next chunk of U), against the oracle on the
+    device's basis; the basis itself is checked for orthonormality and for
+    its eigenvalues against Rayleigh quotients formed on the host."""
+    n, k, l, q, seed = 40000, 16, 32, 1, 2
+    X = workloads.gpu_gaussian_kernel(n, 32, 16, seed=3)
+    ctx = P.symnmf_create(X, k, 0.0, 0, seed)
+    P.symnmf_lai(ctx, l, q)
+    U = torch.empty((n, l), dtype=torch.float64, device="cuda")
+    lam = torch.empty(l, dtype=torch.float64, device="cuda")
+    P.symnmf_get_lai(ctx, U, lam)
+    Ug, lg = host(U), host(lam)
+    assert np.abs(Ug.T @ Ug - np.eye(l)).max() <= 1e-12
+    # Rayleigh quotients u_j^T X u_j for the top four, X streamed in row blocks
+    top = Ug[:, :4]
+    XU = np.zeros_like(top)
+    for r0 in range(0, n, 4096):
+        XU[r0:r0 + 4096] = host(X[r0:r0 + 4096]) @ top
+    rq = np.einsum("ij,ij->j", top, XU)
+    log(f"n=40000: lambda[:4] {lg[:4]}, Rayleigh quotients {rq}")
+    assert rel(lg[:4], rq) <= 1e-5
+    H0 = factor(ctx, P.H)
+    maxval = P.symnmf_get_stats(ctx).maxval
+    del X
+    torch.cuda.empty_cache()
+    iters = 4
+    P.symnmf_iterate(ctx, iters)
+    Wo, Ho, hist = O.lai_symnmf(Ug, lg, k, maxval, H0, iters)
+    hg = np.array(P.symnmf_history(ctx))
+    e = float(np.max(np.abs(hg - hist) / hist))
+    log(f"n=40000 {iters} LAI iterations: history max rel {e:.2e}, H rel {rel(factor(ctx, P.H), Ho):.2e}")
+    assert e <= 1e-4 and rel(factor(ctx, P.H), Ho) <= 1e-4
 
 
 @pytest.mark.parametrize("compute", ["f32", "bf16"])

@@ -7,6 +7,8 @@ them (dropped term, wrong sign or index, transposed operand) would fail it.
 """
 import os
 
+import math
+
 import numpy as np
 import pytest
 import scipy.sparse as sp
@@ -55,6 +57,44 @@ def test_philox_gaussian_and_draws():
     # the draw is floor(v * bound / 2^64): bound 2^64 returns v itself
     v = philox.u64_stream(3, 5, 1, philox.TAG_SAMPLE)
     assert [int(x) for x in philox.draws(3, 5, 1, philox.TAG_SAMPLE, 1 << 64)] == [int(x) for x in v]
+
+
+def test_sketch_log_against_the_math_library():
+    """The sketch's own logarithm agrees with the platform log to a few ulps
+    on (0, 1] (relative where |ln x| > 1/4; near x = 1, where ln x -> 0, an
+    absolute bound; the reduction's e ln 2 + ln m can cancel up to a factor 2
+    for x in [1/2, sqrt(1/2)), hence 8 half-ulps), and is exact at x = 1."""
+    rng = np.random.default_rng(1)
+    a = np.concatenate([rng.integers(0, 2 ** 53, 200000, dtype=np.uint64),
+                        np.array([0, 1, 2 ** 52, 2 ** 53 - 1, 2 ** 53 - 2], dtype=np.uint64)])
+    x = ((np.uint64(1) << np.uint64(53)) - a).astype(np.float64) * 2.0 ** -53
+    L = philox.log_unit(a)
+    ref = np.array([math.log(v) for v in x])
+    far = np.abs(ref) > 0.25
+    assert np.max(np.abs(L - ref)[far] / np.abs(ref[far])) <= 8 * 2.0 ** -53
+    assert np.max(np.abs(L - ref)[~far]) <= 4 * 2.0 ** -53
+    assert L[-5] == 0.0                                   # x = 1
+    # ln 2^-j = -j ln 2 to the accuracy of the split constant
+    for j in (1, 2, 10, 52, 53):
+        v = philox.log_unit(np.array([2 ** 53 - 2 ** (53 - j)], dtype=np.uint64))[0]
+        assert abs(v + j * math.log(2.0)) <= 2 * j * 2.0 ** -53
+
+
+def test_sketch_cosine_identities():
+    """cos(2 pi u) of the sketch: exact at quarter turns, even, the
+    Pythagorean identity with the quarter-turn shift (sin), and within a
+    few ulps of the platform cosine (whose own argument 2 pi u is rounded)."""
+    q = np.array([0, 2 ** 51, 2 ** 52, 3 * 2 ** 51], dtype=np.uint64)
+    assert list(philox.cos_turn(q)) == [1.0, 0.0, -1.0, 0.0]
+    rng = np.random.default_rng(2)
+    b = rng.integers(1, 2 ** 53, 200000, dtype=np.uint64)
+    b = b[(b % np.uint64(2 ** 51)) != np.uint64(2 ** 50)]   # off the half-quadrant ties
+    c = philox.cos_turn(b)
+    assert np.array_equal(philox.cos_turn((np.uint64(1) << np.uint64(53)) - b), c)
+    s = philox.cos_turn((b - np.uint64(2 ** 51)) % np.uint64(2 ** 53))   # cos(x - pi/2) = sin x
+    assert np.max(np.abs(c * c + s * s - 1.0)) <= 6 * 2.0 ** -53
+    u = b.astype(np.float64) * 2.0 ** -53
+    assert np.max(np.abs(c - np.cos(2.0 * np.pi * u))) <= 8 * 2.0 ** -53
 
 
 # --------------------------------------------------------------------------
