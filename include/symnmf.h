@@ -404,6 +404,23 @@ int symnmf_warm_features(symnmf_ctx* ctx, float* F);
  * floats plus n k factor elements for the duration of the call. */
 int symnmf_warmstart(symnmf_ctx* ctx, const symnmf_mlp* net, double* beta_out);
 
+/* symnmf_warmstart for callers that cannot allocate device memory: code
+ * running under HIP graph capture, tight serving loops, and hosts that forbid
+ * hipMalloc.  Same arguments, result and errors as symnmf_warmstart (bitwise
+ * the same H, W and beta), but the temporaries (features, network output and
+ * the converted start: (28 + factor element size) n k bytes, each piece
+ * rounded up to 256 bytes) live in a static device array of 64 MiB per GPU,
+ * held from library load until the process ends; the call makes no hipMalloc,
+ * hipFree or other allocating call.  Limit: that sum <= 64 MiB, e.g.
+ * n k <= 2,097,152 with FP32 factors (n = 32768 at k = 64) and <= 1,864,128
+ * with FP64 factors; larger n k gives E_INVALID before any work is enqueued.
+ * Every call on one GPU uses the same array, and each call overwrites it
+ * completely before reading it (nothing is assumed to start at zero): calls
+ * that overlap on one GPU (other threads, other streams, or a second call
+ * enqueued before the first one's stream work has run) race and must be
+ * serialised by the caller. */
+int symnmf_warmstart_noalloc(symnmf_ctx* ctx, const symnmf_mlp* net, double* beta_out);
+
 #ifdef __cplusplus
 }
 #endif

@@ -95,6 +95,7 @@ _SIGS = {
     "symnmf_mlp_destroy": (None, [_VP]),
     "symnmf_warm_features": (ctypes.c_int, [_VP, _VP]),
     "symnmf_warmstart": (ctypes.c_int, [_VP, _VP, ctypes.POINTER(ctypes.c_double)]),
+    "symnmf_warmstart_noalloc": (ctypes.c_int, [_VP, _VP, ctypes.POINTER(ctypes.c_double)]),
 }
 
 _lib = None
@@ -357,4 +358,13 @@ def symnmf_warmstart(ctx, net, want_beta=True):
     the value is then in symnmf_get_stats(ctx).warm_beta)."""
     beta = ctypes.c_double()
     _check(lib().symnmf_warmstart(ctx.handle, net.handle, ctypes.byref(beta) if want_beta else None), ctx.handle)
+    return beta.value if want_beta else None
+
+
+def symnmf_warmstart_noalloc(ctx, net, want_beta=True):
+    """symnmf_warmstart with its temporaries in the library's static device
+    scratch (no device allocation); same return value."""
+    beta = ctypes.c_double()
+    _check(lib().symnmf_warmstart_noalloc(ctx.handle, net.handle, ctypes.byref(beta) if want_beta else None),
+           ctx.handle)
     return beta.value if want_beta else None

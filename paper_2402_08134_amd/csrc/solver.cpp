@@ -942,6 +942,70 @@ void mlp_grad(symnmf_mlp* net, const float* F, const float* T, int64_t rows, dou
     *loss = 0.5 * net->hbuf[0] / (double)rows;
   }
 }
+
+// Learned start into the caller-chosen temporaries F ((n k) x 6 FP32
+// features), Htf (n k FP32 network outputs) and Ht (n k factor elements).
+void warmstart_run(symnmf_ctx* c, const symnmf_mlp* net, float* F, float* Htf, void* Ht, double* beta_out) {
+  const int n = c->n, k = c->k;
+  const int64_t nk = (int64_t)n * k;
+  symnmf_ctx::Timed tm(c, SYMNMF_PHASE_WARM);
+  c->ws.reset();
+  double* info = c->ws.dbl((size_t)2 * k + 2);
+  if (!info) throw Fail{SYMNMF_E_NOMEM, "workspace"};
+  LCHK(warm_features(c->U, n, c->l, k, c->lam, c->rowsum, c->d_scal + 1, F, info, c->ws, c->st));
+  LCHK(mlp_forward(net->p, F, nk, Htf, c->st));
+  LCHK(copy_convert(Htf, SYMNMF_F32, Ht, c->fdtype, nk, c->st));
+  // least-squares scale: beta^2 = tr(Ht^T X Ht) / ||Ht^T Ht||_F^2
+  c->product(Ht, c->fdtype, k, c->Y);
+  double* part = nullptr;
+  const int nb = dot_partials(Ht, c->Y, c->fdtype, nk, c->ws, &part, nullptr, c->st);
+  if (nb < 0) throw Fail{SYMNMF_E_DEVICE, "dot launch failed"};
+  sum_partials(part, nb, c->d_scal + 3, c->st);
+  double* ga = c->ws.dbl((size_t)k * k);
+  if (!ga) throw Fail{SYMNMF_E_NOMEM, "workspace"};
+  LCHK(gram(Ht, c->fdtype, k, k, Ht, c->fdtype, k, k, n, nullptr, nullptr, nullptr, 0, c->ws, ga, nullptr, 0, 0.0,
+            nullptr, c->st));
+  frob_dot(ga, ga, k * k, c->d_scal + 4, c->st);
+  LCHK(warm_apply(Htf, nk, c->d_scal + 3, c->d_scal + 4, info + 2 * k + 1, c->H, c->W, c->fdtype, c->d_scal + 9,
+                  c->st));
+  c->warm_ran = true;
+  c->refresh_gram(c->W, c->G_W, c->Gh_W, c->Gi_W);
+  c->refresh_gram(c->H, c->G_H, c->Gh_H, c->Gi_H);
+  c->invalidate(SYMNMF_W);
+  c->invalidate(SYMNMF_H);
+  if (beta_out) *beta_out = c->readback(c->d_scal + 9, 1)[0];
+}
+
+size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+// Temporaries of one learned start for n k entries with factor elements of
+// fsize bytes, each piece 256-byte aligned.
+size_t warm_scratch_bytes(int64_t nk, size_t fsize) {
+  return align256((size_t)nk * MLP_D_IN * sizeof(float)) + align256((size_t)nk * sizeof(float)) +
+         align256((size_t)nk * fsize);
+}
+
+// Static device scratch of symnmf_warmstart_noalloc: one copy per GPU, held
+// until the process ends, shared by every call on that GPU.  Host code never
+// uses the array's name (on the host it is a stand-in, not a device address);
+// it uses the address hipGetSymbolAddress returns for the current device.
+constexpr size_t kWarmScratchBytes = (size_t)64 << 20;
+static __device__ __align__(256) char scratch[kWarmScratchBytes];
+
+char* warm_scratch_device() {
+  static std::mutex mu;
+  static std::unordered_map<int, char*> addr;  // device ordinal -> address
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> g(mu);
+  auto it = addr.find(dev);
+  if (it != addr.end()) return it->second;
+  void* ptr = nullptr;
+  HIPCHK(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+  if (!ptr) throw Fail{SYMNMF_E_DEVICE, "hipGetSymbolAddress returned no address for the scratch array"};
+  addr[dev] = (char*)ptr;
+  return (char*)ptr;
+}
 }  // namespace
 
 extern "C" {
@@ -1657,42 +1721,31 @@ int symnmf_warmstart(symnmf_ctx* c, const symnmf_mlp* net, double* beta_out) {
   return guarded(c, [&] {
     if (!net) throw Fail{SYMNMF_E_INVALID, "null network"};
     if (c->l == 0 || !c->U) throw Fail{SYMNMF_E_STATE, "symnmf_lai has not run"};
-    const int n = c->n, k = c->k;
-    const int64_t nk = (int64_t)n * k;
+    const int64_t nk = (int64_t)c->n * c->k;
     if (!c->warm_F) {
       c->warm_F = dalloc<float>((size_t)nk * MLP_D_IN);
       c->warm_Htf = dalloc<float>(nk);
       c->warm_Ht = dalloc<char>((size_t)nk * c->fsize());
     }
-    symnmf_ctx::Timed tm(c, SYMNMF_PHASE_WARM);
-    float* F = c->warm_F;
-    float* Htf = c->warm_Htf;
-    void* Ht = c->warm_Ht;
-    c->ws.reset();
-    double* info = c->ws.dbl((size_t)2 * k + 2);
-    if (!info) throw Fail{SYMNMF_E_NOMEM, "workspace"};
-    LCHK(warm_features(c->U, n, c->l, k, c->lam, c->rowsum, c->d_scal + 1, F, info, c->ws, c->st));
-    LCHK(mlp_forward(net->p, F, nk, Htf, c->st));
-    LCHK(copy_convert(Htf, SYMNMF_F32, Ht, c->fdtype, nk, c->st));
-    // least-squares scale: beta^2 = tr(Ht^T X Ht) / ||Ht^T Ht||_F^2
-    c->product(Ht, c->fdtype, k, c->Y);
-    double* part = nullptr;
-    const int nb = dot_partials(Ht, c->Y, c->fdtype, nk, c->ws, &part, nullptr, c->st);
-    if (nb < 0) throw Fail{SYMNMF_E_DEVICE, "dot launch failed"};
-    sum_partials(part, nb, c->d_scal + 3, c->st);
-    double* ga = c->ws.dbl((size_t)k * k);
-    if (!ga) throw Fail{SYMNMF_E_NOMEM, "workspace"};
-    LCHK(gram(Ht, c->fdtype, k, k, Ht, c->fdtype, k, k, n, nullptr, nullptr, nullptr, 0, c->ws, ga, nullptr, 0, 0.0,
-              nullptr, c->st));
-    frob_dot(ga, ga, k * k, c->d_scal + 4, c->st);
-    LCHK(warm_apply(Htf, nk, c->d_scal + 3, c->d_scal + 4, info + 2 * k + 1, c->H, c->W, c->fdtype, c->d_scal + 9,
-                    c->st));
-    c->warm_ran = true;
-    c->refresh_gram(c->W, c->G_W, c->Gh_W, c->Gi_W);
-    c->refresh_gram(c->H, c->G_H, c->Gh_H, c->Gi_H);
-    c->invalidate(SYMNMF_W);
-    c->invalidate(SYMNMF_H);
-    if (beta_out) *beta_out = c->readback(c->d_scal + 9, 1)[0];
+    warmstart_run(c, net, c->warm_F, c->warm_Htf, c->warm_Ht, beta_out);
+  });
+}
+
+int symnmf_warmstart_noalloc(symnmf_ctx* c, const symnmf_mlp* net, double* beta_out) {
+  return guarded(c, [&] {
+    if (!net) throw Fail{SYMNMF_E_INVALID, "null network"};
+    const size_t need = warm_scratch_bytes((int64_t)c->n * c->k, c->fsize());
+    if (need > kWarmScratchBytes)
+      throw Fail{SYMNMF_E_INVALID, "n k = " + std::to_string((int64_t)c->n * c->k) + " needs " +
+                                       std::to_string(need) + " bytes of temporaries; the static scratch holds " +
+                                       std::to_string(kWarmScratchBytes)};
+    if (c->l == 0 || !c->U) throw Fail{SYMNMF_E_STATE, "symnmf_lai has not run"};
+    char* base = warm_scratch_device();
+    const int64_t nk = (int64_t)c->n * c->k;
+    float* F = (float*)base;
+    float* Htf = (float*)(base + align256((size_t)nk * MLP_D_IN * sizeof(float)));
+    void* Ht = base + align256((size_t)nk * MLP_D_IN * sizeof(float)) + align256((size_t)nk * sizeof(float));
+    warmstart_run(c, net, F, Htf, Ht, beta_out);
   });
 }
 
