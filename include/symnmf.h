@@ -230,8 +230,9 @@ int symnmf_create(symnmf_ctx** out, const symnmf_matrix* X, int32_t k, double al
  * each followed by CholeskyQR in FP64, CholeskyQR2 after the last one;
  * T = Q^T X Q; Jacobi EVD of T;
  * U = Q Q_T) and switch the context to LAI mode (Algorithm LAI-SymNMF).
- * Requires dense X and no sampling.  l: k <= l <= min(n, 96).  q >= 0.
- * Errors: E_INVALID, E_UNSUPPORTED (CSR or s > 0), E_NUMERIC (CholeskyQR2
+ * Dense or CSR X (the algorithms need only products with X: CSR products
+ * run through the sparse kernel), no sampling.  l: k <= l <= min(n, 96).
+ * q >= 0.  Errors: E_INVALID, E_UNSUPPORTED (s > 0), E_NUMERIC (CholeskyQR2
  * breakdown even with the shift), E_STATE. */
 int symnmf_lai(symnmf_ctx* ctx, int32_t l, int32_t q);
 
@@ -388,6 +389,17 @@ int symnmf_mlp_gradient(symnmf_mlp* net, const float* F, const float* T, int64_t
  * by the network) on the gradient of L for this batch; *loss as above (the
  * loss before the step). */
 int symnmf_mlp_train_step(symnmf_mlp* net, const float* F, const float* T, int64_t rows, double lr, double* loss);
+/* Write the parameters to a file (host path; the library's own format, read
+ * by symnmf_mlp_load): 8 bytes "SYMNMLP1", int32 hidden width, int32 feature
+ * count (6), int64 parameter count, then the FP32 parameters in the layout
+ * above, all little-endian.  The Adam state is not written.  Waits for the
+ * network's stream.  Errors: E_INVALID (null path, cannot write), E_DEVICE. */
+int symnmf_mlp_save(symnmf_mlp* net, const char* path);
+/* New network (as symnmf_mlp_create, on hip_stream) with the parameters of a
+ * file written by symnmf_mlp_save; fresh Adam state.  Errors: E_INVALID
+ * (cannot read, wrong magic, widths, count or length; message via
+ * symnmf_mlp_last_error(NULL)), E_NOMEM, E_DEVICE. */
+int symnmf_mlp_load(symnmf_mlp** out, const char* path, void* hip_stream);
 const char* symnmf_mlp_last_error(const symnmf_mlp* net);
 void symnmf_mlp_destroy(symnmf_mlp* net);
 

@@ -91,6 +91,8 @@ _SIGS = {
     "symnmf_mlp_gradient": (ctypes.c_int, [_VP, _VP, _VP, ctypes.c_int64, _VP, ctypes.POINTER(ctypes.c_double)]),
     "symnmf_mlp_train_step": (ctypes.c_int, [_VP, _VP, _VP, ctypes.c_int64, ctypes.c_double,
                                              ctypes.POINTER(ctypes.c_double)]),
+    "symnmf_mlp_save": (ctypes.c_int, [_VP, ctypes.c_char_p]),
+    "symnmf_mlp_load": (ctypes.c_int, [ctypes.POINTER(_VP), ctypes.c_char_p, _VP]),
     "symnmf_mlp_last_error": (ctypes.c_char_p, [_VP]),
     "symnmf_mlp_destroy": (None, [_VP]),
     "symnmf_warm_features": (ctypes.c_int, [_VP, _VP]),
@@ -302,6 +304,16 @@ def _mcheck(rc, net):
 def symnmf_mlp_create(hidden=MLP_HIDDEN, seed=0, stream=None):
     h = ctypes.c_void_p()
     _mcheck(lib().symnmf_mlp_create(ctypes.byref(h), int(hidden), int(seed), _stream_ptr(stream)), None)
+    return Mlp(h)
+
+
+def symnmf_mlp_save(net, path):
+    _mcheck(lib().symnmf_mlp_save(net.handle, os.fsencode(path)), net)
+
+
+def symnmf_mlp_load(path, stream=None):
+    h = ctypes.c_void_p()
+    _mcheck(lib().symnmf_mlp_load(ctypes.byref(h), os.fsencode(path), _stream_ptr(stream)), None)
     return Mlp(h)
 
 

@@ -8,21 +8,64 @@
 
 namespace {
 
+// Scalars pass over CSR values: 16 lanes per row (each group reads its row's
+// values in coalesced 16-element runs and sums them with shuffles inside the
+// group), the 16 groups of a block walk a contiguous range of rows; per block
+// one partial (sum, sum of squares, max) in a fixed order.
 template <typename TV>
 __global__ __launch_bounds__(256) void k_csr_rowstats(const int* __restrict__ rp, const TV* __restrict__ val, int n,
-                                                      double* __restrict__ rowsum, double* __restrict__ bpart) {
+                                                      int rows_per_block, double* __restrict__ rowsum,
+                                                      double* __restrict__ bpart) {
+  __shared__ double red[3][16];
+  const int g = threadIdx.x >> 4, li = threadIdx.x & 15;
+  const int r0 = blockIdx.x * rows_per_block;
+  const int r1 = min(n, r0 + rows_per_block);
+  double s = 0.0, q = 0.0, m = -INFINITY;
+  for (int i = r0 + g; i < r1; i += 16) {
+    double rs = 0.0, rq = 0.0, rm = -INFINITY;
+    const int e1 = rp[i + 1];
+    for (int e = rp[i] + li; e < e1; e += 16) {
+      const double v = (double)val[e];
+      rs += v;
+      rq += v * v;
+      rm = fmax(rm, v);
+    }
+#pragma unroll
+    for (int o = 8; o > 0; o >>= 1) {
+      rs += __shfl_xor(rs, o, 16);
+      rq += __shfl_xor(rq, o, 16);
+      rm = fmax(rm, __shfl_xor(rm, o, 16));
+    }
+    if (li == 0) rowsum[i] = rs;
+    s += rs;
+    q += rq;
+    m = fmax(m, rm);
+  }
+  if (li == 0) {
+    red[0][g] = s;
+    red[1][g] = q;
+    red[2][g] = m;
+  }
+  __syncthreads();
+  if (threadIdx.x < 3) {
+    const int t = threadIdx.x;
+    double v = t == 2 ? -INFINITY : 0.0;
+    for (int j = 0; j < 16; ++j) v = t == 2 ? fmax(v, red[2][j]) : v + red[t][j];
+    bpart[3 * blockIdx.x + t] = v;
+  }
+}
+
+// The block partials in a fixed order: thread t sums partials t, t + 256, ...
+// in turn, then a fixed tree over the threads.
+__global__ __launch_bounds__(256) void k_csr_scalars_final(int nb, const double* __restrict__ bpart,
+                                                           double* __restrict__ out) {
   __shared__ double sc[8];
   __shared__ double smax[256];
-  const int i = blockIdx.x * 256 + threadIdx.x;
   double s = 0.0, q = 0.0, m = -INFINITY;
-  if (i < n) {
-    for (int e = rp[i]; e < rp[i + 1]; ++e) {
-      const double v = (double)val[e];
-      s += v;
-      q += v * v;
-      m = fmax(m, v);
-    }
-    rowsum[i] = s;
+  for (int b = threadIdx.x; b < nb; b += 256) {
+    s += bpart[3 * b];
+    q += bpart[3 * b + 1];
+    m = fmax(m, bpart[3 * b + 2]);
   }
   const double ts = block_sum(s, sc);
   const double tq = block_sum(q, sc);
@@ -33,23 +76,10 @@ __global__ __launch_bounds__(256) void k_csr_rowstats(const int* __restrict__ rp
     __syncthreads();
   }
   if (threadIdx.x == 0) {
-    bpart[3 * blockIdx.x + 0] = ts;
-    bpart[3 * blockIdx.x + 1] = tq;
-    bpart[3 * blockIdx.x + 2] = smax[0];
+    out[0] = tq;
+    out[1] = ts;
+    out[2] = smax[0];
   }
-}
-
-__global__ void k_csr_scalars_final(int nb, const double* __restrict__ bpart, double* __restrict__ out) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  double s = 0.0, q = 0.0, m = -INFINITY;
-  for (int b = 0; b < nb; ++b) {
-    s += bpart[3 * b];
-    q += bpart[3 * b + 1];
-    m = fmax(m, bpart[3 * b + 2]);
-  }
-  out[0] = q;
-  out[1] = s;
-  out[2] = m;
 }
 
 // Wave per row.  CW lanes per group cover the columns (CPL columns per lane,
@@ -258,14 +288,16 @@ void spmm_dispatch(const int* rp, const int* ci, const TV* val, int n, const TB*
 int csr_scalars(const int* rp, const void* val, int vdtype, int n, int64_t nnz, Workspace& ws, double* d_rowsum,
                 double* d_out3, hipStream_t s) {
   (void)nnz;
-  const int nb = ceil_div(n, 256);
+  // about four blocks per CU, at least 16 rows (one per lane group) each
+  const int rows_per_block = std::max(16, ceil_div(n, 1024));
+  const int nb = ceil_div(n, rows_per_block);
   double* bpart = ws.dbl(3 * (size_t)nb);
   if (!bpart) return -1;
   if (vdtype == SYMNMF_F64)
-    k_csr_rowstats<double><<<nb, 256, 0, s>>>(rp, (const double*)val, n, d_rowsum, bpart);
+    k_csr_rowstats<double><<<nb, 256, 0, s>>>(rp, (const double*)val, n, rows_per_block, d_rowsum, bpart);
   else
-    k_csr_rowstats<float><<<nb, 256, 0, s>>>(rp, (const float*)val, n, d_rowsum, bpart);
-  k_csr_scalars_final<<<1, 64, 0, s>>>(nb, bpart, d_out3);
+    k_csr_rowstats<float><<<nb, 256, 0, s>>>(rp, (const float*)val, n, rows_per_block, d_rowsum, bpart);
+  k_csr_scalars_final<<<1, 256, 0, s>>>(nb, bpart, d_out3);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
@@ -283,6 +315,8 @@ int csr_spmm(const int* rp, const int* ci, const void* val, int vdtype, int n, c
       spmm_dispatch<float, __bf16, float>(rp, ci, (const float*)val, n, (const __bf16*)B, c, (float*)Y, ldy, st, s);
     else if (bdtype == SYMNMF_F64 && ydtype == SYMNMF_F64)
       spmm_dispatch<float, double, double>(rp, ci, (const float*)val, n, (const double*)B, c, (double*)Y, ldy, st, s);
+    else if (bdtype == SYMNMF_F64 && ydtype == SYMNMF_F32)
+      spmm_dispatch<float, double, float>(rp, ci, (const float*)val, n, (const double*)B, c, (float*)Y, ldy, st, s);
     else
       return -1;
   }

@@ -931,6 +931,16 @@ int mlp_guarded(symnmf_mlp* net, Fn&& fn) {
   }
 }
 
+// File of a network's parameters (symnmf_mlp_save / symnmf_mlp_load).
+constexpr char kMlpMagic[8] = {'S', 'Y', 'M', 'N', 'M', 'L', 'P', '1'};
+struct MlpFileHeader {
+  char magic[8];
+  int32_t hidden;
+  int32_t features;
+  int64_t count;
+};
+static_assert(sizeof(MlpFileHeader) == 24, "file header layout");
+
 void mlp_grad(symnmf_mlp* net, const float* F, const float* T, int64_t rows, double* loss) {
   if (rows < 1 || !F || !T) throw Fail{SYMNMF_E_INVALID, "argument"};
   net->ensure(rows);
@@ -1269,7 +1279,6 @@ namespace {
 
 // Validation and (re)allocation of the LAI buffers for rank l.
 void lai_prepare(symnmf_ctx* c, int l) {
-  if (c->kind != SYMNMF_DENSE) throw Fail{SYMNMF_E_UNSUPPORTED, "LAI needs dense X"};
   if (c->mode == SYMNMF_MODE_LVS) throw Fail{SYMNMF_E_UNSUPPORTED, "LAI with sampling"};
   if (l < c->k || l > 96 || l > c->n) throw Fail{SYMNMF_E_INVALID, "need k <= l <= min(n, 96)"};
   const int n = c->n;
@@ -1700,6 +1709,67 @@ int symnmf_mlp_train_step(symnmf_mlp* net, const float* F, const float* T, int64
     net->t += 1;
     LCHK(mlp_adam(net->p, net->g, net->m, net->v, net->np, lr, net->t, net->st));
   });
+}
+
+int symnmf_mlp_save(symnmf_mlp* net, const char* path) {
+  return mlp_guarded(net, [&] {
+    if (!path) throw Fail{SYMNMF_E_INVALID, "null path"};
+    std::vector<float> h((size_t)net->np);
+    HIPCHK(hipMemcpyAsync(h.data(), net->p, sizeof(float) * net->np, hipMemcpyDeviceToHost, net->st));
+    HIPCHK(hipStreamSynchronize(net->st));
+    MlpFileHeader hd;
+    std::memcpy(hd.magic, kMlpMagic, sizeof(hd.magic));
+    hd.hidden = net->hidden;
+    hd.features = MLP_D_IN;
+    hd.count = net->np;
+    FILE* f = std::fopen(path, "wb");
+    if (!f) throw Fail{SYMNMF_E_INVALID, std::string("cannot open ") + path + " for writing"};
+    const bool ok = std::fwrite(&hd, sizeof(hd), 1, f) == 1 && std::fwrite(h.data(), sizeof(float), h.size(), f) == h.size();
+    const bool closed = std::fclose(f) == 0;
+    if (!ok || !closed) throw Fail{SYMNMF_E_INVALID, std::string("write to ") + path + " failed"};
+  });
+}
+
+int symnmf_mlp_load(symnmf_mlp** out, const char* path, void* hip_stream) {
+  if (!out || !path) {
+    g_create_error = "null argument";
+    return SYMNMF_E_INVALID;
+  }
+  *out = nullptr;
+  MlpFileHeader hd;
+  std::vector<float> h;
+  {
+    FILE* f = std::fopen(path, "rb");
+    if (!f) {
+      g_create_error = std::string("cannot open ") + path;
+      return SYMNMF_E_INVALID;
+    }
+    bool ok = std::fread(&hd, sizeof(hd), 1, f) == 1 && std::memcmp(hd.magic, kMlpMagic, sizeof(hd.magic)) == 0 &&
+              hd.features == MLP_D_IN && mlp_param_count(hd.hidden) > 0 && hd.count == mlp_param_count(hd.hidden);
+    if (ok) {
+      h.resize((size_t)hd.count);
+      ok = std::fread(h.data(), sizeof(float), h.size(), f) == h.size() && std::fgetc(f) == EOF;
+    }
+    std::fclose(f);
+    if (!ok) {
+      g_create_error = std::string(path) + " is not a network file of this library (magic, sizes or length)";
+      return SYMNMF_E_INVALID;
+    }
+  }
+  symnmf_mlp* net = nullptr;
+  int rc = symnmf_mlp_create(&net, hd.hidden, 0, hip_stream);
+  if (rc != SYMNMF_OK) return rc;
+  rc = mlp_guarded(net, [&] {
+    HIPCHK(hipMemcpyAsync(net->p, h.data(), sizeof(float) * net->np, hipMemcpyHostToDevice, net->st));
+    HIPCHK(hipStreamSynchronize(net->st));
+  });
+  if (rc != SYMNMF_OK) {
+    g_create_error = net->err;
+    delete net;
+    return rc;
+  }
+  *out = net;
+  return SYMNMF_OK;
 }
 
 const char* symnmf_mlp_last_error(const symnmf_mlp* net) { return net ? net->err.c_str() : g_create_error.c_str(); }

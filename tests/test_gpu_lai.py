@@ -162,3 +162,48 @@ def test_ada_rrf_parity(dtype):
     with pytest.raises(P.SymNMFError) as e:
         P.symnmf_lai_adaptive(ctx, l, 0, 1e-3)
     assert e.value.code == P.E_INVALID
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_lai_on_csr_parity(dtype):
+    """Algorithms RRF, Apx-EVD and LAI-SymNMF on a sparse graph (the
+    algorithms need only products with X, which run through the CSR kernel),
+    then the learned start's features and refinement on the CSR X."""
+    from oracle import warmstart as WS
+    from gpu_common import csr_dev
+    import scipy.sparse as sp
+    n, k, l, q, seed, iters = 3001, 8, 24, 2, 6, 8
+    Xs, _ = workloads.sbm(n, 8, 24.0, 20.0, seed=4)
+    if dtype == "f64":
+        Xs = sp.csr_matrix((Xs.data.astype(np.float64), Xs.indices, Xs.indptr), shape=Xs.shape)
+    X64 = sp.csr_matrix((Xs.data.astype(np.float64), Xs.indices, Xs.indptr), shape=Xs.shape)
+    ctx = P.symnmf_create(csr_dev(Xs), k, 0.0, 0, seed)
+    P.symnmf_lai(ctx, l, q)
+    U = torch.empty((n, l), dtype=torch.float64, device="cuda")
+    lam = torch.empty(l, dtype=torch.float64, device="cuda")
+    P.symnmf_get_lai(ctx, U, lam)
+    Ug, lg = host(U), host(lam)
+    Uo, lo = O.apx_evd(lambda M: X64 @ M, O.sketch_omega(n, l, seed), q)
+    tol = 1e-10 if dtype == "f64" else 1e-4
+    S = np.arange(0, n, 37)
+    e_l, e_x = rel(lg, lo), rel((Ug[S] * lg) @ Ug.T, (Uo[S] * lo) @ Uo.T)
+    log(f"csr lai {dtype}: lambda rel {e_l:.2e}, sampled U Lambda U^T rows rel {e_x:.2e}")
+    assert np.abs(Ug.T @ Ug - np.eye(l)).max() <= 1e-12
+    assert e_l <= tol and e_x <= 10 * tol
+    sc = O.data_scalars(X64)
+    F = torch.empty((n * k, P.MLP_FEATURES), dtype=torch.float32, device="cuda")
+    P.symnmf_warm_features(ctx, F)
+    Fo = WS.features(Ug, lg, sc["rowsum"], k)
+    assert max(rel(host(F)[:, c], Fo[:, c]) for c in range(P.MLP_FEATURES)) <= 1e-5
+    H0 = factor(ctx, P.H)
+    P.symnmf_iterate(ctx, iters)
+    Wo, Ho, hist = O.lai_symnmf(Ug, lg, k, sc["maxval"], H0, iters)
+    hg = np.array(P.symnmf_history(ctx))
+    rtol = 1e-8 if dtype == "f64" else 1e-4
+    log(f"csr lai {dtype}: {iters} LAI iterations, history max rel {np.max(np.abs(hg - hist) / hist):.2e}")
+    assert np.max(np.abs(hg - hist) / hist) <= rtol
+    P.symnmf_refine(ctx, P.STOP_NONE, 0.0)
+    P.symnmf_iterate(ctx, 3)
+    W2, H2, h2 = O.anls(lambda B: X64 @ B, sc["normsq"], Ho, sc["maxval"], 3, W0=Wo)
+    hg = np.array(P.symnmf_history(ctx))
+    assert np.max(np.abs(hg[iters:] - h2) / h2) <= rtol

@@ -3,6 +3,8 @@
 gradients, Adam steps, entry features, the scaled start, the fallback, and a
 test that a network trained on the GPU shortens the way to the target
 residual compared with the random start."""
+import os
+
 import numpy as np
 import pytest
 
@@ -61,6 +63,33 @@ def test_mlp_init_matches_oracle():
     assert P.symnmf_mlp_num_params(net) == 8833
     ref = round_to(_flat(WS.init_params(WS.layer_sizes(), 17)), torch.float32)
     assert np.array_equal(_params(net), ref)
+
+
+def test_mlp_save_and_load(tmp_path):
+    """A saved network loads back with the same parameters and outputs; files
+    that are not the library's format are refused."""
+    net = P.symnmf_mlp_create(P.MLP_HIDDEN, 3)
+    P.symnmf_mlp_set_params(net, dev(_flat(_trained_like(8)), torch.float32))
+    path = str(tmp_path / "net.bin")
+    P.symnmf_mlp_save(net, path)
+    assert os.path.getsize(path) == 24 + 4 * 8833
+    back = P.symnmf_mlp_load(path)
+    assert np.array_equal(_params(back), _params(net))
+    F = dev(_random_features(999, 5), torch.float32)
+    Y1 = torch.empty(999, dtype=torch.float32, device="cuda")
+    Y2 = torch.empty_like(Y1)
+    P.symnmf_mlp_forward(net, F, Y1)
+    P.symnmf_mlp_forward(back, F, Y2)
+    assert torch.equal(Y1, Y2)
+    raw = open(path, "rb").read()
+    for bad in (raw[:-4], raw + b"\0", b"XYMNMLP1" + raw[8:]):
+        p2 = str(tmp_path / "bad.bin")
+        open(p2, "wb").write(bad)
+        with pytest.raises(P.SymNMFError) as e:
+            P.symnmf_mlp_load(p2)
+        assert e.value.code == P.E_INVALID
+    with pytest.raises(P.SymNMFError):
+        P.symnmf_mlp_load(str(tmp_path / "missing.bin"))
 
 
 @pytest.mark.parametrize("rows", [1, 257, 5000])
