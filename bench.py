@@ -30,6 +30,15 @@ and the live roofline of the dominant kernel (the X H product).  Also
 reported: the FP64 CPU oracle timed on a bounded sample on the host cores.
 `--pmc-probe` runs the short fixed workload the rocprofv3 counter passes are
 taken on (with `--workload sparse`: the CSR product's).
+
+The default run also measures the other workloads and puts their records
+under config.workloads (each with its own roofline; --only-headline skips
+them): sparse (SBM graph n = 2^20, k = 64: plain CSR HALS, BF16 gathers,
+leverage-score sampling, SpMM roofline), precision (n = 65536, k = 64 in FP32
+and BF16, product rates against HBM and the matrix-core peaks, the FP64
+oracle's check of both) and warmstart (the learned start against the random
+start on the 200 held-out generated instances).  Each can also be run alone
+with --workload.
 """
 import argparse
 import json
@@ -42,6 +51,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 FP32_MFMA_PEAK_TFLOPS = 157.3
+BF16_MFMA_PEAK_TFLOPS = 2500.0
 
 
 def log(msg):
@@ -58,12 +68,19 @@ def main():
     ap.add_argument("--dim", type=int, default=64)
     ap.add_argument("--comps", type=int, default=32)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--only-headline", action="store_true",
+                    help="default workload only, without the sparse, precision and learned-start workloads")
     ap.add_argument("--pmc-probe", action="store_true",
                     help="run the short counter-collection workload and exit")
-    ap.add_argument("--workload", choices=["dense", "sparse", "precision"], default="dense",
+    ap.add_argument("--workload", choices=["dense", "sparse", "precision", "warmstart"], default="dense",
                     help="dense: the Gaussian-kernel similarity (default, the headline line); "
                          "sparse: the normalised SBM graph, plain CSR HALS vs leverage-score sampling; "
-                         "precision: n = 65536, k = 64 dense similarity in FP32 and BF16")
+                         "precision: n = 65536, k = 64 dense similarity in FP32 and BF16; "
+                         "warmstart: learned start vs random start on the held-out generated instances")
+    ap.add_argument("--warm-count", type=int, default=200, help="held-out instances evaluated")
+    ap.add_argument("--warm-first", type=int, default=0, help="index of the first held-out instance")
+    ap.add_argument("--warm-weights", default=None, help="network file (default: the committed one)")
+    ap.add_argument("--warm-out", default=None, help="also write the per-instance records to this JSON file")
     ap.add_argument("--precision-n", type=int, default=65536)
     ap.add_argument("--sparse-n", type=int, default=1 << 20)
     ap.add_argument("--sparse-k", type=int, default=64)
@@ -81,10 +98,13 @@ def main():
             pmc_probe(args)
         return
     if args.workload == "sparse":
-        bench_sparse(args)
+        print(json.dumps(bench_sparse(args)), flush=True)
         return
     if args.workload == "precision":
-        bench_precision(args)
+        print(json.dumps(bench_precision(args)), flush=True)
+        return
+    if args.workload == "warmstart":
+        print(json.dumps(bench_warmstart(args)), flush=True)
         return
 
     import numpy as np
@@ -112,7 +132,7 @@ def main():
     log(f"[bench] plain converged: {iters_conv} iterations, residual {r_conv:.6f}; r* = {r_star:.6f}")
 
     from paper_2402_08134_amd import warmstart as WSP
-    net = WSP.load(os.path.join(WSP.WEIGHTS_DIR, "warmstart_gk.npz"))
+    net = WSP.load(os.path.join(WSP.WEIGHTS_DIR, "warmstart.bin"))
 
     def solve(method, seed, timing):
         """One solve to r* (PGNCG methods: to the stall rule); returns
@@ -208,7 +228,9 @@ def main():
 
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(Xh, k, int(np.median(res["plain"]["iterations"])))
+        log("[bench] oracle: one learned_lai solve on the host ...")
+        cpu = cpu_baseline(Xh, k, l, q, net_params_host(P, net), r_star)
+        log(f"[bench] oracle learned_lai solve {cpu['value']:.1f} s ({cpu['sample']})")
 
     t_val = res["learned_lai"]["s_per_solve"]
     out = {
@@ -242,6 +264,24 @@ def main():
         "phases_ms_per_solve": {m: {kk: v[0] for kk, v in ph.items()} for m, ph in phases.items()},
         "cpu_baseline": cpu,
     }
+    if not args.only_headline:
+        # the other workloads, each with its own roofline: the sparse graph,
+        # the precision sweep and the learned-start study
+        del X, Xh, net
+        torch.cuda.empty_cache()
+        P.symnmf_trim_cache()
+        others = {}
+        for name, fn in (("sparse", bench_sparse), ("precision", bench_precision), ("warmstart", bench_warmstart)):
+            t0 = time.time()
+            r = fn(args) if name != "warmstart" else fn(args, log_each=False)
+            r = {kk: v for kk, v in r.items() if kk not in ("n_gpus", "scaling", "vs_baseline", "data", "steps",
+                                                          "warmup")}
+            r["bench_seconds"] = round(time.time() - t0, 1)
+            others[name] = r
+            log(f"[bench] workload {name} done in {r['bench_seconds']} s")
+            torch.cuda.empty_cache()
+            P.symnmf_trim_cache()
+        out["config"]["workloads"] = others
     print(json.dumps(out), flush=True)
 
 
@@ -347,7 +387,153 @@ def bench_sparse(args):
         "phases_ms_per_iteration": phases,
         "cpu_baseline": None,
     }
-    print(json.dumps(out), flush=True)
+    return out
+
+
+WARM_WEIGHTS = "warmstart.bin"
+
+
+def warm_solve(P, X, k, r_star, method, nets, seed=1):
+    """One solve of a learned-start study instance to r* = r_conv + 1e-3,
+    create included.  plain: random start, iterations on X.  lai: random
+    start, LAI iterations (l = k + 16, q = 2) until their own residual
+    stalls, then refinement on X until r*.  learned / untrained: the start
+    from the trained / untrained network on the LAI basis, then iterations on
+    X; learned_lai / untrained_lai: that start, then LAI iterations and
+    refinement as in lai.  Returns (context, iterations, iterations on X)."""
+    l, q = k + 16, 2
+    lai_stage = method.endswith("lai")
+    o = P.symnmf_default_options(stop_mode=P.STOP_STALL if lai_stage else P.STOP_TARGET,
+                                 target=r_star, check_every=8 if lai_stage else 4)
+    c = P.symnmf_create(X, k, 0.0, 0, seed, o)
+    if method == "plain":
+        it = P.symnmf_iterate(c, 3000)
+        return c, it, it
+    P.symnmf_lai(c, l, q)
+    if method.startswith("learned"):
+        P.symnmf_warmstart(c, nets["learned"], want_beta=False)
+    elif method.startswith("untrained"):
+        P.symnmf_warmstart(c, nets["untrained"], want_beta=False)
+    it = P.symnmf_iterate(c, 2000) if lai_stage else 0
+    P.symnmf_refine(c, P.STOP_TARGET, r_star)
+    it2 = P.symnmf_iterate(c, 3000)
+    return c, it + it2, it2
+
+
+def bench_warmstart(args, log_each=True):
+    """The learned start on the held-out instances of the learned-start study
+    (workloads.warm_instance, ids 1800..1999: SBM graphs and Gaussian-kernel
+    similarities, n in [4096, 32768], k in {16, 32, 64}).  Per instance: the
+    plain method from the random start until the stall rule gives r_conv;
+    then each method is timed once to r* = r_conv + 1e-3 (wall clock around
+    the whole solve, create included, device synchronised on both sides).
+    Reports the per-instance time ratios of learned vs plain (the network's
+    start, then the same iterations on X), learned_lai vs lai (so that the
+    LAI's own gain is not credited to the network), learned_lai vs plain,
+    and the untrained network's starts as the ablation; medians, fractions
+    of wins and histograms of the iteration counts."""
+    import numpy as np
+    import torch
+    import paper_2402_08134_amd as P
+    from paper_2402_08134_amd import warmstart as WSP
+    import workloads
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    P.lib()
+    wpath = args.warm_weights or os.path.join(WSP.WEIGHTS_DIR, WARM_WEIGHTS)
+    nets = {"learned": WSP.load(wpath), "untrained": P.symnmf_mlp_create(P.MLP_HIDDEN, 7)}
+    methods = ["plain", "lai", "learned", "learned_lai", "untrained", "untrained_lai"]
+    ids = list(workloads.WARM_HELD_OUT_IDS)[args.warm_first:args.warm_first + args.warm_count]
+
+    def device_X(spec):
+        X = workloads.warm_instance_data(spec)
+        if spec["kind"] == "sbm":
+            return (torch.from_numpy(X.indptr.astype(np.int32)).cuda(),
+                    torch.from_numpy(X.indices.astype(np.int32)).cuda(), torch.from_numpy(X.data).cuda(), spec["n"])
+        return X
+
+    # warm-up on a small instance: library load, kernels, graph instantiation
+    wspec = dict(workloads.warm_instance(ids[0]), n=4096)
+    for kind in ("sbm", "gmm"):
+        Xw = device_X(dict(wspec, kind=kind))
+        for m in methods:
+            c, _, _ = warm_solve(P, Xw, wspec["k"], 2.0, m, nets)
+            del c
+        del Xw
+    torch.cuda.synchronize()
+
+    recs = []
+    t_all = time.time()
+    for i in ids:
+        spec = workloads.warm_instance(i)
+        n, k = spec["n"], spec["k"]
+        X = device_X(spec)
+        torch.cuda.synchronize()
+        o = P.symnmf_default_options(stop_mode=P.STOP_STALL, check_every=8)
+        ref = P.symnmf_create(X, k, 0.0, 0, 1, o)
+        it_conv = P.symnmf_iterate(ref, 3000)
+        r_conv = P.symnmf_residual(ref, P.RESID_EXACT)[0]
+        del ref
+        r_star = r_conv + 1e-3
+        rec = {"id": i, "kind": spec["kind"], "n": n, "k": k, "r_conv": r_conv, "plain_conv_iterations": it_conv}
+        for m in methods:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            c, it, itx = warm_solve(P, X, k, r_star, m, nets)
+            torch.cuda.synchronize()
+            t = time.perf_counter() - t0
+            r = P.symnmf_residual(c, P.RESID_EXACT)[0]
+            del c
+            rec[m] = {"s": t, "iterations": it, "iterations_on_X": itx, "residual": r, "reached": bool(r <= r_star)}
+        recs.append(rec)
+        del X
+        if log_each:
+            log(f"[warm] {i} {spec['kind']} n={n} k={k} r*={r_star:.5f}: " +
+                " ".join(f"{m} {rec[m]['s'] * 1e3:.1f}ms/{rec[m]['iterations']}" for m in methods) +
+                f"  [{time.time() - t_all:.0f}s]")
+
+    def pair(a, b, sel=None):
+        rs = [r for r in recs if sel is None or sel(r)]
+        if not rs:
+            return None
+        ratio = np.array([r[a]["s"] / r[b]["s"] if r[a]["reached"] else np.inf for r in rs])
+        iratio = np.array([r[a]["iterations"] / max(r[b]["iterations"], 1) for r in rs])
+        return {"instances": len(rs), "median_time_ratio": float(np.median(ratio)),
+                "geomean_time_ratio": float(np.exp(np.mean(np.log(ratio)))) if np.all(np.isfinite(ratio)) else None,
+                "fraction_faster": float(np.mean(ratio < 1.0)),
+                "median_iteration_ratio": float(np.median(iratio)),
+                "not_reached": int(sum(1 for r in rs if not r[a]["reached"]))}
+
+    kinds = {"all": None, "sbm": lambda r: r["kind"] == "sbm", "gmm": lambda r: r["kind"] == "gmm"}
+    for kk in (16, 32, 64):
+        kinds[f"k{kk}"] = (lambda kk_: (lambda r: r["k"] == kk_))(kk)
+    pairs = {"learned_vs_plain": ("learned", "plain"), "learned_lai_vs_lai": ("learned_lai", "lai"),
+             "learned_lai_vs_plain": ("learned_lai", "plain"), "lai_vs_plain": ("lai", "plain"),
+             "untrained_vs_plain": ("untrained", "plain"), "untrained_lai_vs_lai": ("untrained_lai", "lai")}
+    summary = {name: {g: pair(a, b, sel) for g, sel in kinds.items()} for name, (a, b) in pairs.items()}
+    edges = [0, 5, 10, 20, 40, 80, 160, 320, 640, 1280, 100000]
+    hist = {m: np.histogram([r[m]["iterations"] for r in recs], bins=edges)[0].tolist() for m in methods}
+    if args.warm_out:
+        with open(args.warm_out, "w") as f:
+            json.dump(recs, f)
+    med = summary["learned_vs_plain"]["all"]["median_time_ratio"]
+    return {
+        "metric": "learned-start vs random-start time to r* = r_conv + 1e-3 (median per-instance time ratio, "
+                  "learned / plain)",
+        "value": med,
+        "unit": "ratio",
+        "n_gpus": 1,
+        "higher_is_better": False,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"{len(recs)} held-out generated instances (ids {ids[0]}..{ids[-1]}; SBM graphs and "
+                               f"Gaussian-kernel similarities, n in [4096, 32768], k in {{16, 32, 64}}), "
+                               f"HALS, l = k + 16, q = 2",
+                   "weights": os.path.basename(wpath), "pairs": summary,
+                   "iteration_histogram": {"bin_edges": edges, **hist},
+                   "median_s": {m: float(np.median([r[m]["s"] for r in recs])) for m in methods},
+                   "eval_seconds": round(time.time() - t_all, 1)},
+    }
 
 
 def bench_precision(args):
@@ -370,7 +556,7 @@ def bench_precision(args):
     t0 = time.time()
     X = workloads.gpu_gaussian_kernel(n, 128, 64, seed=0)
     log(f"[bench] generated X n={n} on the GPU in {time.time() - t0:.1f}s")
-    net = WSP.load(os.path.join(WSP.WEIGHTS_DIR, "warmstart_gk.npz"))
+    net = WSP.load(os.path.join(WSP.WEIGHTS_DIR, "warmstart.bin"))
     o = P.symnmf_default_options(stop_mode=P.STOP_STALL, check_every=8)
     ref = P.symnmf_create(X, k, 0.0, 0, 1, o)
     iters_conv = P.symnmf_iterate(ref, 2000)
@@ -385,6 +571,8 @@ def bench_precision(args):
                                      check_every=8 if lai_stage else 4, timing=timing)
         if prec == "bf16":
             o.compute_dtype = P.BF16
+        elif prec == "f32x3":
+            o.compute_dtype = P.F32X3
         c = P.symnmf_create(X, k, 0.0, 0, seed, o)
         if method == "plain":
             it = P.symnmf_iterate(c, 600)
@@ -411,16 +599,35 @@ def bench_precision(args):
             res[f"{m}_{prec}"] = {"s_per_solve": t, "iterations": it, "iterations_on_X": itx, "final_residual": r,
                                   "reached_r_star": bool(r <= r_star + 1e-12)}
             log(f"[bench] {m:12s} {prec:5s} {t * 1e3:9.2f} ms/solve  iterations {it} (on X {itx})  residual {r:.6f}")
-    # live roofline of the BF16 product (dominant kernel of the BF16 solves)
-    c, _, _ = solve("plain", "bf16", 1, 1)
-    ph = phase_totals(P, [c])
-    del c
-    ms, calls = ph["product"]
-    t_prod = ms / 1e3 / calls
-    alg_bytes = float(n) * n * 2 + 2.0 * n * k * 4
+    # live roofline of the BF16 product (dominant kernel of the BF16 solves),
+    # and the FP32 products' rate against the FP32 matrix-core peak (X H at
+    # k = 64 is bound by the matrix cores in FP32: 2 n^2 k flop on 4 n^2
+    # bytes); also FP32 through three BF16 pieces on the BF16 matrix cores
+    products = {}
+    for prec in ("bf16", "f32", "f32x3"):
+        c, it, _ = solve("plain", prec, 1, 1)
+        ph = phase_totals(P, [c])
+        r = P.symnmf_residual(c, P.RESID_EXACT)[0]
+        del c
+        ms_, calls_ = ph["product"]
+        t_ = ms_ / 1e3 / calls_
+        xb = 2 if prec == "bf16" else 4
+        alg_ = float(n) * n * xb + 2.0 * n * k * 4
+        products[prec] = {"us_per_launch": t_ * 1e6, "launches": calls_, "algorithmic_bytes_per_launch": alg_,
+                          "hbm_gbs": alg_ / t_ / 1e9, "hbm_frac": alg_ / t_ / 1e9 / HBM_PEAK_GBS,
+                          "tflops": 2.0 * n * n * k / t_ / 1e12,
+                          "mfma_frac": 2.0 * n * n * k / t_ / 1e12 /
+                                       (BF16_MFMA_PEAK_TFLOPS if prec == "bf16" else FP32_MFMA_PEAK_TFLOPS),
+                          "plain_iterations": it, "plain_final_residual": r}
+        log(f"[bench] {prec:5s} X*H {t_ * 1e6:8.1f} us over {calls_} launches -> {alg_ / t_ / 1e9:.0f} GB/s "
+            f"algorithmic, {2.0 * n * n * k / t_ / 1e12:.1f} TFLOP/s")
+    res["products"] = products
+    t_prod = products["bf16"]["us_per_launch"] / 1e6
+    calls = products["bf16"]["launches"]
+    alg_bytes = products["bf16"]["algorithmic_bytes_per_launch"]
     achieved = alg_bytes / t_prod / 1e9
-    log(f"[bench] BF16 X*H {t_prod * 1e6:.1f} us over {calls} launches -> {achieved:.0f} GB/s algorithmic")
-    best = min((v["s_per_solve"], kk) for kk, v in res.items() if kk.endswith("bf16") and v["reached_r_star"])
+    best = min((v["s_per_solve"], kk) for kk, v in res.items()
+               if kk.endswith("bf16") and kk != "products" and v["reached_r_star"])
     cpu = None if args.no_cpu_baseline else precision_oracle_leg(X, k, res)
     out = {
         "metric": "SymNMF time-to-residual (s) and X*H GB/s or MFMA %, learned-init vs plain",
@@ -435,7 +642,8 @@ def bench_precision(args):
                      "us_per_launch": t_prod * 1e6, "launches": calls, "algorithmic_bytes_per_launch": alg_bytes},
         "cpu_baseline": cpu,
     }
-    print(json.dumps(out), flush=True)
+    del X
+    return out
 
 
 def precision_oracle_leg(X, k, res):
@@ -563,23 +771,46 @@ def pmc_probe_sparse(args):
         del c
 
 
-def cpu_baseline(Xh, k, iters_gpu):
-    """The FP64 oracle (as it stands) on the host: two plain HALS iterations
-    on the same matrix, scaled to the iterations the GPU needed."""
+def cpu_baseline(Xh, k, l, q, net_params, r_star, seed=1):
+    """The FP64 oracle (as it stands) on the host cores, timed on the method
+    `value` times, learned_lai, on the same X: scalars pass, Algorithms RRF +
+    Apx-EVD (Householder QR, eigh) from the same sketch bits, the learned
+    start (features, the same network parameters, scale fit), LAI iterations
+    until the stall rule, then iterations on X until r*."""
     import numpy as np
     from oracle import symnmf as O
+    from oracle import warmstart as WS
+    n = Xh.shape[0]
     t0 = time.perf_counter()
     sc = O.data_scalars(Xh)
-    t_sc = time.perf_counter() - t0
-    H0 = O.initial_factor(Xh.shape[0], k, sc["zeta"], 1)
-    it = 2
-    t0 = time.perf_counter()
-    O.plain_symnmf(Xh, k, sc["maxval"], H0, it)
-    t_it = (time.perf_counter() - t0) / it
+    X64 = np.asarray(Xh, dtype=np.float64)
+    U, lam = O.apx_evd(lambda M: X64 @ M, O.sketch_omega(n, l, seed), q)
+    H0 = WS.warm_start(net_params, U, lam, sc["rowsum"], k, lambda B: X64 @ B)
+    if H0 is None:
+        H0 = O.initial_factor(n, k, sc["zeta"], seed)
+    W, H, h1 = O.lai_symnmf(U, lam, k, sc["maxval"], H0, 2000, stop=O.StallRule(1e-4, 4))
+    W, H, h2 = O.anls(lambda B: X64 @ B, sc["normsq"], H, sc["maxval"], 4000, W0=W, target=r_star)
+    t = time.perf_counter() - t0
     threads = os.environ.get("OMP_NUM_THREADS") or str(os.cpu_count())
-    return {"value": t_sc + t_it * iters_gpu, "unit": "s", "cores": int(threads), "kind": "oracle",
-            "sample": f"{it} plain HALS iterations + scalars pass on the same X, "
-                      f"scaled to {iters_gpu} iterations ({t_it:.2f} s/iteration)"}
+    return {"value": t, "unit": "s", "cores": int(threads), "kind": "oracle",
+            "sample": f"one whole learned_lai solve on the same X (n={n}, k={k}, l={l}, q={q}): "
+                      f"{len(h1)} LAI iterations + {len(h2)} on X, final residual {h2[-1]:.6f}"}
+
+
+def net_params_host(P, net):
+    """The network's parameters as the oracle's list of (W, b) layers."""
+    import numpy as np
+    import torch
+    from oracle import warmstart as WS
+    p = torch.empty(P.symnmf_mlp_num_params(net), dtype=torch.float32, device="cuda")
+    P.symnmf_mlp_get_params(net, p)
+    v = p.cpu().double().numpy()
+    out, o = [], 0
+    sizes = WS.layer_sizes()
+    for a, b in zip(sizes[:-1], sizes[1:]):
+        out.append((v[o:o + a * b].reshape(a, b), v[o + a * b:o + a * b + b]))
+        o += a * b + b
+    return out
 
 
 if __name__ == "__main__":

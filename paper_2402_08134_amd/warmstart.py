@@ -48,21 +48,24 @@ def align_targets(H, U, k):
 
 
 def instance_data(X, k, l, q, seed, max_iters=2000):
-    """Features (device, (n k) x 6) and targets (host, n k) of one dense
-    symmetric X (a device tensor): plain run from the random start until the
-    stall rule stops it, then the LAI basis of the same X."""
+    """Features (device, (n k) x 6) and targets (host, n k) of one symmetric
+    X (a dense device tensor, or a (row_ptr, col_idx, values, n) tuple of
+    device tensors for CSR): plain run from the random start until the stall
+    rule stops it, then the LAI basis of the same X."""
     import torch
-    n = X.shape[0]
+    dense = not isinstance(X, tuple)
+    n = X.shape[0] if dense else int(X[3])
+    device = X.device if dense else X[0].device
     o = P.symnmf_default_options(stop_mode=P.STOP_STALL, check_every=8)
     ctx = P.symnmf_create(X, k, 0.0, 0, seed, o)
     iters = P.symnmf_iterate(ctx, max_iters)
     dt = torch.float64 if ctx.fdtype == P.F64 else torch.float32
-    Hd = torch.empty((n, k), dtype=dt, device=X.device)
+    Hd = torch.empty((n, k), dtype=dt, device=device)
     P.symnmf_get_factor(ctx, P.H, Hd)
     P.symnmf_lai(ctx, l, q)
-    U = torch.empty((n, l), dtype=torch.float64, device=X.device)
+    U = torch.empty((n, l), dtype=torch.float64, device=device)
     P.symnmf_get_lai(ctx, U, None)
-    F = torch.empty((n * k, P.MLP_FEATURES), dtype=torch.float32, device=X.device)
+    F = torch.empty((n * k, P.MLP_FEATURES), dtype=torch.float32, device=device)
     P.symnmf_warm_features(ctx, F)
     torch.cuda.synchronize()
     T = align_targets(Hd.cpu().numpy(), U.cpu().numpy(), k).reshape(-1)
@@ -94,16 +97,43 @@ def train(net, data, epochs, lr, batch, seed=0, log=None):
     return losses
 
 
-def save(net, path, meta=None):
+def train_pooled(net, F, T, epochs, lr, batch, seed=0, log=None, lr_final=None):
+    """Adam over shuffled batches of a pooled entry set (F: device (m, 6)
+    FP32, T: device (m,) FP32); the step size goes geometrically from lr in
+    the first epoch to lr_final (default lr) in the last.  Returns the mean
+    loss of each epoch."""
     import torch
-    p = torch.empty(P.symnmf_mlp_num_params(net), dtype=torch.float32, device="cuda")
-    P.symnmf_mlp_get_params(net, p)
-    torch.cuda.synchronize()
-    np.savez(path, params=p.cpu().numpy(), hidden=np.int64(P.MLP_HIDDEN),
-             meta=np.array(repr(meta or {})))
+    g = torch.Generator(device="cpu")
+    g.manual_seed(int(seed))
+    m = F.shape[0]
+    losses = []
+    lr_final = lr if lr_final is None else lr_final
+    for ep in range(epochs):
+        step = lr * (lr_final / lr) ** (ep / max(epochs - 1, 1))
+        perm = torch.randperm(m, generator=g).to(F.device)
+        Fs = F.index_select(0, perm).contiguous()
+        Ts = T.index_select(0, perm).contiguous()
+        tot, cnt = 0.0, 0
+        for s in range(0, m - batch + 1, batch):
+            tot += P.symnmf_mlp_train_step(net, Fs[s:s + batch], Ts[s:s + batch], step)
+            cnt += 1
+        losses.append(tot / max(cnt, 1))
+        if log:
+            log(f"epoch {ep}: loss {losses[-1]:.5f}")
+        del Fs, Ts
+    return losses
+
+
+def save(net, path):
+    """The network's parameters in the library's file format."""
+    P.symnmf_mlp_save(net, path)
 
 
 def load(path, stream=None):
+    """A network from a file written by save (symnmf_mlp_load), or from the
+    older .npz files (parameters array and hidden width)."""
+    if not path.endswith(".npz"):
+        return P.symnmf_mlp_load(path, stream)
     import torch
     z = np.load(path, allow_pickle=False)
     if int(z["hidden"]) != P.MLP_HIDDEN:

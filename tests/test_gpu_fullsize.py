@@ -106,7 +106,7 @@ def test_dense_16384_lai_learned_start_and_iterations(dense16k):
     Fo = WS.features(Ug, lg, rowsum, k)
     Fg = host(F)
     e_f = max(rel(Fg[:, c], Fo[:, c]) for c in range(P.MLP_FEATURES))
-    net = WSP.load(os.path.join(WSP.WEIGHTS_DIR, "warmstart_gk.npz"))
+    net = WSP.load(os.path.join(WSP.WEIGHTS_DIR, "warmstart.bin"))
     p = torch.empty(P.symnmf_mlp_num_params(net), dtype=torch.float32, device="cuda")
     P.symnmf_mlp_get_params(net, p)
     ps = []

@@ -91,20 +91,35 @@ def gaussian_kernel(n=16384, dim=64, comps=32, seed=0, dtype=np.float32, median_
     return X, lab
 
 
-def gpu_gaussian_kernel(n, dim, comps, seed):
+def gpu_gaussian_kernel(n, dim, comps, seed, median_on_gpu=False):
     """The Gaussian-kernel similarity of gaussian_kernel (same points, same
     sampled-pairs median for n > 16384), formed on the GPU in FP64 blocks
     and stored as FP32 (a torch tensor on the GPU), bitwise symmetric, zero
-    diagonal.  For sizes whose host copy would be too large."""
+    diagonal.  For sizes whose host copy would be too large.  With
+    median_on_gpu the squared distances of the sampled pairs are formed and
+    ranked on the GPU (same pairs and definition; the rounding of the
+    distances may differ in the last bits)."""
     import torch
     Pp, _ = gmm_points(n, dim, comps, seed)
     rng = np.random.default_rng(seed + 1)
     i = rng.integers(0, n, size=1 << 22)
     j = rng.integers(0, n, size=1 << 22)
     keep = i != j
-    d2 = np.maximum(np.sum((Pp[i[keep]] - Pp[j[keep]]) ** 2, axis=1), 0.0)
-    m = (d2.shape[0] - 1) // 2
-    med2 = float(np.partition(d2, m)[m])
+    if median_on_gpu:
+        Pg = torch.from_numpy(Pp).cuda()
+        ii = torch.from_numpy(i[keep]).cuda()
+        jj = torch.from_numpy(j[keep]).cuda()
+        d2g = torch.zeros(ii.shape[0], dtype=torch.float64, device="cuda")
+        for c0 in range(0, dim, 16):
+            d2g += ((Pg[ii, c0:c0 + 16] - Pg[jj, c0:c0 + 16]) ** 2).sum(1)
+        d2g.clamp_min_(0.0)
+        m = (d2g.shape[0] - 1) // 2
+        med2 = float(torch.kthvalue(d2g, m + 1).values)
+        del Pg, ii, jj, d2g
+    else:
+        d2 = np.maximum(np.sum((Pp[i[keep]] - Pp[j[keep]]) ** 2, axis=1), 0.0)
+        m = (d2.shape[0] - 1) // 2
+        med2 = float(np.partition(d2, m)[m])
     Pd = torch.from_numpy(Pp).cuda()
     sq = (Pd * Pd).sum(1)
     X = torch.empty((n, n), dtype=torch.float32, device="cuda")
@@ -176,6 +191,34 @@ def sbm(n=1 << 20, blocks=64, avg_degree=32.0, ratio=20.0, seed=0):
                       shape=(n, n))
     labels = np.arange(n) // b
     return X, labels
+
+
+# Instances of the learned-start study: 2000 generated problems, ids 0..1799
+# for training and 1800..1999 held out.  Instance i: a stochastic block model
+# graph when i is even, a Gaussian-kernel similarity when i is odd;
+# n uniform in [4096, 32768], k uniform in {16, 32, 64}.  SBM: k equal
+# blocks, average degree 32, p_in / p_out = 20, X = D^-1/2 A D^-1/2.
+# Gaussian kernel: k equal-weight components in R^(2k), FP32, median over
+# 2^22 sampled pairs.
+WARM_TRAIN_IDS = range(0, 1800)
+WARM_HELD_OUT_IDS = range(1800, 2000)
+
+
+def warm_instance(i):
+    """Kind, n, k and data seed of instance i of the learned-start study."""
+    rng = np.random.default_rng([20240208, int(i)])
+    n = 4096 + int(rng.integers(0, 28673))
+    k = (16, 32, 64)[int(rng.integers(0, 3))]
+    return {"id": int(i), "kind": "sbm" if i % 2 == 0 else "gmm", "n": n, "k": k, "seed": 100000 + int(i)}
+
+
+def warm_instance_data(spec):
+    """The matrix of an instance: a scipy CSR (SBM) or a GPU tensor (Gaussian
+    kernel, formed on the GPU)."""
+    if spec["kind"] == "sbm":
+        X, _ = sbm(spec["n"], spec["k"], 32.0, 20.0, seed=spec["seed"])
+        return X
+    return gpu_gaussian_kernel(spec["n"], 2 * spec["k"], spec["k"], spec["seed"], median_on_gpu=True)
 
 
 def random_factor(n, k, seed, scale=1.0, zero_cols=()):
