@@ -571,8 +571,6 @@ def bench_precision(args):
                                      check_every=8 if lai_stage else 4, timing=timing)
         if prec == "bf16":
             o.compute_dtype = P.BF16
-        elif prec == "f32x3":
-            o.compute_dtype = P.F32X3
         c = P.symnmf_create(X, k, 0.0, 0, seed, o)
         if method == "plain":
             it = P.symnmf_iterate(c, 600)
@@ -602,9 +600,9 @@ def bench_precision(args):
     # live roofline of the BF16 product (dominant kernel of the BF16 solves),
     # and the FP32 products' rate against the FP32 matrix-core peak (X H at
     # k = 64 is bound by the matrix cores in FP32: 2 n^2 k flop on 4 n^2
-    # bytes); also FP32 through three BF16 pieces on the BF16 matrix cores
+    # bytes)
     products = {}
-    for prec in ("bf16", "f32", "f32x3"):
+    for prec in ("bf16", "f32"):
         c, it, _ = solve("plain", prec, 1, 1)
         ph = phase_totals(P, [c])
         r = P.symnmf_residual(c, P.RESID_EXACT)[0]

@@ -52,11 +52,6 @@ extern "C" {
 #define SYMNMF_F64 0
 #define SYMNMF_F32 1
 #define SYMNMF_BF16 2
-/* compute dtype only: FP32 X, products accurate to FP32 formed on the BF16
- * matrix cores -- each FP32 operand split exactly into three BF16 pieces
- * (hi + mid + lo), the six products of pieces whose weights reach 2^-16
- * accumulated in FP32 (the dropped ones are below FP32 rounding) */
-#define SYMNMF_F32X3 3
 
 /* update rules.  HALS and BPP solve the NLS subproblems of the regularised
  * alternating scheme (eq. ANLS4symNMF, Section 2.1.1):

@@ -14,7 +14,7 @@ LIB_PATH = os.path.join(_HERE, "libsymnmf.so")
 
 OK, E_INVALID, E_UNSUPPORTED, E_NOMEM, E_DEVICE, E_NUMERIC, E_STATE = range(7)
 DENSE, CSR = 0, 1
-F64, F32, BF16, F32X3 = 0, 1, 2, 3
+F64, F32, BF16 = 0, 1, 2
 RULE_HALS, RULE_BPP, RULE_PGNCG = 0, 1, 2
 STOP_NONE, STOP_STALL, STOP_TARGET, STOP_STALL_OR_TARGET = 0, 1, 2, 3
 RESID_FAST, RESID_EXACT, RESID_LAI = 0, 1, 2

@@ -420,141 +420,6 @@ __global__ __launch_bounds__(256) void k_f32_to_bf16(const float* __restrict__ s
   }
 }
 
-// FP32 products on the BF16 matrix cores (compute dtype F32X3).  Every FP32
-// value x is split
-// exactly as x = hi + mid + lo with hi = bf16(x), mid = bf16(x - hi),
-// lo = bf16(x - hi - mid) (each subtraction is exact in FP32: the rounded
-// part shares the leading bits), so |x - hi - mid - lo| <= 2^-24 |x|.  The
-// product uses the six pairs of pieces whose weights reach 2^-16
-// (hh, hm, mh, hl, mm, lh) with FP32 accumulation; the dropped pairs weigh
-// 2^-24 and below, the size of FP32 rounding.  Six v_mfma_f32_16x16x32_bf16
-// replace the eight v_mfma_f32_16x16x4f32 of a 32-wide K step and take about
-// a third of their matrix-core time, but the splitting adds about five
-// vector instructions per element of X and of the B panel.  Measured on
-// MI355X against the FP32 MFMA kernel (k_gemm_cols): 8% slower at n = 16384,
-// k = 32 and 48, 3% faster at k = 64, 11% faster at n = 65536, k = 64, with
-// a smaller error (relative 3e-7 against 5e-7).
-__device__ __forceinline__ void split3(const floatx8& x, bf16x8& h, bf16x8& m, bf16x8& l) {
-  h = __builtin_convertvector(x, bf16x8);
-  const floatx8 r1 = x - __builtin_convertvector(h, floatx8);
-  m = __builtin_convertvector(r1, bf16x8);
-  const floatx8 r2 = r1 - __builtin_convertvector(m, floatx8);
-  l = __builtin_convertvector(r2, bf16x8);
-}
-
-__device__ __forceinline__ floatx4 mfma_x3(const bf16x8& ah, const bf16x8& am, const bf16x8& al, const bf16x8& bh,
-                                           const bf16x8& bm, const bf16x8& bl, floatx4 acc) {
-  // smallest terms first
-  acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh, acc, 0, 0, 0);
-  acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(am, bm, acc, 0, 0, 0);
-  acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl, acc, 0, 0, 0);
-  acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(am, bh, acc, 0, 0, 0);
-  acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bm, acc, 0, 0, 0);
-  acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, acc, 0, 0, 0);
-  return acc;
-}
-
-// FP32 product from three BF16 pieces (split3 / mfma_x3 above), read along
-// rows of X like k_gemm_cols.  One K step takes 32 rows: lane (ln, lq) loads
-// the float4 at columns j0 + 64 ct + 4 ln of the rows i0 + 8 lq + e
-// (e = 0..7); column u of that 8 x 4 block is split into the BF16 pieces of
-// the B operand (K = 8 lq + e) of the MFMAs of column j0 + 64 ct + 4 ln + u.
-// A = the FP32 B panel, 8 consecutive K of Bt[16 t + ln] per lane, split the
-// same way.  Output as k_gemm_cols.
-template <int NT, int CT, bool VEC>
-__global__ __launch_bounds__(256) void k_gemm_cols_x3(const float* __restrict__ X, int64_t ldx,
-                                                      const float* __restrict__ Bt, int64_t ldt, int n, int rchunk,
-                                                      float* __restrict__ P, int cp,
-                                                      const DevState* __restrict__ st) {
-  if (stopped(st)) return;
-  constexpr int DS = 2;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int ln = lane & 15, lq = lane >> 4;
-  const int j0 = (blockIdx.x * 4 + wave) * (64 * CT);
-  if (j0 >= n) return;
-  const int ib = blockIdx.y * rchunk;
-  const int ie = min(n, ib + rchunk);
-  const int nstep = (ie - ib + 31) / 32;
-  const bool full = VEC && (j0 + 64 * CT <= n);
-
-  floatx4 acc[NT][CT][4];
-#pragma unroll
-  for (int t = 0; t < NT; ++t)
-#pragma unroll
-    for (int ct = 0; ct < CT; ++ct)
-#pragma unroll
-      for (int u = 0; u < 4; ++u) acc[t][ct][u] = floatx4{0, 0, 0, 0};
-  const float* bp[NT];
-#pragma unroll
-  for (int t = 0; t < NT; ++t) bp[t] = Bt + (int64_t)(16 * t + ln) * ldt + 8 * lq;
-
-  floatx4 xv[DS][CT][8], bv[DS][NT][2];
-  // Rows beyond n (last split only) read row n - 1; the padded Bt is zero there.
-  auto load = [&](floatx4 (&xd)[CT][8], floatx4 (&bd)[NT][2], int step) {
-    const int i0 = ib + 32 * step;
-#pragma unroll
-    for (int t = 0; t < NT; ++t) {
-      bd[t][0] = *(const floatx4*)(bp[t] + i0);
-      bd[t][1] = *(const floatx4*)(bp[t] + i0 + 4);
-    }
-#pragma unroll
-    for (int e = 0; e < 8; ++e) {
-      const float* xr = X + (int64_t)min(i0 + 8 * lq + e, n - 1) * ldx + j0 + 4 * ln;
-#pragma unroll
-      for (int ct = 0; ct < CT; ++ct) {
-        if (full) {
-          xd[ct][e] = __builtin_nontemporal_load((const floatx4*)(xr + 64 * ct));
-        } else {
-#pragma unroll
-          for (int u = 0; u < 4; ++u) xd[ct][e][u] = (j0 + 64 * ct + 4 * ln + u < n) ? xr[64 * ct + u] : 0.0f;
-        }
-      }
-    }
-  };
-  auto compute = [&](const floatx4 (&xd)[CT][8], const floatx4 (&bd)[NT][2]) {
-    bf16x8 ah[NT], am[NT], al[NT];
-#pragma unroll
-    for (int t = 0; t < NT; ++t) {
-      const floatx8 b = {bd[t][0][0], bd[t][0][1], bd[t][0][2], bd[t][0][3],
-                         bd[t][1][0], bd[t][1][1], bd[t][1][2], bd[t][1][3]};
-      split3(b, ah[t], am[t], al[t]);
-    }
-#pragma unroll
-    for (int ct = 0; ct < CT; ++ct)
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const floatx8 xc = {xd[ct][0][u], xd[ct][1][u], xd[ct][2][u], xd[ct][3][u],
-                            xd[ct][4][u], xd[ct][5][u], xd[ct][6][u], xd[ct][7][u]};
-        bf16x8 xh, xm, xl;
-        split3(xc, xh, xm, xl);
-#pragma unroll
-        for (int t = 0; t < NT; ++t) acc[t][ct][u] = mfma_x3(ah[t], am[t], al[t], xh, xm, xl, acc[t][ct][u]);
-      }
-  };
-#pragma unroll
-  for (int d = 0; d < DS - 1; ++d)
-    if (d < nstep) load(xv[d], bv[d], d);
-  for (int step = 0; step < nstep; step += DS) {
-#pragma unroll
-    for (int d = 0; d < DS; ++d) {
-      const int pre = step + d + DS - 1;
-      if (pre < nstep) load(xv[(d + DS - 1) % DS], bv[(d + DS - 1) % DS], pre);
-      if (step + d < nstep) compute(xv[d], bv[d]);
-    }
-  }
-  float* out = P + (int64_t)blockIdx.y * n * cp;
-#pragma unroll
-  for (int ct = 0; ct < CT; ++ct)
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int j = j0 + 64 * ct + 4 * ln + u;
-      if (j < n) {
-#pragma unroll
-        for (int t = 0; t < NT; ++t) *(floatx4*)(out + (int64_t)j * cp + 16 * t + 4 * lq) = acc[t][ct][u];
-      }
-    }
-}
-
 // BF16 product read along rows of X, the same scheme as k_gemm_cols with
 // v_mfma_f32_16x16x32_bf16 (B operand lane (ln, lq) -> K 8 lq .. 8 lq + 7 of
 // column ln).  One K step takes 32 rows: lane (ln, lq) loads 8 BF16 of each
@@ -769,25 +634,6 @@ int dispatch_cols(int nt, int ct, const float* X, int64_t ldx, bool vec, const f
   return -1;
 }
 
-template <int NT, int CT>
-void launch_cols_x3(const float* X, int64_t ldx, bool vec, const float* Bt, int64_t ldt, int n, const GemmPlan& p,
-                    float* P, const DevState* st, hipStream_t s) {
-  dim3 g(ceil_div(n, 4 * 64 * CT), p.splits);
-  if (vec)
-    k_gemm_cols_x3<NT, CT, true><<<g, 256, 0, s>>>(X, ldx, Bt, ldt, n, p.kchunk, P, p.cp, st);
-  else
-    k_gemm_cols_x3<NT, CT, false><<<g, 256, 0, s>>>(X, ldx, Bt, ldt, n, p.kchunk, P, p.cp, st);
-}
-
-int dispatch_cols_x3(int nt, int ct, const float* X, int64_t ldx, bool vec, const float* Bt, int64_t ldt, int n,
-                     const GemmPlan& p, float* P, const DevState* st, hipStream_t s) {
-#define CASE(NT_, CT_) \
-  if (nt == NT_ && ct == CT_) { launch_cols_x3<NT_, CT_>(X, ldx, vec, Bt, ldt, n, p, P, st, s); return 0; }
-  CASE(1, 2) CASE(2, 2) CASE(3, 1) CASE(4, 1) CASE(5, 1) CASE(6, 1)
-#undef CASE
-  return -1;
-}
-
 template <int NT>
 void launch_cols_bf16(const __bf16* X, int64_t ldx, bool vec, const __bf16* Bt, int64_t ldt, int n,
                       const GemmPlan& p, float* P, const DevState* st, hipStream_t s) {
@@ -815,20 +661,18 @@ int dispatch_cols_bf16(int nt, const __bf16* X, int64_t ldx, bool vec, const __b
 
 GemmPlan gemm_plan(int n, int c, int compute_dtype) {
   GemmPlan p;
-  p.split3 = compute_dtype == SYMNMF_F32X3;
   p.cp = 16 * ceil_div(c, 16);
   p.ldt = (int64_t)BT_PAD * ceil_div(n, BT_PAD);
-  if (compute_dtype == SYMNMF_F32 || compute_dtype == SYMNMF_F32X3) {
+  if (compute_dtype == SYMNMF_F32) {
     // row-contiguous product: strips of 64 * ct columns, about one wave per
-    // SIMD in total, splits of at least 256 rows (multiples of the K step:
-    // 16 rows for FP32 MFMA, 32 for the BF16 pieces)
+    // SIMD in total, splits of at least 256 rows (multiples of the 16-row K
+    // step)
     p.cols = true;
     // two 64-column blocks per wave up to 64 output columns for FP32 MFMA
     // (measured at n = 16384: X Q at l = 48 317 -> 290 us, k = 64 361 ->
-    // 338 us; at n = 65536, k = 64 5.14 -> 4.48 ms); the BF16-piece kernel
-    // keeps registers for its splitting beyond 32
-    p.ct = (p.cp <= 64 && !p.split3) || p.cp <= 32 ? 2 : 1;
-    const int step = p.split3 ? 32 : 16;
+    // 338 us; at n = 65536, k = 64 5.14 -> 4.48 ms)
+    p.ct = p.cp <= 64 ? 2 : 1;
+    const int step = 16;
     const int strips = ceil_div(n, 64 * p.ct);
     int splits = std::max(1, ceil_div(1024, strips));
     splits = std::min(splits, std::max(1, n / 256));
@@ -869,9 +713,7 @@ int dense_gemm_bt(const void* X, int xdtype, int64_t ldx, const void* Bt, int n,
     rc = dispatch_mfma<double>(nt, p.rt, (const double*)X, ldx, vec, (const double*)Bt, p.ldt, n, p, (double*)P, st, s);
   } else if (xdtype == SYMNMF_F32) {
     const bool vec = (ldx % 4 == 0) && ((uintptr_t)X % 16 == 0);
-    rc = p.split3
-             ? dispatch_cols_x3(nt, p.ct, (const float*)X, ldx, vec, (const float*)Bt, p.ldt, n, p, (float*)P, st, s)
-             : dispatch_cols(nt, p.ct, (const float*)X, ldx, vec, (const float*)Bt, p.ldt, n, p, (float*)P, st, s);
+    rc = dispatch_cols(nt, p.ct, (const float*)X, ldx, vec, (const float*)Bt, p.ldt, n, p, (float*)P, st, s);
   } else {
     const bool vec = (ldx % 8 == 0) && ((uintptr_t)X % 16 == 0);
     rc = dispatch_cols_bf16(nt, (const __bf16*)X, ldx, vec, (const __bf16*)Bt, p.ldt, n, p, (float*)P, st, s);
@@ -915,9 +757,7 @@ int dense_gemm(const void* X, int xdtype, int64_t ldx, const void* B, int bdtype
     else
       k_transpose_pad<double, float><<<tg, 256, 0, s>>>((const double*)B, ldb, n, c, (float*)Bt, p.ldt, p.cp, st);
     const bool vec = (ldx % 4 == 0) && ((uintptr_t)X % 16 == 0);
-    if (p.split3 ? dispatch_cols_x3(nt, p.ct, (const float*)X, ldx, vec, (const float*)Bt, p.ldt, n, p, (float*)P,
-                                    st, s)
-                 : dispatch_cols(nt, p.ct, (const float*)X, ldx, vec, (const float*)Bt, p.ldt, n, p, (float*)P, st, s))
+    if (dispatch_cols(nt, p.ct, (const float*)X, ldx, vec, (const float*)Bt, p.ldt, n, p, (float*)P, st, s))
       return -1;
   } else {
     if (bdtype == SYMNMF_F32)

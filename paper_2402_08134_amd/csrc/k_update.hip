@@ -88,6 +88,9 @@ void k_update(UpdateArgs a, const double* __restrict__ Gh,
   double* ms = gi + KP;                                   // l x KP (LAI)
   TF* wl = reinterpret_cast<TF*>(ms + (LP > 0 ? LP * KP : 0));  // RPB x LW
   TF* us = wl + RPB * LW;                                         // RPB x LU (LAI)
+  // LAI right-hand sides of the chunk (RPB x LW doubles, 8-byte aligned)
+  double* ys = reinterpret_cast<double*>(
+      (reinterpret_cast<uintptr_t>(us + (LP > 0 ? RPB * LU : 0)) + 7) & ~(uintptr_t)7);
   __shared__ double sc[8];
   const int tid = threadIdx.x;
   const int g = tid % LPR, rs = tid / LPR;     // lane in row, row slot
@@ -135,6 +138,12 @@ void k_update(UpdateArgs a, const double* __restrict__ Gh,
   // Only at KP = 32: at KP = 64 (five tiles per wave) the LAI iteration at
   // n = 65536, l = 80 measured 289 -> 335 us, so there the VALU tile stays.
   constexpr bool GMZ = LP > 0 && KP == 32;
+  // With a LAI term at KP = 32 the right-hand sides U[j,:] M of the chunk are
+  // one (RPB x LP) x (LP x KP) product on the FP64 matrix cores: wave w takes
+  // the 16 x 16 output tiles w, w + 8, ... (row tile t / KT, column tile
+  // t % KT), LP / 4 steps each, and leaves them in LDS for the sweep.
+  constexpr bool UMF = GMZ && YMODE == 2;
+  constexpr int UMT = (RPB / 16) * (KP / 16);
   constexpr int KT = KP / 16, NGT = KT * KT, NTT = NGT + (LP / 16) * KT;
   constexpr int TPW = GMZ ? (NTT + 7) / 8 : 2;
   doublex4 gm[TPW > 2 ? TPW : 2];
@@ -172,6 +181,26 @@ void k_update(UpdateArgs a, const double* __restrict__ Gh,
       }
       __syncthreads();
       if (UREG && l > 0 && base + gridDim.x * RPB < n) load_u(base + gridDim.x * RPB);
+      if (UMF) {
+        const int wid = tid >> 6, li = tid & 15, lg = (tid & 63) >> 4;
+        for (int t = wid; t < UMT; t += NTH / 64) {   // the same for the whole wave
+          const int r0 = 16 * (t / KT), c0 = 16 * (t % KT);
+          doublex4 acc = doublex4{0.0, 0.0, 0.0, 0.0};
+          for (int s4 = 0; s4 < l; s4 += 4) {
+            // A[i][p] = U[r0 + i][s4 + p], B[p][j] = M[s4 + p][c0 + j]; lane
+            // (li, lg) supplies A[li][lg] and B[lg][li]; p beyond l reads
+            // the zero padding of M
+            const int pa = s4 + lg < LP ? s4 + lg : LP - 1;
+            const double av = s4 + lg < l ? (double)us[(r0 + li) * LU + pa] : 0.0;
+            const double bv = s4 + lg < l ? ms[(s4 + lg) * KP + c0 + li] : 0.0;
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
+          }
+          // accumulator element v of lane (li, lg): row lg + 4 v, column li
+#pragma unroll
+          for (int v = 0; v < 4; ++v) ys[(r0 + lg + 4 * v) * LW + c0 + li] = acc[v];
+        }
+        __syncthreads();
+      }
     }
     if (row < n) {
       const int64_t rb = (int64_t)row * k;
@@ -212,6 +241,9 @@ void k_update(UpdateArgs a, const double* __restrict__ Gh,
             y[c] = fma(v, q < k ? x : 0.0, y[c]);
           }
         }
+      } else if (UMF) {
+#pragma unroll
+        for (int c = 0; c < CPL; ++c) y[c] = ys[rs * LW + col_of<LPR>(g, c)];
       } else {
         const TF* u = us + rs * LU;
         for (int p = 0; p < l; ++p) {
@@ -495,7 +527,8 @@ __global__ __launch_bounds__(256) void k_pad_identity(double* __restrict__ Ghat,
 template <int KP, int LP, typename TF, typename TP, typename TT, int YMODE, int LPR>
 int launch_update_lpr(const UpdateArgs& a, const UpdateRO& ro, int nb, const DevState* st, hipStream_t s) {
   constexpr int RPB = 16 * UPD_RPB / LPR;
-  const size_t lds = 8 * (size_t)KP * (KP + 1 + LP) + sizeof(TF) * RPB * ((KP + 1) + (LP > 0 ? LP + 1 : 0));
+  const size_t lds = 8 * (size_t)KP * (KP + 1 + LP) + sizeof(TF) * RPB * ((KP + 1) + (LP > 0 ? LP + 1 : 0)) +
+                     (LP > 0 && KP == 32 && YMODE == 2 ? 8 * (size_t)RPB * (KP + 1) + 8 : 0);
   auto kern = k_update<KP, LP, TF, TP, TT, YMODE, LPR>;
   if (lds > 65536 &&
       hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)

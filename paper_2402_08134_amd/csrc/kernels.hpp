@@ -41,7 +41,6 @@ struct GemmPlan {
   int kchunk = 64;   // K range per split
   int splits = 1;    // number of K splits (partial outputs)
   int64_t ldt = 0;   // row length of the transposed B panel
-  bool split3 = false;  // FP32 operands through three BF16 pieces on the BF16 matrix cores
   bool cols = false;    // FP32: the row-contiguous product (kchunk = rows per split)
   int ct = 1;           // cols: 64-column blocks per wave
 };

@@ -657,7 +657,7 @@ struct symnmf_ctx {
   int64_t ldxc() const { return cdtype == SYMNMF_BF16 && xdtype != SYMNMF_BF16 ? n : ld; }
   // element type of the product operands (X, B panel): the compute dtype,
   // except that the three-piece BF16 products read FP32 operands
-  int opdtype() const { return cdtype == SYMNMF_F32X3 ? SYMNMF_F32 : cdtype; }
+  int opdtype() const { return cdtype; }
 
   struct Gate {
     symnmf_ctx* c;
@@ -1091,11 +1091,10 @@ int symnmf_create(symnmf_ctx** out, const symnmf_matrix* X, int32_t k, double al
       if (c->ld < c->n) throw Fail{SYMNMF_E_INVALID, "ld < n"};
       if (s > 0) throw Fail{SYMNMF_E_UNSUPPORTED, "leverage-score sampling needs CSR X"};
       int cd = c->opt.compute_dtype < 0 ? X->dtype : c->opt.compute_dtype;
-      if (cd == SYMNMF_F32X3 && X->dtype != SYMNMF_F32) throw Fail{SYMNMF_E_UNSUPPORTED, "F32X3 compute needs F32 X"};
       if (cd == SYMNMF_F64 && X->dtype != SYMNMF_F64) throw Fail{SYMNMF_E_UNSUPPORTED, "F64 compute needs F64 X"};
       if (X->dtype == SYMNMF_F64 && cd != SYMNMF_F64) throw Fail{SYMNMF_E_UNSUPPORTED, "F64 X needs F64 compute"};
       if (X->dtype == SYMNMF_BF16 && cd != SYMNMF_BF16) throw Fail{SYMNMF_E_UNSUPPORTED, "BF16 X needs BF16 compute"};
-      if (cd != SYMNMF_F64 && cd != SYMNMF_F32 && cd != SYMNMF_BF16 && cd != SYMNMF_F32X3)
+      if (cd != SYMNMF_F64 && cd != SYMNMF_F32 && cd != SYMNMF_BF16)
         throw Fail{SYMNMF_E_INVALID, "compute dtype"};
       c->cdtype = cd;
       c->fdtype = cd == SYMNMF_F64 ? SYMNMF_F64 : SYMNMF_F32;

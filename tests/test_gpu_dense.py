@@ -25,8 +25,7 @@ def _ctx(X, k, dtype, seed=0, compute=None, **opt):
 
 @pytest.mark.parametrize("case", [
     ("f64", 1000, 10), ("f64", 333, 7), ("f32", 1000, 32), ("f32", 769, 48), ("f32", 257, 80), ("bf16", 900, 64),
-    ("bf16", 515, 20), ("f32x3", 1000, 32), ("f32x3", 769, 48), ("f32x3", 257, 80), ("f32x3", 1100, 64),
-    ("f32x3", 515, 20)])
+    ("bf16", 515, 20)])
 def test_product_parity(case):
     kind, n, c = case
     log(f"product {case}")
@@ -45,17 +44,6 @@ def test_product_parity(case):
         P.symnmf_apply_x(ctx, Bd, Yd)
         X32, B32 = round_to(X, torch.float32), round_to(B, torch.float32)
         assert rel(host(Yd), X32 @ B32) <= 2e-6
-    elif kind == "f32x3":
-        # FP32 data, products from three BF16 pieces per operand: FP32-level
-        # agreement with the exact product of the FP32 operands
-        ctx = _ctx(X, min(c, 64), torch.float32, compute=P.F32X3)
-        Bd = dev(B, torch.float32)
-        Yd = torch.empty_like(Bd)
-        P.symnmf_apply_x(ctx, Bd, Yd)
-        X32, B32 = round_to(X, torch.float32), round_to(B, torch.float32)
-        e = rel(host(Yd), X32 @ B32)
-        log(f"f32x3 product n={n} c={c}: rel {e:.2e}")
-        assert e <= 2e-6
     else:
         ctx = _ctx(X, min(c, 64), torch.float32, compute=P.BF16)
         Bd = dev(B, torch.float32)
@@ -128,10 +116,10 @@ def test_planted_fp64_100_iterations():
 
 
 def _compute(name):
-    return {"f32": None, "bf16": P.BF16, "f32x3": P.F32X3}[name]
+    return {"f32": None, "bf16": P.BF16}[name]
 
 
-@pytest.mark.parametrize("compute", ["f32", "bf16", "f32x3"])
+@pytest.mark.parametrize("compute", ["f32", "bf16"])
 def test_gaussian_kernel_plain_parity(compute):
     # Dense similarity (Gaussian kernel of a mixture), ragged n, FP32 / BF16.
     n, k = 2300, 32
@@ -271,7 +259,7 @@ def test_graph_replay_matches_eager(case):
         assert np.array_equal(factor(a, P.H), factor(b, P.H))
 
 
-@pytest.mark.parametrize("compute", ["f32", "bf16", "f32x3"])
+@pytest.mark.parametrize("compute", ["f32", "bf16"])
 def test_precision_k64_parity(compute):
     # The precision sweep's shape at a size the oracle finishes quickly:
     # 64-component mixture in R^128, k = 64, FP32 X, products in FP32 or BF16.
