@@ -86,6 +86,24 @@ __device__ __forceinline__ float wave_sum_f(float v) {
   return v;
 }
 
+// Sum of a double over the 16 lanes of a DPP row, every lane receiving the
+// total: quad_perm [1,0,3,2] and [2,3,0,1] (pairs, quads), then
+// row_half_mirror and row_mirror (halves, full row).  DPP moves are plain
+// VALU operations, unlike the LDS permutes behind __shfl_xor.
+template <int CTRL>
+__device__ __forceinline__ double dpp_double(double v) {
+  const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ double row16_sum(double v) {
+  v += dpp_double<0xB1>(v);   // quad_perm(1,0,3,2)
+  v += dpp_double<0x4E>(v);   // quad_perm(2,3,0,1)
+  v += dpp_double<0x141>(v);  // row_half_mirror
+  v += dpp_double<0x140>(v);  // row_mirror
+  return v;
+}
+
 // Block-wide FP64 sum with a fixed reduction tree (deterministic).
 // `scratch` holds >= blockDim.x/64 doubles.  Result valid in thread 0.
 __device__ __forceinline__ double block_sum(double v, double* scratch) {

@@ -722,8 +722,14 @@ int gram(const void* A, int adtype, int64_t lda, int ca, const void* B, int bdty
   const int t = ceil_div(std::max(ca, cb), 16);
   const int nrows = rows ? max_rows : n;
   // 64 rows per block (256 blocks at n = 16384; more rows per block chain
-  // more load latencies)
-  const int nb = std::max(1, std::min(256, ceil_div(std::max(nrows, 1), 64)));
+  // more load latencies); past 2^16 rows up to 1024 blocks, so that each SIMD
+  // has several waves whose chunk loads overlap (the partials must fit the
+  // workspace)
+  int nbmax = nrows > (1 << 16) ? 1024 : 256;
+  // at most half of the free workspace: callers take several Gram matrices
+  // one after another without releasing it
+  nbmax = (int)std::min<size_t>((size_t)nbmax, std::max<size_t>(1, ws.avail_doubles() / (2 * (size_t)ca * cb)));
+  const int nb = std::max(1, std::min(nbmax, ceil_div(std::max(nrows, 1), 64)));
   const int rpb = 16 * ceil_div(ceil_div(std::max(nrows, 1), nb), 16);
   double* part = ws.dbl((size_t)nb * ca * cb);
   if (!part) return -1;

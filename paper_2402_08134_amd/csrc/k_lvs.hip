@@ -16,10 +16,13 @@
 //      (1, or c W_R / (s_R w_i) for a row drawn c times: c draws of
 //      1 / (s_R p~_i) with p~_i = w_i / W_R).
 //
-// Sampled product X S^T S F: X is symmetric, so the sampled columns are the
-// sampled CSR rows.  They are scattered into a transposed slab (segment i
-// holds the (r, X_ri w_r) of all sampled rows r with X_ri != 0), sorted by r
-// inside each segment so the HALS sweep sums them in a fixed order.
+// Sampled product X S^T S F: row j of it is the sum over the stored X[j][r]
+// with r in the sample of X[j][r] w_r F[r, :].  The emit step writes w_r for
+// every row (0 off the sample).  The slab of these entries is built without
+// sorting: the sampled rows' entries are counted per column (X symmetric: the
+// rows j that have any), the counts scanned, and then only those rows j walk
+// their own CSR row against the weights and write the sampled entries in
+// column order, each at its rank among the row's sampled entries.
 #include "kernels.hpp"
 
 namespace {
@@ -56,6 +59,100 @@ __global__ __launch_bounds__(256) void k_leverage(const TF* __restrict__ F, int 
     }
   }
   lev[j] = acc;
+}
+
+// FP32 factors on the FP64 matrix cores: Z = F R^{-1} for 16 rows at a time
+// with v_mfma_f64_16x16x4f64, lev = row sums of Z o Z.  R^{-1} is upper
+// triangular, so the output tile of columns 16 J .. 16 J + 15 needs only the
+// K steps p < 16 (J + 1): 4 (J + 1) steps of 4.  Each wave keeps those B
+// operands (R^{-1}[4 s + lg][16 J + li] in lane (li, lg), zero below the
+// diagonal) in registers for all its row groups.  A group's 16 rows are
+// read with coalesced loads into the wave's LDS slab (row stride KP + 1
+// floats), from which lane (li, lg) takes A[li][lg] = F[r0 + li][4 s + lg].
+// The four accumulator registers of lane (li, lg) hold rows lg + 4 v of
+// column li; squares are summed over the tiles and then over the 16 lanes
+// of a DPP row.
+template <int KP>
+__global__ __launch_bounds__(256) void k_leverage_mfma(const float* __restrict__ F, int n, int k,
+                                                       const double* __restrict__ Rinv, double* __restrict__ lev,
+                                                       int iters, const DevState* __restrict__ st) {
+  if (stopped(st)) return;
+  constexpr int KT = KP / 16, NB = 2 * KT * (KT + 1), LW = KP + 1;
+  __shared__ float slab[4][16 * LW];
+  const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63, li = lane & 15, lg = lane >> 4;
+  float* hs = slab[wid];
+  double breg[NB];
+  {
+    int b = 0;
+#pragma unroll
+    for (int J = 0; J < KT; ++J)
+#pragma unroll
+      for (int s4 = 0; s4 < 4 * (J + 1); ++s4, ++b) {
+        const int p = 4 * s4 + lg, i = 16 * J + li;
+        const bool in = p <= i && i < k;
+        const double v = Rinv[in ? p * k + i : 0];   // clamped index, masked value
+        breg[b] = in ? v : 0.0;
+      }
+  }
+  const int groups = (n + 15) / 16;
+  for (int it = 0; it < iters; ++it) {
+    const int grp = (it * gridDim.x + blockIdx.x) * 4 + wid;
+    const int r0 = 16 * grp;
+    // the group's rows (16 k floats, contiguous) into the slab
+    const int rows = grp < groups ? min(16, n - r0) : 0;
+    if (k == KP) {
+      // 16 KP floats as float4 pieces: piece e is row e / (KP / 4)
+      constexpr int P4 = KP / 4;
+      const float4* src = reinterpret_cast<const float4*>(F);
+#pragma unroll
+      for (int e = lane; e < 16 * P4; e += 64) {
+        const int r = e / P4, c = 4 * (e - r * P4);
+        const float4 v = src[r < rows ? (int64_t)r0 * P4 + e : 0];   // clamped index, masked value
+        float* d = hs + r * LW + c;
+        d[0] = r < rows ? v.x : 0.0f;
+        d[1] = r < rows ? v.y : 0.0f;
+        d[2] = r < rows ? v.z : 0.0f;
+        d[3] = r < rows ? v.w : 0.0f;
+      }
+    } else {
+      for (int e = lane; e < 16 * k; e += 64) {
+        const int r = e / k, c = e - r * k;
+        const float v = F[r < rows ? (int64_t)r0 * k + e : 0];   // clamped index, masked value
+        hs[r * LW + c] = r < rows ? v : 0.0f;
+      }
+    }
+    __syncthreads();
+    double a[4 * KT];
+#pragma unroll
+    for (int s4 = 0; s4 < 4 * KT; ++s4) {
+      const int p = 4 * s4 + lg;
+      a[s4] = p < k ? (double)hs[li * LW + p] : 0.0;
+    }
+    // K step outermost, so the tiles' matrix-core chains interleave
+    doublex4 acc[KT];
+#pragma unroll
+    for (int J = 0; J < KT; ++J) acc[J] = doublex4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int s4 = 0; s4 < 4 * KT; ++s4) {
+#pragma unroll
+      for (int J = s4 / 4; J < KT; ++J) {
+        // B operand of tile J, step s4: index 2 J (J + 1) + s4 in breg
+        acc[J] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[s4], breg[2 * J * (J + 1) + s4], acc[J], 0, 0, 0);
+      }
+    }
+    double t[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int J = 0; J < KT; ++J)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) t[v] = fma(acc[J][v], acc[J][v], t[v]);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const double tot = row16_sum(t[v]);
+      const int r = lg + 4 * v;
+      if (li == 0 && r < rows) lev[r0 + r] = tot;
+    }
+    __syncthreads();
+  }
 }
 
 __global__ void k_sample_reset(int* info, double* theta) {
@@ -128,7 +225,8 @@ __global__ __launch_bounds__(256) void k_emit(const int* __restrict__ det, int* 
                                               const uint64_t* __restrict__ w, const uint64_t* __restrict__ prefix,
                                               const int* __restrict__ sel, const int* __restrict__ pos, int n,
                                               int* __restrict__ rows, double* __restrict__ weights, int64_t cap,
-                                              int* __restrict__ info, const DevState* __restrict__ st) {
+                                              int* __restrict__ info, double* __restrict__ wmask,
+                                              const DevState* __restrict__ st) {
   if (stopped(st)) return;
   const int i = blockIdx.x * 256 + threadIdx.x;
   if (i == 0) {
@@ -136,21 +234,25 @@ __global__ __launch_bounds__(256) void k_emit(const int* __restrict__ det, int* 
     info[3] = pos[n];
   }
   if (i >= n) return;
+  double wt = 0.0;
   if (sel[i] && pos[i] < cap) {
     const int p = pos[i];
     rows[p] = i;
     if (det[i]) {
-      weights[p] = 1.0;
+      wt = 1.0;
     } else {
       const double WR = (double)prefix[n - 1];
       const double sR = (double)info[1];
-      weights[p] = ((double)counts[i] * WR) / (sR * (double)w[i]);
+      wt = ((double)counts[i] * WR) / (sR * (double)w[i]);
     }
+    weights[p] = wt;
   }
+  if (wmask) wmask[i] = wt;
   counts[i] = 0;
 }
 
-// One wave per sampled row; lanes walk the row's nonzeros.
+// One wave per sampled row; lanes walk the row's nonzeros.  X symmetric:
+// the row's column i gets one entry in segment i.
 __global__ __launch_bounds__(256) void k_slab_count(const int* __restrict__ rp, const int* __restrict__ ci,
                                                     const int* __restrict__ rows, const int* __restrict__ d_count,
                                                     int* __restrict__ cnt, const DevState* __restrict__ st) {
@@ -161,51 +263,57 @@ __global__ __launch_bounds__(256) void k_slab_count(const int* __restrict__ rp, 
   for (int e = rp[r] + (threadIdx.x & 63); e < rp[r + 1]; e += 64) atomicAdd(&cnt[ci[e]], 1);
 }
 
+// 16 lanes per row j; rows without sampled entries (cnt 0) are skipped.  The
+// lanes check 16 entries at a time against the weights; each sampled entry
+// goes to seg_ptr[j] + (sampled entries of the row before it), found from the
+// wave's ballot, so the segment is in column order.  cnt[j] is cleared.
 template <typename TV>
-__global__ __launch_bounds__(256) void k_slab_fill(const int* __restrict__ rp, const int* __restrict__ ci,
-                                                   const TV* __restrict__ val, const int* __restrict__ rows,
-                                                   const double* __restrict__ weights, const int* __restrict__ d_count,
-                                                   int* __restrict__ cnt, const int* __restrict__ seg_ptr,
-                                                   int* __restrict__ seg_src, double* __restrict__ seg_val,
-                                                   int64_t seg_cap, const DevState* __restrict__ st) {
+__global__ __launch_bounds__(256) void k_slab_fill_rows(const int* __restrict__ rp, const int* __restrict__ ci,
+                                                        const TV* __restrict__ val, int n,
+                                                        const double* __restrict__ wmask, int* __restrict__ cnt,
+                                                        const int* __restrict__ seg_ptr, int* __restrict__ seg_src,
+                                                        double* __restrict__ seg_val, int64_t seg_cap,
+                                                        const DevState* __restrict__ st) {
   if (stopped(st)) return;
-  const int t = blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (t >= *d_count) return;
-  const int r = rows[t];
-  const double wr = weights[t];
-  for (int e = rp[r] + (threadIdx.x & 63); e < rp[r + 1]; e += 64) {
-    const int i = ci[e];
-    const int p = seg_ptr[i] + atomicSub(&cnt[i], 1) - 1;
-    if (p < seg_cap) {
-      seg_src[p] = r;
-      seg_val[p] = (double)val[e] * wr;
+  const int j = blockIdx.x * 16 + (threadIdx.x >> 4);
+  const int li = threadIdx.x & 15, sh = threadIdx.x & 48;   // lane in row, row's bit offset in the wave
+  const bool on = j < n && cnt[j] > 0;
+  if (!on) return;            // the same for the 16 lanes of a row
+  cnt[j] = 0;
+  const int e0 = rp[j], e1 = rp[j + 1];
+  int base = seg_ptr[j];
+  for (int e = e0 + li; e - li < e1; e += 16) {   // the same trips for the row's lanes
+    const bool ok = e < e1;
+    const int r = ci[ok ? e : e0];   // clamped index (e0 < e1: the row has entries), masked value
+    const double w = ok ? wmask[r] : 0.0;
+    const bool hit = w != 0.0;
+    const uint64_t m = (__ballot(hit) >> sh) & 0xFFFFull;
+    if (hit) {
+      const int p = base + __popcll(m & ((1ull << li) - 1ull));
+      if (p < seg_cap) {
+        seg_src[p] = r;
+        seg_val[p] = (double)val[e] * w;
+      }
     }
-  }
-}
-
-__global__ __launch_bounds__(256) void k_slab_sort(const int* __restrict__ seg_ptr, int n, int* __restrict__ seg_src,
-                                                   double* __restrict__ seg_val, int64_t seg_cap,
-                                                   const DevState* __restrict__ st) {
-  if (stopped(st)) return;
-  const int i = blockIdx.x * 256 + threadIdx.x;
-  if (i >= n) return;
-  const int e0 = (int)min((int64_t)seg_ptr[i], seg_cap), e1 = (int)min((int64_t)seg_ptr[i + 1], seg_cap);
-  for (int a = e0 + 1; a < e1; ++a) {
-    const int ks = seg_src[a];
-    const double kv = seg_val[a];
-    int b = a - 1;
-    while (b >= e0 && seg_src[b] > ks) {
-      seg_src[b + 1] = seg_src[b];
-      seg_val[b + 1] = seg_val[b];
-      --b;
-    }
-    seg_src[b + 1] = ks;
-    seg_val[b + 1] = kv;
+    base += __popcll(m);
   }
 }
 
 template <int KP, typename TF>
 void lev_launch(const void* F, int n, int k, const double* Rinv, double* lev, const DevState* st, hipStream_t s) {
+  if constexpr (std::is_same<TF, float>::value) {
+    // four 16-row groups per block and step; about four blocks per CU
+    // (float4 row pieces need a 16-byte aligned factor)
+    if ((reinterpret_cast<uintptr_t>(F) & 15) != 0) {
+      k_leverage<KP, TF><<<ceil_div(n, 256), 256, 0, s>>>((const TF*)F, n, k, Rinv, lev, st);
+      return;
+    }
+    const int groups = ceil_div(n, 16);
+    const int nb = std::max(1, std::min(1024, ceil_div(groups, 4)));
+    const int iters = ceil_div(groups, 4 * nb);
+    k_leverage_mfma<KP><<<nb, 256, 0, s>>>((const float*)F, n, k, Rinv, lev, iters, st);
+    return;
+  }
   k_leverage<KP, TF><<<ceil_div(n, 256), 256, 0, s>>>((const TF*)F, n, k, Rinv, lev, st);
 }
 
@@ -229,7 +337,7 @@ int leverage_scores(const void* F, int fdtype, int n, int k, const double* Rinv,
 
 int hybrid_sample(const double* lev, int n, int k, int64_t s_total, double tau, uint64_t seed, uint32_t half_iter,
                   SampleBuffers& sb, int* rows, double* weights, int64_t cap, Workspace& ws, const DevState* st,
-                  hipStream_t s) {
+                  hipStream_t s, double* wmask) {
   const int nb = ceil_div(n, 256);
   double* tpart = ws.dbl(nb);
   int* sel = ws.i32(n);
@@ -242,22 +350,22 @@ int hybrid_sample(const double* lev, int n, int k, int64_t s_total, double tau, 
   if (s_total > 0) k_draw<<<ceil_div(s_total, 256), 256, 0, s>>>(sb.prefix, n, s_total, seed, half_iter, sb.counts, sb.info, st);
   k_select<<<nb, 256, 0, s>>>(sb.flags, sb.counts, n, sel, st);
   if (exclusive_scan_i32(sel, pos, n, ws, s)) return -1;
-  k_emit<<<nb, 256, 0, s>>>(sb.flags, sb.counts, sb.w, sb.prefix, sel, pos, n, rows, weights, cap, sb.info, st);
+  k_emit<<<nb, 256, 0, s>>>(sb.flags, sb.counts, sb.w, sb.prefix, sel, pos, n, rows, weights, cap, sb.info, wmask,
+                            st);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
 int sampled_slab(const int* rp, const int* ci, const void* val, int vdtype, int n, const int* rows,
-                 const double* weights, const int* d_count, int max_rows, int* seg_cnt, int* seg_ptr, int* seg_src,
+                 const int* d_count, int max_rows, const double* wmask, int* seg_cnt, int* seg_ptr, int* seg_src,
                  double* seg_val, int64_t seg_cap, Workspace& ws, const DevState* st, hipStream_t s) {
   const int nbw = std::max(1, ceil_div(max_rows, 4));
   k_slab_count<<<nbw, 256, 0, s>>>(rp, ci, rows, d_count, seg_cnt, st);
   if (exclusive_scan_i32(seg_cnt, seg_ptr, n, ws, s)) return -1;
   if (vdtype == SYMNMF_F64)
-    k_slab_fill<double><<<nbw, 256, 0, s>>>(rp, ci, (const double*)val, rows, weights, d_count, seg_cnt, seg_ptr,
-                                            seg_src, seg_val, seg_cap, st);
+    k_slab_fill_rows<double><<<ceil_div(n, 16), 256, 0, s>>>(rp, ci, (const double*)val, n, wmask, seg_cnt, seg_ptr,
+                                                             seg_src, seg_val, seg_cap, st);
   else
-    k_slab_fill<float><<<nbw, 256, 0, s>>>(rp, ci, (const float*)val, rows, weights, d_count, seg_cnt, seg_ptr,
-                                           seg_src, seg_val, seg_cap, st);
-  k_slab_sort<<<ceil_div(n, 256), 256, 0, s>>>(seg_ptr, n, seg_src, seg_val, seg_cap, st);
+    k_slab_fill_rows<float><<<ceil_div(n, 16), 256, 0, s>>>(rp, ci, (const float*)val, n, wmask, seg_cnt, seg_ptr,
+                                                            seg_src, seg_val, seg_cap, st);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }

@@ -8,7 +8,8 @@
 // Right-hand side of row j (Update(G, Y) of the Appendix with the
 // regularised pair; Y stored as X F, row-major):
 //   YMODE 0  y_j = sum_s P[s][j]          split-K partials of X F (or X F)
-//   YMODE 1  y_j = sum_e v_e F[src_e]     transposed sampled slab (LvS)
+//   YMODE 1  y_j = sum_e v_e F[src_e]     sampled slab (LvS): the stored
+//            X[j][r] w_r of row j with r in the sample, in column order
 //   YMODE 2  y_j = U[j,:] M,  M = Lambda U^T F   (LAI)
 // and the HALS target is y_j + alpha F[j].
 #include "kernels.hpp"
@@ -19,24 +20,6 @@ namespace {
 // MI355X at n = 16384: a LAI iteration 68 us with 16-row, 256-thread blocks,
 // 62 us with 32, 67 us with 64; the same 512 blocks in each case).
 constexpr int UPD_RPB = 32;
-
-// Sum of a double over the 16 lanes of a DPP row, every lane receiving the
-// total: quad_perm [1,0,3,2] and [2,3,0,1] (pairs, quads), then
-// row_half_mirror and row_mirror (halves, full row).  DPP moves are plain
-// VALU operations, unlike the LDS permutes behind __shfl_xor.
-template <int CTRL>
-__device__ __forceinline__ double dpp_double(double v) {
-  const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), CTRL, 0xF, 0xF, false);
-  const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, 0xF, 0xF, false);
-  return __hiloint2double(hi, lo);
-}
-__device__ __forceinline__ double row16_sum(double v) {
-  v += dpp_double<0xB1>(v);   // quad_perm(1,0,3,2)
-  v += dpp_double<0x4E>(v);   // quad_perm(2,3,0,1)
-  v += dpp_double<0x141>(v);  // row_half_mirror
-  v += dpp_double<0x140>(v);  // row_mirror
-  return v;
-}
 
 // Column held in slot c by lane g of a row: with 16 lanes per row the
 // columns interleave (g + 16 c); with 8 lanes each lane holds runs of 4

@@ -25,6 +25,11 @@ struct Workspace {
     return base + a;
   }
   double* dbl(size_t n) { return (double*)raw(n * sizeof(double)); }
+  // doubles still available after alignment of the next request
+  size_t avail_doubles() const {
+    const size_t a = (off + 255) & ~(size_t)255;
+    return base == nullptr || a >= cap ? 0 : (cap - a) / sizeof(double);
+  }
   int* i32(size_t n) { return (int*)raw(n * sizeof(int)); }
   uint64_t* u64(size_t n) { return (uint64_t*)raw(n * sizeof(uint64_t)); }
 };
@@ -119,9 +124,9 @@ struct UpdateArgs {
   int n = 0, k = 0, l = 0, splits = 1, cp = 0;
   int64_t ldt = 0;
   const void* P = nullptr;           // YMODE 0: partials [splits][n][cp]
-  const int* seg_ptr = nullptr;      // YMODE 1: transposed sampled slab
-  const int* seg_src = nullptr;
-  const double* seg_val = nullptr;
+  const int* seg_ptr = nullptr;      // YMODE 1: sampled slab, segment j = the stored
+  const int* seg_src = nullptr;      // X[j][r] w_r of row j with r in the sample,
+  const double* seg_val = nullptr;   // in column order
   const double* U = nullptr;         // YMODE 2: U (n x l) and M = Lambda U^T F (l x k)
   const double* M = nullptr;
   const void* Src = nullptr;         // the fixed factor (alpha term, YMODE 1 rows)
@@ -238,16 +243,18 @@ struct SampleBuffers {
   double* theta = nullptr;     // deterministic leverage mass
 };
 // rows/weights: capacity >= s; the number of rows lands in info[2].
+// wmask (n doubles, may be nullptr): each row's weight, 0 off the sample.
 int hybrid_sample(const double* lev, int n, int k, int64_t s_total, double tau, uint64_t seed, uint32_t half_iter,
                   SampleBuffers& sb, int* rows, double* weights, int64_t cap, Workspace& ws, const DevState* st,
-                  hipStream_t s);
+                  hipStream_t s, double* wmask = nullptr);
 
-// Transposed slab of the sampled rows: for each listed row r (weight w_r) and
-// each stored X[r][i], an entry (src r, value X[r][i] w_r) in segment i; the
-// segments are sorted by src.  seg_ptr has n+1 entries; seg_cnt (n ints) must
-// be zero on entry and is zero again on exit.
+// Sampled slab of X S^T S: segment j lists (r, X[j][r] w_r) for the stored
+// entries of row j whose column r is in the sample (w: the sample's weight of
+// every row, 0 off it), in column order.  X is symmetric, so these are the
+// entries of the sampled rows.  seg_cnt (n ints) must be zero on entry and is
+// zero again on exit; seg_ptr has n + 1 entries.
 int sampled_slab(const int* rp, const int* ci, const void* val, int vdtype, int n, const int* rows,
-                 const double* weights, const int* d_count, int max_rows, int* seg_cnt, int* seg_ptr, int* seg_src,
+                 const int* d_count, int max_rows, const double* wmask, int* seg_cnt, int* seg_ptr, int* seg_src,
                  double* seg_val, int64_t seg_cap, Workspace& ws, const DevState* st, hipStream_t s);
 
 // ---- learned warm start ------------------------------------------------------

@@ -242,6 +242,7 @@ struct symnmf_ctx {
   int* rows = nullptr;
   double* weights = nullptr;
   int64_t max_sel = 0;
+  double* wmask = nullptr;  // LvS: weight of every row in the current sample, 0 off it
   int* seg_cnt = nullptr;
   int* seg_ptr = nullptr;
   int* seg_src = nullptr;
@@ -249,7 +250,6 @@ struct symnmf_ctx {
   int64_t seg_cap = 0;
   double* lev = nullptr;
   double *R = nullptr, *Rinv = nullptr;
-  std::vector<int> host_rp;
   std::string err;
   // phase timing (options.timing): event pairs recorded on the stream,
   // harvested into phase_ms when the pool fills or the stats are read
@@ -287,7 +287,7 @@ struct symnmf_ctx {
     else (void)hipDeviceSynchronize();
     void* ptrs[] = {Xb_owned, W, H, Y, Yk, Yhat, P, Bt, BtW, BtH, part, dpart, M_W, M_H, Gi_W, Gi_H, Gi_S, G_W, G_H, Gh_W, Gh_H, Gh_S, d_scal, rowsum, dstate, hist, d_fail,
                     ws.base, Q, Q1, U, YQ, Tm, QT, Vw, lam, Rl, Rlinv, Z, sb.w, sb.prefix, sb.counts, sb.flags,
-                    sb.info, sb.theta, rows, weights, seg_cnt, seg_ptr, seg_src, seg_val, lev, R, Rinv};
+                    sb.info, sb.theta, rows, weights, wmask, seg_cnt, seg_ptr, seg_src, seg_val, lev, R, Rinv};
     for (void* p : ptrs) dfree(p);
     pinned_pool().put(hbuf);
     for (auto& t : ev_pending) {
@@ -559,12 +559,13 @@ struct symnmf_ctx {
       ws.reset();
       LCHK(chol_inverse(Gs, k, R, Rinv, &dstate->flags, SYMNMF_FLAG_LEV_SHIFT, d_fail, st));
       LCHK(leverage_scores(Src, fdtype, n, k, Rinv, lev, gate_, st));
-      LCHK(hybrid_sample(lev, n, k, s, tau, seed, (uint32_t)half_iter, sb, rows, weights, max_sel, ws, gate_, st));
+      LCHK(hybrid_sample(lev, n, k, s, tau, seed, (uint32_t)half_iter, sb, rows, weights, max_sel, ws, gate_, st,
+                         wmask));
       ws.reset();
       LCHK(gram(Src, fdtype, k, k, Src, fdtype, k, k, n, rows, weights, sb.info + 2, (int)max_sel, ws, nullptr, Gh_S,
                 kp, alpha, gate_, st, Gi_S));
       ws.reset();
-      LCHK(sampled_slab(rp, ci, Xv, xdtype, n, rows, weights, sb.info + 2, (int)max_sel, seg_cnt, seg_ptr, seg_src,
+      LCHK(sampled_slab(rp, ci, Xv, xdtype, n, rows, sb.info + 2, (int)max_sel, wmask, seg_cnt, seg_ptr, seg_src,
                         seg_val, seg_cap, ws, gate_, st));
       a.seg_ptr = seg_ptr;
       a.seg_src = seg_src;
@@ -1128,6 +1129,8 @@ int symnmf_create(symnmf_ctx** out, const symnmf_matrix* X, int32_t k, double al
       wsd = std::max(wsd, nb * nb + 4096);
     }
     wsd = std::max(wsd, (size_t)3 * n + 65536);
+    // Gram partials of 1024 blocks past 2^16 rows, twice over
+    if (n > (1 << 16)) wsd = std::max(wsd, (size_t)4 * 1024 * k * k + 65536);
     c->ws.cap = wsd * sizeof(double);
     c->ws.base = dalloc<char>(c->ws.cap);
 
@@ -1229,7 +1232,10 @@ int symnmf_create(symnmf_ctx** out, const symnmf_matrix* X, int32_t k, double al
     LCHK(init_uniform_factor(c->H, c->fdtype, n, k, 2.0 * std::sqrt(c->zeta / k), seed, c->st));
     HIPCHK(hipMemcpyAsync(c->W, c->H, (size_t)n * k * fs, hipMemcpyDeviceToDevice, c->st));
     c->refresh_gram(c->H, c->G_H, c->Gh_H, c->Gi_H);
-    c->refresh_gram(c->W, c->G_W, c->Gh_W, c->Gi_W);
+    // W0 = H0: its Gram matrices are copies
+    HIPCHK(hipMemcpyAsync(c->G_W, c->G_H, sizeof(double) * k * k, hipMemcpyDeviceToDevice, c->st));
+    HIPCHK(hipMemcpyAsync(c->Gh_W, c->Gh_H, sizeof(double) * c->kp * c->kp, hipMemcpyDeviceToDevice, c->st));
+    HIPCHK(hipMemcpyAsync(c->Gi_W, c->Gi_H, sizeof(double) * c->kp, hipMemcpyDeviceToDevice, c->st));
 
     if (s > 0) {
       if (c->kind != SYMNMF_CSR) throw Fail{SYMNMF_E_UNSUPPORTED, "sampling needs CSR X"};
@@ -1238,11 +1244,12 @@ int symnmf_create(symnmf_ctx** out, const symnmf_matrix* X, int32_t k, double al
       // (sum p_i = 1 up to rounding, so at most about 1/tau of them)
       int64_t ms = c->tau > 0.0 ? s + (int64_t)std::ceil(1.01 / c->tau) + 1 : (int64_t)n;
       c->max_sel = std::min<int64_t>(ms, n);
-      c->host_rp.resize((size_t)n + 1);
-      HIPCHK(hipMemcpyAsync(c->host_rp.data(), c->rp, sizeof(int) * (n + 1), hipMemcpyDeviceToHost, c->st));
+      // slab capacity: the stored entries of the max_sel longest rows
+      std::vector<int> hrp((size_t)n + 1);
+      HIPCHK(hipMemcpyAsync(hrp.data(), c->rp, sizeof(int) * (n + 1), hipMemcpyDeviceToHost, c->st));
       c->sync();
       std::vector<int> len(n);
-      for (int i = 0; i < n; ++i) len[i] = c->host_rp[i + 1] - c->host_rp[i];
+      for (int i = 0; i < n; ++i) len[i] = hrp[i + 1] - hrp[i];
       std::nth_element(len.begin(), len.begin() + (c->max_sel - 1), len.end(), std::greater<int>());
       int64_t cap = 0;
       for (int64_t i = 0; i < c->max_sel; ++i) cap += len[i];
@@ -1250,6 +1257,7 @@ int symnmf_create(symnmf_ctx** out, const symnmf_matrix* X, int32_t k, double al
       c->ensure_sampling_buffers();
       c->rows = dalloc<int>(c->max_sel);
       c->weights = dalloc<double>(c->max_sel);
+      c->wmask = dalloc<double>(n);
       c->seg_cnt = dalloc<int>(n);
       c->seg_ptr = dalloc<int>((size_t)n + 1);
       c->seg_src = dalloc<int>(c->seg_cap);
