@@ -22,31 +22,38 @@ namespace {
 constexpr int UPD_RPB = 32;
 
 // Column held in slot c by lane g of a row: with 16 lanes per row the
-// columns interleave (g + 16 c); with 8 lanes each lane holds runs of 4
-// adjacent columns (32 (c / 4) + 4 g + c mod 4), so the 8 lanes of a row read
-// 32 adjacent values per step.
+// columns interleave (g + 16 c); with LPR = 2, 4 or 8 lanes each lane holds
+// runs of 4 adjacent columns (4 LPR (c / 4) + 4 g + c mod 4), so the lanes of
+// a row read 4 LPR adjacent values per step.
 template <int LPR>
 __device__ __forceinline__ constexpr int col_of(int g, int c) {
-  return LPR == 8 ? 32 * (c >> 2) + 4 * g + (c & 3) : g + 16 * c;
+  return LPR == 16 ? g + 16 * c : 4 * LPR * (c >> 2) + 4 * g + (c & 3);
 }
-// Sum over the LPR lanes of a row: 8 lanes are half a DPP row (pairs, quads,
-// then row_half_mirror), 16 a full row.
+// Slot and owning lane of column i.
+template <int LPR>
+__device__ __forceinline__ constexpr int slot_of(int i) {
+  return LPR == 16 ? i >> 4 : 4 * (i / (4 * LPR)) + (i & 3);
+}
+template <int LPR>
+__device__ __forceinline__ constexpr int owner_of(int i) {
+  return LPR == 16 ? i & 15 : (i >> 2) % LPR;
+}
+// Sum over the LPR lanes of a row (contiguous lanes of a DPP row): pairs,
+// quads, halves (row_half_mirror), full row (row_mirror) as needed.
 template <int LPR>
 __device__ __forceinline__ double lanes_sum(double v) {
-  if (LPR == 8) {
-    v += dpp_double<0xB1>(v);
-    v += dpp_double<0x4E>(v);
-    v += dpp_double<0x141>(v);
-    return v;
-  }
-  return row16_sum(v);
+  v += dpp_double<0xB1>(v);
+  if (LPR >= 4) v += dpp_double<0x4E>(v);
+  if (LPR >= 8) v += dpp_double<0x141>(v);
+  if (LPR >= 16) v += dpp_double<0x140>(v);
+  return v;
 }
 
 // Waves per SIMD the register allocation must leave room for: the long-factor
 // update without a LAI term (KP = 64) otherwise takes more than 128 VGPRs and
 // runs one 512-thread block per CU.
-template <int KP, int LP>
-constexpr int upd_waves() { return KP == 64 && LP == 0 ? 4 : 1; }
+template <int KP, int LP, int LPR>
+constexpr int upd_waves() { return KP == 64 && LP == 0 ? (LPR >= 8 ? 4 : 2) : 1; }
 
 // LPR lanes per row (16, or 8 for long factors with KP a multiple of 32:
 // three DPP steps per column sum instead of four and half as many lanes per
@@ -54,7 +61,7 @@ constexpr int upd_waves() { return KP == 64 && LP == 0 ? 4 : 1; }
 // col_of(g, c).  The HALS sweep over column i sums w_q Ghat[i][q] over the
 // row's lanes and the lane owning column i applies the update.
 template <int KP, int LP, typename TF, typename TP, typename TT, int YMODE, int LPR>
-__global__ __launch_bounds__(16 * UPD_RPB) __attribute__((amdgpu_waves_per_eu(upd_waves<KP, LP>())))
+__global__ __launch_bounds__(16 * UPD_RPB) __attribute__((amdgpu_waves_per_eu(upd_waves<KP, LP, LPR>())))
 void k_update(UpdateArgs a, const double* __restrict__ Gh,
                                                 const double* __restrict__ Ginv, const double* __restrict__ M,
                                                 const TF* __restrict__ Src, const DevState* __restrict__ st) {
@@ -257,7 +264,7 @@ void k_update(UpdateArgs a, const double* __restrict__ Gh,
         for (int i = 0; i < KP; ++i) {
           // slot changed by column i - 1 goes last: the other terms of the
           // dot product do not wait for that column's result
-          const int cp = i == 0 ? -1 : (LPR == 8 ? 4 * ((i - 1) >> 5) + ((i - 1) & 3) : (i - 1) >> 4);
+          const int cp = i == 0 ? -1 : slot_of<LPR>(i - 1);
           double part = 0.0;
 #pragma unroll
           for (int c = 0; c < CPL; ++c)
@@ -265,8 +272,8 @@ void k_update(UpdateArgs a, const double* __restrict__ Gh,
           if (cp >= 0) part = fma(w[cp], gs[i * KP + col_of<LPR>(g, cp)], part);
           part = lanes_sum<LPR>(part);
           // slot and owning lane of column i
-          const int ci = LPR == 8 ? 4 * (i >> 5) + (i & 3) : i >> 4;
-          const int own = LPR == 8 ? (i >> 2) & 7 : i & 15;
+          const int ci = slot_of<LPR>(i);
+          const int own = owner_of<LPR>(i);
           const double cand = fmax(0.0, fma(y[ci] - part, gi[i], w[ci]));
           w[ci] = (g == own) ? cand : w[ci];
         }
@@ -522,6 +529,10 @@ int launch_update_lpr(const UpdateArgs& a, const UpdateRO& ro, int nb, const Dev
   return 0;
 }
 
+// 8 lanes per row where update_lpr8 allows it, else 16.  Fewer lanes per row
+// for the long factor without a LAI term (KP = 64, n = 2^20, FP32) passed the
+// parity tests and measured slower: 4 lanes (232 VGPRs, two waves per SIMD)
+// plain iteration 3.80 -> 4.02 ms, 2 lanes (256 VGPRs and spills) 22.9 ms.
 template <int KP, int LP, typename TF, typename TP, typename TT, int YMODE>
 int launch_update(const UpdateArgs& a, const UpdateRO& ro, int nb, const DevState* st, hipStream_t s) {
   if constexpr (KP % 32 == 0) {
