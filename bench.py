@@ -82,6 +82,8 @@ def main():
     ap.add_argument("--warm-weights", default=None, help="network file (default: the committed one)")
     ap.add_argument("--warm-out", default=None, help="also write the per-instance records to this JSON file")
     ap.add_argument("--precision-n", type=int, default=65536)
+    ap.add_argument("--precision-oracle-iters", type=int, default=2,
+                    help="iterations of the precision workload's oracle check (the converged run: 80)")
     ap.add_argument("--sparse-n", type=int, default=1 << 20)
     ap.add_argument("--sparse-k", type=int, default=64)
     ap.add_argument("--sparse-s", type=int, default=8192)
@@ -224,7 +226,28 @@ def main():
     alg_bytes = float(n) * n * 4 + 2.0 * n * k * 4
     achieved = alg_bytes / t_prod / 1e9
     log(f"[bench] X*H product {t_prod * 1e6:.1f} us over {calls} launches -> {achieved:.0f} GB/s algorithmic")
-    traffic = stored_traffic(n, k)
+    traffic = stored_traffic("k_gemm_cols_f32_gk16384_k32_pmc.txt", "k_dense.hip", n, k)
+
+    # The dominant kernel of the timed learned_lai solve by device time is
+    # the LAI update (two launches per LAI iteration): timed alone on a
+    # context in LAI mode after the learned start (HIP events around every
+    # update launch).  Algorithmic bytes per launch: U (n x l FP64), the
+    # source factor and the old factor read, the new factor written (n x k
+    # FP32 each): n (8 l + 12 k).
+    o = P.symnmf_default_options(timing=1)
+    c = P.symnmf_create(X, k, 0.0, 0, seeds[0], o)
+    P.symnmf_lai(c, l, q)
+    P.symnmf_warmstart(c, net, want_beta=False)
+    P.symnmf_iterate(c, 40)
+    ph = phase_totals(P, [c])
+    del c
+    t_upd = ph["update"][0] / 1e3 / ph["update"][1]
+    t_red = ph["reduce"][0] / 1e3 / ph["reduce"][1]
+    alg_upd = float(n) * (8.0 * l + 12.0 * k)
+    ach_upd = alg_upd / t_upd / 1e9
+    log(f"[bench] LAI update {t_upd * 1e6:.1f} us over {ph['update'][1]} launches -> {ach_upd:.0f} GB/s "
+        f"algorithmic; partial-sum reduction {t_red * 1e6:.1f} us")
+    traffic_upd = stored_traffic("k_update_lai_gk16384_k32_l48_pmc.txt", "k_update.hip", n, k)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -251,16 +274,23 @@ def main():
                                f"trained network, scale fit), LAI iterations, refinement on X",
                    "n": n, "k": k, "l": l, "q": q, "r_conv": r_conv, "r_star": r_star,
                    "learned_vs_plain": t_plain / t_val,
-                   "methods": res},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": "k_gemm_cols<2, 2, true> (X H read along rows of X, one launch per half-iteration)",
-                     "us_per_launch": t_prod * 1e6, "launches": calls,
-                     "algorithmic_bytes_per_launch": alg_bytes,
-                     # the same launches against the FP32 matrix-core peak
-                     # (2 n^2 k flop per product)
-                     "mfma_tflops": 2.0 * n * n * k / t_prod / 1e12,
-                     "mfma_frac": 2.0 * n * n * k / t_prod / 1e12 / FP32_MFMA_PEAK_TFLOPS},
+                   "methods": res,
+                   # the X H product (the plain method's dominant kernel)
+                   "roofline_xh": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                   "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                                   "kernel": "k_gemm_cols<2, 2, true> (X H read along rows of X)",
+                                   "us_per_launch": t_prod * 1e6, "launches": calls,
+                                   "algorithmic_bytes_per_launch": alg_bytes,
+                                   "mfma_tflops": 2.0 * n * n * k / t_prod / 1e12,
+                                   "mfma_frac": 2.0 * n * n * k / t_prod / 1e12 / FP32_MFMA_PEAK_TFLOPS}},
+        "roofline": {"bound": "hbm", "achieved": ach_upd, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": ach_upd / HBM_PEAK_GBS, "traffic": traffic_upd,
+                     "kernel": "k_update<32, 48, float, float, float, 2, 8> (fused LAI update: U M + alpha F, "
+                               "HALS sweep, new factor, block partials of F^T F and U^T F; two launches per LAI "
+                               "iteration, the largest device-time share of the learned_lai solve)",
+                     "us_per_launch": t_upd * 1e6, "launches": ph["update"][1],
+                     "algorithmic_bytes_per_launch": alg_upd,
+                     "reduction_us_per_launch": t_red * 1e6},
         "phases_ms_per_solve": {m: {kk: v[0] for kk, v in ph.items()} for m, ph in phases.items()},
         "cpu_baseline": cpu,
     }
@@ -626,7 +656,7 @@ def bench_precision(args):
     achieved = alg_bytes / t_prod / 1e9
     best = min((v["s_per_solve"], kk) for kk, v in res.items()
                if kk.endswith("bf16") and kk != "products" and v["reached_r_star"])
-    cpu = None if args.no_cpu_baseline else precision_oracle_leg(X, k, res)
+    cpu = None if args.no_cpu_baseline else precision_oracle_leg(X, k, res, args.precision_oracle_iters)
     out = {
         "metric": "SymNMF time-to-residual (s) and X*H GB/s or MFMA %, learned-init vs plain",
         "value": best[0], "unit": "s", "n_gpus": 1, "steps": 1, "warmup": 1, "ms_per_step": best[0] * 1e3,
@@ -644,10 +674,12 @@ def bench_precision(args):
     return out
 
 
-def precision_oracle_leg(X, k, res):
-    """The FP64 oracle on the host: two plain HALS iterations on the same X
-    bits and start as the GPU's FP32 and BF16 runs of two iterations; timed
-    (the baseline) and compared (relative residual error of each precision)."""
+def precision_oracle_leg(X, k, res, iters=2):
+    """The FP64 oracle on the host: `iters` plain HALS iterations (2 by
+    default; --precision-oracle-iters for a run as long as the converged
+    GPU run) on the same X bits and start as the GPU's FP32 and BF16 runs of
+    as many iterations; timed (the baseline) and compared (relative residual
+    error of each precision)."""
     import numpy as np
     import torch
     import paper_2402_08134_amd as P
@@ -660,29 +692,38 @@ def precision_oracle_leg(X, k, res):
         if prec == "bf16":
             o.compute_dtype = P.BF16
         c = P.symnmf_create(X, k, 0.0, 0, 1, o)
-        P.symnmf_iterate(c, 2)
+        P.symnmf_iterate(c, iters)
         out[prec] = P.symnmf_residual(c, P.RESID_EXACT)[0]
         del c
-    log("[bench] oracle: scalars + 2 FP64 iterations on the host ...")
+    log(f"[bench] oracle: scalars + {iters} FP64 iterations on the host ...")
     t0 = time.perf_counter()
     sc = O.data_scalars(Xh)
     H0 = O.initial_factor(n, k, sc["zeta"], 1).astype(np.float32).astype(np.float64)
-    Wo, Ho, hist = O.plain_symnmf(Xh, k, sc["maxval"], H0, 2)
+    done = [0]
+
+    def progress(r):
+        done[0] += 1
+        if iters > 2:
+            log(f"[bench] oracle iteration {done[0]}/{iters}: residual {r:.6f} [{time.perf_counter() - t0:.0f}s]")
+        return False
+
+    Wo, Ho, hist = O.plain_symnmf(Xh, k, sc["maxval"], H0, iters, stop=progress)
     t = time.perf_counter() - t0
     ro = O.residual_direct(Xh, Wo, Ho) / np.sqrt(sc["normsq"])
     errs = {p: abs(v - ro) / ro for p, v in out.items()}
-    log(f"[bench] oracle residual after 2 iterations {ro:.6f}; GPU relative error FP32 {errs['f32']:.2e} "
+    log(f"[bench] oracle residual after {iters} iterations {ro:.6f}; GPU relative error FP32 {errs['f32']:.2e} "
         f"BF16 {errs['bf16']:.2e}; oracle time {t:.1f}s")
     threads = os.environ.get("OMP_NUM_THREADS") or str(os.cpu_count())
     return {"value": t, "unit": "s", "cores": int(threads), "kind": "oracle",
-            "sample": "scalars pass + 2 plain FP64 HALS iterations at full size on the same X bits and start",
-            "residual_after_2": ro, "gpu_relative_error": errs}
+            "sample": f"scalars pass + {iters} plain FP64 HALS iterations at full size on the same X bits and start",
+            "iterations": iters, "residual_oracle": ro,
+            "residual_gpu": out, "gpu_relative_error": errs}
 
 
 def phase_totals(P, ctxs):
     """Summed (ms, launches) per phase over the contexts of a timed loop."""
     names = {P.PHASE_PRODUCT: "product", P.PHASE_UPDATE: "update", P.PHASE_SAMPLE: "sample", P.PHASE_LAI: "lai",
-             P.PHASE_WARM: "warm"}
+             P.PHASE_WARM: "warm", P.PHASE_REDUCE: "reduce"}
     tot = {v: [0.0, 0] for v in names.values()}
     for c in ctxs:
         st = P.symnmf_get_stats(c)
@@ -692,13 +733,13 @@ def phase_totals(P, ctxs):
     return tot
 
 
-def stored_traffic(n, k):
-    """HBM bytes per launch of the product kernel from the committed
-    rocprofv3 counter summary, or None when that summary is missing, was
-    taken at another size, or the kernel source changed since."""
+def stored_traffic(summary, source, n, k):
+    """HBM bytes per launch of a kernel from a committed rocprofv3 counter
+    summary (profiles/<summary>), or None when that summary is missing, was
+    taken at another size, or the kernel's source changed since."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", "k_gemm_cols_f32_gk16384_k32_pmc.txt")
-    src = os.path.join(ROOT, "paper_2402_08134_amd", "csrc", "k_dense.hip")
+    path = os.path.join(ROOT, "profiles", summary)
+    src = os.path.join(ROOT, "paper_2402_08134_amd", "csrc", source)
     if not os.path.exists(path):
         return None
     kv = {}
@@ -707,7 +748,7 @@ def stored_traffic(n, k):
             key, _, val = line.partition(":")
             kv[key.strip()] = val.strip()
     digest = hashlib.sha256(open(src, "rb").read()).hexdigest()
-    if kv.get("k_dense.hip sha256") != digest or kv.get("n") != str(n) or kv.get("k") != str(k):
+    if kv.get(f"{source} sha256") != digest or kv.get("n") != str(n) or kv.get("k") != str(k):
         return None
     try:
         return float(kv["hbm bytes per launch (scaled)"])
@@ -718,7 +759,8 @@ def stored_traffic(n, k):
 def pmc_probe(args):
     """Short fixed workload for the rocprofv3 counter passes: a 1 GiB device
     copy (the calibration kernel of known traffic), then ten plain
-    iterations at the bench size."""
+    iterations at the bench size, then the learned start and ten LAI
+    iterations."""
     import numpy as np
     import torch
     import paper_2402_08134_amd as P
@@ -736,6 +778,14 @@ def pmc_probe(args):
     P.symnmf_iterate(c, 10)
     torch.cuda.synchronize()
     log("[pmc-probe] 10 plain iterations done")
+    from paper_2402_08134_amd import warmstart as WSP
+    net = WSP.load(os.path.join(WSP.WEIGHTS_DIR, WARM_WEIGHTS))
+    c = P.symnmf_create(X, args.k, 0.0, 0, 1)
+    P.symnmf_lai(c, args.k + 16, 2)
+    P.symnmf_warmstart(c, net, want_beta=False)
+    P.symnmf_iterate(c, 10)
+    torch.cuda.synchronize()
+    log("[pmc-probe] learned start and 10 LAI iterations done")
 
 
 def pmc_probe_sparse(args):

@@ -96,16 +96,21 @@ extern "C" {
 /* phases of symnmf_stats.phase_ms (options.timing = 1):
  *   PRODUCT: the X-product kernel of each half-iteration (dense GEMM or CSR
  *            SpMM; one launch each), and the residual products of LvS
- *   UPDATE:  the fused NLS update and its partial-sum reduction
+ *   UPDATE:  the fused NLS update kernel of each HALS / BPP half-iteration
+ *            (one launch; BPP: the right-hand-side pass, the pivoting kernel
+ *            and the write-back pass), and the PGNCG passes
  *   SAMPLE:  LvS leverage scores, sampler and sampled operands
  *   LAI:     the whole randomized range finder and Apx-EVD (symnmf_lai)
- *   WARM:    the learned warm start (symnmf_warmstart) */
+ *   WARM:    the learned warm start (symnmf_warmstart)
+ *   REDUCE:  the fixed-order reduction of the update's block partials (Gram
+ *            matrices, Lambda U^T F) after each HALS / BPP half-iteration */
 #define SYMNMF_PHASE_PRODUCT 0
 #define SYMNMF_PHASE_UPDATE 1
 #define SYMNMF_PHASE_SAMPLE 2
 #define SYMNMF_PHASE_LAI 3
 #define SYMNMF_PHASE_WARM 4   /* symnmf_warmstart: features, network, scale fit */
-#define SYMNMF_NUM_PHASES 5
+#define SYMNMF_PHASE_REDUCE 5
+#define SYMNMF_NUM_PHASES 6
 
 /* stats flags */
 #define SYMNMF_FLAG_LEV_SHIFT 1    /* chol(H^T H) needed a diagonal shift   */

@@ -20,8 +20,8 @@ STOP_NONE, STOP_STALL, STOP_TARGET, STOP_STALL_OR_TARGET = 0, 1, 2, 3
 RESID_FAST, RESID_EXACT, RESID_LAI = 0, 1, 2
 W, H = 0, 1
 MODE_PLAIN, MODE_LAI, MODE_LVS = 0, 1, 2
-PHASE_PRODUCT, PHASE_UPDATE, PHASE_SAMPLE, PHASE_LAI, PHASE_WARM = 0, 1, 2, 3, 4
-NUM_PHASES = 5
+PHASE_PRODUCT, PHASE_UPDATE, PHASE_SAMPLE, PHASE_LAI, PHASE_WARM, PHASE_REDUCE = 0, 1, 2, 3, 4, 5
+NUM_PHASES = 6
 MLP_FEATURES, MLP_HIDDEN = 6, 64
 FLAG_LEV_SHIFT, FLAG_CHOLQR_SHIFT, FLAG_BPP_CAP = 1, 2, 4
 
@@ -53,8 +53,8 @@ class Stats(ctypes.Structure):
                 ("alpha", ctypes.c_double), ("zeta", ctypes.c_double), ("normsq", ctypes.c_double),
                 ("maxval", ctypes.c_double), ("last_residual", ctypes.c_double), ("s_D", ctypes.c_int64),
                 ("sample_rows", ctypes.c_int64), ("theta_over_k", ctypes.c_double), ("flags", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 7), ("warm_beta", ctypes.c_double), ("phase_ms", ctypes.c_double * 5),
-                ("phase_calls", ctypes.c_int64 * 5), ("graph_launches", ctypes.c_int64)]
+                ("reserved", ctypes.c_int32 * 7), ("warm_beta", ctypes.c_double), ("phase_ms", ctypes.c_double * NUM_PHASES),
+                ("phase_calls", ctypes.c_int64 * NUM_PHASES), ("graph_launches", ctypes.c_int64)]
 
 
 _VP = ctypes.c_void_p

@@ -618,29 +618,35 @@ struct symnmf_ctx {
     const int nb = update_blocks(n, kp, ymode == 2 ? 16 * ceil_div(l, 16) : 0, fdtype);
     if (want_dot) nb_dot = nb;
     if (opt.rule == SYMNMF_RULE_HALS) {
-      Timed tm(this, SYMNMF_PHASE_UPDATE);
       UpdateRO ro;
       ro.Ghat = a.Ghat;
       ro.Ginv = Gis;
       ro.M = a.M;
-      LCHK(fused_update(a, ro, kp, ymode, fdtype, pdt, tdt, nb, gate_, st));
+      {
+        Timed tm(this, SYMNMF_PHASE_UPDATE);
+        LCHK(fused_update(a, ro, kp, ymode, fdtype, pdt, tdt, nb, gate_, st));
+      }
+      Timed tr(this, SYMNMF_PHASE_REDUCE);
       LCHK(update_reduce(part, nb, a.pstride, k, l, kp, alpha, lam, Gd, Ghd, Gid,
                          side == 0 ? M_W : M_H, gate_, st));
     } else {
       // BPP: the update kernel writes the right-hand sides, the pivoting
       // kernel solves every row in place, and the update kernel then takes
       // the solutions through its usual write-back and partials.
-      Timed tm(this, SYMNMF_PHASE_UPDATE);
       UpdateRO ro;
       ro.Ghat = a.Ghat;
       ro.Ginv = Gis;
       ro.M = a.M;
       a.Yhat = Yhat;
-      a.rule = 1;
-      LCHK(fused_update(a, ro, kp, ymode, fdtype, pdt, tdt, nb, gate_, st));
-      LCHK(bpp_update(n, k, kp, Yhat, Dst, fdtype, a.Ghat, &dstate->flags, SYMNMF_FLAG_BPP_CAP, gate_, st));
-      a.rule = 2;
-      LCHK(fused_update(a, ro, kp, ymode, fdtype, pdt, tdt, nb, gate_, st));
+      {
+        Timed tm(this, SYMNMF_PHASE_UPDATE);
+        a.rule = 1;
+        LCHK(fused_update(a, ro, kp, ymode, fdtype, pdt, tdt, nb, gate_, st));
+        LCHK(bpp_update(n, k, kp, Yhat, Dst, fdtype, a.Ghat, &dstate->flags, SYMNMF_FLAG_BPP_CAP, gate_, st));
+        a.rule = 2;
+        LCHK(fused_update(a, ro, kp, ymode, fdtype, pdt, tdt, nb, gate_, st));
+      }
+      Timed tr(this, SYMNMF_PHASE_REDUCE);
       LCHK(update_reduce(part, nb, a.pstride, k, l, kp, alpha, lam, Gd, Ghd, Gid,
                          side == 0 ? M_W : M_H, gate_, st));
     }
