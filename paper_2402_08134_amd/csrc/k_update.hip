@@ -525,7 +525,11 @@ int launch_update_lpr(const UpdateArgs& a, const UpdateRO& ro, int nb, const Dev
     return -1;
   // exactly nb blocks (the reduction reads nb partials); rows beyond
   // RPB * nb are covered by the grid-stride loop
-  kern<<<nb, 16 * UPD_RPB, lds, s>>>(a, ro.Ghat, ro.Ginv, ro.M, (const TF*)a.Src, st);
+  if (a.ev_start)
+    hipExtLaunchKernelGGL(kern, dim3(nb), dim3(16 * UPD_RPB), (uint32_t)lds, s, a.ev_start, a.ev_stop, 0u, a, ro.Ghat,
+                          ro.Ginv, ro.M, (const TF*)a.Src, st);
+  else
+    kern<<<nb, 16 * UPD_RPB, lds, s>>>(a, ro.Ghat, ro.Ginv, ro.M, (const TF*)a.Src, st);
   return 0;
 }
 

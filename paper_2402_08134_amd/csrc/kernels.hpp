@@ -6,6 +6,7 @@
 #include <cstdint>
 
 #include "common.hpp"
+#include <hip/hip_ext.h>
 #include "../../include/symnmf.h"
 
 // A bump allocator over one device buffer owned by the context.  Every
@@ -143,6 +144,9 @@ struct UpdateArgs {
   // new rows from Yhat (an exact NLS solution) instead of the sweep
   int rule = 0;
   double* Yhat = nullptr;
+  // when set, the update kernel is launched with hipExtLaunchKernel and these
+  // events take its start and end times (phase timing)
+  hipEvent_t ev_start = nullptr, ev_stop = nullptr;
 };
 // Read-only small operands of the update, passed as separate restrict-
 // qualified kernel arguments so the compiler reads them with scalar loads.

@@ -622,8 +622,15 @@ struct symnmf_ctx {
       ro.Ghat = a.Ghat;
       ro.Ginv = Gis;
       ro.M = a.M;
-      {
-        Timed tm(this, SYMNMF_PHASE_UPDATE);
+      if (opt.timing) {
+        // the update kernel's own start and end (events taken by its launch)
+        if (ev_pending.size() >= 4096) harvest_timers();
+        a.ev_start = take_event();
+        a.ev_stop = take_event();
+        const int rc = fused_update(a, ro, kp, ymode, fdtype, pdt, tdt, nb, gate_, st);
+        ev_pending.push_back({a.ev_start, a.ev_stop, SYMNMF_PHASE_UPDATE});
+        LCHK(rc);
+      } else {
         LCHK(fused_update(a, ro, kp, ymode, fdtype, pdt, tdt, nb, gate_, st));
       }
       Timed tr(this, SYMNMF_PHASE_REDUCE);
