@@ -252,6 +252,71 @@ __global__ __launch_bounds__(256) void k_rowmat(const TA* __restrict__ A, int64_
   out[(int64_t)j * ldo + q] = (TO)acc;
 }
 
+// out = A diag(scale) M on the FP64 matrix cores, for l, c <= 96: each wave
+// takes 16 rows and all CT = c / 16 (rounded up) output tiles; the block
+// stages diag(scale) M in LDS (rows padded to a multiple of 4 and columns to
+// CT 16 with zeros), lane (li, lg) feeds A[r0 + li][4 s + lg] and
+// M[4 s + lg][16 t + li] to v_mfma_f64_16x16x4f64 and holds output rows
+// lg + 4 v of column li of each tile.  A row's entries are read 4 at a time
+// by the 4 lane groups (one 16- or 32-byte run per row and step).
+template <typename TA, typename TO, int CT>
+__global__ __launch_bounds__(256) void k_rowmat_mfma(const TA* __restrict__ A, int64_t lda, int n, int l,
+                                                     const double* __restrict__ M, const double* __restrict__ scale,
+                                                     int c, TO* __restrict__ out, int64_t ldo,
+                                                     const DevState* __restrict__ st) {
+  if (stopped(st)) return;
+  constexpr int CP = 16 * CT;
+  __shared__ double Ms[96 * CP];
+  const int l4 = 4 * ((l + 3) / 4);
+  for (int e = threadIdx.x; e < l4 * CP; e += 256) {
+    const int p = e / CP, q = e - p * CP;
+    const bool in = p < l && q < c;
+    const double v = M[in ? p * c + q : 0];   // clamped index, masked value
+    const double sv = scale ? scale[in ? p : 0] : 1.0;
+    Ms[e] = in ? v * sv : 0.0;
+  }
+  __syncthreads();
+  const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63, li = lane & 15, lg = lane >> 4;
+  const int r0 = (blockIdx.x * 4 + wid) * 16;
+  if (r0 >= n) return;   // after the only barrier
+  const int ra = r0 + li < n ? r0 + li : n - 1;   // clamped row, its values unused beyond n
+  const TA* arow = A + (int64_t)ra * lda;
+  doublex4 acc[CT];
+#pragma unroll
+  for (int t = 0; t < CT; ++t) acc[t] = doublex4{0.0, 0.0, 0.0, 0.0};
+  for (int s4 = 0; s4 < l4; s4 += 4) {
+    const int p = s4 + lg;
+    const double av = p < l ? (double)arow[p < l ? p : 0] : 0.0;
+#pragma unroll
+    for (int t = 0; t < CT; ++t)
+      acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, Ms[p * CP + 16 * t + li], acc[t], 0, 0, 0);
+  }
+#pragma unroll
+  for (int t = 0; t < CT; ++t) {
+    const int q = 16 * t + li;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int r = r0 + lg + 4 * v;
+      if (r < n && q < c) out[(int64_t)r * ldo + q] = (TO)acc[t][v];
+    }
+  }
+}
+
+template <typename TA, typename TO>
+int rowmat_mfma(const TA* A, int64_t lda, int n, int l, const double* M, const double* scale, int c, TO* out,
+                int64_t ldo, const DevState* st, hipStream_t s) {
+  const int nb = ceil_div(n, 64);
+  switch ((c + 15) / 16) {
+    case 1: k_rowmat_mfma<TA, TO, 1><<<nb, 256, 0, s>>>(A, lda, n, l, M, scale, c, out, ldo, st); return 0;
+    case 2: k_rowmat_mfma<TA, TO, 2><<<nb, 256, 0, s>>>(A, lda, n, l, M, scale, c, out, ldo, st); return 0;
+    case 3: k_rowmat_mfma<TA, TO, 3><<<nb, 256, 0, s>>>(A, lda, n, l, M, scale, c, out, ldo, st); return 0;
+    case 4: k_rowmat_mfma<TA, TO, 4><<<nb, 256, 0, s>>>(A, lda, n, l, M, scale, c, out, ldo, st); return 0;
+    case 5: k_rowmat_mfma<TA, TO, 5><<<nb, 256, 0, s>>>(A, lda, n, l, M, scale, c, out, ldo, st); return 0;
+    case 6: k_rowmat_mfma<TA, TO, 6><<<nb, 256, 0, s>>>(A, lda, n, l, M, scale, c, out, ldo, st); return 0;
+    default: return -1;
+  }
+}
+
 // ---------------------------------------------------------------------------
 // One-workgroup Cholesky (upper R, R^T R = G + shift I) and R^{-1}.
 // ---------------------------------------------------------------------------
@@ -771,6 +836,21 @@ void finish_iteration(const double* dot_part, int nb, const double* Ga, const do
 
 int rowmat(const void* A, int adtype, int64_t lda, int n, int l, const double* M, const double* scale, int c,
            void* out, int odtype, int64_t ldo, const DevState* st, hipStream_t s) {
+  if (l >= 1 && l <= 96 && c >= 1 && c <= 96) {
+    int rc;
+    if (adtype == SYMNMF_F64 && odtype == SYMNMF_F64)
+      rc = rowmat_mfma<double, double>((const double*)A, lda, n, l, M, scale, c, (double*)out, ldo, st, s);
+    else if (adtype == SYMNMF_F64 && odtype == SYMNMF_F32)
+      rc = rowmat_mfma<double, float>((const double*)A, lda, n, l, M, scale, c, (float*)out, ldo, st, s);
+    else if (adtype == SYMNMF_F32 && odtype == SYMNMF_F64)
+      rc = rowmat_mfma<float, double>((const float*)A, lda, n, l, M, scale, c, (double*)out, ldo, st, s);
+    else if (adtype == SYMNMF_F32 && odtype == SYMNMF_F32)
+      rc = rowmat_mfma<float, float>((const float*)A, lda, n, l, M, scale, c, (float*)out, ldo, st, s);
+    else
+      return -1;
+    if (rc) return rc;
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+  }
   const int nb = ceil_div((int64_t)n * c, 256);
   if (adtype == SYMNMF_F64 && odtype == SYMNMF_F64)
     k_rowmat<double, double><<<nb, 256, 0, s>>>((const double*)A, lda, n, l, M, scale, c, (double*)out, ldo, st);
