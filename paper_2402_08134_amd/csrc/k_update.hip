@@ -14,6 +14,8 @@
 // and the HALS target is y_j + alpha F[j].
 #include "kernels.hpp"
 
+#include <type_traits>
+
 namespace {
 
 // Rows per block chunk: 32 rows x 16 lanes = 512 threads (measured on
@@ -101,16 +103,32 @@ void k_update(UpdateArgs a, const double* __restrict__ Gh,
   constexpr bool UREG = LP > 0 && KP <= 32;
   constexpr bool EARLY = LP == 0 || KP <= 32;
   constexpr int UPT = UREG ? (RPB * LP + NTH - 1) / NTH : 1;
+  const TF* __restrict__ Ut = (const TF*)a.U;  // U in the factor type
   TF ureg[UPT];
   auto load_u = [&](int b) {
 #pragma unroll
     for (int t = 0; t < UPT; ++t) {
       const int e = tid + t * NTH, r = e / l, p = e - r * l;
       const bool ok = e < RPB * l && b + r < n;
-      const TF v = (TF)a.U[ok ? (int64_t)(b + r) * l + p : 0];
+      const TF v = Ut[ok ? (int64_t)(b + r) * l + p : 0];
       ureg[t] = ok ? v : (TF)0;
     }
   };
+  // this row's old factor and the source of the alpha term (EARLY): with U
+  // in registers the first chunk's are issued here, before the staging
+  // loads, so their latency overlaps the staging and U M
+  TF xs_r[CPL], xd_r[CPL];
+  auto load_rows = [&](int b) {
+    const int64_t rb = (int64_t)min(b + rs, n - 1) * k;
+#pragma unroll
+    for (int c = 0; c < CPL; ++c) {
+      const int q = col_of<LPR>(g, c);
+      const int qc = q < k ? q : k - 1;
+      xs_r[c] = Src[rb + qc];
+      xd_r[c] = Dst[rb + qc];
+    }
+  };
+  if (UREG) load_rows(blockIdx.x * RPB);
   if (UREG && l > 0) load_u(blockIdx.x * RPB);
   for (int e = tid; e < KP * KP; e += NTH) gs[e] = Gh[e];
   for (int e = tid; e < KP; e += NTH) gi[e] = Ginv[e];
@@ -166,7 +184,7 @@ void k_update(UpdateArgs a, const double* __restrict__ Gh,
       } else {
         for (int e = tid; e < RPB * l; e += NTH) {
           const int r = e / l, p = e - r * l;
-          us[r * LU + p] = (base + r < n) ? (TF)a.U[(int64_t)(base + r) * l + p] : (TF)0;
+          us[r * LU + p] = (base + r < n) ? Ut[(int64_t)(base + r) * l + p] : (TF)0;
         }
       }
       __syncthreads();
@@ -195,18 +213,9 @@ void k_update(UpdateArgs a, const double* __restrict__ Gh,
     if (row < n) {
       const int64_t rb = (int64_t)row * k;
       double y[CPL], w[CPL];
-      // this row's old factor and the source of the alpha term, issued
-      // before the right-hand side so their latency overlaps it
-      TF xs_r[CPL], xd_r[CPL];
-      if (EARLY) {
-#pragma unroll
-        for (int c = 0; c < CPL; ++c) {
-          const int q = col_of<LPR>(g, c);
-          const int qc = q < k ? q : k - 1;
-          xs_r[c] = Src[rb + qc];
-          xd_r[c] = Dst[rb + qc];
-        }
-      }
+      // otherwise issued here, before the right-hand side, so their latency
+      // overlaps it
+      if (EARLY && !(UREG && base == blockIdx.x * RPB)) load_rows(base);
 #pragma unroll
       for (int c = 0; c < CPL; ++c) y[c] = 0.0;
       // Loads are never guarded by a branch (a branch per element makes the
@@ -514,6 +523,438 @@ __global__ __launch_bounds__(256) void k_pad_identity(double* __restrict__ Ghat,
   if (Ginv && e < kp && e >= k) Ginv[e] = 1.0;
 }
 
+// ---------------------------------------------------------------------------
+// Blocked HALS sweep for long factors: padded width 64, FP32 factors, no LAI
+// term, the HALS rule.  The sweep over the columns (Update of the Appendix)
+// is reassociated per block B of 16 columns: the terms of the 48 columns
+// outside B, W[:, not B] Ghat[not B, B] with the current values (new before
+// B, old after it), are one product on the FP64 matrix cores per 16-row tile,
+// and only the 16 x 16 part inside B stays serial.  A lane owns a whole row,
+// so that serial part needs no cross-lane sums: 16 FMAs per column instead of
+// 64 plus a lane reduction.
+//
+// A wave owns 64 rows and keeps them in an LDS slab (FP32, the values the
+// matrix-core operands read; the row's block values are FP64 in registers
+// during the block's sweep).  The product's 16 x 16 tiles come out with a row
+// spread over four lanes 16 apart; a 4 x 4 transpose across the wave's four
+// 16-lane rows (two lane-half swaps and two row-pair swaps per 32-bit word)
+// leaves each lane its own row.  The block's four slabs form a 256-row chunk
+// whose Gram partial F^T F the waves share: the 10 tiles on and above the
+// diagonal, each mirrored when written.
+//
+// The earlier blocks' new values enter the later blocks' products as the
+// FP32 values the factor stores; at n = 65536, k = 64 the blocked and the
+// unblocked sweep agree to 2e-8 (relative).  At n = 2^20, k = 64 (sparse
+// graph) the update takes 472 us against 700 us unblocked (LvS 596 against
+// 725); about 6700 FP64 FMAs per row, on the FP64 units the matrix and the
+// vector instructions share on this chip, put its floor near 180 us.
+constexpr int BK_LW = 68;     // slab row stride in floats (16-byte rows, 272 B)
+constexpr int BK_ROWS = 256;  // rows per block chunk (4 waves x 64)
+
+__device__ __forceinline__ void swap_words(double& x, double& y, bool halves) {
+  const unsigned long long ux = (unsigned long long)__double_as_longlong(x);
+  const unsigned long long uy = (unsigned long long)__double_as_longlong(y);
+  const unsigned xl = (unsigned)ux, xh = (unsigned)(ux >> 32), yl = (unsigned)uy, yh = (unsigned)(uy >> 32);
+  unsigned nxl, nyl, nxh, nyh;
+  if (halves) {   // lanes 32..63 of x <-> lanes 0..31 of y
+    const auto l = __builtin_amdgcn_permlane32_swap(xl, yl, false, false);
+    const auto h = __builtin_amdgcn_permlane32_swap(xh, yh, false, false);
+    nxl = l[0]; nyl = l[1]; nxh = h[0]; nyh = h[1];
+  } else {        // odd 16-lane rows of x <-> even 16-lane rows of y
+    const auto l = __builtin_amdgcn_permlane16_swap(xl, yl, false, false);
+    const auto h = __builtin_amdgcn_permlane16_swap(xh, yh, false, false);
+    nxl = l[0]; nyl = l[1]; nxh = h[0]; nyh = h[1];
+  }
+  x = __longlong_as_double((long long)(((unsigned long long)nxh << 32) | nxl));
+  y = __longlong_as_double((long long)(((unsigned long long)nyh << 32) | nyl));
+}
+
+// LDS written by some lanes of a wave and read by others: order the two at
+// wavefront scope
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// e[t] in lane (li, r) holds entry (r, t) of a 4 x 4 matrix per li; after the
+// call e[t] in lane (li, r) holds entry (t, r).
+__device__ __forceinline__ void transpose4(double (&e)[4]) {
+  swap_words(e[0], e[2], true);
+  swap_words(e[1], e[3], true);
+  swap_words(e[0], e[1], false);
+  swap_words(e[2], e[3], false);
+}
+
+template <typename TT, int YMODE, bool DOT>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
+void k_update_blk(UpdateArgs a, const double* __restrict__ Gh, const double* __restrict__ Ginv,
+                  const float* __restrict__ Src, const DevState* __restrict__ st) {
+  if (stopped(st)) return;
+  extern __shared__ __align__(16) unsigned char smem[];
+  float* slab = reinterpret_cast<float*>(smem);  // BK_ROWS x BK_LW
+  // the four diagonal 16 x 16 blocks of Ghat and 1 / diag(Ghat), read by
+  // every lane alike (wave-uniform values kept out of scalar registers)
+  double* gd = reinterpret_cast<double*>(smem + sizeof(float) * BK_ROWS * BK_LW);
+  double* gv = gd + 4 * 256;
+  __shared__ double sc[8];
+  const int tid = threadIdx.x, wid = tid >> 6, lane = tid & 63, li = lane & 15, lg = lane >> 4;
+  float* sw = slab + wid * 64 * BK_LW;
+  const int n = a.n, k = a.k, k4 = a.k >> 2;   // k a multiple of 4
+  const double alpha = a.alpha;
+  float* __restrict__ Dst = (float*)a.Dst;
+  // padding columns k..63 of the slab stay zero (the sweep writes back zeros there)
+  for (int e = tid; e < BK_ROWS * 64; e += 256) {
+    const int r = e >> 6, q = e & 63;
+    if (q >= k) slab[r * BK_LW + q] = 0.f;
+  }
+  for (int e = tid; e < 4 * 256; e += 256) {
+    const int b = e >> 8, i = (e >> 4) & 15, q = e & 15;
+    gd[e] = Gh[(16 * b + i) * 64 + 16 * b + q];
+  }
+  if (tid < 64) gv[tid] = Ginv[tid];
+  __syncthreads();
+  // Gram tiles of this wave: tau = wid, wid + 4, wid + 8 of the 10 tiles
+  // (I, J), I <= J, numbered row by row
+  doublex4 gt[3];
+#pragma unroll
+  for (int h = 0; h < 3; ++h) gt[h] = doublex4{0.0, 0.0, 0.0, 0.0};
+  double dot = 0.0;
+
+  // The row's loads of the next block (the next chunk's first after the last
+  // block) are issued during the current block, after its other global
+  // loads, so that waiting for those does not wait for these: the
+  // alpha-term source, and the product part (YMODE 0 with one partial) or
+  // the gathered row of the row's first sampled entry (YMODE 1, within a
+  // chunk: the entry is known from the chunk's start).  With more than one
+  // partial every block loads its own at its start.
+  const bool pre = YMODE == 1 || a.splits == 1;
+  float4 pp[4], ps[4];
+  auto load_p = [&](int rowq, int bq) {   // product partial 0 of row rowq, or gathered row rowq
+    const float* pr = YMODE == 0 ? (const float*)a.P + (int64_t)rowq * a.cp + 16 * bq
+                                 : Src + (int64_t)rowq * k;
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      const int q = 16 * bq + 4 * m;
+      pp[m] = *reinterpret_cast<const float4*>(YMODE == 0 ? pr + 4 * m : pr + (q < k ? q : k - 4));
+    }
+  };
+  auto load_s = [&](int rowq, int bq) {   // alpha-term source
+    const float* sr = Src + (int64_t)rowq * k;
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      const int q = 16 * bq + 4 * m;
+      ps[m] = *reinterpret_cast<const float4*>(sr + (q < k ? q : k - 4));
+    }
+  };
+  if (pre && blockIdx.x * BK_ROWS < n) {
+    const int r = min(blockIdx.x * BK_ROWS + 64 * wid + lane, n - 1);
+    if (YMODE == 0) load_p(r, 0);
+    load_s(r, 0);
+  }
+
+  for (int base = blockIdx.x * BK_ROWS; base < n; base += gridDim.x * BK_ROWS) {
+    const int r0 = base + 64 * wid;
+    const int row = r0 + lane;
+    const bool live = row < n;
+    const int rowc = live ? row : n - 1;
+    const int nbase = base + gridDim.x * BK_ROWS;   // the next chunk, if any
+    // YMODE 1: the row's segment of the sampled slab, and its first entry
+    int e0 = 0, e1 = 0, s0 = rowc;
+    double v0 = 0.0;
+    if (YMODE == 1) {
+      e0 = live ? a.seg_ptr[row] : 0;
+      e1 = live ? a.seg_ptr[row + 1] : 0;
+      if (e0 < e1) {
+        v0 = a.seg_val[e0];
+        s0 = a.seg_src[e0];
+      }
+    }
+    // old factor rows of the wave -> slab; the 64 rows are contiguous (64 k
+    // floats), read as float4 with a clamped index and a zero mask
+    {
+      const float4* s4 = reinterpret_cast<const float4*>(Dst + (int64_t)min(r0, n - 1) * k);
+      const int tot = 64 * k4, lim = (n - r0) * k4;
+      for (int e = lane; e < tot; e += 64) {
+        const int rr = e / k4, c4 = e - rr * k4;
+        const float4 v = s4[e < lim ? e : 0];
+        *reinterpret_cast<float4*>(sw + rr * BK_LW + 4 * c4) = e < lim ? v : make_float4(0.f, 0.f, 0.f, 0.f);
+      }
+    }
+    wave_sync();
+    // the block loop stays rolled: unrolled, the compiler hoists the LDS reads
+    // of all four blocks and spills
+#pragma unroll 1
+    for (int b = 0; b < 4; ++b) {
+      // this row's right-hand side (with the alpha term) on the block's 16
+      // columns
+      double y[16], w[16];
+      if (!pre) {
+        load_p(rowc, b);
+        load_s(rowc, b);
+      } else if (YMODE == 1 && b == 0) {
+        load_p(s0, 0);
+      }
+      // the product part (summed over the partials in FP64; kept raw for the
+      // residual's dot with one partial) and the alpha-term source
+      float4 pc[4];
+      if (YMODE == 0) {
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+          pc[m] = pp[m];
+          y[4 * m] = (double)pp[m].x;
+          y[4 * m + 1] = (double)pp[m].y;
+          y[4 * m + 2] = (double)pp[m].z;
+          y[4 * m + 3] = (double)pp[m].w;
+        }
+        const float* pr = (const float*)a.P + (int64_t)rowc * a.cp + 16 * b;
+        const int64_t sstride = (int64_t)n * a.cp;
+        for (int sp = 1; sp < a.splits; ++sp) {
+#pragma unroll
+          for (int m = 0; m < 4; ++m) {
+            const float4 v = *reinterpret_cast<const float4*>(pr + sp * sstride + 4 * m);
+            y[4 * m] += (double)v.x;
+            y[4 * m + 1] += (double)v.y;
+            y[4 * m + 2] += (double)v.z;
+            y[4 * m + 3] += (double)v.w;
+          }
+        }
+      } else {
+        // the first entry's row (prefetched), then the rest of the segment
+        const double v = e0 < e1 ? v0 : 0.0;
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+          const bool ok = 16 * b + 4 * m < k;
+          y[4 * m] = v * (ok ? (double)pp[m].x : 0.0);
+          y[4 * m + 1] = v * (ok ? (double)pp[m].y : 0.0);
+          y[4 * m + 2] = v * (ok ? (double)pp[m].z : 0.0);
+          y[4 * m + 3] = v * (ok ? (double)pp[m].w : 0.0);
+        }
+        for (int e = e0 + 1; e < e1; ++e) {
+          const double v = a.seg_val[e];
+          const float* sr = Src + (int64_t)a.seg_src[e] * k;
+#pragma unroll
+          for (int m = 0; m < 4; ++m) {
+            const int q = 16 * b + 4 * m;
+            const float4 x = *reinterpret_cast<const float4*>(sr + (q < k ? q : k - 4));
+            const bool ok = q < k;
+            y[4 * m] = fma(v, ok ? (double)x.x : 0.0, y[4 * m]);
+            y[4 * m + 1] = fma(v, ok ? (double)x.y : 0.0, y[4 * m + 1]);
+            y[4 * m + 2] = fma(v, ok ? (double)x.z : 0.0, y[4 * m + 2]);
+            y[4 * m + 3] = fma(v, ok ? (double)x.w : 0.0, y[4 * m + 3]);
+          }
+        }
+      }
+#pragma unroll
+      for (int m = 0; m < 4; ++m) {
+        const bool ok = live && 16 * b + 4 * m < k;
+        const float4 x = ok ? ps[m] : make_float4(0.f, 0.f, 0.f, 0.f);
+        y[4 * m] = live ? fma(alpha, (double)x.x, y[4 * m]) : 0.0;
+        y[4 * m + 1] = live ? fma(alpha, (double)x.y, y[4 * m + 1]) : 0.0;
+        y[4 * m + 2] = live ? fma(alpha, (double)x.z, y[4 * m + 2]) : 0.0;
+        y[4 * m + 3] = live ? fma(alpha, (double)x.w, y[4 * m + 3]) : 0.0;
+      }
+
+      // W[:, not B] Ghat[not B, B] for the wave's four 16-row tiles, as its
+      // transpose: A[m][p] = Ghat[4 s + p][16 b + m] (lane (li, lg) supplies
+      // A[li][lg]), B[p][r] = W[16 t + r][4 s + p] (lane supplies B[lg][li]),
+      // over the 12 K steps s outside the block (s = j, or j + 4 from the
+      // block on); lane (li, lg) ends with rows 16 t + li, columns
+      // 16 b + lg + 4 v
+      double ga[12];
+#pragma unroll
+      for (int j = 0; j < 12; ++j) {
+        const int s = j < 4 * b ? j : j + 4;
+        ga[j] = Gh[(4 * s + lg) * 64 + 16 * b + li];
+      }
+      // the next block's loads go out now and stay in flight through this
+      // block's products and sweep
+      if (pre) {
+        if (b < 3) {
+          load_p(YMODE == 0 ? rowc : s0, b + 1);
+          load_s(rowc, b + 1);
+        } else if (nbase < n) {
+          const int r = min(nbase + 64 * wid + lane, n - 1);
+          if (YMODE == 0) load_p(r, 0);
+          load_s(r, 0);
+        }
+      }
+      doublex4 acc[4];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        acc[t] = doublex4{0.0, 0.0, 0.0, 0.0};
+        const float* wr = sw + (16 * t + li) * BK_LW + lg;
+#pragma unroll
+        for (int j = 0; j < 12; ++j) {
+          const int s = j < 4 * b ? j : j + 4;
+          acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(ga[j], (double)wr[4 * s], acc[t], 0, 0, 0);
+        }
+      }
+      // lane (li, g) collects row 16 g + li, column 16 b + t + 4 v from
+      // e[t] of round v, and takes it off the right-hand side at once
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        double e[4] = {acc[0][v], acc[1][v], acc[2][v], acc[3][v]};
+        transpose4(e);
+#pragma unroll
+        for (int t = 0; t < 4; ++t) y[t + 4 * v] -= e[t];
+      }
+      // this row's old values on the block (read after the products: fewer
+      // live registers there)
+#pragma unroll
+      for (int m = 0; m < 4; ++m) {
+        const float4 wo = *reinterpret_cast<const float4*>(sw + lane * BK_LW + 16 * b + 4 * m);
+        w[4 * m] = wo.x;
+        w[4 * m + 1] = wo.y;
+        w[4 * m + 2] = wo.z;
+        w[4 * m + 3] = wo.w;
+      }
+      // the serial part: columns 16 b .. 16 b + 15 in order, the sum over the
+      // block's columns in four chains with the term of the column changed
+      // last added last; row i of the block of Ghat is read at column i (the
+      // barrier, which takes column i's result, keeps later reads from being
+      // hoisted: all 256 values held in registers at once spill)
+      const double* gb = gd + 256 * b;
+#pragma unroll
+      for (int i = 0; i < 16; ++i) {
+        double gc[16];
+#pragma unroll
+        for (int q = 0; q < 16; ++q) gc[q] = gb[16 * i + q];
+        double sc4[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+          if (q == i - 1) continue;
+          sc4[q & 3] = fma(w[q], gc[q], sc4[q & 3]);
+        }
+        double part = (sc4[0] + sc4[1]) + (sc4[2] + sc4[3]);
+        if (i > 0) part = fma(w[i - 1], gc[i - 1], part);
+        w[i] = fmax(0.0, fma(y[i] - part, gv[16 * b + i], w[i]));
+        asm volatile("" : "+v"(w[i]) : : "memory");   // column i done before the next reads
+      }
+      // new values back to the slab; the residual's product part
+#pragma unroll
+      for (int m = 0; m < 4; ++m) {
+        float4 o;
+        o.x = (float)w[4 * m];
+        o.y = (float)w[4 * m + 1];
+        o.z = (float)w[4 * m + 2];
+        o.w = (float)w[4 * m + 3];
+        *reinterpret_cast<float4*>(sw + lane * BK_LW + 16 * b + 4 * m) = o;
+      }
+      if (DOT && YMODE == 0) {
+        // <new factor, product part> over the block (rows past n: zero); the
+        // partials past the first are read again (no prefetch is in flight
+        // with more than one)
+        const float* pr = (const float*)a.P + (int64_t)rowc * a.cp + 16 * b;
+        const int64_t sstride = (int64_t)n * a.cp;
+        const double f = live ? 1.0 : 0.0;
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+          double q0 = (double)pc[m].x, q1 = (double)pc[m].y, q2 = (double)pc[m].z, q3 = (double)pc[m].w;
+          for (int sp = 1; sp < a.splits; ++sp) {
+            const float4 v = *reinterpret_cast<const float4*>(pr + sp * sstride + 4 * m);
+            q0 += (double)v.x;
+            q1 += (double)v.y;
+            q2 += (double)v.z;
+            q3 += (double)v.w;
+          }
+          dot = fma((double)(float)w[4 * m] * f, q0, dot);
+          dot = fma((double)(float)w[4 * m + 1] * f, q1, dot);
+          dot = fma((double)(float)w[4 * m + 2] * f, q2, dot);
+          dot = fma((double)(float)w[4 * m + 3] * f, q3, dot);
+        }
+      }
+      wave_sync();
+    }
+    // the new rows: factor (row-major, float4), then the copy for the next product
+    {
+      float4* d4 = reinterpret_cast<float4*>(Dst + (int64_t)min(r0, n - 1) * k);
+      const int tot = 64 * k4, lim = (n - r0) * k4;
+      for (int e = lane; e < tot && e < lim; e += 64) {
+        const int rr = e / k4, c4 = e - rr * k4;
+        d4[e] = *reinterpret_cast<const float4*>(sw + rr * BK_LW + 4 * c4);
+      }
+    }
+    if (a.Dt) {
+      TT* dt = (TT*)a.Dt;
+      if (a.dt_rows) {
+        for (int e = lane; e < 64 * k; e += 64) {
+          const int rr = e / k, q = e - rr * k;
+          if (r0 + rr < n) dt[(int64_t)(r0 + rr) * a.ldt + q] = (TT)sw[rr * BK_LW + q];
+        }
+      } else if (live) {
+        for (int q = 0; q < k; ++q) dt[(int64_t)q * a.ldt + row] = (TT)sw[lane * BK_LW + q];
+      }
+    }
+    __syncthreads();
+    // Gram partial of the chunk's 256 rows: lane supplies A[li][lg] =
+    // F[4 s + lg][16 I + li] and B[lg][li] = F[4 s + lg][16 J + li]
+#pragma unroll
+    for (int h = 0; h < 3; ++h) {
+      const int tau = wid + 4 * h;
+      if (tau < 10) {   // wave-uniform
+        const int I = tau < 4 ? 0 : tau < 7 ? 1 : tau < 9 ? 2 : 3;
+        const int J = I + tau - (I == 0 ? 0 : I == 1 ? 4 : I == 2 ? 7 : 9);
+        const float* ca = slab + 16 * I + li;
+        const float* cb = slab + 16 * J + li;
+#pragma unroll 8
+        for (int s = 0; s < BK_ROWS / 4; ++s) {
+          const int r = (4 * s + lg) * BK_LW;
+          gt[h] = __builtin_amdgcn_mfma_f64_16x16x4f64((double)ca[r], (double)cb[r], gt[h], 0, 0, 0);
+        }
+      }
+    }
+    __syncthreads();
+  }
+  // this block's partial row: F^T F (k x k), each upper tile and its mirror
+  double* gp = a.part + (int64_t)blockIdx.x * a.pstride;
+#pragma unroll
+  for (int h = 0; h < 3; ++h) {
+    const int tau = wid + 4 * h;
+    if (tau < 10) {
+      const int I = tau < 4 ? 0 : tau < 7 ? 1 : tau < 9 ? 2 : 3;
+      const int J = I + tau - (I == 0 ? 0 : I == 1 ? 4 : I == 2 ? 7 : 9);
+      // accumulator element v: row 16 I + lg + 4 v, column 16 J + li
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int p = 16 * I + lg + 4 * v, q = 16 * J + li;
+        if (p < k && q < k) {
+          gp[p * k + q] = gt[h][v];
+          if (I != J) gp[q * k + p] = gt[h][v];
+        }
+      }
+    }
+  }
+  if (DOT) {
+    const double t = block_sum(dot, sc);
+    if (tid == 0) a.dpart[blockIdx.x] = t;
+  }
+}
+
+// Whether the blocked sweep takes a HALS half-step: padded width 64, FP32
+// factors and products, no LAI term, k a multiple of 4 (float4 rows), and a
+// long factor (n >= 32768).  BPP's passes keep the unblocked kernel (the same
+// block count, so the reduction reads the same partial rows).
+bool use_blocked(const UpdateArgs& a, int kp, int lp) {
+  return kp == 64 && lp == 0 && a.rule == 0 && (a.k & 3) == 0 && a.n >= 32768;
+}
+
+template <typename TT, int YMODE>
+int launch_update_blk(const UpdateArgs& a, const UpdateRO& ro, int nb, const DevState* st, hipStream_t s) {
+  const size_t lds = sizeof(float) * BK_ROWS * BK_LW + sizeof(double) * (4 * 256 + 64);
+  // the residual's dot product (YMODE 0 only) is its own instantiation: the
+  // kept product part costs registers
+  auto kern = YMODE == 0 && a.dpart ? k_update_blk<TT, YMODE, true> : k_update_blk<TT, YMODE, false>;
+  if (hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
+    return -1;
+  if (a.ev_start)
+    hipExtLaunchKernelGGL(kern, dim3(nb), dim3(256), (uint32_t)lds, s, a.ev_start, a.ev_stop, 0u, a, ro.Ghat, ro.Ginv,
+                          (const float*)a.Src, st);
+  else
+    kern<<<nb, 256, lds, s>>>(a, ro.Ghat, ro.Ginv, (const float*)a.Src, st);
+  return 0;
+}
+
 template <int KP, int LP, typename TF, typename TP, typename TT, int YMODE, int LPR>
 int launch_update_lpr(const UpdateArgs& a, const UpdateRO& ro, int nb, const DevState* st, hipStream_t s) {
   constexpr int RPB = 16 * UPD_RPB / LPR;
@@ -539,6 +980,9 @@ int launch_update_lpr(const UpdateArgs& a, const UpdateRO& ro, int nb, const Dev
 // plain iteration 3.80 -> 4.02 ms, 2 lanes (256 VGPRs and spills) 22.9 ms.
 template <int KP, int LP, typename TF, typename TP, typename TT, int YMODE>
 int launch_update(const UpdateArgs& a, const UpdateRO& ro, int nb, const DevState* st, hipStream_t s) {
+  if constexpr (KP == 64 && LP == 0 && YMODE < 2 && std::is_same_v<TF, float> && std::is_same_v<TP, float>) {
+    if (use_blocked(a, KP, LP)) return launch_update_blk<TT, YMODE>(a, ro, nb, st, s);
+  }
   if constexpr (KP % 32 == 0) {
     if (update_lpr8(a.n, KP, LP, sizeof(TF))) return launch_update_lpr<KP, LP, TF, TP, TT, YMODE, 8>(a, ro, nb, st, s);
   }

@@ -128,7 +128,7 @@ struct UpdateArgs {
   const int* seg_ptr = nullptr;      // YMODE 1: sampled slab, segment j = the stored
   const int* seg_src = nullptr;      // X[j][r] w_r of row j with r in the sample,
   const double* seg_val = nullptr;   // in column order
-  const double* U = nullptr;         // YMODE 2: U (n x l) and M = Lambda U^T F (l x k)
+  const void* U = nullptr;           // YMODE 2: U (n x l, the factor type) and M = Lambda U^T F (l x k)
   const double* M = nullptr;
   const void* Src = nullptr;         // the fixed factor (alpha term, YMODE 1 rows)
   void* Dst = nullptr;               // the factor being updated (in place)

@@ -236,6 +236,7 @@ struct symnmf_ctx {
   // LAI
   int l = 0;
   double *Q = nullptr, *Q1 = nullptr, *U = nullptr, *YQ = nullptr;
+  float* Uf = nullptr;  // U rounded to FP32, read by the update when the factors are FP32
   double *Tm = nullptr, *QT = nullptr, *Vw = nullptr, *lam = nullptr, *Rl = nullptr, *Rlinv = nullptr, *Z = nullptr;
   // LvS / leverage
   SampleBuffers sb;
@@ -286,7 +287,7 @@ struct symnmf_ctx {
     if (st) (void)hipStreamSynchronize(st);
     else (void)hipDeviceSynchronize();
     void* ptrs[] = {Xb_owned, W, H, Y, Yk, Yhat, P, Bt, BtW, BtH, part, dpart, M_W, M_H, Gi_W, Gi_H, Gi_S, G_W, G_H, Gh_W, Gh_H, Gh_S, d_scal, rowsum, dstate, hist, d_fail,
-                    ws.base, Q, Q1, U, YQ, Tm, QT, Vw, lam, Rl, Rlinv, Z, sb.w, sb.prefix, sb.counts, sb.flags,
+                    ws.base, Q, Q1, U, Uf, YQ, Tm, QT, Vw, lam, Rl, Rlinv, Z, sb.w, sb.prefix, sb.counts, sb.flags,
                     sb.info, sb.theta, rows, weights, wmask, seg_cnt, seg_ptr, seg_src, seg_val, lev, R, Rinv};
     for (void* p : ptrs) dfree(p);
     pinned_pool().put(hbuf);
@@ -575,7 +576,9 @@ struct symnmf_ctx {
       a.dpart = nullptr;
       ymode = 1;
     } else if (mode == SYMNMF_MODE_LAI) {
-      a.U = U;
+      // the update rounds U to the factor type as it loads it: FP32 factors
+      // read the FP32 copy (half the bytes, the same values)
+      a.U = fdtype == SYMNMF_F32 ? (const void*)Uf : (const void*)U;
       a.M = side == 0 ? M_H : M_W;
       a.l = l;
       a.pstride = k * k + l * k;
@@ -1309,10 +1312,13 @@ void lai_prepare(symnmf_ctx* c, int l) {
       dfree(*b);
       *b = nullptr;
     }
+    dfree(c->Uf);
+    c->Uf = nullptr;
     c->l = l;
     c->Q = dalloc<double>((size_t)n * l);
     c->Q1 = dalloc<double>((size_t)n * l);
     c->U = dalloc<double>((size_t)n * l);
+    if (c->fdtype == SYMNMF_F32) c->Uf = dalloc<float>((size_t)n * l);
     c->YQ = dalloc<double>((size_t)n * l);  // holds fdtype values
     c->Tm = dalloc<double>((size_t)l * l);
     c->QT = dalloc<double>((size_t)l * l);
@@ -1352,6 +1358,7 @@ void lai_finish(symnmf_ctx* c) {
     LCHK(rowmat(c->Q, SYMNMF_F64, l, n, l, c->QT, nullptr, l, c->U, SYMNMF_F64, l, nullptr, c->st));
     c->ws.reset();
     LCHK(column_sign_fix(c->U, n, l, c->ws, c->st));
+    if (c->Uf) LCHK(copy_convert(c->U, SYMNMF_F64, c->Uf, SYMNMF_F32, (int64_t)n * l, c->st));
     frob_dot(c->lam, c->lam, l, c->d_scal + 8, c->st);
   }
   HIPCHK(hipMemcpyAsync(c->hbuf, c->d_scal + 8, sizeof(double), hipMemcpyDeviceToHost, c->st));

@@ -192,6 +192,51 @@ def test_precision_65536_products(compute):
         assert e <= 1e-5 and e2 <= 1e-2
 
 
+@pytest.mark.parametrize("compute", ["f32", "bf16"])
+def test_precision_65536_half_steps(compute):
+    # both half-steps at the precision sweep's size, where the HALS sweep runs
+    # blocked (16-column blocks, the other columns' terms on the FP64 matrix
+    # cores, split-K product partials); the second product reads the
+    # transposed panel the first update wrote.  Sampled rows against the
+    # sweep with the exact Gram, (1) on the library's own product X F (the
+    # same inputs: the sweep itself within 1e-5) and (2) on the FP64 product:
+    # there the FP32 product's own error over 65536 terms (about 1e-5) comes
+    # out of the sweep amplified, measured 8.5e-5 with either sweep layout
+    n, k = 65536, 64
+    X = workloads.gpu_gaussian_kernel(n, 128, 64, seed=0)
+    o = P.symnmf_default_options()
+    if compute == "bf16":
+        o.compute_dtype = P.BF16
+    ctx = P.symnmf_create(X, k, 0.0, 0, 1, o)
+    alpha = P.symnmf_get_stats(ctx).alpha
+    H = factor(ctx, P.H)
+    W0 = factor(ctx, P.W)
+    P.symnmf_half_step(ctx, 0, 0)
+    W = factor(ctx, P.W)
+    P.symnmf_half_step(ctx, 1, 1)
+    H1 = factor(ctx, P.H)
+    S = _rows(n, 64, 4)
+    Sd = torch.from_numpy(S).cuda()
+    prods = []
+    for F in (H, W):
+        Y = torch.empty((n, k), dtype=torch.float32, device="cuda")
+        P.symnmf_apply_x(ctx, dev(F, torch.float32), Y)
+        prods.append(host(Y[Sd]))
+    XS = host(X[Sd])
+    del ctx, X
+    torch.cuda.empty_cache()
+    GH, GW = H.T @ H + alpha * np.eye(k), W.T @ W + alpha * np.eye(k)
+    e = rel(W[S], O.hals_gy(GH, prods[0] + alpha * H[S], W0[S]))
+    e2 = rel(H1[S], O.hals_gy(GW, prods[1] + alpha * W[S], H[S]))
+    q = (lambda A: round_to(A, torch.bfloat16)) if compute == "bf16" else (lambda A: A)
+    f = rel(W[S], O.hals_gy(GH, q(XS) @ q(H) + alpha * H[S], W0[S]))
+    f2 = rel(H1[S], O.hals_gy(GW, q(XS) @ q(W) + alpha * W[S], H[S]))
+    log(f"n=65536 {compute} half-steps sampled rows: on the library's product W rel {e:.2e}, H rel {e2:.2e}; "
+        f"on the FP64 product W rel {f:.2e}, H rel {f2:.2e}")
+    assert e <= 1e-5 and e2 <= 1e-5
+    assert f <= 2e-4 and f2 <= 2e-4
+
+
 def test_sparse_2pow20_spmm_and_leverage():
     X, _ = workloads.sbm(1 << 20, 64, 32.0, 20.0, seed=0)
     n, k = X.shape[0], 64

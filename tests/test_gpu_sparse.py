@@ -170,17 +170,49 @@ def test_long_factor_half_step(case):
     assert e <= (1e-12 if vt == np.float64 else 1e-5)
 
 
+@pytest.mark.parametrize("compute", ["f32", "bf16"])
+def test_long_factor_plain_run(compute):
+    # k = 64 on a long factor (n >= 32768): the HALS sweep runs blocked (16
+    # columns at a time, the other columns' terms on the FP64 matrix cores)
+    # in whole iterations.  The residual history comes from the trace
+    # identity with the update's dot product; with BF16 gathers every
+    # product reads the row copy the update writes.
+    X = _sbm(66001, 32, 16.0, seed=5)
+    n, k, iters = X.shape[0], 64, 3
+    log(f"long factor plain run n={n} k={k} {compute}")
+    o = _bf16_opts() if compute == "bf16" else P.symnmf_default_options()
+    ctx = P.symnmf_create(csr_dev(X), k, 0.0, 0, 3, o)
+    P.symnmf_iterate(ctx, iters)
+    X64 = _X64(X)
+    sc = O.data_scalars(X64)
+    H0 = round_to(O.initial_factor(n, k, sc["zeta"], 3), torch.float32)
+    Wo, Ho, hist = O.plain_symnmf(X64, k, sc["maxval"], H0, iters)
+    hg = np.array(P.symnmf_history(ctx))
+    tol = 1e-4 if compute == "f32" else 1e-3
+    eh = np.max(np.abs(hg - hist) / hist)
+    r = P.symnmf_residual(ctx, P.RESID_EXACT)[0]
+    ro = O.residual_trace(sc["normsq"], Wo, Ho, X64 @ Wo) / np.sqrt(sc["normsq"])
+    log(f"   history max rel {eh:.2e}; exact residual gpu {r:.8f} oracle {ro:.8f}")
+    assert eh <= tol
+    assert abs(r - ro) / ro <= tol
+    if compute == "f32":
+        e = rel(factor(ctx, P.H), Ho)
+        log(f"   H rel {e:.2e}")
+        assert e <= 1e-4
+
+
 def _bf16_opts(**kw):
     o = P.symnmf_default_options(**kw)
     o.compute_dtype = P.BF16
     return o
 
 
-@pytest.mark.parametrize("k", [16, 33, 64])
-def test_bf16_gather_half_steps(k):
+@pytest.mark.parametrize("n,k", [(6007, 16), (6007, 33), (6007, 64), (66001, 64)])
+def test_bf16_gather_half_steps(n, k):
     # the product gathers a BF16 copy of the source rows (FP32 values, FP64
     # sums); both half-steps, so the copy written by the update is used too
-    X = _sbm(6007, 12, 24.0, seed=k)
+    # (at n = 66001, k = 64 by the blocked sweep)
+    X = _sbm(n, 12 if n < 10000 else 32, 24.0 if n < 10000 else 16.0, seed=k)
     n = X.shape[0]
     log(f"bf16 gathers n={n} k={k}")
     ctx = P.symnmf_create(csr_dev(X), k, 0.0, 0, 4, _bf16_opts())
