@@ -104,6 +104,14 @@ __device__ __forceinline__ double row16_sum(double v) {
   return v;
 }
 
+// LDS written by some lanes of a wave and read by others: order the two at
+// wavefront scope
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // Block-wide FP64 sum with a fixed reduction tree (deterministic).
 // `scratch` holds >= blockDim.x/64 doubles.  Result valid in thread 0.
 __device__ __forceinline__ double block_sum(double v, double* scratch) {

@@ -402,16 +402,31 @@ __global__ __launch_bounds__(256) void k_chol_inverse(const double* __restrict__
 }
 
 // ---------------------------------------------------------------------------
-// Cholesky G + shift I = L L^T and L^{-1} in the registers of one wavefront:
-// lane r holds row r (KM doubles, KM = k rounded up to 16; rows and columns
-// beyond k are the identity).  Step j of the factorisation takes the pivot
-// from lane j, scales column j in every lane, then broadcasts column j
-// (v_readlane, one per entry) for the rank-one update of the trailing rows;
-// the inverse is built row by row the same way (row t of L^{-1} is final
-// after step t, broadcast, and subtracted from the rows below).  With all
-// loops unrolled every register index is static; only the lower triangle is
-// meaningful.  Retries with the same growing shifts as the workgroup kernel.
+// Cholesky G + shift I = L L^T and L^{-1} in one wavefront: lane r holds row r
+// (KM = k rounded up to 16; rows and columns beyond k are the identity).
+// Step j of the factorisation takes the pivot from lane j, forms column j of
+// L in every lane, stores it (LDS, and row j of R = L^T), and updates the
+// trailing entries of the row with the column read back by broadcast reads
+// (all lanes one address).  A column once stored is no longer held in
+// registers, so the register file has room to keep many of those reads in
+// flight; the single wave has nothing else to hide their latency with.  The
+// inverse is that of the unit lower triangle, L = Lu D with D = diag(L):
+// row t of Lu^{-1} is final after step t, written to LDS by its lane and
+// subtracted, times Lu[r][t], from the rows below; each row is scaled by
+// 1 / L[r][r] once at the end (L^{-1} = D^{-1} Lu^{-1}).  With all loops
+// unrolled every register index is static.  Retries with the same growing
+// shifts as the workgroup kernel.  (A version with the whole of L and of the
+// inverse in registers, columns broadcast with v_readlane or through LDS:
+// k = 64 in 92-97 us, l = 48 in 46 us.)
 // ---------------------------------------------------------------------------
+// one step of a wave's LDS exchange: ordered at wavefront scope, and no
+// memory access moved across it by the compiler (which would otherwise
+// hoist every later step's reads and run out of registers)
+__device__ __forceinline__ void step_sync() {
+  wave_sync();
+  asm volatile("" ::: "memory");
+}
+
 __device__ __forceinline__ double lane_value(double v, int lane) {
   const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
   const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
@@ -422,22 +437,32 @@ template <int KM>
 __global__ __launch_bounds__(64) void k_chol_regs(const double* __restrict__ G, int k, double* __restrict__ R,
                                                   double* __restrict__ Rinv, int* d_flags, int flag_bit,
                                                   int* d_fail) {
+  __shared__ __align__(16) double Ls[KM][KM + 2];   // Ls[j][r] = L[r][j]
+  __shared__ __align__(16) double xb[KM];           // row t of Lu^{-1}
+  __shared__ double rs[KM];                         // 1 / L[j][j]
   const int r = threadIdx.x;
   const bool act = r < k;
   double tr = act ? G[r * k + r] : 0.0;
   tr = wave_sum(tr);
   double shift = 0.0, grow = 1e-12 * fmax(tr, 1e-300) / k;
-  double a[KM];
   bool ok = false;
   for (int attempt = 0; attempt < 6 && !ok; ++attempt) {
     if (attempt > 0) {
       shift = grow;  // 1e-12, 1e-10, ... times tr(G) / k
       grow *= 100.0;
     }
-    // row r of G (identity rows and columns beyond k), reloaded for a retry
+    // The lane and the size pass through an empty asm: nothing derived from
+    // them is loop-invariant, so the compiler does not compute it once for
+    // all the attempts and hold it (addresses, masks and constants of every
+    // step: out of registers).
+    int rr = r, kk = k;
+    asm volatile("" : "+v"(rr), "+s"(kk) : : "memory");
+    const bool ac = rr < kk;
+    // row r of G (identity rows and columns beyond k)
+    double a[KM];
 #pragma unroll
     for (int c = 0; c < KM; ++c)
-      a[c] = ((act && c < k) ? G[r * k + c] : (c == r ? 1.0 : 0.0)) + ((act && c == r) ? shift : 0.0);
+      a[c] = ((ac && c < kk) ? G[rr * kk + c] : (c == rr ? 1.0 : 0.0)) + ((ac && c == rr) ? shift : 0.0);
     ok = true;
 #pragma unroll
     for (int j = 0; j < KM; ++j) {
@@ -448,9 +473,17 @@ __global__ __launch_bounds__(64) void k_chol_regs(const double* __restrict__ G, 
         } else {
           const double ljj = sqrt(d);
           const double rl = 1.0 / ljj;
-          a[j] = r > j ? a[j] * rl : (r == j ? ljj : a[j]);
+          const double lj = rr > j ? a[j] * rl : (rr == j ? ljj : 0.0);   // L[r][j]
+          if (rr < KM) Ls[j][rr] = lj;   // lanes past the padded width hold no row
+          if (rr == 0) rs[j] = rl;
+          wave_sync();
 #pragma unroll
-          for (int c = j + 1; c < KM; ++c) a[c] = fma(-a[j], lane_value(a[j], c), a[c]);
+          for (int c = j + 1; c < KM; ++c) a[c] = fma(-lj, Ls[j][c], a[c]);
+          // each entry's update happens in its step: the compiler would
+          // otherwise sink the updates to where the entry is next needed and
+          // keep every column read alive until then (out of registers)
+#pragma unroll
+          for (int c = j + 1; c < KM; ++c) asm volatile("" : "+v"(a[c]));
         }
       }
     }
@@ -460,39 +493,44 @@ __global__ __launch_bounds__(64) void k_chol_regs(const double* __restrict__ G, 
     return;
   }
   if (r == 0 && shift > 0.0 && d_flags) atomicOr(d_flags, flag_bit);
-  // R = L^T: R[c][r] = L[r][c]
+  step_sync();
+  // R = L^T: row j of R is column j of L
   if (act) {
-#pragma unroll
-    for (int c = 0; c < KM; ++c)
-      if (c < k) R[c * k + r] = c <= r ? a[c] : 0.0;
+    for (int j = 0; j < k; ++j) R[j * k + r] = Ls[j][r];
   }
   double x[KM];
 #pragma unroll
   for (int c = 0; c < KM; ++c) x[c] = c == r ? 1.0 : 0.0;
-  // per step one scale and one multiplier per lane instead of a select per
-  // entry: lane t scales its row by 1 / L[t][t] (the others by 1, exactly),
-  // rows below t subtract L[r][t] times row t (the others 0, exactly)
 #pragma unroll
   for (int t = 0; t < KM; ++t) {
-    const double rt = 1.0 / lane_value(a[t], t);
-    const double sc = r == t ? rt : 1.0;
-    const double mt = r > t ? a[t] : 0.0;
+    if (r == t) {
 #pragma unroll
-    for (int c = 0; c <= t; ++c) x[c] *= sc;
+      for (int c = 0; c <= t; ++c) xb[c] = x[c];
+    }
+    step_sync();
+    const double m = (r > t && r < KM) ? Ls[t][r < KM ? r : 0] * rs[t] : 0.0;   // Lu[r][t]
 #pragma unroll
-    for (int c = 0; c <= t; ++c) x[c] = fma(-mt, lane_value(x[c], t), x[c]);
+    for (int c = 0; c <= t; ++c) x[c] = fma(-m, xb[c], x[c]);
+#pragma unroll
+    for (int c = 0; c <= t; ++c) asm volatile("" : "+v"(x[c]));
+    step_sync();
   }
-  // R^{-1} = (L^{-1})^T: Rinv[c][r] = X[r][c]
+  // R^{-1} = (L^{-1})^T: Rinv[c][r] = L^{-1}[r][c] = Lu^{-1}[r][c] / L[r][r]
+  const double dr = rs[r < KM ? r : 0];
   if (act) {
 #pragma unroll
     for (int c = 0; c < KM; ++c)
-      if (c < k) Rinv[c * k + r] = x[c];
+      if (c < k) Rinv[c * k + r] = x[c] * dr;
   }
 }
 
 // Threads of the Jacobi workgroup: one pass over the (m/2)^2 2 x 2 blocks and
 // the m^2/2 eigenvector pairs of a step (measured at l = 48: the whole
-// symnmf_lai 3.07 ms with 256 threads, 2.92 ms with 1024).
+// symnmf_lai 3.07 ms with 256 threads, 2.92 ms with 1024).  A variant with A
+// in two copies, where every task computes its two rotations itself and a
+// step takes one barrier instead of two, measured slower (l = 48: 539 against
+// 322 us): the rotations' square roots and divisions, repeated by all sixteen
+// waves, cost the one CU more FP64 issue time than the barrier.
 constexpr int JACOBI_NT = 1024;
 
 // ---------------------------------------------------------------------------

@@ -569,14 +569,6 @@ __device__ __forceinline__ void swap_words(double& x, double& y, bool halves) {
   y = __longlong_as_double((long long)(((unsigned long long)nyh << 32) | nyl));
 }
 
-// LDS written by some lanes of a wave and read by others: order the two at
-// wavefront scope
-__device__ __forceinline__ void wave_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
 // e[t] in lane (li, r) holds entry (r, t) of a 4 x 4 matrix per li; after the
 // call e[t] in lane (li, r) holds entry (t, r).
 __device__ __forceinline__ void transpose4(double (&e)[4]) {
