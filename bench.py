@@ -231,9 +231,9 @@ def main():
     # The dominant kernel of the timed learned_lai solve by device time is
     # the LAI update (two launches per LAI iteration): timed alone on a
     # context in LAI mode after the learned start (HIP events around every
-    # update launch).  Algorithmic bytes per launch: U (n x l FP64), the
-    # source factor and the old factor read, the new factor written (n x k
-    # FP32 each): n (8 l + 12 k).
+    # update launch).  Algorithmic bytes per launch: U (its n x l FP32 copy),
+    # the source factor and the old factor read, the new factor written
+    # (n x k FP32 each): n (4 l + 12 k).
     o = P.symnmf_default_options(timing=1)
     c = P.symnmf_create(X, k, 0.0, 0, seeds[0], o)
     P.symnmf_lai(c, l, q)
@@ -243,7 +243,7 @@ def main():
     del c
     t_upd = ph["update"][0] / 1e3 / ph["update"][1]
     t_red = ph["reduce"][0] / 1e3 / ph["reduce"][1]
-    alg_upd = float(n) * (8.0 * l + 12.0 * k)
+    alg_upd = float(n) * (4.0 * l + 12.0 * k)
     ach_upd = alg_upd / t_upd / 1e9
     log(f"[bench] LAI update {t_upd * 1e6:.1f} us over {ph['update'][1]} launches -> {ach_upd:.0f} GB/s "
         f"algorithmic; partial-sum reduction {t_red * 1e6:.1f} us")
@@ -410,7 +410,8 @@ def bench_sparse(args):
                    "n": n, "nnz": int(nnz), "k": k, "lvs_vs_plain_per_iteration":
                        res["plain"]["s_per_iteration"] / t_val, "methods": res},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": stored_traffic("k_csr_spmm_vec_sbm2p20_k64_pmc.txt", "k_sparse.hip", n, k),
                      "kernel": "k_csr_spmm_vec<float, float, float, 16, 4> (X H, one launch per half-iteration)",
                      "us_per_launch": t_prod * 1e6, "launches": calls, "algorithmic_bytes_per_launch": alg_bytes,
                      "row_gather_bytes_per_launch": gather},
