@@ -1,6 +1,6 @@
 // Dense-X kernels: one-time scalars pass, the product Y = X B on MFMA
-// (FP64, FP32 and BF16 inputs, and FP32 from three BF16 pieces), split-K
-// reduction, FP32 -> BF16 conversion and the exact residual pass.
+// (FP64, FP32 and BF16 inputs), split-K reduction, FP32 -> BF16 conversion
+// and the exact residual pass.
 //
 // The product X B (B = H, W, the sketch Omega or the basis Q) is the main
 // cost of every iteration (Section 2.1.2: X H is reused by a whole HALS
@@ -674,6 +674,7 @@ GemmPlan gemm_plan(int n, int c, int compute_dtype) {
     p.ct = p.cp <= 64 ? 2 : 1;
     const int step = 16;
     const int strips = ceil_div(n, 64 * p.ct);
+    // about 1024 waves (2048 or 512 measured slower at n = 16384)
     int splits = std::max(1, ceil_div(1024, strips));
     splits = std::min(splits, std::max(1, n / 256));
     p.kchunk = step * ceil_div(ceil_div(n, splits), step);
