@@ -140,13 +140,17 @@ def test_lvs_tau_zero_matches_plain():
 
 
 @pytest.mark.parametrize("case", [(66_001, 64, 0, np.float32), (66_001, 64, 6000, np.float32),
+                                  (66_001, 52, 0, np.float32), (66_001, 60, 5000, np.float32),
+                                  (40_003, 50, 0, np.float32),
                                   (65_600, 10, 0, np.float32), (65_600, 40, 3000, np.float32),
                                   (65_551, 33, 0, np.float64), (65_551, 64, 4000, np.float64),
                                   (40_003, 32, 0, np.float32), (40_003, 20, 3000, np.float32)])
 def test_long_factor_half_step(case):
     # long factors: every one of the update's blocks walks several row chunks
-    # (grid stride), the 8-lanes-per-row layout where the padded width is a
-    # multiple of 32, and n is ragged against the chunk; every padded width
+    # (grid stride), and n is ragged against the chunk; every padded width:
+    # at 64 with FP32 factors the blocked sweep (k = 64, and k = 52, 60 with
+    # padding columns), k = 50 (not a multiple of 4) the 8-lanes-per-row
+    # kernel, as at width 32 and for FP64
     n, k, s, vt = case
     log(f"long factor half step n={n} k={k} s={s} {np.dtype(vt).name}")
     X = _sbm(n, 32, 16.0, seed=n + k)
