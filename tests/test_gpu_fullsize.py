@@ -2,7 +2,8 @@
 times: the dense similarity n = 16384, k = 32 (FP32; plain iterations, and
 the LAI basis l = 48, q = 2 with the learned start and LAI iterations), a
 LAI run past n = 32768 (the update's U prefetch), the precision sweep
-n = 65536, k = 64 (FP32 and BF16 products) and the sparse graph n = 2^20,
+n = 65536, k = 64 (FP32 and BF16 products, both half-steps, the LAI path at
+l = 80) and the sparse graph n = 2^20,
 k = 64.  The FP64 oracle computes sampled output rows one by one (a row of
 X H, a row of the HALS update given the exact Gram) or, at n = 16384, whole
 plain iterations; at n = 2^20 a property that holds at any size is checked
@@ -162,6 +163,40 @@ def test_lai_iterations_past_32768_rows():
     hg = np.array(P.symnmf_history(ctx))
     e = float(np.max(np.abs(hg - hist) / hist))
     log(f"n=40000 {iters} LAI iterations: history max rel {e:.2e}, H rel {rel(factor(ctx, P.H), Ho):.2e}")
+    assert e <= 1e-4 and rel(factor(ctx, P.H), Ho) <= 1e-4
+
+
+def test_lai_65536_width_64():
+    """The precision sweep's LAI path at its size: n = 65536, k = 64, l = 80,
+    q = 2 (padded width 64: the update with the vector partial tile and U
+    loaded where it is used, l / 16 = 5 tiles), against the oracle on the
+    device's basis, checked as at n = 40000."""
+    n, k, l, q, seed = 65536, 64, 80, 2, 1
+    X = workloads.gpu_gaussian_kernel(n, 128, 64, seed=0)
+    ctx = P.symnmf_create(X, k, 0.0, 0, seed)
+    P.symnmf_lai(ctx, l, q)
+    U = torch.empty((n, l), dtype=torch.float64, device="cuda")
+    lam = torch.empty(l, dtype=torch.float64, device="cuda")
+    P.symnmf_get_lai(ctx, U, lam)
+    Ug, lg = host(U), host(lam)
+    assert np.abs(Ug.T @ Ug - np.eye(l)).max() <= 1e-12
+    top = Ug[:, :4]
+    XU = np.zeros_like(top)
+    for r0 in range(0, n, 4096):
+        XU[r0:r0 + 4096] = host(X[r0:r0 + 4096]) @ top
+    rq = np.einsum("ij,ij->j", top, XU)
+    log(f"n=65536: lambda[:4] {lg[:4]}, Rayleigh quotients {rq}")
+    assert rel(lg[:4], rq) <= 1e-5
+    H0 = factor(ctx, P.H)
+    maxval = P.symnmf_get_stats(ctx).maxval
+    del X
+    torch.cuda.empty_cache()
+    iters = 4
+    P.symnmf_iterate(ctx, iters)
+    Wo, Ho, hist = O.lai_symnmf(Ug, lg, k, maxval, H0, iters)
+    hg = np.array(P.symnmf_history(ctx))
+    e = float(np.max(np.abs(hg - hist) / hist))
+    log(f"n=65536 {iters} LAI iterations: history max rel {e:.2e}, H rel {rel(factor(ctx, P.H), Ho):.2e}")
     assert e <= 1e-4 and rel(factor(ctx, P.H), Ho) <= 1e-4
 
 
