@@ -414,7 +414,10 @@ def bench_sparse(args):
                      "traffic": stored_traffic("k_csr_spmm_vec_sbm2p20_k64_pmc.txt", "k_sparse.hip", n, k),
                      "kernel": "k_csr_spmm_vec<float, float, float, 16, 4> (X H, one launch per half-iteration)",
                      "us_per_launch": t_prod * 1e6, "launches": calls, "algorithmic_bytes_per_launch": alg_bytes,
-                     "row_gather_bytes_per_launch": gather},
+                     "row_gather_bytes_per_launch": gather,
+                     # the gather-bound ceiling: the nnz 256-byte factor rows at the HBM peak
+                     "row_gather_gbs": gather / t_prod / 1e9,
+                     "row_gather_frac": gather / t_prod / 1e9 / HBM_PEAK_GBS},
         "phases_ms_per_iteration": phases,
         "cpu_baseline": None,
     }
