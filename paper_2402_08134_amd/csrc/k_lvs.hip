@@ -72,8 +72,11 @@ __global__ __launch_bounds__(256) void k_leverage(const TF* __restrict__ F, int 
 // The four accumulator registers of lane (li, lg) hold rows lg + 4 v of
 // column li; squares are summed over the tiles and then over the 16 lanes
 // of a DPP row.
+// At KP = 64 the kernel is held to 168 registers, three waves per SIMD
+// instead of two (137 VGPRs + 32 AGPRs otherwise): n = 2^20, leverage with
+// its Cholesky 216 -> 210 us.
 template <int KP>
-__global__ __launch_bounds__(256) void k_leverage_mfma(const float* __restrict__ F, int n, int k,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KP == 64 ? 3 : 1))) void k_leverage_mfma(const float* __restrict__ F, int n, int k,
                                                        const double* __restrict__ Rinv, double* __restrict__ lev,
                                                        int iters, const DevState* __restrict__ st) {
   if (stopped(st)) return;
@@ -226,29 +229,35 @@ __global__ __launch_bounds__(256) void k_emit(const int* __restrict__ det, int* 
                                               const int* __restrict__ sel, const int* __restrict__ pos, int n,
                                               int* __restrict__ rows, double* __restrict__ weights, int64_t cap,
                                               int* __restrict__ info, double* __restrict__ wmask,
-                                              const DevState* __restrict__ st) {
+                                              uint64_t* __restrict__ wbits, const DevState* __restrict__ st) {
   if (stopped(st)) return;
   const int i = blockIdx.x * 256 + threadIdx.x;
   if (i == 0) {
     info[2] = (int)min((int64_t)pos[n], cap);
     info[3] = pos[n];
   }
-  if (i >= n) return;
   double wt = 0.0;
-  if (sel[i] && pos[i] < cap) {
-    const int p = pos[i];
-    rows[p] = i;
-    if (det[i]) {
-      wt = 1.0;
-    } else {
-      const double WR = (double)prefix[n - 1];
-      const double sR = (double)info[1];
-      wt = ((double)counts[i] * WR) / (sR * (double)w[i]);
+  if (i < n) {
+    if (sel[i] && pos[i] < cap) {
+      const int p = pos[i];
+      rows[p] = i;
+      if (det[i]) {
+        wt = 1.0;
+      } else {
+        const double WR = (double)prefix[n - 1];
+        const double sR = (double)info[1];
+        wt = ((double)counts[i] * WR) / (sR * (double)w[i]);
+      }
+      weights[p] = wt;
     }
-    weights[p] = wt;
+    if (wmask) wmask[i] = wt;
+    counts[i] = 0;
   }
-  if (wmask) wmask[i] = wt;
-  counts[i] = 0;
+  if (wbits) {   // the wave's 64 rows as one word (all lanes take part in the ballot)
+    const uint64_t b = __ballot(wt != 0.0);
+    const int word = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if ((threadIdx.x & 63) == 0 && word < (n + 63) / 64) wbits[word] = b;
+  }
 }
 
 // One wave per sampled row; lanes walk the row's nonzeros.  X symmetric:
@@ -263,39 +272,60 @@ __global__ __launch_bounds__(256) void k_slab_count(const int* __restrict__ rp, 
   for (int e = rp[r] + (threadIdx.x & 63); e < rp[r + 1]; e += 64) atomicAdd(&cnt[ci[e]], 1);
 }
 
-// 16 lanes per row j; rows without sampled entries (cnt 0) are skipped.  The
-// lanes check 16 entries at a time against the weights; each sampled entry
-// goes to seg_ptr[j] + (sampled entries of the row before it), found from the
-// wave's ballot, so the segment is in column order.  cnt[j] is cleared.
+// A wave takes 64 consecutive rows j: their counts, bounds and segment starts
+// in one coalesced read, then only the rows with sampled entries (cnt > 0,
+// found by a ballot), four at a time, 16 lanes per row (a block of 16 rows
+// per 256 threads, each row's reads one after another, took 115 us at
+// n = 2^20: three quarters of the rows have no sampled entry).  The lanes of
+// a row check 16 entries at a time against the sample's bitmask (n / 8
+// bytes, cache-resident) and read the weight for the sampled entries only;
+// each sampled entry goes to seg_ptr[j] + (sampled entries of the row before
+// it), found from the wave's ballot, so the segment is in column order.
+// cnt is cleared.
 template <typename TV>
 __global__ __launch_bounds__(256) void k_slab_fill_rows(const int* __restrict__ rp, const int* __restrict__ ci,
                                                         const TV* __restrict__ val, int n,
-                                                        const double* __restrict__ wmask, int* __restrict__ cnt,
+                                                        const double* __restrict__ wmask,
+                                                        const uint64_t* __restrict__ wbits, int* __restrict__ cnt,
                                                         const int* __restrict__ seg_ptr, int* __restrict__ seg_src,
                                                         double* __restrict__ seg_val, int64_t seg_cap,
                                                         const DevState* __restrict__ st) {
   if (stopped(st)) return;
-  const int j = blockIdx.x * 16 + (threadIdx.x >> 4);
-  const int li = threadIdx.x & 15, sh = threadIdx.x & 48;   // lane in row, row's bit offset in the wave
-  const bool on = j < n && cnt[j] > 0;
-  if (!on) return;            // the same for the 16 lanes of a row
-  cnt[j] = 0;
-  const int e0 = rp[j], e1 = rp[j + 1];
-  int base = seg_ptr[j];
-  for (int e = e0 + li; e - li < e1; e += 16) {   // the same trips for the row's lanes
-    const bool ok = e < e1;
-    const int r = ci[ok ? e : e0];   // clamped index (e0 < e1: the row has entries), masked value
-    const double w = ok ? wmask[r] : 0.0;
-    const bool hit = w != 0.0;
-    const uint64_t m = (__ballot(hit) >> sh) & 0xFFFFull;
-    if (hit) {
-      const int p = base + __popcll(m & ((1ull << li) - 1ull));
-      if (p < seg_cap) {
-        seg_src[p] = r;
-        seg_val[p] = (double)val[e] * w;
+  const int lane = threadIdx.x & 63, g = lane >> 4, li = lane & 15, sh = lane & 48;
+  const int j0 = (blockIdx.x * 4 + (threadIdx.x >> 6)) * 64;
+  if (j0 >= n) return;   // the same for the whole wave
+  const int jl = j0 + lane;
+  const bool inb = jl < n;
+  const int c = inb ? cnt[jl] : 0;
+  const int rb = inb ? rp[jl] : 0, re = inb ? rp[jl + 1] : 0, sp = inb ? seg_ptr[jl] : 0;
+  if (c > 0) cnt[jl] = 0;
+  uint64_t act = __ballot(c > 0);
+  while (act) {   // the same for the whole wave
+    // group g takes the g-th lowest row left in act
+    uint64_t m = act;
+    for (int t = 0; t < g; ++t) m &= m - 1;
+    const bool have = m != 0;
+    const int src = have ? __ffsll((unsigned long long)m) - 1 : 0;
+    const int e0 = __shfl(rb, src), e1b = __shfl(re, src), base0 = __shfl(sp, src);
+    const int e1 = have ? e1b : e0;   // no trips without a row
+    int base = base0;
+    for (int e = e0 + li; e - li < e1; e += 16) {   // the same trips for the group's lanes
+      const bool ok = e < e1;
+      const int r = ci[ok ? e : e0];   // clamped index (e0 < e1: the row has entries), masked value
+      const bool hit = ok && ((wbits[r >> 6] >> (r & 63)) & 1ull);
+      const uint64_t mb = (__ballot(hit) >> sh) & 0xFFFFull;
+      if (hit) {
+        const int p = base + __popcll(mb & ((1ull << li) - 1ull));
+        if (p < seg_cap) {
+          seg_src[p] = r;
+          seg_val[p] = (double)val[e] * wmask[r];
+        }
       }
+      base += __popcll(mb);
     }
-    base += __popcll(m);
+    // the four rows taken are done
+#pragma unroll
+    for (int t = 0; t < 4; ++t) act &= act - 1;
   }
 }
 
@@ -337,7 +367,7 @@ int leverage_scores(const void* F, int fdtype, int n, int k, const double* Rinv,
 
 int hybrid_sample(const double* lev, int n, int k, int64_t s_total, double tau, uint64_t seed, uint32_t half_iter,
                   SampleBuffers& sb, int* rows, double* weights, int64_t cap, Workspace& ws, const DevState* st,
-                  hipStream_t s, double* wmask) {
+                  hipStream_t s, double* wmask, uint64_t* wbits) {
   const int nb = ceil_div(n, 256);
   double* tpart = ws.dbl(nb);
   int* sel = ws.i32(n);
@@ -351,21 +381,23 @@ int hybrid_sample(const double* lev, int n, int k, int64_t s_total, double tau, 
   k_select<<<nb, 256, 0, s>>>(sb.flags, sb.counts, n, sel, st);
   if (exclusive_scan_i32(sel, pos, n, ws, s)) return -1;
   k_emit<<<nb, 256, 0, s>>>(sb.flags, sb.counts, sb.w, sb.prefix, sel, pos, n, rows, weights, cap, sb.info, wmask,
-                            st);
+                            wbits, st);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
 int sampled_slab(const int* rp, const int* ci, const void* val, int vdtype, int n, const int* rows,
-                 const int* d_count, int max_rows, const double* wmask, int* seg_cnt, int* seg_ptr, int* seg_src,
-                 double* seg_val, int64_t seg_cap, Workspace& ws, const DevState* st, hipStream_t s) {
+                 const int* d_count, int max_rows, const double* wmask, const uint64_t* wbits, int* seg_cnt,
+                 int* seg_ptr, int* seg_src, double* seg_val, int64_t seg_cap, Workspace& ws, const DevState* st,
+                 hipStream_t s) {
+  if (!wmask || !wbits) return -1;
   const int nbw = std::max(1, ceil_div(max_rows, 4));
   k_slab_count<<<nbw, 256, 0, s>>>(rp, ci, rows, d_count, seg_cnt, st);
   if (exclusive_scan_i32(seg_cnt, seg_ptr, n, ws, s)) return -1;
   if (vdtype == SYMNMF_F64)
-    k_slab_fill_rows<double><<<ceil_div(n, 16), 256, 0, s>>>(rp, ci, (const double*)val, n, wmask, seg_cnt, seg_ptr,
-                                                             seg_src, seg_val, seg_cap, st);
+    k_slab_fill_rows<double><<<ceil_div(n, 256), 256, 0, s>>>(rp, ci, (const double*)val, n, wmask, wbits, seg_cnt,
+                                                             seg_ptr, seg_src, seg_val, seg_cap, st);
   else
-    k_slab_fill_rows<float><<<ceil_div(n, 16), 256, 0, s>>>(rp, ci, (const float*)val, n, wmask, seg_cnt, seg_ptr,
-                                                            seg_src, seg_val, seg_cap, st);
+    k_slab_fill_rows<float><<<ceil_div(n, 256), 256, 0, s>>>(rp, ci, (const float*)val, n, wmask, wbits, seg_cnt,
+                                                            seg_ptr, seg_src, seg_val, seg_cap, st);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
