@@ -545,11 +545,12 @@ __global__ __launch_bounds__(256) void k_pad_identity(double* __restrict__ Ghat,
 // The earlier blocks' new values enter the later blocks' products as the
 // FP32 values the factor stores; at n = 65536, k = 64 the blocked and the
 // unblocked sweep agree to 2e-8 (relative).  At n = 2^20, k = 64 (sparse
-// graph) the update takes 472 us against 700 us unblocked (LvS 596 against
+// graph) the update takes 472 us against 700 us unblocked (LvS 477 against
 // 725); about 6700 FP64 FMAs per row, on the FP64 units the matrix and the
 // vector instructions share on this chip, put its floor near 180 us.
 constexpr int BK_LW = 68;     // slab row stride in floats (16-byte rows, 272 B)
 constexpr int BK_ROWS = 256;  // rows per block chunk (4 waves x 64)
+constexpr int BK_XR = 13;     // sampled-slab rows whose extra entries a chunk holds in LDS
 
 __device__ __forceinline__ void swap_words(double& x, double& y, bool halves) {
   const unsigned long long ux = (unsigned long long)__double_as_longlong(x);
@@ -590,6 +591,8 @@ void k_update_blk(UpdateArgs a, const double* __restrict__ Gh, const double* __r
   double* gd = reinterpret_cast<double*>(smem + sizeof(float) * BK_ROWS * BK_LW);
   double* gv = gd + 4 * 256;
   __shared__ double sc[8];
+  __shared__ double hx[BK_XR - 8][64];   // held extras' sums beyond the slab's padding (sampled slab)
+  __shared__ int wx[4];                   // rows with held extras per wave (sampled slab)
   const int tid = threadIdx.x, wid = tid >> 6, lane = tid & 63, li = lane & 15, lg = lane >> 4;
   float* sw = slab + wid * 64 * BK_LW;
   const int n = a.n, k = a.k, k4 = a.k >> 2;   // k a multiple of 4
@@ -651,15 +654,76 @@ void k_update_blk(UpdateArgs a, const double* __restrict__ Gh, const double* __r
     const bool live = row < n;
     const int rowc = live ? row : n - 1;
     const int nbase = base + gridDim.x * BK_ROWS;   // the next chunk, if any
-    // YMODE 1: the row's segment of the sampled slab, and its first entry
+    // YMODE 1: the row's segment of the sampled slab, and its first entry.
+    // Rows with more entries (a few per cent, but in most waves, and a few
+    // rows with tens of entries once the scores concentrate) have the sum
+    // of their later entries ("extras") formed once per chunk: the chunk's
+    // first BK_XR such rows, numbered in row order, each by a 16-lane group
+    // of the wave that owns it (4 columns per lane, FP64, the entries in
+    // segment order), kept in LDS as 64 doubles -- slot p < 8 in the slab's
+    // unused columns 64..67 of rows 32 p .. 32 p + 31, the rest in hx -- and
+    // each block the owning lane adds its block's 16 values.  Read per
+    // block, the extras were chains of dependent global reads, and the block
+    // with the most of them set the kernel's time (n = 2^20, k = 64: 596 us;
+    // 477 us held).
     int e0 = 0, e1 = 0, s0 = rowc;
     double v0 = 0.0;
+    int xq = BK_XR;   // the row's slot (< BK_XR when its extras are held)
     if (YMODE == 1) {
       e0 = live ? a.seg_ptr[row] : 0;
       e1 = live ? a.seg_ptr[row + 1] : 0;
       if (e0 < e1) {
         v0 = a.seg_val[e0];
         s0 = a.seg_src[e0];
+      }
+      const bool xr = e1 - e0 > 1;
+      const uint64_t bm = __ballot(xr);
+      const int inc = __popcll(bm & ((2ull << lane) - 1ull));   // inclusive rank among the wave's such rows
+      if (lane == 0) wx[wid] = __popcll(bm);
+      __syncthreads();
+      int before = 0;   // such rows of the lower waves
+#pragma unroll
+      for (int u = 0; u < 3; ++u) before += u < wid ? wx[u] : 0;
+      if (xr && before + inc - 1 < BK_XR) xq = before + inc - 1;
+      // group lg sums wave-local such row t = 4 r + lg, the row of the first
+      // lane whose inclusive rank exceeds t
+      const int nh = min(__popcll(bm), BK_XR - before);
+      for (int r = 0; 4 * r < nh; ++r) {
+        int own = 0;
+#pragma unroll
+        for (int g = 0; g < 4; ++g) {
+          const int o = __popcll(__ballot(inc <= 4 * r + g));
+          own = lg == g ? o : own;
+        }
+        const int t = 4 * r + lg;
+        const int f0 = __shfl(e0, own & 63) + 1, f1 = __shfl(e1, own & 63);
+        if (t < nh) {
+          const int q = 4 * li, qc = q < k ? q : k - 4;
+          double z[4] = {0.0, 0.0, 0.0, 0.0};
+          for (int e = f0; e < f1; e += 4) {   // four entries' loads in flight at once
+            double vu[4];
+            float4 xu[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+              const int eu = min(e + u, f1 - 1);
+              vu[u] = e + u < f1 ? a.seg_val[eu] : 0.0;
+              xu[u] = *reinterpret_cast<const float4*>(Src + (int64_t)a.seg_src[eu] * k + qc);
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+              z[0] = fma(vu[u], (double)xu[u].x, z[0]);
+              z[1] = fma(vu[u], (double)xu[u].y, z[1]);
+              z[2] = fma(vu[u], (double)xu[u].z, z[2]);
+              z[3] = fma(vu[u], (double)xu[u].w, z[3]);
+            }
+          }
+          if (q >= k) z[0] = z[1] = z[2] = z[3] = 0.0;
+          const int p = before + t;
+          double* d0 = p < 8 ? reinterpret_cast<double*>(slab + (32 * p + 2 * li) * BK_LW + 64) : &hx[p - 8][4 * li];
+          double* d1 = p < 8 ? reinterpret_cast<double*>(slab + (32 * p + 2 * li + 1) * BK_LW + 64) : &hx[p - 8][4 * li + 2];
+          *reinterpret_cast<double2*>(d0) = make_double2(z[0], z[1]);
+          *reinterpret_cast<double2*>(d1) = make_double2(z[2], z[3]);
+        }
       }
     }
     // old factor rows of the wave -> slab; the 64 rows are contiguous (64 k
@@ -673,7 +737,10 @@ void k_update_blk(UpdateArgs a, const double* __restrict__ Gh, const double* __r
         *reinterpret_cast<float4*>(sw + rr * BK_LW + 4 * c4) = e < lim ? v : make_float4(0.f, 0.f, 0.f, 0.f);
       }
     }
-    wave_sync();
+    if (YMODE == 1)
+      __syncthreads();   // the held extras are read across the waves
+    else
+      wave_sync();
     // the block loop stays rolled: unrolled, the compiler hoists the LDS reads
     // of all four blocks and spills
 #pragma unroll 1
@@ -712,17 +779,39 @@ void k_update_blk(UpdateArgs a, const double* __restrict__ Gh, const double* __r
           }
         }
       } else {
-        // the first entry's row (prefetched), then the rest of the segment
+        // the first entry's row (prefetched) and the alpha term, then the
+        // rest of the segment (the alpha source taken first frees its
+        // registers before the segment's loads)
         const double v = e0 < e1 ? v0 : 0.0;
 #pragma unroll
         for (int m = 0; m < 4; ++m) {
           const bool ok = 16 * b + 4 * m < k;
-          y[4 * m] = v * (ok ? (double)pp[m].x : 0.0);
-          y[4 * m + 1] = v * (ok ? (double)pp[m].y : 0.0);
-          y[4 * m + 2] = v * (ok ? (double)pp[m].z : 0.0);
-          y[4 * m + 3] = v * (ok ? (double)pp[m].w : 0.0);
+          const bool oks = live && ok;
+          y[4 * m] = live ? fma(alpha, oks ? (double)ps[m].x : 0.0, v * (ok ? (double)pp[m].x : 0.0)) : 0.0;
+          y[4 * m + 1] = live ? fma(alpha, oks ? (double)ps[m].y : 0.0, v * (ok ? (double)pp[m].y : 0.0)) : 0.0;
+          y[4 * m + 2] = live ? fma(alpha, oks ? (double)ps[m].z : 0.0, v * (ok ? (double)pp[m].z : 0.0)) : 0.0;
+          y[4 * m + 3] = live ? fma(alpha, oks ? (double)ps[m].w : 0.0, v * (ok ? (double)pp[m].w : 0.0)) : 0.0;
         }
-        for (int e = e0 + 1; e < e1; ++e) {
+        // the row's held extras: columns 16 b + 4 m .. + 3 of slot p sit in
+        // padding rows 32 p + 8 b + 2 m and + 1, or in hx[p - 8]
+        if (xq < BK_XR) {
+#pragma unroll
+          for (int m = 0; m < 4; ++m) {
+            const int c = 4 * (4 * b + m);
+            const double* d0 = xq < 8 ? reinterpret_cast<const double*>(slab + (32 * xq + 8 * b + 2 * m) * BK_LW + 64)
+                                      : &hx[xq - 8][c];
+            const double* d1 = xq < 8 ? reinterpret_cast<const double*>(slab + (32 * xq + 8 * b + 2 * m + 1) * BK_LW + 64)
+                                      : &hx[xq - 8][c + 2];
+            const double2 z0 = *reinterpret_cast<const double2*>(d0), z1 = *reinterpret_cast<const double2*>(d1);
+            y[4 * m] += z0.x;
+            y[4 * m + 1] += z0.y;
+            y[4 * m + 2] += z1.x;
+            y[4 * m + 3] += z1.y;
+          }
+        }
+        // the extras of rows beyond the held ones
+        const int nheld = xq < BK_XR ? e1 - e0 : 1;
+        for (int e = e0 + nheld; e < e1; ++e) {
           const double v = a.seg_val[e];
           const float* sr = Src + (int64_t)a.seg_src[e] * k;
 #pragma unroll
@@ -738,7 +827,7 @@ void k_update_blk(UpdateArgs a, const double* __restrict__ Gh, const double* __r
         }
       }
 #pragma unroll
-      for (int m = 0; m < 4; ++m) {
+      for (int m = 0; m < 4 && YMODE == 0; ++m) {
         const bool ok = live && 16 * b + 4 * m < k;
         const float4 x = ok ? ps[m] : make_float4(0.f, 0.f, 0.f, 0.f);
         y[4 * m] = live ? fma(alpha, (double)x.x, y[4 * m]) : 0.0;

@@ -140,6 +140,7 @@ def test_lvs_tau_zero_matches_plain():
 
 
 @pytest.mark.parametrize("case", [(66_001, 64, 0, np.float32), (66_001, 64, 6000, np.float32),
+                                  (66_001, 64, 500, np.float32),
                                   (66_001, 52, 0, np.float32), (66_001, 60, 5000, np.float32),
                                   (40_003, 50, 0, np.float32),
                                   (65_600, 10, 0, np.float32), (65_600, 40, 3000, np.float32),
@@ -150,7 +151,9 @@ def test_long_factor_half_step(case):
     # (grid stride), and n is ragged against the chunk; every padded width:
     # at 64 with FP32 factors the blocked sweep (k = 64, and k = 52, 60 with
     # padding columns), k = 50 (not a multiple of 4) the 8-lanes-per-row
-    # kernel, as at width 32 and for FP64
+    # kernel, as at width 32 and for FP64.  Sampled: about 3 entries per row
+    # at s = 6000 (most rows' later entries beyond the chunk's held ones) and
+    # 0.25 at s = 500 (nearly all of them held)
     n, k, s, vt = case
     log(f"long factor half step n={n} k={k} s={s} {np.dtype(vt).name}")
     X = _sbm(n, 32, 16.0, seed=n + k)
