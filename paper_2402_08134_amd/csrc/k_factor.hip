@@ -401,126 +401,203 @@ __global__ __launch_bounds__(256) void k_chol_inverse(const double* __restrict__
   }
 }
 
-// ---------------------------------------------------------------------------
-// Cholesky G + shift I = L L^T and L^{-1} in one wavefront: lane r holds row r
-// (KM = k rounded up to 16; rows and columns beyond k are the identity).
-// Step j of the factorisation takes the pivot from lane j, forms column j of
-// L in every lane, stores it (LDS, and row j of R = L^T), and updates the
-// trailing entries of the row with the column read back by broadcast reads
-// (all lanes one address).  A column once stored is no longer held in
-// registers, so the register file has room to keep many of those reads in
-// flight; the single wave has nothing else to hide their latency with.  The
-// inverse is that of the unit lower triangle, L = Lu D with D = diag(L):
-// row t of Lu^{-1} is final after step t, written to LDS by its lane and
-// subtracted, times Lu[r][t], from the rows below; each row is scaled by
-// 1 / L[r][r] once at the end (L^{-1} = D^{-1} Lu^{-1}).  With all loops
-// unrolled every register index is static.  Retries with the same growing
-// shifts as the workgroup kernel.  (A version with the whole of L and of the
-// inverse in registers, columns broadcast with v_readlane or through LDS:
-// k = 64 in 92-97 us, l = 48 in 46 us.)
-// ---------------------------------------------------------------------------
-// one step of a wave's LDS exchange: ordered at wavefront scope, and no
-// memory access moved across it by the compiler (which would otherwise
-// hoist every later step's reads and run out of registers)
-__device__ __forceinline__ void step_sync() {
-  wave_sync();
-  asm volatile("" ::: "memory");
-}
-
+// v of lane `lane` (a constant), in every lane
 __device__ __forceinline__ double lane_value(double v, int lane) {
   const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
   const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
   return __hiloint2double(hi, lo);
 }
 
-template <int KM>
-__global__ __launch_bounds__(64) void k_chol_regs(const double* __restrict__ G, int k, double* __restrict__ R,
+// ---------------------------------------------------------------------------
+// Blocked Cholesky G + shift I = L L^T and L^{-1} (k <= 64) in one workgroup
+// of four waves, on 16 x 16 tiles (KT a side; rows and columns beyond k are
+// the identity).  For each tile column J: wave 0 factors the diagonal tile
+// in registers (lane r holds row r; pivots and rows broadcast with
+// v_readlane) and inverts it by forward substitution; then the tiles below
+// it become L_IJ = A_IJ L_JJ^{-T} and the trailing tiles A_II' -= L_IJ
+// L_I'J^T, on the FP64 matrix cores, a tile a wave.  The inverse's
+// off-diagonal tiles follow by diagonals, X_IJ = -X_II (sum_P L_IP X_PJ):
+// register v of the inner sum's accumulator holds K index lg + 4 v, which
+// is the outer product's B operand of step v, so the sum never leaves the
+// registers.  Retries with the same growing shifts as k_chol_inverse.  At
+// k = 64: 22 us, against 68 us for a single wave holding a row per lane
+// (64 dependent steps with a square root and a division each) and 47 us
+// for this kernel with its 16-step loop not unrolled (a conditional exit
+// in it: the tile's rows then need dynamic register indexing).
+// ---------------------------------------------------------------------------
+// 1 / a for a positive normal a: v_rcp_f64 refined by two Newton steps
+__device__ __forceinline__ double recip_nr(double a) {
+  double y = __builtin_amdgcn_rcp(a);
+  double e = fma(-a, y, 1.0);
+  y = fma(y, e, y);
+  e = fma(-a, y, 1.0);
+  return fma(y, e, y);
+}
+
+template <int KT>
+__global__ __launch_bounds__(256) void k_chol_blk(const double* __restrict__ G, int k, double* __restrict__ R,
                                                   double* __restrict__ Rinv, int* d_flags, int flag_bit,
                                                   int* d_fail) {
-  __shared__ __align__(16) double Ls[KM][KM + 2];   // Ls[j][r] = L[r][j]
-  __shared__ __align__(16) double xb[KM];           // row t of Lu^{-1}
-  __shared__ double rs[KM];                         // 1 / L[j][j]
-  const int r = threadIdx.x;
-  const bool act = r < k;
-  double tr = act ? G[r * k + r] : 0.0;
-  tr = wave_sum(tr);
-  double shift = 0.0, grow = 1e-12 * fmax(tr, 1e-300) / k;
-  bool ok = false;
-  for (int attempt = 0; attempt < 6 && !ok; ++attempt) {
+  constexpr int KM = 16 * KT, LD = KM + 1;
+  extern __shared__ double chol_lds[];
+  double* A = chol_lds;       // KM x LD: the matrix, then L in its lower triangle
+  double* X = A + KM * LD;    // KM x LD: L^{-1} in its lower triangle
+  __shared__ int bad;
+  const int tid = threadIdx.x, wid = tid >> 6, lane = tid & 63, li = lane & 15, lg = lane >> 4;
+  double shift = 0.0, grow = 0.0;
+  for (int attempt = 0; attempt < 6; ++attempt) {
+    if (attempt == 1) {   // the trace, only when a shift is needed
+      double tr = 0.0;
+      for (int i = lane; i < k; i += 64) tr += G[i * k + i];
+      tr = wave_sum(tr);
+      grow = 1e-12 * fmax(tr, 1e-300) / k;
+    }
     if (attempt > 0) {
       shift = grow;  // 1e-12, 1e-10, ... times tr(G) / k
       grow *= 100.0;
     }
-    // The lane and the size pass through an empty asm: nothing derived from
-    // them is loop-invariant, so the compiler does not compute it once for
-    // all the attempts and hold it (addresses, masks and constants of every
-    // step: out of registers).
-    int rr = r, kk = k;
-    asm volatile("" : "+v"(rr), "+s"(kk) : : "memory");
-    const bool ac = rr < kk;
-    // row r of G (identity rows and columns beyond k)
-    double a[KM];
+    // all of a thread's loads in flight at once (clamped index, masked value)
 #pragma unroll
-    for (int c = 0; c < KM; ++c)
-      a[c] = ((ac && c < kk) ? G[rr * kk + c] : (c == rr ? 1.0 : 0.0)) + ((ac && c == rr) ? shift : 0.0);
-    ok = true;
+    for (int i = 0; i < KM * KM / 256; ++i) {
+      const int e = tid + 256 * i, p = e / KM, q = e - p * KM;
+      const bool in = p < k && q < k;
+      const double g = G[in ? p * k + q : 0];
+      A[p * LD + q] = in ? g + (p == q ? shift : 0.0) : (p == q ? 1.0 : 0.0);
+    }
+    if (tid == 0) bad = 0;
+    __syncthreads();
+    for (int J = 0; J < KT; ++J) {
+      if (wid == 0) {
+        // symmetric elimination: step j takes row j (lane j) off the rows
+        // below with the factor A[r][j] / pivot, so only a reciprocal
+        // (v_rcp_f64 and two Newton steps) is on the chain of dependent
+        // steps; the columns are scaled by 1 / sqrt(pivot) at the end
+        const int r = li;
+        double* at = A + (16 * J + r) * LD + 16 * J;
+        double d[16], pv[16];
 #pragma unroll
-    for (int j = 0; j < KM; ++j) {
-      if (ok) {
-        const double d = lane_value(a[j], j);
-        if (!(d > 0.0) || !isfinite(d)) {
-          ok = false;
+        for (int c = 0; c < 16; ++c) d[c] = at[c];
+        bool fail = false;
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+          // no early exit: a break would keep the loop from being
+          // unrolled, and d[j] would need dynamic register indexing
+          const double piv = lane_value(d[j], j);   // the same in every lane
+          fail = fail || !(piv > 0.0) || !isfinite(piv);
+          pv[j] = piv;
+          const double cj = !fail && r > j ? d[j] * recip_nr(piv) : 0.0;
+#pragma unroll
+          for (int c = j + 1; c < 16; ++c) d[c] = fma(-cj, lane_value(d[c], j), d[c]);
+        }
+        if (fail) {
+          if (lane == 0) bad = 1;
         } else {
-          const double ljj = sqrt(d);
-          const double rl = 1.0 / ljj;
-          const double lj = rr > j ? a[j] * rl : (rr == j ? ljj : 0.0);   // L[r][j]
-          if (rr < KM) Ls[j][rr] = lj;   // lanes past the padded width hold no row
-          if (rr == 0) rs[j] = rl;
+          // lane r: 1 / L[r][r]; L[r][j] = d[j] / sqrt(pivot j) for r >= j
+          double mp = 1.0;
+#pragma unroll
+          for (int j = 0; j < 16; ++j) mp = r == j ? pv[j] : mp;
+          const double rs = 1.0 / sqrt(mp);
+          double rsv[16];
+#pragma unroll
+          for (int j = 0; j < 16; ++j) {
+            rsv[j] = lane_value(rs, j);
+            d[j] = r >= j ? d[j] * rsv[j] : 0.0;
+          }
+          if (lane < 16) {
+#pragma unroll
+            for (int c = 0; c < 16; ++c) at[c] = d[c];
+          }
           wave_sync();
+          // X = L^{-1} by forward substitution, lane c column c (rows above
+          // c come out zero)
+          double x[16];
+          const double* lt = A + 16 * J * LD + 16 * J;
 #pragma unroll
-          for (int c = j + 1; c < KM; ++c) a[c] = fma(-lj, Ls[j][c], a[c]);
-          // each entry's update happens in its step: the compiler would
-          // otherwise sink the updates to where the entry is next needed and
-          // keep every column read alive until then (out of registers)
+          for (int rr = 0; rr < 16; ++rr) {
+            double s0 = rr == li ? 1.0 : 0.0, s1 = 0.0;
 #pragma unroll
-          for (int c = j + 1; c < KM; ++c) asm volatile("" : "+v"(a[c]));
+            for (int q = 0; q < rr; ++q) {
+              if (q & 1)
+                s1 = fma(-lt[rr * LD + q], x[q], s1);
+              else
+                s0 = fma(-lt[rr * LD + q], x[q], s0);
+            }
+            x[rr] = (s0 + s1) * rsv[rr];
+          }
+          if (lane < 16) {
+#pragma unroll
+            for (int rr = 0; rr < 16; ++rr) X[(16 * J + rr) * LD + 16 * J + li] = x[rr];
+          }
         }
       }
+      __syncthreads();
+      if (bad) break;
+      // the tiles below the diagonal one: L_IJ = A_IJ X_JJ^T
+      if (wid < KT - 1 - J) {
+        const int I = J + 1 + wid;
+        doublex4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+          acc = __builtin_amdgcn_mfma_f64_16x16x4f64(A[(16 * I + li) * LD + 16 * J + 4 * s + lg],
+                                                     X[(16 * J + li) * LD + 16 * J + 4 * s + lg], acc, 0, 0, 0);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) A[(16 * I + lg + 4 * v) * LD + 16 * J + li] = acc[v];
+      }
+      __syncthreads();
+      // the trailing tiles (I, I2), J < I2 <= I: A_II2 -= L_IJ L_I2J^T
+      const int m = KT - 1 - J;
+      for (int t = wid; t < m * (m + 1) / 2; t += 4) {
+        int t2 = t, I = J + 1;
+        while (t2 >= I - J) {
+          t2 -= I - J;
+          ++I;
+        }
+        const int I2 = J + 1 + t2;
+        doublex4 acc;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc[v] = A[(16 * I + lg + 4 * v) * LD + 16 * I2 + li];
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+          acc = __builtin_amdgcn_mfma_f64_16x16x4f64(-A[(16 * I + li) * LD + 16 * J + 4 * s + lg],
+                                                     A[(16 * I2 + li) * LD + 16 * J + 4 * s + lg], acc, 0, 0, 0);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) A[(16 * I + lg + 4 * v) * LD + 16 * I2 + li] = acc[v];
+      }
+      __syncthreads();
     }
+    if (!bad) break;
+    __syncthreads();   // every wave has read the flag before the next attempt resets it
   }
-  if (!ok) {
-    if (r == 0) *d_fail = 1;
+  if (bad) {
+    if (tid == 0) *d_fail = 1;
     return;
   }
-  if (r == 0 && shift > 0.0 && d_flags) atomicOr(d_flags, flag_bit);
-  step_sync();
-  // R = L^T: row j of R is column j of L
-  if (act) {
-    for (int j = 0; j < k; ++j) R[j * k + r] = Ls[j][r];
-  }
-  double x[KM];
+  if (tid == 0 && shift > 0.0 && d_flags) atomicOr(d_flags, flag_bit);
+  // the inverse's off-diagonal tiles, diagonal dd by diagonal
+  for (int dd = 1; dd < KT; ++dd) {
+    if (wid < KT - dd) {
+      const int I = dd + wid, J = I - dd;
+      doublex4 T = {0.0, 0.0, 0.0, 0.0};
+      for (int P = J; P < I; ++P) {
 #pragma unroll
-  for (int c = 0; c < KM; ++c) x[c] = c == r ? 1.0 : 0.0;
+        for (int s = 0; s < 4; ++s)
+          T = __builtin_amdgcn_mfma_f64_16x16x4f64(A[(16 * I + li) * LD + 16 * P + 4 * s + lg],
+                                                   X[(16 * P + 4 * s + lg) * LD + 16 * J + li], T, 0, 0, 0);
+      }
+      doublex4 acc = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-  for (int t = 0; t < KM; ++t) {
-    if (r == t) {
+      for (int s = 0; s < 4; ++s)
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(-X[(16 * I + li) * LD + 16 * I + 4 * s + lg], T[s], acc, 0, 0, 0);
 #pragma unroll
-      for (int c = 0; c <= t; ++c) xb[c] = x[c];
+      for (int v = 0; v < 4; ++v) X[(16 * I + lg + 4 * v) * LD + 16 * J + li] = acc[v];
     }
-    step_sync();
-    const double m = (r > t && r < KM) ? Ls[t][r < KM ? r : 0] * rs[t] : 0.0;   // Lu[r][t]
-#pragma unroll
-    for (int c = 0; c <= t; ++c) x[c] = fma(-m, xb[c], x[c]);
-#pragma unroll
-    for (int c = 0; c <= t; ++c) asm volatile("" : "+v"(x[c]));
-    step_sync();
+    __syncthreads();
   }
-  // R^{-1} = (L^{-1})^T: Rinv[c][r] = L^{-1}[r][c] = Lu^{-1}[r][c] / L[r][r]
-  const double dr = rs[r < KM ? r : 0];
-  if (act) {
-#pragma unroll
-    for (int c = 0; c < KM; ++c)
-      if (c < k) Rinv[c * k + r] = x[c] * dr;
+  // R = L^T, R^{-1} = (L^{-1})^T
+  for (int e = tid; e < k * k; e += 256) {
+    const int p = e / k, q = e - p * k;
+    R[e] = q >= p ? A[q * LD + p] : 0.0;
+    Rinv[e] = q >= p ? X[q * LD + p] : 0.0;
   }
 }
 
@@ -906,11 +983,18 @@ int rowmat(const void* A, int adtype, int64_t lda, int n, int l, const double* M
 int chol_inverse(const double* G, int k, double* R, double* Rinv, int* d_flags, int flag_bit, int* d_fail,
                  hipStream_t s) {
   if (k >= 1 && k <= 64) {
-    switch (16 * ceil_div(k, 16)) {
-      case 16: k_chol_regs<16><<<1, 64, 0, s>>>(G, k, R, Rinv, d_flags, flag_bit, d_fail); break;
-      case 32: k_chol_regs<32><<<1, 64, 0, s>>>(G, k, R, Rinv, d_flags, flag_bit, d_fail); break;
-      case 48: k_chol_regs<48><<<1, 64, 0, s>>>(G, k, R, Rinv, d_flags, flag_bit, d_fail); break;
-      default: k_chol_regs<64><<<1, 64, 0, s>>>(G, k, R, Rinv, d_flags, flag_bit, d_fail); break;
+    const int kt = ceil_div(k, 16);
+    const size_t lds = 2 * sizeof(double) * (16 * kt) * (16 * kt + 1);
+    switch (kt) {
+      case 1: k_chol_blk<1><<<1, 256, lds, s>>>(G, k, R, Rinv, d_flags, flag_bit, d_fail); break;
+      case 2: k_chol_blk<2><<<1, 256, lds, s>>>(G, k, R, Rinv, d_flags, flag_bit, d_fail); break;
+      case 3: k_chol_blk<3><<<1, 256, lds, s>>>(G, k, R, Rinv, d_flags, flag_bit, d_fail); break;
+      default:
+        if (hipFuncSetAttribute((const void*)k_chol_blk<4>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) !=
+            hipSuccess)
+          return -1;
+        k_chol_blk<4><<<1, 256, lds, s>>>(G, k, R, Rinv, d_flags, flag_bit, d_fail);
+        break;
     }
     return hipGetLastError() == hipSuccess ? 0 : -1;
   }
