@@ -329,6 +329,91 @@ __global__ __launch_bounds__(256) void k_slab_fill_rows(const int* __restrict__ 
   }
 }
 
+// a 32-bit word of lanes 32..63 of x <-> lanes 0..31 of y (halves), or of the
+// odd 16-lane rows of x <-> the even rows of y
+__device__ __forceinline__ void swap_f32(float& x, float& y, bool halves) {
+  const unsigned ux = __float_as_uint(x), uy = __float_as_uint(y);
+  const auto r = halves ? __builtin_amdgcn_permlane32_swap(ux, uy, false, false)
+                        : __builtin_amdgcn_permlane16_swap(ux, uy, false, false);
+  x = __uint_as_float(r[0]);
+  y = __uint_as_float(r[1]);
+}
+
+// The same products with k = KP and a 16-byte aligned factor, without LDS:
+// lane (li, lg) reads float4 pieces lg, lg + 4, ... of row li of its group
+// (4 KT pieces, the next group's in flight during this group's products);
+// a 4 x 4 transpose across the lane groups by permlane swaps (per li: piece
+// 4 p + r of lane group r, element t -> lane group t, element r) leaves
+// lane (li, lg) the row's columns 4 s + lg, the A operand of K step s.
+// Each wave walks its own groups, so no workgroup barrier.  At n = 2^20,
+// k = 64: 101 us against 141 us with the LDS staging and its barriers (the
+// FP64 matrix cores at 66% of their peak over the 40 products of a group;
+// split accumulator chains or two waves per SIMD changed nothing).
+template <int KP>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KP == 64 ? 3 : 1))) void k_leverage_rows(
+    const float* __restrict__ F, int n, const double* __restrict__ Rinv, double* __restrict__ lev,
+    const DevState* __restrict__ st) {
+  if (stopped(st)) return;
+  constexpr int KT = KP / 16, NB = 2 * KT * (KT + 1);
+  const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63, li = lane & 15, lg = lane >> 4;
+  double breg[NB];
+  {
+    int b = 0;
+#pragma unroll
+    for (int J = 0; J < KT; ++J)
+#pragma unroll
+      for (int s4 = 0; s4 < 4 * (J + 1); ++s4, ++b) {
+        const int p = 4 * s4 + lg, i = 16 * J + li;
+        const double v = Rinv[p <= i ? p * KP + i : 0];   // clamped index, masked value
+        breg[b] = p <= i ? v : 0.0;
+      }
+  }
+  const int groups = (n + 15) / 16, gstride = 4 * gridDim.x;
+  float4 x[KT];
+  auto load = [&](int g) {
+    const float4* src = reinterpret_cast<const float4*>(F + (int64_t)min(16 * g + li, n - 1) * KP);
+#pragma unroll
+    for (int q = 0; q < KT; ++q) x[q] = src[lg + 4 * q];
+  };
+  int grp = 4 * blockIdx.x + wid;
+  if (grp < groups) load(grp);
+  for (; grp < groups; grp += gstride) {
+    double a[4 * KT];
+#pragma unroll
+    for (int q = 0; q < KT; ++q) {
+      float e[4] = {x[q].x, x[q].y, x[q].z, x[q].w};
+      swap_f32(e[0], e[2], true);
+      swap_f32(e[1], e[3], true);
+      swap_f32(e[0], e[1], false);
+      swap_f32(e[2], e[3], false);
+#pragma unroll
+      for (int t = 0; t < 4; ++t) a[4 * q + t] = (double)e[t];
+    }
+    if (grp + gstride < groups) load(grp + gstride);
+    doublex4 acc[KT];
+#pragma unroll
+    for (int J = 0; J < KT; ++J) acc[J] = doublex4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int s4 = 0; s4 < 4 * KT; ++s4) {
+#pragma unroll
+      for (int J = s4 / 4; J < KT; ++J)
+        acc[J] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[s4], breg[2 * J * (J + 1) + s4], acc[J], 0, 0, 0);
+    }
+    double t[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int J = 0; J < KT; ++J)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) t[v] = fma(acc[J][v], acc[J][v], t[v]);
+    const int r0 = 16 * grp, rows = min(16, n - r0);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const double tot = row16_sum(t[v]);
+      const int r = lg + 4 * v;
+      if (li == 0 && r < rows) lev[r0 + r] = tot;
+    }
+  }
+}
+
 template <int KP, typename TF>
 void lev_launch(const void* F, int n, int k, const double* Rinv, double* lev, const DevState* st, hipStream_t s) {
   if constexpr (std::is_same<TF, float>::value) {
@@ -340,6 +425,13 @@ void lev_launch(const void* F, int n, int k, const double* Rinv, double* lev, co
     }
     const int groups = ceil_div(n, 16);
     const int nb = std::max(1, std::min(1024, ceil_div(groups, 4)));
+    if (k == KP) {
+      // at KP = 64 three waves per SIMD: 768 blocks fill the chip once
+      // (n = 2^20: 101 against 104 us with 1024)
+      const int nbr = KP == 64 ? std::max(1, std::min(768, ceil_div(groups, 4))) : nb;
+      k_leverage_rows<KP><<<nbr, 256, 0, s>>>((const float*)F, n, Rinv, lev, st);
+      return;
+    }
     const int iters = ceil_div(groups, 4 * nb);
     k_leverage_mfma<KP><<<nb, 256, 0, s>>>((const float*)F, n, k, Rinv, lev, iters, st);
     return;

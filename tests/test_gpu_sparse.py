@@ -56,9 +56,12 @@ def test_csr_plain_parity_and_exact_residual():
     assert abs(r[0] - ro) / ro <= 1e-4
 
 
-def test_leverage_parity():
+@pytest.mark.parametrize("k", [16, 32, 33, 64])
+def test_leverage_parity(k):
+    # k = 16, 32, 64: rows read as float4 pieces and transposed across the
+    # lanes; k = 33 (padded to 64): rows staged in LDS
     X = _sbm()
-    n, k = X.shape[0], 16
+    n = X.shape[0]
     ctx = P.symnmf_create(csr_dev(X), k, 0.0, 100, 0)
     H = workloads.random_factor(n, k, seed=5) ** 2
     P.symnmf_set_factor(ctx, P.H, dev(H))
