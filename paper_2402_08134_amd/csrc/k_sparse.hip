@@ -62,7 +62,21 @@ __global__ __launch_bounds__(256) void k_csr_scalars_final(int nb, const double*
   __shared__ double sc[8];
   __shared__ double smax[256];
   double s = 0.0, q = 0.0, m = -INFINITY;
-  for (int b = threadIdx.x; b < nb; b += 256) {
+  int b = threadIdx.x;
+  for (; b + 7 * 256 < nb; b += 8 * 256) {   // 8 partials' loads in flight, added in order
+    double u[8][3];
+#pragma unroll
+    for (int j = 0; j < 8; ++j)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) u[j][c] = bpart[3 * (b + 256 * j) + c];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      s += u[j][0];
+      q += u[j][1];
+      m = fmax(m, u[j][2]);
+    }
+  }
+  for (; b < nb; b += 256) {
     s += bpart[3 * b];
     q += bpart[3 * b + 1];
     m = fmax(m, bpart[3 * b + 2]);
@@ -288,8 +302,11 @@ void spmm_dispatch(const int* rp, const int* ci, const TV* val, int n, const TB*
 int csr_scalars(const int* rp, const void* val, int vdtype, int n, int64_t nnz, Workspace& ws, double* d_rowsum,
                 double* d_out3, hipStream_t s) {
   (void)nnz;
-  // about four blocks per CU, at least 16 rows (one per lane group) each
-  const int rows_per_block = std::max(16, ceil_div(n, 1024));
+  // at least 16 rows (one per lane group) a block and up to 16384 blocks:
+  // a lane group walks its rows one after another, each a chain of
+  // dependent reads, so short walks and many waves (n = 2^20: 64 rows a
+  // block, four a group; with 1024 rows a block the pass took 137 us)
+  const int rows_per_block = std::max(16, ceil_div(n, 16384));
   const int nb = ceil_div(n, rows_per_block);
   double* bpart = ws.dbl(3 * (size_t)nb);
   if (!bpart) return -1;
