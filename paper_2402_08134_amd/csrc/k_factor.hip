@@ -799,29 +799,17 @@ __global__ __launch_bounds__(256) void k_scan_blocks(const T* __restrict__ in, i
   if (threadIdx.x == 0) bsum[blockIdx.x] = tot;
 }
 
-template <typename T>
-__global__ __launch_bounds__(256) void k_scan_totals(T* bsum, int nb, T* grand) {
-  // exclusive scan of the nb block sums in one workgroup: each thread scans
-  // a contiguous chunk, the chunk totals are scanned across the block
-  __shared__ T ws[4];
-  const int per = (nb + 255) / 256;
-  const int b0 = min(nb, (int)threadIdx.x * per), b1 = min(nb, b0 + per);
-  T sum = 0;
-  for (int b = b0; b < b1; ++b) sum += bsum[b];
-  T total;
-  T run = block_exclusive_scan<T>(sum, ws, total);
-  for (int b = b0; b < b1; ++b) {
-    const T v = bsum[b];
-    bsum[b] = run;
-    run += v;
-  }
-  if (grand && threadIdx.x == 0) *grand = total;
-}
-
+// Each block's offset is the sum of the block totals before it, read by the
+// block itself (integers: exact in any order; at most a few thousand totals,
+// cache-resident), so the scan takes two launches, not three.
 template <typename T, bool INCLUSIVE>
-__global__ __launch_bounds__(256) void k_scan_apply(const T* __restrict__ in, int n, const T* __restrict__ boff,
-                                                    T* __restrict__ out) {
+__global__ __launch_bounds__(256) void k_scan_apply(const T* __restrict__ in, int n, const T* __restrict__ bsum,
+                                                    T* __restrict__ out, T* __restrict__ grand) {
   __shared__ T ws[4];
+  T pre = 0;
+  for (int b = threadIdx.x; b < (int)blockIdx.x; b += 256) pre += bsum[b];
+  T off;
+  block_exclusive_scan<T>(pre, ws, off);
   const int base = blockIdx.x * 1024 + threadIdx.x * 4;
   T v[4];
   T s = 0;
@@ -831,7 +819,8 @@ __global__ __launch_bounds__(256) void k_scan_apply(const T* __restrict__ in, in
     s += v[u];
   }
   T tot;
-  T run = block_exclusive_scan<T>(s, ws, tot) + boff[blockIdx.x];
+  T run = block_exclusive_scan<T>(s, ws, tot) + off;
+  if (grand && blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) *grand = off + tot;
 #pragma unroll
   for (int u = 0; u < 4; ++u) {
     if (INCLUSIVE) run += v[u];
@@ -1034,8 +1023,7 @@ int exclusive_scan_i32(const int* in, int* out, int n, Workspace& ws, hipStream_
   int* bsum = ws.i32(nb);
   if (!bsum) return -1;
   k_scan_blocks<int><<<nb, 256, 0, s>>>(in, n, bsum);
-  k_scan_totals<int><<<1, 256, 0, s>>>(bsum, nb, out + n);
-  k_scan_apply<int, false><<<nb, 256, 0, s>>>(in, n, bsum, out);
+  k_scan_apply<int, false><<<nb, 256, 0, s>>>(in, n, bsum, out, out + n);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
@@ -1044,7 +1032,6 @@ int inclusive_scan_u64(const uint64_t* in, uint64_t* out, int n, Workspace& ws, 
   uint64_t* bsum = ws.u64(nb);
   if (!bsum) return -1;
   k_scan_blocks<uint64_t><<<nb, 256, 0, s>>>(in, n, bsum);
-  k_scan_totals<uint64_t><<<1, 256, 0, s>>>(bsum, nb, (uint64_t*)nullptr);
-  k_scan_apply<uint64_t, true><<<nb, 256, 0, s>>>(in, n, bsum, out);
+  k_scan_apply<uint64_t, true><<<nb, 256, 0, s>>>(in, n, bsum, out, (uint64_t*)nullptr);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
