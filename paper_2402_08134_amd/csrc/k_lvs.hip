@@ -229,7 +229,7 @@ __global__ __launch_bounds__(256) void k_emit(const int* __restrict__ det, int* 
                                               const int* __restrict__ sel, const int* __restrict__ pos, int n,
                                               int* __restrict__ rows, double* __restrict__ weights, int64_t cap,
                                               int* __restrict__ info, double* __restrict__ wmask,
-                                              uint64_t* __restrict__ wbits, const DevState* __restrict__ st) {
+                                              const DevState* __restrict__ st) {
   if (stopped(st)) return;
   const int i = blockIdx.x * 256 + threadIdx.x;
   if (i == 0) {
@@ -253,11 +253,6 @@ __global__ __launch_bounds__(256) void k_emit(const int* __restrict__ det, int* 
     if (wmask) wmask[i] = wt;
     counts[i] = 0;
   }
-  if (wbits) {   // the wave's 64 rows as one word (all lanes take part in the ballot)
-    const uint64_t b = __ballot(wt != 0.0);
-    const int word = blockIdx.x * 4 + (threadIdx.x >> 6);
-    if ((threadIdx.x & 63) == 0 && word < (n + 63) / 64) wbits[word] = b;
-  }
 }
 
 // One wave per sampled row; lanes walk the row's nonzeros.  X symmetric:
@@ -272,58 +267,97 @@ __global__ __launch_bounds__(256) void k_slab_count(const int* __restrict__ rp, 
   for (int e = rp[r] + (threadIdx.x & 63); e < rp[r + 1]; e += 64) atomicAdd(&cnt[ci[e]], 1);
 }
 
-// A wave takes 64 consecutive rows j: their counts, bounds and segment starts
-// in one coalesced read, then only the rows with sampled entries (cnt > 0,
-// found by a ballot), four at a time, 16 lanes per row (a block of 16 rows
-// per 256 threads, each row's reads one after another, took 115 us at
-// n = 2^20: three quarters of the rows have no sampled entry).  The lanes of
-// a row check 16 entries at a time against the sample's bitmask (n / 8
-// bytes, cache-resident) and read the weight for the sampled entries only;
-// each sampled entry goes to seg_ptr[j] + (sampled entries of the row before
-// it), found from the wave's ballot, so the segment is in column order.
-// cnt is cleared.
+// The sampled slab by scatter: a wave per sampled row r puts each stored
+// entry X[r][i] (times r's weight) into row i's segment (X is symmetric),
+// at a slot taken by counting cnt[i] down (which leaves cnt cleared); the
+// slots within a segment depend on the order of the atomics, so
+// k_slab_order then puts every segment in column order.
 template <typename TV>
-__global__ __launch_bounds__(256) void k_slab_fill_rows(const int* __restrict__ rp, const int* __restrict__ ci,
-                                                        const TV* __restrict__ val, int n,
-                                                        const double* __restrict__ wmask,
-                                                        const uint64_t* __restrict__ wbits, int* __restrict__ cnt,
-                                                        const int* __restrict__ seg_ptr, int* __restrict__ seg_src,
-                                                        double* __restrict__ seg_val, int64_t seg_cap,
-                                                        const DevState* __restrict__ st) {
+__global__ __launch_bounds__(256) void k_slab_scatter(const int* __restrict__ rp, const int* __restrict__ ci,
+                                                      const TV* __restrict__ val, const int* __restrict__ rows,
+                                                      const int* __restrict__ d_count, const double* __restrict__ wmask,
+                                                      int* __restrict__ cnt, const int* __restrict__ seg_ptr,
+                                                      int* __restrict__ seg_src, double* __restrict__ seg_val,
+                                                      int64_t seg_cap, const DevState* __restrict__ st) {
   if (stopped(st)) return;
-  const int lane = threadIdx.x & 63, g = lane >> 4, li = lane & 15, sh = lane & 48;
+  const int t = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (t >= *d_count) return;
+  const int r = rows[t];
+  const double w = wmask[r];
+  for (int e = rp[r] + (threadIdx.x & 63); e < rp[r + 1]; e += 64) {
+    const int i = ci[e];
+    const int64_t p = (int64_t)seg_ptr[i] + atomicSub(&cnt[i], 1) - 1;
+    if (p < seg_cap) {
+      seg_src[p] = r;
+      seg_val[p] = (double)val[e] * w;
+    }
+  }
+}
+
+// Column order within every segment of two or more entries (a few per cent
+// of the rows; a few have tens).  A wave reads the bounds of 64 consecutive
+// rows, takes those rows four at a time, 16 lanes each: up to 64 entries
+// are read into registers (four per lane), each entry's rank is counted
+// against all the row's keys (broadcast by lane shuffles within the 16-lane
+// row), and every entry is written to its rank: keys are distinct, so the
+// ranks are a permutation.  Longer segments are sorted by one lane in
+// place (insertion sort).
+__global__ __launch_bounds__(256) void k_slab_order(const int* __restrict__ seg_ptr, int n, int64_t seg_cap,
+                                                    int* __restrict__ seg_src, double* __restrict__ seg_val,
+                                                    const DevState* __restrict__ st) {
+  if (stopped(st)) return;
+  const int lane = threadIdx.x & 63, g = lane >> 4, li = lane & 15;
   const int j0 = (blockIdx.x * 4 + (threadIdx.x >> 6)) * 64;
   if (j0 >= n) return;   // the same for the whole wave
   const int jl = j0 + lane;
-  const bool inb = jl < n;
-  const int c = inb ? cnt[jl] : 0;
-  const int rb = inb ? rp[jl] : 0, re = inb ? rp[jl + 1] : 0, sp = inb ? seg_ptr[jl] : 0;
-  if (c > 0) cnt[jl] = 0;
-  uint64_t act = __ballot(c > 0);
+  const int sb = jl < n ? seg_ptr[jl] : 0;
+  const int se = jl < n ? (int)min((int64_t)seg_ptr[jl + 1], seg_cap) : 0;
+  uint64_t act = __ballot(se - sb >= 2);
   while (act) {   // the same for the whole wave
-    // group g takes the g-th lowest row left in act
     uint64_t m = act;
     for (int t = 0; t < g; ++t) m &= m - 1;
     const bool have = m != 0;
     const int src = have ? __ffsll((unsigned long long)m) - 1 : 0;
-    const int e0 = __shfl(rb, src), e1b = __shfl(re, src), base0 = __shfl(sp, src);
-    const int e1 = have ? e1b : e0;   // no trips without a row
-    int base = base0;
-    for (int e = e0 + li; e - li < e1; e += 16) {   // the same trips for the group's lanes
-      const bool ok = e < e1;
-      const int r = ci[ok ? e : e0];   // clamped index (e0 < e1: the row has entries), masked value
-      const bool hit = ok && ((wbits[r >> 6] >> (r & 63)) & 1ull);
-      const uint64_t mb = (__ballot(hit) >> sh) & 0xFFFFull;
-      if (hit) {
-        const int p = base + __popcll(mb & ((1ull << li) - 1ull));
-        if (p < seg_cap) {
-          seg_src[p] = r;
-          seg_val[p] = (double)val[e] * wmask[r];
+    const int b = __shfl(sb, src);
+    const int c = have ? __shfl(se, src) - b : 0;
+    if (c <= 64) {
+      int key[4];
+      double v[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int q = li + 16 * u;
+        key[u] = q < c ? seg_src[b + q] : 0x7fffffff;
+        v[u] = q < c ? seg_val[b + q] : 0.0;
+      }
+      int rank[4] = {0, 0, 0, 0};
+      // c is the same in the 16 lanes of a row, so every lane a shuffle
+      // reads from is active
+      for (int q = 0; q < c; ++q) {
+        const int kq = __shfl(key[q >> 4], (lane & 48) + (q & 15));
+#pragma unroll
+        for (int u = 0; u < 4; ++u) rank[u] += kq < key[u] ? 1 : 0;
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        if (li + 16 * u < c) {
+          seg_src[b + rank[u]] = key[u];
+          seg_val[b + rank[u]] = v[u];
         }
       }
-      base += __popcll(mb);
+    } else if (li == 0) {
+      for (int p = b + 1; p < b + c; ++p) {
+        const int kk = seg_src[p];
+        const double vv = seg_val[p];
+        int q = p - 1;
+        while (q >= b && seg_src[q] > kk) {
+          seg_src[q + 1] = seg_src[q];
+          seg_val[q + 1] = seg_val[q];
+          --q;
+        }
+        seg_src[q + 1] = kk;
+        seg_val[q + 1] = vv;
+      }
     }
-    // the four rows taken are done
 #pragma unroll
     for (int t = 0; t < 4; ++t) act &= act - 1;
   }
@@ -459,7 +493,7 @@ int leverage_scores(const void* F, int fdtype, int n, int k, const double* Rinv,
 
 int hybrid_sample(const double* lev, int n, int k, int64_t s_total, double tau, uint64_t seed, uint32_t half_iter,
                   SampleBuffers& sb, int* rows, double* weights, int64_t cap, Workspace& ws, const DevState* st,
-                  hipStream_t s, double* wmask, uint64_t* wbits) {
+                  hipStream_t s, double* wmask) {
   const int nb = ceil_div(n, 256);
   double* tpart = ws.dbl(nb);
   int* sel = ws.i32(n);
@@ -472,24 +506,24 @@ int hybrid_sample(const double* lev, int n, int k, int64_t s_total, double tau, 
   if (s_total > 0) k_draw<<<ceil_div(s_total, 256), 256, 0, s>>>(sb.prefix, n, s_total, seed, half_iter, sb.counts, sb.info, st);
   k_select<<<nb, 256, 0, s>>>(sb.flags, sb.counts, n, sel, st);
   if (exclusive_scan_i32(sel, pos, n, ws, s)) return -1;
-  k_emit<<<nb, 256, 0, s>>>(sb.flags, sb.counts, sb.w, sb.prefix, sel, pos, n, rows, weights, cap, sb.info, wmask,
-                            wbits, st);
+  k_emit<<<nb, 256, 0, s>>>(sb.flags, sb.counts, sb.w, sb.prefix, sel, pos, n, rows, weights, cap, sb.info, wmask, st);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
 int sampled_slab(const int* rp, const int* ci, const void* val, int vdtype, int n, const int* rows,
-                 const int* d_count, int max_rows, const double* wmask, const uint64_t* wbits, int* seg_cnt,
+                 const int* d_count, int max_rows, const double* wmask, int* seg_cnt,
                  int* seg_ptr, int* seg_src, double* seg_val, int64_t seg_cap, Workspace& ws, const DevState* st,
                  hipStream_t s) {
-  if (!wmask || !wbits) return -1;
+  if (!wmask) return -1;
   const int nbw = std::max(1, ceil_div(max_rows, 4));
   k_slab_count<<<nbw, 256, 0, s>>>(rp, ci, rows, d_count, seg_cnt, st);
   if (exclusive_scan_i32(seg_cnt, seg_ptr, n, ws, s)) return -1;
   if (vdtype == SYMNMF_F64)
-    k_slab_fill_rows<double><<<ceil_div(n, 256), 256, 0, s>>>(rp, ci, (const double*)val, n, wmask, wbits, seg_cnt,
-                                                             seg_ptr, seg_src, seg_val, seg_cap, st);
+    k_slab_scatter<double><<<nbw, 256, 0, s>>>(rp, ci, (const double*)val, rows, d_count, wmask, seg_cnt, seg_ptr,
+                                               seg_src, seg_val, seg_cap, st);
   else
-    k_slab_fill_rows<float><<<ceil_div(n, 256), 256, 0, s>>>(rp, ci, (const float*)val, n, wmask, wbits, seg_cnt,
-                                                            seg_ptr, seg_src, seg_val, seg_cap, st);
+    k_slab_scatter<float><<<nbw, 256, 0, s>>>(rp, ci, (const float*)val, rows, d_count, wmask, seg_cnt, seg_ptr,
+                                              seg_src, seg_val, seg_cap, st);
+  k_slab_order<<<ceil_div(n, 256), 256, 0, s>>>(seg_ptr, n, seg_cap, seg_src, seg_val, st);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }

@@ -247,20 +247,18 @@ struct SampleBuffers {
   double* theta = nullptr;     // deterministic leverage mass
 };
 // rows/weights: capacity >= s; the number of rows lands in info[2].
-// wmask (n doubles, may be nullptr): each row's weight, 0 off the sample;
-// wbits (ceil(n / 64) words, may be nullptr): bit i % 64 of word i / 64 set
-// iff row i is in the sample.
+// wmask (n doubles, may be nullptr): each row's weight, 0 off the sample.
 int hybrid_sample(const double* lev, int n, int k, int64_t s_total, double tau, uint64_t seed, uint32_t half_iter,
                   SampleBuffers& sb, int* rows, double* weights, int64_t cap, Workspace& ws, const DevState* st,
-                  hipStream_t s, double* wmask = nullptr, uint64_t* wbits = nullptr);
+                  hipStream_t s, double* wmask = nullptr);
 
-// Sampled slab of X S^T S: segment j lists (r, X[j][r] w_r) for the stored
-// entries of row j whose column r is in the sample (w: the sample's weight of
-// every row, 0 off it; wbits: the sample as one bit per row), in column order.  X is symmetric, so these are the
-// entries of the sampled rows.  seg_cnt (n ints) must be zero on entry and is
-// zero again on exit; seg_ptr has n + 1 entries.
+// Sampled slab of X S^T S: segment j lists (r, X[r][j] w_r) for the stored
+// entries of the sampled rows r that have column j (w: the sample's weight
+// of every row, 0 off it), in column order; X is symmetric, so these are the
+// entries of row j whose column is in the sample.  seg_cnt (n ints) must be
+// zero on entry and is zero again on exit; seg_ptr has n + 1 entries.
 int sampled_slab(const int* rp, const int* ci, const void* val, int vdtype, int n, const int* rows,
-                 const int* d_count, int max_rows, const double* wmask, const uint64_t* wbits, int* seg_cnt,
+                 const int* d_count, int max_rows, const double* wmask, int* seg_cnt,
                  int* seg_ptr, int* seg_src, double* seg_val, int64_t seg_cap, Workspace& ws, const DevState* st,
                  hipStream_t s);
 

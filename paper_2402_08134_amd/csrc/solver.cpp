@@ -244,7 +244,6 @@ struct symnmf_ctx {
   double* weights = nullptr;
   int64_t max_sel = 0;
   double* wmask = nullptr;  // LvS: weight of every row in the current sample, 0 off it
-  uint64_t* wbits = nullptr;  // LvS: the current sample, one bit per row
   int* seg_cnt = nullptr;
   int* seg_ptr = nullptr;
   int* seg_src = nullptr;
@@ -289,7 +288,7 @@ struct symnmf_ctx {
     else (void)hipDeviceSynchronize();
     void* ptrs[] = {Xb_owned, W, H, Y, Yk, Yhat, P, Bt, BtW, BtH, part, dpart, M_W, M_H, Gi_W, Gi_H, Gi_S, G_W, G_H, Gh_W, Gh_H, Gh_S, d_scal, rowsum, dstate, hist, d_fail,
                     ws.base, Q, Q1, U, Uf, YQ, Tm, QT, Vw, lam, Rl, Rlinv, Z, sb.w, sb.prefix, sb.counts, sb.flags,
-                    sb.info, sb.theta, rows, weights, wmask, wbits, seg_cnt, seg_ptr, seg_src, seg_val, lev, R, Rinv};
+                    sb.info, sb.theta, rows, weights, wmask, seg_cnt, seg_ptr, seg_src, seg_val, lev, R, Rinv};
     for (void* p : ptrs) dfree(p);
     pinned_pool().put(hbuf);
     for (auto& t : ev_pending) {
@@ -562,12 +561,12 @@ struct symnmf_ctx {
       LCHK(chol_inverse(Gs, k, R, Rinv, &dstate->flags, SYMNMF_FLAG_LEV_SHIFT, d_fail, st));
       LCHK(leverage_scores(Src, fdtype, n, k, Rinv, lev, gate_, st));
       LCHK(hybrid_sample(lev, n, k, s, tau, seed, (uint32_t)half_iter, sb, rows, weights, max_sel, ws, gate_, st,
-                         wmask, wbits));
+                         wmask));
       ws.reset();
       LCHK(gram(Src, fdtype, k, k, Src, fdtype, k, k, n, rows, weights, sb.info + 2, (int)max_sel, ws, nullptr, Gh_S,
                 kp, alpha, gate_, st, Gi_S));
       ws.reset();
-      LCHK(sampled_slab(rp, ci, Xv, xdtype, n, rows, sb.info + 2, (int)max_sel, wmask, wbits, seg_cnt, seg_ptr,
+      LCHK(sampled_slab(rp, ci, Xv, xdtype, n, rows, sb.info + 2, (int)max_sel, wmask, seg_cnt, seg_ptr,
                         seg_src, seg_val, seg_cap, ws, gate_, st));
       a.seg_ptr = seg_ptr;
       a.seg_src = seg_src;
@@ -1275,7 +1274,6 @@ int symnmf_create(symnmf_ctx** out, const symnmf_matrix* X, int32_t k, double al
       c->rows = dalloc<int>(c->max_sel);
       c->weights = dalloc<double>(c->max_sel);
       c->wmask = dalloc<double>(n);
-      c->wbits = dalloc<uint64_t>((size_t)(n + 63) / 64);
       c->seg_cnt = dalloc<int>(n);
       c->seg_ptr = dalloc<int>((size_t)n + 1);
       c->seg_src = dalloc<int>(c->seg_cap);

@@ -73,6 +73,20 @@ def test_leverage_parity(k):
     assert abs(lg.sum() - k) <= 1e-9 * k
 
 
+@pytest.mark.parametrize("n,k,s", [(20000, 16, 3000), (40003, 64, 4000)])
+def test_lvs_bitwise_reproducible(n, k, s):
+    # the sampled slab's entries land in their segments by atomics and are
+    # then put in column order: two runs give the same bits (k = 64 and
+    # n >= 32768: the blocked sampled update)
+    X = _sbm(n, 16, 24.0, seed=9)
+    out = []
+    for _ in range(2):
+        ctx = P.symnmf_create(csr_dev(X), k, 0.0, s, 5)
+        P.symnmf_iterate(ctx, 3)
+        out.append((factor(ctx, P.H), factor(ctx, P.W)))
+    assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][1], out[1][1])
+
+
 @pytest.mark.parametrize("tau", [-1.0, 0.3e-3, 0.0])
 def test_sampler_bitwise(tau):
     n, k, s = 20000, 16, 2000
