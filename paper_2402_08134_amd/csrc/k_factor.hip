@@ -53,8 +53,12 @@ __global__ __launch_bounds__(256) void k_gram(const TA* __restrict__ A, int64_t 
   __shared__ double Bs[RB][CM + 1];
   const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
   const int nrows = rows ? *d_count : n;
-  const int r0 = blockIdx.x * rows_per_block;
-  const int r1 = min(nrows, r0 + rows_per_block);
+  // selected rows: the device-side count (about half the capacity the grid
+  // is sized for) spread over all the blocks, 16-row chunks (n = 2^20,
+  // s = 8192: two chunks a block instead of five in 96 of 256 blocks)
+  const int rpb = rows ? 16 * ((nrows + 16 * (int)gridDim.x - 1) / (16 * (int)gridDim.x)) : rows_per_block;
+  const int r0 = blockIdx.x * rpb;
+  const int r1 = min(nrows, r0 + rpb);
   double acc[T][T];
 #pragma unroll
   for (int i = 0; i < T; ++i)
