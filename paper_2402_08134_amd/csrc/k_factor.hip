@@ -790,14 +790,27 @@ __device__ T block_exclusive_scan(T v, T* wsum, T& total) {
   return off + x - v;
 }
 
+// The scans' input: an array, or the sampler's selection flag of each row
+// (deterministic, or drawn at least once) formed on the fly.
 template <typename T>
-__global__ __launch_bounds__(256) void k_scan_blocks(const T* __restrict__ in, int n, T* __restrict__ bsum) {
+struct ScanArray {
+  const T* p;
+  __device__ T operator()(int i) const { return p[i]; }
+};
+struct ScanSelected {
+  const int* det;
+  const int* counts;
+  __device__ int operator()(int i) const { return (det[i] || counts[i] > 0) ? 1 : 0; }
+};
+
+template <typename T, typename L>
+__global__ __launch_bounds__(256) void k_scan_blocks(L in, int n, T* __restrict__ bsum) {
   __shared__ T ws[4];
   const int base = blockIdx.x * 1024 + threadIdx.x * 4;
   T s = 0;
 #pragma unroll
   for (int u = 0; u < 4; ++u)
-    if (base + u < n) s += in[base + u];
+    if (base + u < n) s += in(base + u);
   T tot;
   block_exclusive_scan<T>(s, ws, tot);
   if (threadIdx.x == 0) bsum[blockIdx.x] = tot;
@@ -806,9 +819,9 @@ __global__ __launch_bounds__(256) void k_scan_blocks(const T* __restrict__ in, i
 // Each block's offset is the sum of the block totals before it, read by the
 // block itself (integers: exact in any order; at most a few thousand totals,
 // cache-resident), so the scan takes two launches, not three.
-template <typename T, bool INCLUSIVE>
-__global__ __launch_bounds__(256) void k_scan_apply(const T* __restrict__ in, int n, const T* __restrict__ bsum,
-                                                    T* __restrict__ out, T* __restrict__ grand) {
+template <typename T, bool INCLUSIVE, typename L>
+__global__ __launch_bounds__(256) void k_scan_apply(L in, int n, const T* __restrict__ bsum, T* __restrict__ out,
+                                                    T* __restrict__ grand) {
   __shared__ T ws[4];
   T pre = 0;
   for (int b = threadIdx.x; b < (int)blockIdx.x; b += 256) pre += bsum[b];
@@ -819,7 +832,7 @@ __global__ __launch_bounds__(256) void k_scan_apply(const T* __restrict__ in, in
   T s = 0;
 #pragma unroll
   for (int u = 0; u < 4; ++u) {
-    v[u] = (base + u < n) ? in[base + u] : (T)0;
+    v[u] = (base + u < n) ? in(base + u) : (T)0;
     s += v[u];
   }
   T tot;
@@ -1026,8 +1039,17 @@ int exclusive_scan_i32(const int* in, int* out, int n, Workspace& ws, hipStream_
   const int nb = std::max(1, ceil_div(n, 1024));
   int* bsum = ws.i32(nb);
   if (!bsum) return -1;
-  k_scan_blocks<int><<<nb, 256, 0, s>>>(in, n, bsum);
-  k_scan_apply<int, false><<<nb, 256, 0, s>>>(in, n, bsum, out, out + n);
+  k_scan_blocks<int><<<nb, 256, 0, s>>>(ScanArray<int>{in}, n, bsum);
+  k_scan_apply<int, false><<<nb, 256, 0, s>>>(ScanArray<int>{in}, n, bsum, out, out + n);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int exclusive_scan_selected(const int* det, const int* counts, int* out, int n, Workspace& ws, hipStream_t s) {
+  const int nb = std::max(1, ceil_div(n, 1024));
+  int* bsum = ws.i32(nb);
+  if (!bsum) return -1;
+  k_scan_blocks<int><<<nb, 256, 0, s>>>(ScanSelected{det, counts}, n, bsum);
+  k_scan_apply<int, false><<<nb, 256, 0, s>>>(ScanSelected{det, counts}, n, bsum, out, out + n);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
@@ -1035,7 +1057,7 @@ int inclusive_scan_u64(const uint64_t* in, uint64_t* out, int n, Workspace& ws, 
   const int nb = std::max(1, ceil_div(n, 1024));
   uint64_t* bsum = ws.u64(nb);
   if (!bsum) return -1;
-  k_scan_blocks<uint64_t><<<nb, 256, 0, s>>>(in, n, bsum);
-  k_scan_apply<uint64_t, true><<<nb, 256, 0, s>>>(in, n, bsum, out, (uint64_t*)nullptr);
+  k_scan_blocks<uint64_t><<<nb, 256, 0, s>>>(ScanArray<uint64_t>{in}, n, bsum);
+  k_scan_apply<uint64_t, true><<<nb, 256, 0, s>>>(ScanArray<uint64_t>{in}, n, bsum, out, (uint64_t*)nullptr);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }

@@ -158,42 +158,55 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KP == 64 ? 
   }
 }
 
-__global__ void k_sample_reset(int* info, double* theta) {
+// The block partials of the deterministic rows' leverage mass (summed in the
+// order of a fixed-order partial sum: 8 loads in flight per thread) and their
+// count; info[1] is cleared for a sample without draws.
+__global__ __launch_bounds__(256) void k_sample_totals(const double* __restrict__ tpart,
+                                                       const int* __restrict__ cpart, int nb,
+                                                       double* __restrict__ theta, int* __restrict__ info) {
+  __shared__ double sc[8];
+  double v = 0.0;
+  int c = 0;
+  int i = threadIdx.x;
+  for (; i + 7 * 256 < nb; i += 8 * 256) {
+    double u[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) u[q] = tpart[i + q * 256];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) v += u[q];
+  }
+  for (; i < nb; i += 256) v += tpart[i];
+  for (int j = threadIdx.x; j < nb; j += 256) c += cpart[j];
+  const double t = block_sum(v, sc);
+  const double ct = block_sum((double)c, sc);   // an integer count, exact in FP64
   if (threadIdx.x == 0) {
-    info[0] = 0;
+    theta[0] = t;
+    info[0] = (int)ct;
     info[1] = 0;
-    info[2] = 0;
-    info[3] = 0;
-    theta[0] = 0.0;
   }
 }
 
 __global__ __launch_bounds__(256) void k_quantize(const double* __restrict__ lev, int n, int k, double tau,
                                                   uint64_t* __restrict__ w, int* __restrict__ det,
-                                                  int* __restrict__ info, double* __restrict__ tpart,
+                                                  double* __restrict__ tpart, int* __restrict__ cpart,
                                                   const DevState* __restrict__ st) {
   if (stopped(st)) return;
   __shared__ double sc[8];
-  __shared__ int cnt;
-  if (threadIdx.x == 0) cnt = 0;
-  __syncthreads();
   const int i = blockIdx.x * 256 + threadIdx.x;
   double th = 0.0;
+  bool d = false;
   if (i < n) {
     const double l = lev[i];
-    const bool d = (l / (double)k) >= tau;
+    d = (l / (double)k) >= tau;
     det[i] = d ? 1 : 0;
     w[i] = d ? 0ull : (uint64_t)(l * 1099511627776.0);  // floor(l * 2^40), l >= 0
-    if (d) {
-      th = l;
-      atomicAdd(&cnt, 1);
-    }
+    if (d) th = l;
   }
+  const int cnt = __syncthreads_count(d);
   const double t = block_sum(th, sc);
-  __syncthreads();
   if (threadIdx.x == 0) {
     tpart[blockIdx.x] = t;
-    if (cnt) atomicAdd(&info[0], cnt);
+    cpart[blockIdx.x] = cnt;
   }
 }
 
@@ -217,16 +230,9 @@ __global__ __launch_bounds__(256) void k_draw(const uint64_t* __restrict__ prefi
   atomicAdd(&counts[lo], 1);
 }
 
-__global__ __launch_bounds__(256) void k_select(const int* __restrict__ det, const int* __restrict__ counts, int n,
-                                                int* __restrict__ sel, const DevState* __restrict__ st) {
-  if (stopped(st)) return;
-  const int i = blockIdx.x * 256 + threadIdx.x;
-  if (i < n) sel[i] = (det[i] || counts[i] > 0) ? 1 : 0;
-}
-
 __global__ __launch_bounds__(256) void k_emit(const int* __restrict__ det, int* __restrict__ counts,
                                               const uint64_t* __restrict__ w, const uint64_t* __restrict__ prefix,
-                                              const int* __restrict__ sel, const int* __restrict__ pos, int n,
+                                              const int* __restrict__ pos, int n,
                                               int* __restrict__ rows, double* __restrict__ weights, int64_t cap,
                                               int* __restrict__ info, double* __restrict__ wmask,
                                               const DevState* __restrict__ st) {
@@ -238,7 +244,7 @@ __global__ __launch_bounds__(256) void k_emit(const int* __restrict__ det, int* 
   }
   double wt = 0.0;
   if (i < n) {
-    if (sel[i] && pos[i] < cap) {
+    if ((det[i] || counts[i] > 0) && pos[i] < cap) {
       const int p = pos[i];
       rows[p] = i;
       if (det[i]) {
@@ -496,17 +502,15 @@ int hybrid_sample(const double* lev, int n, int k, int64_t s_total, double tau, 
                   hipStream_t s, double* wmask) {
   const int nb = ceil_div(n, 256);
   double* tpart = ws.dbl(nb);
-  int* sel = ws.i32(n);
+  int* cpart = ws.i32(nb);
   int* pos = ws.i32((size_t)n + 1);
-  if (!tpart || !sel || !pos) return -1;
-  k_sample_reset<<<1, 64, 0, s>>>(sb.info, sb.theta);
-  k_quantize<<<nb, 256, 0, s>>>(lev, n, k, tau, sb.w, sb.flags, sb.info, tpart, st);
-  sum_partials(tpart, nb, sb.theta, s);
+  if (!tpart || !cpart || !pos) return -1;
+  k_quantize<<<nb, 256, 0, s>>>(lev, n, k, tau, sb.w, sb.flags, tpart, cpart, st);
+  k_sample_totals<<<1, 256, 0, s>>>(tpart, cpart, nb, sb.theta, sb.info);
   if (inclusive_scan_u64(sb.w, sb.prefix, n, ws, s)) return -1;
   if (s_total > 0) k_draw<<<ceil_div(s_total, 256), 256, 0, s>>>(sb.prefix, n, s_total, seed, half_iter, sb.counts, sb.info, st);
-  k_select<<<nb, 256, 0, s>>>(sb.flags, sb.counts, n, sel, st);
-  if (exclusive_scan_i32(sel, pos, n, ws, s)) return -1;
-  k_emit<<<nb, 256, 0, s>>>(sb.flags, sb.counts, sb.w, sb.prefix, sel, pos, n, rows, weights, cap, sb.info, wmask, st);
+  if (exclusive_scan_selected(sb.flags, sb.counts, pos, n, ws, s)) return -1;
+  k_emit<<<nb, 256, 0, s>>>(sb.flags, sb.counts, sb.w, sb.prefix, pos, n, rows, weights, cap, sb.info, wmask, st);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
