@@ -170,13 +170,22 @@ __global__ __launch_bounds__(256) void k_sample_totals(const double* __restrict_
   int i = threadIdx.x;
   for (; i + 7 * 256 < nb; i += 8 * 256) {
     double u[8];
+    int cu[8];
 #pragma unroll
-    for (int q = 0; q < 8; ++q) u[q] = tpart[i + q * 256];
+    for (int q = 0; q < 8; ++q) {
+      u[q] = tpart[i + q * 256];
+      cu[q] = cpart[i + q * 256];
+    }
 #pragma unroll
-    for (int q = 0; q < 8; ++q) v += u[q];
+    for (int q = 0; q < 8; ++q) {
+      v += u[q];
+      c += cu[q];
+    }
   }
-  for (; i < nb; i += 256) v += tpart[i];
-  for (int j = threadIdx.x; j < nb; j += 256) c += cpart[j];
+  for (; i < nb; i += 256) {
+    v += tpart[i];
+    c += cpart[i];
+  }
   const double t = block_sum(v, sc);
   const double ct = block_sum((double)c, sc);   // an integer count, exact in FP64
   if (threadIdx.x == 0) {
