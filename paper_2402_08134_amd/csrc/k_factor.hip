@@ -737,7 +737,20 @@ __global__ __launch_bounds__(256) void k_col_argmax(const double* __restrict__ U
   const int j = blockIdx.x;
   double best = -1.0;
   int bidx = 0x7fffffff;
-  for (int i = threadIdx.x; i < n; i += 256) {
+  int i = threadIdx.x;
+  for (; i + 7 * 256 < n; i += 8 * 256) {   // 8 loads in flight, compared in row order
+    double a[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) a[u] = fabs(U[(int64_t)(i + 256 * u) * l + j]);
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      if (a[u] > best) {
+        best = a[u];
+        bidx = i + 256 * u;
+      }
+    }
+  }
+  for (; i < n; i += 256) {
     const double a = fabs(U[(int64_t)i * l + j]);
     if (a > best) {
       best = a;

@@ -32,7 +32,19 @@ __global__ __launch_bounds__(256) void k_ws_colparts(const double* __restrict__ 
   const int j = threadIdx.x & 63, r = threadIdx.x >> 6;
   double p = 0.0, q = 0.0;
   if (j < k) {
-    for (int i = blockIdx.x * 4 + r; i < n; i += gridDim.x * 4) {
+    const int step = gridDim.x * 4;
+    int i = blockIdx.x * 4 + r;
+    for (; i + 7 * step < n; i += 8 * step) {   // 8 loads in flight, added in row order
+      double u[8];
+#pragma unroll
+      for (int t = 0; t < 8; ++t) u[t] = U[(int64_t)(i + t * step) * l + j];
+#pragma unroll
+      for (int t = 0; t < 8; ++t) {
+        p += u[t] > 0.0 ? u[t] * u[t] : 0.0;
+        q += u[t] < 0.0 ? u[t] * u[t] : 0.0;
+      }
+    }
+    for (; i < n; i += step) {
       const double u = U[(int64_t)i * l + j];
       p += u > 0.0 ? u * u : 0.0;
       q += u < 0.0 ? u * u : 0.0;
@@ -78,30 +90,46 @@ __global__ __launch_bounds__(256) void k_ws_info(const double* __restrict__ part
   }
 }
 
+// 16 lanes per row (columns li, li + 16, ... of the k <= 64), so the row's
+// reads and its 6 k feature writes are spread over the lanes; the row's norm
+// and max are combined across the 16 lanes in a fixed order.
 __global__ __launch_bounds__(256) void k_ws_features(const double* __restrict__ U, int n, int l, int k,
                                                      const double* __restrict__ info,
                                                      const double* __restrict__ rowsum, float* __restrict__ F) {
-  const int i = blockIdx.x * 256 + threadIdx.x;
-  if (i >= n) return;
+  const int i = blockIdx.x * 16 + (threadIdx.x >> 4), li = threadIdx.x & 15;
+  const bool live = i < n;   // the whole 16-lane group alike
   const double sn = sqrt((double)n);
-  const double* u = U + (int64_t)i * l;
+  const double* u = U + (int64_t)(live ? i : 0) * l;
+  double c[4];
   double r2 = 0.0, m = -INFINITY;
-  for (int j = 0; j < k; ++j) {
-    const double c = sn * u[j];
-    r2 += c * c;
-    m = fmax(m, info[j] * c);
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    const int j = li + 16 * t;
+    c[t] = live && j < k ? sn * u[j] : 0.0;
+    r2 += c[t] * c[t];
+    if (j < k) m = fmax(m, info[j] * c[t]);
   }
+#pragma unroll
+  for (int o = 1; o < 16; o <<= 1) {
+    r2 += __shfl_xor(r2, o, 16);
+    m = fmax(m, __shfl_xor(m, o, 16));
+  }
+  if (!live) return;
   const double r = sqrt(r2);
   const double ld = log(fmax(rowsum[i] / info[2 * k], 1e-6));
   float* f = F + (int64_t)i * k * 6;
-  for (int j = 0; j < k; ++j) {
-    const double a = info[j] * sn * u[j];
-    f[6 * j + 0] = (float)a;
-    f[6 * j + 1] = (float)r;
-    f[6 * j + 2] = (float)m;
-    f[6 * j + 3] = (float)(a - m);
-    f[6 * j + 4] = (float)info[k + j];
-    f[6 * j + 5] = (float)ld;
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    const int j = li + 16 * t;
+    if (j < k) {
+      const double a = info[j] * c[t];
+      f[6 * j + 0] = (float)a;
+      f[6 * j + 1] = (float)r;
+      f[6 * j + 2] = (float)m;
+      f[6 * j + 3] = (float)(a - m);
+      f[6 * j + 4] = (float)info[k + j];
+      f[6 * j + 5] = (float)ld;
+    }
   }
 }
 
@@ -386,7 +414,7 @@ int warm_features(const double* U, int n, int l, int k, const double* lam, const
   if (!part) return -1;
   k_ws_colparts<<<nb, 256, 0, s>>>(U, n, l, k, part);
   k_ws_info<<<1, 256, 0, s>>>(part, nb, k, lam, d_total, n, info);
-  k_ws_features<<<ceil_div(n, 256), 256, 0, s>>>(U, n, l, k, info, rowsum, F);
+  k_ws_features<<<ceil_div(n, 16), 256, 0, s>>>(U, n, l, k, info, rowsum, F);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
