@@ -214,6 +214,103 @@ __global__ __launch_bounds__(256) void k_mlp_forward(const float* __restrict__ P
   }
 }
 
+// Inference of the 6-64-64-64-1 network on the FP32 matrix cores
+// (v_mfma_f32_16x16x4f32), 16 entries a wave per pass.  Every layer is taken
+// as outputs x entries, D = W^T X^T: lane (e, g) = (lane % 16, lane / 16)
+// ends with register v of output tile T holding output 16 T + 4 g + v of
+// entry e, which is, as it stands, the next layer's B operand of K step
+// (T, v) for the K index 16 T + 4 g + v; the A operands are the weights
+// W[i][16 T_out + e] for that index, staged in LDS once per block in lane
+// order.  The biases start the accumulators; the last layer is a dot
+// product of each lane's 16 outputs, summed over the four lane groups.
+// Sums are taken in another order than the one-entry-per-thread forward
+// (FP32 rounding differences only).
+template <int D, int H>
+__global__ __launch_bounds__(256) void k_mlp_infer(const float* __restrict__ P, const float* __restrict__ F,
+                                                   int64_t rows, float* __restrict__ Y) {
+  static_assert(D <= 8 && H == 64, "two K steps for the inputs, four 16-wide output tiles");
+  using Lay = Layout<D, H>;
+  __shared__ float w1s[4 * 2 * 64];    // [T_out][s][lane]
+  __shared__ float w2s[4 * 16 * 64];   // [T_out][T][v][lane]
+  __shared__ float w3s[4 * 16 * 64];
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6, ln = lane & 15, g = lane >> 4;
+  for (int x = tid; x < 4 * 2 * 64; x += 256) {
+    const int L = x & 63, s = (x >> 6) & 1, to = x >> 7;
+    const int i = 4 * s + (L >> 4), o = 16 * to + (L & 15);
+    w1s[x] = i < D ? P[Lay::W1 + i * H + o] : 0.f;
+  }
+  for (int x = tid; x < 4 * 16 * 64; x += 256) {
+    const int L = x & 63, st = (x >> 6) & 15, to = x >> 10;
+    const int i = 16 * (st >> 2) + 4 * (L >> 4) + (st & 3), o = 16 * to + (L & 15);
+    w2s[x] = P[Lay::W2 + i * H + o];
+    w3s[x] = P[Lay::W3 + i * H + o];
+  }
+  // this lane's biases and last-layer weights (outputs 16 T + 4 g + v)
+  float b1[4][4], b2[4][4], b3[4][4], w4[4][4];
+#pragma unroll
+  for (int T = 0; T < 4; ++T)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int o = 16 * T + 4 * g + v;
+      b1[T][v] = P[Lay::B1 + o];
+      b2[T][v] = P[Lay::B2 + o];
+      b3[T][v] = P[Lay::B3 + o];
+      w4[T][v] = P[Lay::W4 + o];
+    }
+  const float b4 = P[Lay::B4];
+  __syncthreads();
+  const int64_t groups = (rows + 15) / 16;
+  for (int64_t grp = (int64_t)blockIdx.x * 4 + wid; grp < groups; grp += (int64_t)gridDim.x * 4) {
+    const int64_t e = 16 * grp + ln;
+    const bool valid = e < rows;
+    float xb[2];
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+      const int i = 4 * s + g;
+      xb[s] = valid && i < D ? F[e * D + i] : 0.f;
+    }
+    floatx4 a[4], c[4];
+#pragma unroll
+    for (int T = 0; T < 4; ++T) {
+      c[T] = floatx4{b1[T][0], b1[T][1], b1[T][2], b1[T][3]};
+#pragma unroll
+      for (int s = 0; s < 2; ++s)
+        c[T] = __builtin_amdgcn_mfma_f32_16x16x4f32(w1s[(T * 2 + s) * 64 + lane], xb[s], c[T], 0, 0, 0);
+    }
+#pragma unroll
+    for (int T = 0; T < 4; ++T)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) a[T][v] = fmaxf(c[T][v], 0.f);
+#pragma unroll
+    for (int layer = 0; layer < 2; ++layer) {
+      const float* ws = layer == 0 ? w2s : w3s;
+#pragma unroll
+      for (int T = 0; T < 4; ++T)
+        c[T] = layer == 0 ? floatx4{b2[T][0], b2[T][1], b2[T][2], b2[T][3]}
+                          : floatx4{b3[T][0], b3[T][1], b3[T][2], b3[T][3]};
+#pragma unroll
+      for (int Tk = 0; Tk < 4; ++Tk)
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+#pragma unroll
+          for (int T = 0; T < 4; ++T)
+            c[T] = __builtin_amdgcn_mfma_f32_16x16x4f32(ws[((T * 4 + Tk) * 4 + v) * 64 + lane], a[Tk][v], c[T], 0, 0, 0);
+#pragma unroll
+      for (int T = 0; T < 4; ++T)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) a[T][v] = fmaxf(c[T][v], 0.f);
+    }
+    float z = 0.f;
+#pragma unroll
+    for (int T = 0; T < 4; ++T)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) z = fmaf(a[T][v], w4[T][v], z);
+    z += __shfl_xor(z, 16);
+    z += __shfl_xor(z, 32);
+    if (g == 0 && valid) Y[e] = softplus_f(z + b4);
+  }
+}
+
 // dz_in[e][i] = (sum_o dz_out[e][o] W[i][o]) * (h_in[e][i] > 0), W (IN x OUT)
 // at offset woff of the parameters.
 template <int IN, int OUT>
@@ -358,8 +455,9 @@ int mlp_init(float* p, uint64_t seed, hipStream_t s) {
 
 int mlp_forward(const float* p, const float* F, int64_t rows, float* Y, hipStream_t s) {
   if (rows <= 0) return 0;
-  k_mlp_forward<MLP_D_IN, MLP_HIDDEN, false><<<nblocks(rows), 256, 0, s>>>(p, F, nullptr, rows, 0.f, Y, nullptr,
-                                                                           nullptr, nullptr, nullptr, nullptr);
+  // two blocks per CU, each staging the weights in LDS once
+  const int nb = (int)std::max<int64_t>(1, std::min<int64_t>(512, (rows + 63) / 64));
+  k_mlp_infer<MLP_D_IN, MLP_HIDDEN><<<nb, 256, 0, s>>>(p, F, rows, Y);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
