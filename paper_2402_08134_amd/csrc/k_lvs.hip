@@ -315,9 +315,15 @@ __global__ __launch_bounds__(256) void k_slab_scatter(const int* __restrict__ rp
 // are read into registers (four per lane), each entry's rank is counted
 // against all the row's keys (broadcast by lane shuffles within the 16-lane
 // row), and every entry is written to its rank: keys are distinct, so the
-// ranks are a permutation.  Longer segments are sorted by one lane in
-// place (insertion sort).
-__global__ __launch_bounds__(256) void k_slab_order(const int* __restrict__ seg_ptr, int n, int64_t seg_cap,
+// ranks are a permutation.  A longer segment (a row adjacent to many
+// sampled rows: hubs of a skewed graph) is written again in order from the
+// row's own stored entries, 16 at a time, each tested against the sample's
+// weights (a ballot gives each hit its place): time in the row's length, not
+// in the square of the segment's.
+template <typename TV>
+__global__ __launch_bounds__(256) void k_slab_order(const int* __restrict__ rp, const int* __restrict__ ci,
+                                                    const TV* __restrict__ val, const double* __restrict__ wmask,
+                                                    const int* __restrict__ seg_ptr, int n, int64_t seg_cap,
                                                     int* __restrict__ seg_src, double* __restrict__ seg_val,
                                                     const DevState* __restrict__ st) {
   if (stopped(st)) return;
@@ -335,6 +341,7 @@ __global__ __launch_bounds__(256) void k_slab_order(const int* __restrict__ seg_
     const int src = have ? __ffsll((unsigned long long)m) - 1 : 0;
     const int b = __shfl(sb, src);
     const int c = have ? __shfl(se, src) - b : 0;
+    const int row = __shfl(jl, src);   // every lane takes part in the shuffles
     if (c <= 64) {
       int key[4];
       double v[4];
@@ -359,18 +366,24 @@ __global__ __launch_bounds__(256) void k_slab_order(const int* __restrict__ seg_
           seg_val[b + rank[u]] = v[u];
         }
       }
-    } else if (li == 0) {
-      for (int p = b + 1; p < b + c; ++p) {
-        const int kk = seg_src[p];
-        const double vv = seg_val[p];
-        int q = p - 1;
-        while (q >= b && seg_src[q] > kk) {
-          seg_src[q + 1] = seg_src[q];
-          seg_val[q + 1] = seg_val[q];
-          --q;
+    } else {
+      const int e0 = rp[row], e1 = rp[row + 1];
+      const int sh = lane & 48;
+      int base = b;
+      for (int e = e0 + li; e - li < e1; e += 16) {   // the same trips for the row's 16 lanes
+        const bool ok = e < e1;
+        const int r = ci[ok ? e : e0];
+        const double w = wmask[r];
+        const bool hit = ok && w != 0.0;
+        const uint64_t mb = (__ballot(hit) >> sh) & 0xFFFFull;
+        if (hit) {
+          const int p = base + __popcll(mb & ((1ull << li) - 1ull));
+          if (p < seg_cap) {
+            seg_src[p] = r;
+            seg_val[p] = (double)val[e] * w;
+          }
         }
-        seg_src[q + 1] = kk;
-        seg_val[q + 1] = vv;
+        base += __popcll(mb);
       }
     }
 #pragma unroll
@@ -537,6 +550,11 @@ int sampled_slab(const int* rp, const int* ci, const void* val, int vdtype, int 
   else
     k_slab_scatter<float><<<nbw, 256, 0, s>>>(rp, ci, (const float*)val, rows, d_count, wmask, seg_cnt, seg_ptr,
                                               seg_src, seg_val, seg_cap, st);
-  k_slab_order<<<ceil_div(n, 256), 256, 0, s>>>(seg_ptr, n, seg_cap, seg_src, seg_val, st);
+  if (vdtype == SYMNMF_F64)
+    k_slab_order<double><<<ceil_div(n, 256), 256, 0, s>>>(rp, ci, (const double*)val, wmask, seg_ptr, n, seg_cap,
+                                                          seg_src, seg_val, st);
+  else
+    k_slab_order<float><<<ceil_div(n, 256), 256, 0, s>>>(rp, ci, (const float*)val, wmask, seg_ptr, n, seg_cap,
+                                                         seg_src, seg_val, st);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }

@@ -194,6 +194,39 @@ def test_long_factor_half_step(case):
     assert e <= (1e-12 if vt == np.float64 else 1e-5)
 
 
+def test_lvs_hub_rows_half_step():
+    # two hub rows adjacent to a third of the graph: with a large sample their
+    # slab segments hold hundreds of entries (the segment order's one-lane
+    # sort past 64 entries, the chunk's held extras summed over hundreds of
+    # rows, and the per-block fallback past the chunk's held rows)
+    n, k, s = 40003, 64, 12000
+    X = _sbm(n, 16, 24.0, seed=21).tolil()
+    rng = np.random.default_rng(5)
+    for hub in (7, 20011):
+        nb = rng.choice(n, n // 3, replace=False)
+        nb = nb[nb != hub]
+        X[hub, nb] = 0.5
+        X[nb, hub] = 0.5
+    X = sp.csr_matrix(X, dtype=np.float32)
+    X.sort_indices()
+    ctx = P.symnmf_create(csr_dev(X), k, 0.0, s, 3)
+    alpha = P.symnmf_get_stats(ctx).alpha
+    H = workloads.random_factor(n, k, seed=8, scale=0.2)
+    W = workloads.random_factor(n, k, seed=9, scale=0.2)
+    P.symnmf_set_factor(ctx, P.H, dev(H))
+    P.symnmf_set_factor(ctx, P.W, dev(W))
+    Hr, Wr = round_to(H, torch.float32), round_to(W, torch.float32)
+    P.symnmf_half_step(ctx, 0, 2)
+    Wg = factor(ctx, P.W)
+    Wo, _ = O.lvs_half_step(_X64(X), Hr, Wr, alpha, s, 1.0 / s, 3, 2)
+    e = rel(Wg, Wo)
+    log(f"lvs hub rows n={n} k={k} s={s}: W rel {e:.2e}")
+    assert e <= 1e-5
+    P.symnmf_set_factor(ctx, P.W, dev(W))
+    P.symnmf_half_step(ctx, 0, 2)
+    assert np.array_equal(factor(ctx, P.W), Wg)   # the same bits again
+
+
 @pytest.mark.parametrize("compute", ["f32", "bf16"])
 def test_long_factor_plain_run(compute):
     # k = 64 on a long factor (n >= 32768): the HALS sweep runs blocked (16
