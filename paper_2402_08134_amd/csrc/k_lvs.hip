@@ -219,6 +219,8 @@ __global__ __launch_bounds__(256) void k_quantize(const double* __restrict__ lev
   }
 }
 
+constexpr int DRAW_COARSE = 4096;   // pieces of 1024 rows the draw's LDS table covers (32 KB)
+
 __global__ __launch_bounds__(256) void k_draw(const uint64_t* __restrict__ prefix, int n, int64_t s_total,
                                               uint64_t seed, uint32_t half_iter, int* __restrict__ counts,
                                               int* __restrict__ info, const DevState* __restrict__ st) {
@@ -226,12 +228,31 @@ __global__ __launch_bounds__(256) void k_draw(const uint64_t* __restrict__ prefi
   const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
   const int64_t s_R = s_total - (int64_t)info[0];
   if (j == 0) info[1] = (int)(s_R > 0 ? s_R : 0);
+  // the prefix at the end of every 1024 rows, in LDS, narrows each search to
+  // one 1024-row piece (half of the dependent reads from memory)
+  __shared__ uint64_t coarse[DRAW_COARSE];
+  const int nbk = (n + 1023) / 1024;
+  const bool two_level = nbk <= DRAW_COARSE;
+  if (two_level) {
+    for (int b = threadIdx.x; b < nbk; b += 256) coarse[b] = prefix[min(1024 * b + 1023, n - 1)];
+    __syncthreads();
+  }
   if (j >= s_R) return;
   const uint64_t WR = prefix[n - 1];
   if (WR == 0) return;
   const uint64_t v = philox_value(seed, (uint64_t)j, half_iter, TAG_SAMPLE);
   const uint64_t r = __umul64hi(v, WR);
-  int lo = 0, hi = n - 1;  // smallest i with prefix[i] > r (exists: prefix[n-1] = WR > r)
+  // smallest i with prefix[i] > r (exists: prefix[n-1] = WR > r)
+  int lo = 0, hi = n - 1;
+  if (two_level) {
+    int bl = 0, bh = nbk - 1;   // smallest piece whose last prefix exceeds r
+    while (bl < bh) {
+      const int mid = (bl + bh) >> 1;
+      if (coarse[mid] > r) bh = mid; else bl = mid + 1;
+    }
+    lo = 1024 * bl;
+    hi = min(1024 * bl + 1023, n - 1);
+  }
   while (lo < hi) {
     const int mid = (lo + hi) >> 1;
     if (prefix[mid] > r) hi = mid; else lo = mid + 1;
