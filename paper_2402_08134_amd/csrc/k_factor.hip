@@ -1066,6 +1066,12 @@ int exclusive_scan_selected(const int* det, const int* counts, int* out, int n, 
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
+int inclusive_scan_u64_from_sums(const uint64_t* in, uint64_t* out, int n, const uint64_t* bsum, hipStream_t s) {
+  const int nb = std::max(1, ceil_div(n, 1024));
+  k_scan_apply<uint64_t, true><<<nb, 256, 0, s>>>(ScanArray<uint64_t>{in}, n, bsum, out, (uint64_t*)nullptr);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
 int inclusive_scan_u64(const uint64_t* in, uint64_t* out, int n, Workspace& ws, hipStream_t s) {
   const int nb = std::max(1, ceil_div(n, 1024));
   uint64_t* bsum = ws.u64(nb);

@@ -195,27 +195,48 @@ __global__ __launch_bounds__(256) void k_sample_totals(const double* __restrict_
   }
 }
 
+// 1024 rows a block, four a thread in the order of the device scans, so the
+// block's sum of the quantised weights is the prefix scan's block total
+// (wsum) and that scan takes one launch.
 __global__ __launch_bounds__(256) void k_quantize(const double* __restrict__ lev, int n, int k, double tau,
                                                   uint64_t* __restrict__ w, int* __restrict__ det,
                                                   double* __restrict__ tpart, int* __restrict__ cpart,
-                                                  const DevState* __restrict__ st) {
+                                                  uint64_t* __restrict__ wsum, const DevState* __restrict__ st) {
   if (stopped(st)) return;
   __shared__ double sc[8];
-  const int i = blockIdx.x * 256 + threadIdx.x;
+  __shared__ unsigned long long su[4];
+  const int base = blockIdx.x * 1024 + threadIdx.x * 4;
   double th = 0.0;
-  bool d = false;
-  if (i < n) {
-    const double l = lev[i];
-    d = (l / (double)k) >= tau;
-    det[i] = d ? 1 : 0;
-    w[i] = d ? 0ull : (uint64_t)(l * 1099511627776.0);  // floor(l * 2^40), l >= 0
-    if (d) th = l;
+  int cnt = 0;
+  unsigned long long ws = 0;
+  double lv[4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) lv[u] = lev[min(base + u, n - 1)];   // the four loads in flight together
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int i = base + u;
+    if (i < n) {
+      const double l = lv[u];
+      const bool d = (l / (double)k) >= tau;
+      const uint64_t q = d ? 0ull : (uint64_t)(l * 1099511627776.0);  // floor(l * 2^40), l >= 0
+      det[i] = d ? 1 : 0;
+      w[i] = q;
+      ws += q;
+      if (d) {
+        th += l;
+        ++cnt;
+      }
+    }
   }
-  const int cnt = __syncthreads_count(d);
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) ws += __shfl_xor(ws, o);
+  if ((threadIdx.x & 63) == 0) su[threadIdx.x >> 6] = ws;
   const double t = block_sum(th, sc);
+  const double c = block_sum((double)cnt, sc);   // an integer count, exact in FP64
   if (threadIdx.x == 0) {
     tpart[blockIdx.x] = t;
-    cpart[blockIdx.x] = cnt;
+    cpart[blockIdx.x] = (int)c;
+    wsum[blockIdx.x] = (uint64_t)(su[0] + su[1] + su[2] + su[3]);
   }
 }
 
@@ -544,13 +565,15 @@ int hybrid_sample(const double* lev, int n, int k, int64_t s_total, double tau, 
                   SampleBuffers& sb, int* rows, double* weights, int64_t cap, Workspace& ws, const DevState* st,
                   hipStream_t s, double* wmask) {
   const int nb = ceil_div(n, 256);
-  double* tpart = ws.dbl(nb);
-  int* cpart = ws.i32(nb);
+  const int nq = ceil_div(n, 1024);
+  double* tpart = ws.dbl(nq);
+  int* cpart = ws.i32(nq);
+  uint64_t* wsum = ws.u64(nq);
   int* pos = ws.i32((size_t)n + 1);
-  if (!tpart || !cpart || !pos) return -1;
-  k_quantize<<<nb, 256, 0, s>>>(lev, n, k, tau, sb.w, sb.flags, tpart, cpart, st);
-  k_sample_totals<<<1, 256, 0, s>>>(tpart, cpart, nb, sb.theta, sb.info);
-  if (inclusive_scan_u64(sb.w, sb.prefix, n, ws, s)) return -1;
+  if (!tpart || !cpart || !wsum || !pos) return -1;
+  k_quantize<<<nq, 256, 0, s>>>(lev, n, k, tau, sb.w, sb.flags, tpart, cpart, wsum, st);
+  k_sample_totals<<<1, 256, 0, s>>>(tpart, cpart, nq, sb.theta, sb.info);
+  if (inclusive_scan_u64_from_sums(sb.w, sb.prefix, n, wsum, s)) return -1;
   if (s_total > 0) k_draw<<<ceil_div(s_total, 256), 256, 0, s>>>(sb.prefix, n, s_total, seed, half_iter, sb.counts, sb.info, st);
   if (exclusive_scan_selected(sb.flags, sb.counts, pos, n, ws, s)) return -1;
   k_emit<<<nb, 256, 0, s>>>(sb.flags, sb.counts, sb.w, sb.prefix, pos, n, rows, weights, cap, sb.info, wmask, st);

@@ -233,6 +233,8 @@ int column_sign_fix(double* U, int n, int l, Workspace& ws, hipStream_t s);
 // Scans.
 int exclusive_scan_i32(const int* in, int* out, int n, Workspace& ws, hipStream_t s);  // out has n+1 entries
 int inclusive_scan_u64(const uint64_t* in, uint64_t* out, int n, Workspace& ws, hipStream_t s);
+// the same with the block totals (sums of in over 1024-item blocks) given
+int inclusive_scan_u64_from_sums(const uint64_t* in, uint64_t* out, int n, const uint64_t* bsum, hipStream_t s);
 // exclusive scan of (det[i] || counts[i] > 0) (out has n + 1 entries)
 int exclusive_scan_selected(const int* det, const int* counts, int* out, int n, Workspace& ws, hipStream_t s);
 
