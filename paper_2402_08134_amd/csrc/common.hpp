@@ -104,6 +104,27 @@ __device__ __forceinline__ double row16_sum(double v) {
   return v;
 }
 
+// Exclusive prefix of v over a 256-thread block (4 waves; wsum: 4 entries of
+// LDS); total receives the block's sum in every thread.
+template <typename T>
+__device__ inline T block_exclusive_scan(T v, T* wsum, T& total) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  T x = v;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const T y = __shfl_up(x, o, 64);
+    if (lane >= o) x += y;
+  }
+  if (lane == 63) wsum[w] = x;
+  __syncthreads();
+  T off = 0;
+  for (int i = 0; i < w; ++i) off += wsum[i];
+  total = 0;
+  for (int i = 0; i < 4; ++i) total += wsum[i];
+  __syncthreads();
+  return off + x - v;
+}
+
 // LDS written by some lanes of a wave and read by others: order the two at
 // wavefront scope
 __device__ __forceinline__ void wave_sync() {

@@ -784,24 +784,6 @@ __global__ __launch_bounds__(256) void k_col_scale(double* __restrict__ U, int n
 // Scans: 1024 items per block (4 per thread), block totals scanned by one
 // block, then offsets added.
 // ---------------------------------------------------------------------------
-template <typename T>
-__device__ T block_exclusive_scan(T v, T* wsum, T& total) {
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  T x = v;
-#pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
-    const T y = __shfl_up(x, o, 64);
-    if (lane >= o) x += y;
-  }
-  if (lane == 63) wsum[w] = x;
-  __syncthreads();
-  T off = 0;
-  for (int i = 0; i < w; ++i) off += wsum[i];
-  total = 0;
-  for (int i = 0; i < 4; ++i) total += wsum[i];
-  __syncthreads();
-  return off + x - v;
-}
 
 // The scans' input: an array, or the sampler's selection flag of each row
 // (deterministic, or drawn at least once) formed on the fly.
@@ -1057,12 +1039,9 @@ int exclusive_scan_i32(const int* in, int* out, int n, Workspace& ws, hipStream_
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
-int exclusive_scan_selected(const int* det, const int* counts, int* out, int n, Workspace& ws, hipStream_t s) {
+int selected_block_sums(const int* det, const int* counts, int n, int* bsum, hipStream_t s) {
   const int nb = std::max(1, ceil_div(n, 1024));
-  int* bsum = ws.i32(nb);
-  if (!bsum) return -1;
   k_scan_blocks<int><<<nb, 256, 0, s>>>(ScanSelected{det, counts}, n, bsum);
-  k_scan_apply<int, false><<<nb, 256, 0, s>>>(ScanSelected{det, counts}, n, bsum, out, out + n);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 

@@ -281,34 +281,56 @@ __global__ __launch_bounds__(256) void k_draw(const uint64_t* __restrict__ prefi
   atomicAdd(&counts[lo], 1);
 }
 
-__global__ __launch_bounds__(256) void k_emit(const int* __restrict__ det, int* __restrict__ counts,
-                                              const uint64_t* __restrict__ w, const uint64_t* __restrict__ prefix,
-                                              const int* __restrict__ pos, int n,
-                                              int* __restrict__ rows, double* __restrict__ weights, int64_t cap,
-                                              int* __restrict__ info, double* __restrict__ wmask,
-                                              const DevState* __restrict__ st) {
+// The sample's rows in order: the selected rows (deterministic, or drawn at
+// least once) get their places from an exclusive scan over 1024-row blocks
+// (each block adds the totals of the blocks before it, given in bsum), and
+// each takes its row index and weight at its place; every row's weight (0
+// off the sample) goes to wmask and the draw counts are cleared.
+__global__ __launch_bounds__(256) void k_select_emit(const int* __restrict__ det, int* __restrict__ counts,
+                                                     const uint64_t* __restrict__ w,
+                                                     const uint64_t* __restrict__ prefix,
+                                                     const int* __restrict__ bsum, int n, int* __restrict__ rows,
+                                                     double* __restrict__ weights, int64_t cap,
+                                                     int* __restrict__ info, double* __restrict__ wmask,
+                                                     const DevState* __restrict__ st) {
   if (stopped(st)) return;
-  const int i = blockIdx.x * 256 + threadIdx.x;
-  if (i == 0) {
-    info[2] = (int)min((int64_t)pos[n], cap);
-    info[3] = pos[n];
+  __shared__ int wsi[4];
+  int pre = 0;
+  for (int b = threadIdx.x; b < (int)blockIdx.x; b += 256) pre += bsum[b];
+  int off;
+  block_exclusive_scan<int>(pre, wsi, off);
+  const int base = blockIdx.x * 1024 + threadIdx.x * 4;
+  int dt[4], cu[4], sel[4], s = 0;
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int i = base + u;
+    dt[u] = i < n ? det[i] : 0;
+    cu[u] = i < n ? counts[i] : 0;
+    sel[u] = (dt[u] || cu[u] > 0) ? 1 : 0;
+    s += sel[u];
   }
-  double wt = 0.0;
-  if (i < n) {
-    if ((det[i] || counts[i] > 0) && pos[i] < cap) {
-      const int p = pos[i];
-      rows[p] = i;
-      if (det[i]) {
-        wt = 1.0;
-      } else {
-        const double WR = (double)prefix[n - 1];
-        const double sR = (double)info[1];
-        wt = ((double)counts[i] * WR) / (sR * (double)w[i]);
+  int tot;
+  int run = block_exclusive_scan<int>(s, wsi, tot) + off;
+  if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) {
+    info[2] = (int)min((int64_t)(off + tot), cap);
+    info[3] = off + tot;
+  }
+  const double WR = (double)prefix[n - 1];
+  const double sR = (double)info[1];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int i = base + u;
+    if (i < n) {
+      double wt = 0.0;
+      if (sel[u] && run < cap) {
+        rows[run] = i;
+        wt = dt[u] ? 1.0 : ((double)cu[u] * WR) / (sR * (double)w[i]);
+        weights[run] = wt;
       }
-      weights[p] = wt;
+      if (wmask) wmask[i] = wt;
+      counts[i] = 0;
     }
-    if (wmask) wmask[i] = wt;
-    counts[i] = 0;
+    run += sel[u];
   }
 }
 
@@ -564,19 +586,19 @@ int leverage_scores(const void* F, int fdtype, int n, int k, const double* Rinv,
 int hybrid_sample(const double* lev, int n, int k, int64_t s_total, double tau, uint64_t seed, uint32_t half_iter,
                   SampleBuffers& sb, int* rows, double* weights, int64_t cap, Workspace& ws, const DevState* st,
                   hipStream_t s, double* wmask) {
-  const int nb = ceil_div(n, 256);
   const int nq = ceil_div(n, 1024);
   double* tpart = ws.dbl(nq);
   int* cpart = ws.i32(nq);
   uint64_t* wsum = ws.u64(nq);
-  int* pos = ws.i32((size_t)n + 1);
-  if (!tpart || !cpart || !wsum || !pos) return -1;
+  int* bsel = ws.i32(nq);
+  if (!tpart || !cpart || !wsum || !bsel) return -1;
   k_quantize<<<nq, 256, 0, s>>>(lev, n, k, tau, sb.w, sb.flags, tpart, cpart, wsum, st);
   k_sample_totals<<<1, 256, 0, s>>>(tpart, cpart, nq, sb.theta, sb.info);
   if (inclusive_scan_u64_from_sums(sb.w, sb.prefix, n, wsum, s)) return -1;
   if (s_total > 0) k_draw<<<ceil_div(s_total, 256), 256, 0, s>>>(sb.prefix, n, s_total, seed, half_iter, sb.counts, sb.info, st);
-  if (exclusive_scan_selected(sb.flags, sb.counts, pos, n, ws, s)) return -1;
-  k_emit<<<nb, 256, 0, s>>>(sb.flags, sb.counts, sb.w, sb.prefix, pos, n, rows, weights, cap, sb.info, wmask, st);
+  if (selected_block_sums(sb.flags, sb.counts, n, bsel, s)) return -1;
+  k_select_emit<<<nq, 256, 0, s>>>(sb.flags, sb.counts, sb.w, sb.prefix, bsel, n, rows, weights, cap, sb.info, wmask,
+                                   st);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 

@@ -235,8 +235,8 @@ int exclusive_scan_i32(const int* in, int* out, int n, Workspace& ws, hipStream_
 int inclusive_scan_u64(const uint64_t* in, uint64_t* out, int n, Workspace& ws, hipStream_t s);
 // the same with the block totals (sums of in over 1024-item blocks) given
 int inclusive_scan_u64_from_sums(const uint64_t* in, uint64_t* out, int n, const uint64_t* bsum, hipStream_t s);
-// exclusive scan of (det[i] || counts[i] > 0) (out has n + 1 entries)
-int exclusive_scan_selected(const int* det, const int* counts, int* out, int n, Workspace& ws, hipStream_t s);
+// the totals of (det[i] || counts[i] > 0) over 1024-row blocks (bsum: ceil(n / 1024) ints)
+int selected_block_sums(const int* det, const int* counts, int n, int* bsum, hipStream_t s);
 
 // ---- leverage-score sampling -----------------------------------------------
 int leverage_scores(const void* F, int fdtype, int n, int k, const double* Rinv, double* lev, const DevState* st,
