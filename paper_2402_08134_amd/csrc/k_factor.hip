@@ -781,8 +781,8 @@ __global__ __launch_bounds__(256) void k_col_scale(double* __restrict__ U, int n
 }
 
 // ---------------------------------------------------------------------------
-// Scans: 1024 items per block (4 per thread), block totals scanned by one
-// block, then offsets added.
+// Scans: 1024 items per block (4 per thread); the block totals, then each
+// block's pass adding the totals of the blocks before it.
 // ---------------------------------------------------------------------------
 
 // The scans' input: an array, or the sampler's selection flag of each row
@@ -1051,11 +1051,3 @@ int inclusive_scan_u64_from_sums(const uint64_t* in, uint64_t* out, int n, const
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
-int inclusive_scan_u64(const uint64_t* in, uint64_t* out, int n, Workspace& ws, hipStream_t s) {
-  const int nb = std::max(1, ceil_div(n, 1024));
-  uint64_t* bsum = ws.u64(nb);
-  if (!bsum) return -1;
-  k_scan_blocks<uint64_t><<<nb, 256, 0, s>>>(ScanArray<uint64_t>{in}, n, bsum);
-  k_scan_apply<uint64_t, true><<<nb, 256, 0, s>>>(ScanArray<uint64_t>{in}, n, bsum, out, (uint64_t*)nullptr);
-  return hipGetLastError() == hipSuccess ? 0 : -1;
-}

@@ -232,8 +232,7 @@ int column_sign_fix(double* U, int n, int l, Workspace& ws, hipStream_t s);
 
 // Scans.
 int exclusive_scan_i32(const int* in, int* out, int n, Workspace& ws, hipStream_t s);  // out has n+1 entries
-int inclusive_scan_u64(const uint64_t* in, uint64_t* out, int n, Workspace& ws, hipStream_t s);
-// the same with the block totals (sums of in over 1024-item blocks) given
+// inclusive scan of in, with its totals over 1024-item blocks given (bsum)
 int inclusive_scan_u64_from_sums(const uint64_t* in, uint64_t* out, int n, const uint64_t* bsum, hipStream_t s);
 // the totals of (det[i] || counts[i] > 0) over 1024-row blocks (bsum: ceil(n / 1024) ints)
 int selected_block_sums(const int* det, const int* counts, int n, int* bsum, hipStream_t s);
